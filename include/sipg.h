@@ -1,0 +1,208 @@
+/*
+ * sipg.h -- C ABI of the MI355X (gfx950) library for the matrix-free
+ * symmetric interior penalty (SIPG) discontinuous Galerkin Laplacian on
+ * hexahedra in the Hermite-like basis (Kronbichler, Kormann, Pasichnyk,
+ * Allalen: "A Hermite-like basis for faster matrix-free evaluation of interior
+ * penalty discontinuous Galerkin operators").
+ *
+ * Conventions shared by every entry point
+ * ---------------------------------------
+ *  - Every call returns a sipg_status (0 = success, < 0 = error).  No C++
+ *    exception crosses this boundary.  sipg_last_error() returns a
+ *    thread-local text for the most recent failure of the calling thread.
+ *  - Vectors are device pointers to ndofs contiguous elements of the
+ *    operator's precision (double for SIPG_F64, float for SIPG_F32), in the
+ *    cell-wise layout of Section 5: dof = cell * n^3 + i1 + n*i2 + n^2*i3 with
+ *    n = degree + 1, cell = ix + nx*(iy + ny*iz), xi_1 varying fastest.
+ *  - `stream` is a hipStream_t (NULL = the default stream).  Unless stated,
+ *    calls are stream ordered and do not synchronise the host.
+ *  - A sipg_op is immutable after sipg_setup: several streams may apply the
+ *    same operator concurrently as long as their output buffers differ.
+ */
+#ifndef SIPG_H
+#define SIPG_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+    SIPG_OK = 0,
+    SIPG_E_ARG = -1,         /* invalid argument (null pointer, bad size, aliasing, ...) */
+    SIPG_E_OOM = -2,         /* device allocation failed */
+    SIPG_E_HIP = -3,         /* a HIP runtime call failed; text in sipg_last_error() */
+    SIPG_E_UNSUPPORTED = -4, /* valid request this build does not provide */
+    SIPG_E_NOTREADY = -5,    /* asynchronous result not finished yet */
+    SIPG_E_NOCONV = -6,      /* iterative solve hit its iteration limit */
+    SIPG_E_BUDGET = -7       /* request exceeds the configured memory budget */
+} sipg_status;
+
+typedef enum { SIPG_BASIS_HERMITE_LIKE = 0, SIPG_BASIS_NODAL_GL = 1 } sipg_basis;
+typedef enum { SIPG_F64 = 0, SIPG_F32 = 1 } sipg_dtype;
+
+/* How metric terms are stored (Section 3 and Section 4.2):
+ *  SIPG_GEOM_AUTO   : SIPG_GEOM_CELL on undeformed meshes, else SIPG_GEOM_QPOINT.
+ *  SIPG_GEOM_CELL   : one merged tensor J^-1 J^-T det J per cell and one
+ *                     7-value record per face; the kernel multiplies by the
+ *                     quadrature weights.  Only valid for affine cells.
+ *  SIPG_GEOM_QPOINT : the merged tensor at every cell quadrature point
+ *                     (6 values) and a 7-value record at every face
+ *                     quadrature point, as for general (deformed) cells. */
+typedef enum { SIPG_GEOM_AUTO = 0, SIPG_GEOM_CELL = 1, SIPG_GEOM_QPOINT = 2 } sipg_geometry;
+
+/* Structured brick of n[0] x n[1] x n[2] hexahedra.  Cell (ix,iy,iz) is
+ * mapped from the reference cube [0,1]^3 by
+ *     X = lo + ((ix,iy,iz) + xi) * (hi - lo) / n,
+ *     Y = L X                 (L = lin, row major; all zeros means identity),
+ *     x = Y + deform_amp * sin(pi Y1) sin(pi Y2) sin(pi Y3) * (1,1,1).
+ * The first two steps give the affine benchmark geometry of Section 5; the
+ * last one is a smooth deformation that keeps the unit cube's boundary. */
+typedef struct {
+    int32_t n[3];
+    double lo[3];
+    double hi[3];
+    double lin[9];
+    double deform_amp;
+} sipg_mesh;
+
+typedef struct sipg_op sipg_op;
+
+/*
+ * Build the operator of the weak form of Section 2 (eq. discrete_laplace):
+ * cell term, interior-penalty face terms, homogeneous Dirichlet boundaries
+ * by the mirror principle (u+ = -u-, grad u+ = grad u-), tensor Gauss
+ * quadrature with degree+1 points per direction (Section 3), basis of
+ * Section 4.1 (or the nodal Gauss-Lobatto basis for comparison).
+ * Penalty: sigma_F = penalty_factor * (degree+1)^2 * max(|F|/|K-|, |F|/|K+|),
+ * which is penalty_factor * (degree+1)^2 / h on a Cartesian cell of size h
+ * (Section 2 uses penalty_factor = 1).
+ *
+ *   mesh            brick description (host memory, read during the call).
+ *   degree          polynomial degree k, 1 <= k <= 8.
+ *   penalty_factor  > 0.
+ *   basis, dtype, geometry   see the enums above.
+ *   stream          stream for the set-up kernels; the call synchronises
+ *                   that stream before it returns.
+ *   out             receives the operator handle (owned by the caller, freed
+ *                   with sipg_destroy).
+ * The operator owns all its device memory (1D tables and metric terms),
+ * allocated here with hipMalloc.  Errors: SIPG_E_ARG (null pointers, k out of
+ * range, non-positive n or penalty, SIPG_GEOM_CELL on a deformed mesh, a
+ * non-invertible map), SIPG_E_OOM, SIPG_E_HIP.
+ */
+int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int basis,
+               int dtype, int geometry, void* stream, sipg_op** out);
+
+/* Release an operator and its device memory (NULL is accepted).  The caller
+ * must make sure no work that uses it is still queued. */
+int sipg_destroy(sipg_op* op);
+
+/* Number of unknowns n_cells * (degree+1)^3, or -1 for NULL. */
+int64_t sipg_ndofs(const sipg_op* op);
+
+/* Description of the operator (host memory).  `geometry` is the resolved
+ * storage mode; `device_bytes` the operator's own device memory. */
+typedef struct {
+    int32_t degree, basis, dtype, geometry;
+    int32_t n[3];
+    int64_t ndofs;
+    int64_t device_bytes;
+    int32_t cells_per_block, threads_per_block;
+} sipg_op_info;
+int sipg_get_info(const sipg_op* op, sipg_op_info* info);
+
+/*
+ * y = A x, matrix-free (Section 3): per cell, sum factorization of the cell
+ * integral (eq. tensor_cell and its transpose), the six face integrals
+ * evaluated element-wise with the neighbour's value and derivative layers
+ * (eq. tensor_face; Section 4.2), and one write of y per cell.
+ *   x, y  device pointers, ndofs elements each, operator precision; they
+ *         must not overlap (SIPG_E_ARG).
+ * Allocates nothing; stream ordered.
+ */
+int sipg_apply(const sipg_op* op, const void* x, void* y, void* stream);
+
+/*
+ * Cell-wise tensor-product basis change between the operator's basis and the
+ * nodal Gauss-Lobatto basis, and the preconditioner of eq. (jacobi)
+ * (Section 6.3).  With E_ij = phi_i(x^GL_j), T = E^-1:
+ *   SIPG_BC_T        out = (T x T x T) in        : HL residual -> GL residual
+ *   SIPG_BC_TT       out = (T^T x T^T x T^T) in  : GL coefficients -> HL coefficients
+ *   SIPG_BC_VALUES   out = (E^T x E^T x E^T) in  : HL coefficients -> values at GL nodes
+ *   SIPG_BC_PJACOBI  out = (T^T)^{x3} diag(A_GL)^-1 T^{x3} in, the point-Jacobi
+ *                    preconditioner of the nodal GL basis expressed in the
+ *                    operator's basis (needs sipg_set_gl_diagonal first).
+ * in, out: device pointers, ndofs elements, must not overlap.  Allocates
+ * nothing; stream ordered.  SIPG_E_ARG for a bad mode or missing diagonal.
+ */
+enum { SIPG_BC_T = 0, SIPG_BC_TT = 1, SIPG_BC_VALUES = 2, SIPG_BC_PJACOBI = 3 };
+int sipg_basis_change(const sipg_op* op, int mode, const void* in, void* out, void* stream);
+
+/*
+ * Compute diag(A) of the operator in the nodal Gauss-Lobatto basis, i.e. the
+ * element-wise diagonal P_d of eq. (jacobi), and keep its inverse inside the
+ * operator for SIPG_BC_PJACOBI.  Computed on the device by the same weak form.
+ * If `diag_out` is not NULL it also receives diag(A_GL) (ndofs elements,
+ * operator precision, device memory).  Synchronises `stream`.
+ */
+int sipg_compute_gl_diagonal(sipg_op* op, void* diag_out, void* stream);
+
+/*
+ * Conjugate gradient solve of A x = b in FP64 (the outer solver of Section
+ * 6.2).  b, x: device pointers (double, ndofs); x holds the initial guess
+ * on entry and the solution on exit.  Stops when ||b - A x||_2 <= rel_tol *
+ * ||b||_2 (recursive CG residual) or after max_iter iterations
+ * (SIPG_E_NOCONV, info still filled).  Blocks the host: it reads one scalar
+ * per iteration.  Workspace (3 vectors) is allocated and freed by the call.
+ * Requires an SIPG_F64 operator.
+ */
+typedef struct {
+    int32_t iterations;
+    double initial_residual;    /* ||b - A x0||_2 */
+    double final_residual;      /* recursive residual at exit */
+    double true_residual;       /* ||b - A x||_2 recomputed at exit */
+} sipg_solve_info;
+int sipg_cg_solve(const sipg_op* op, const double* b, double* x, double rel_tol,
+                  int max_iter, sipg_solve_info* info, void* stream);
+
+/* Host-only: launch shape of the matrix-free kernel for a degree and precision:
+ * cells per workgroup, threads per workgroup and dynamic LDS bytes. */
+int sipg_launch_shape(int degree, int dtype, int32_t* cells_per_block, int32_t* threads_per_block,
+                      int64_t* lds_bytes);
+
+/* Text of the calling thread's last error ("" if none). */
+const char* sipg_last_error(void);
+
+/*
+ * Host-only: the 1D tables the kernels use, computed in double precision on
+ * the CPU (no GPU needed).  With n = degree + 1 and Gauss points x_q:
+ *   points[n], weights[n]     Gauss-Legendre rule on (0,1)
+ *   shape[n*n]                S[q*n + j]  = phi_j(x_q)
+ *   shape_grad[n*n]           S'[q*n + j] = phi_j'(x_q)
+ *   colloc_grad[n*n]          D[q*n + j]  = l_j'(x_q), Lagrange basis in the Gauss points
+ *   face_value0[n], face_grad0[n], face_value1[n], face_grad1[n]
+ *                             phi_j(0), phi_j'(0), phi_j(1), phi_j'(1)
+ *   to_gl[n*n]                T = E^-1 with E[i*n + j] = phi_i(x^GL_j), row major
+ * Any pointer may be NULL.  SIPG_E_ARG for a bad degree or basis.
+ */
+typedef struct {
+    double* points;
+    double* weights;
+    double* shape;
+    double* shape_grad;
+    double* colloc_grad;
+    double* face_value0;
+    double* face_grad0;
+    double* face_value1;
+    double* face_grad1;
+    double* to_gl;
+} sipg_tables1d;
+int sipg_host_tables(int degree, int basis, sipg_tables1d* out);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* SIPG_H */

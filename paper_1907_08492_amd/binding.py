@@ -1,0 +1,232 @@
+"""Thin ctypes binding of the C ABI in include/sipg.h.
+
+Argument marshalling only: every step of the operator runs in the HIP
+library libsipg.so.  PyTorch provides device memory and streams.  If the
+library has not been built, importing this module raises ImportError (there
+is no fallback path).
+"""
+from __future__ import annotations
+
+import ctypes as C
+import os
+from dataclasses import dataclass
+from typing import Optional
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libsipg.so")
+
+if not os.path.exists(LIB_PATH):
+    raise ImportError(f"{LIB_PATH} is missing: build it with paper_1907_08492_amd/build.py")
+lib = C.CDLL(LIB_PATH)
+
+# ----------------------------------------------------------------- constants
+SIPG_OK, SIPG_E_ARG, SIPG_E_OOM, SIPG_E_HIP, SIPG_E_UNSUPPORTED = 0, -1, -2, -3, -4
+SIPG_E_NOTREADY, SIPG_E_NOCONV, SIPG_E_BUDGET = -5, -6, -7
+BASIS = {"hermite_like": 0, "nodal_gl": 1}
+DTYPE = {"f64": 0, "f32": 1}
+GEOMETRY = {"auto": 0, "cell": 1, "qpoint": 2}
+BC_MODES = {"T": 0, "TT": 1, "VALUES": 2, "PJACOBI": 3}
+
+EXPORTED = [
+    "sipg_setup", "sipg_destroy", "sipg_ndofs", "sipg_get_info", "sipg_apply",
+    "sipg_basis_change", "sipg_compute_gl_diagonal", "sipg_cg_solve",
+    "sipg_last_error", "sipg_host_tables", "sipg_launch_shape",
+]
+
+
+class SipgMesh(C.Structure):
+    _fields_ = [("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
+                ("lin", C.c_double * 9), ("deform_amp", C.c_double)]
+
+
+class SipgOpInfo(C.Structure):
+    _fields_ = [("degree", C.c_int32), ("basis", C.c_int32), ("dtype", C.c_int32),
+                ("geometry", C.c_int32), ("n", C.c_int32 * 3), ("ndofs", C.c_int64),
+                ("device_bytes", C.c_int64), ("cells_per_block", C.c_int32),
+                ("threads_per_block", C.c_int32)]
+
+
+class SipgSolveInfo(C.Structure):
+    _fields_ = [("iterations", C.c_int32), ("initial_residual", C.c_double),
+                ("final_residual", C.c_double), ("true_residual", C.c_double)]
+
+
+class SipgTables1D(C.Structure):
+    _fields_ = [(name, C.POINTER(C.c_double)) for name in (
+        "points", "weights", "shape", "shape_grad", "colloc_grad", "face_value0",
+        "face_grad0", "face_value1", "face_grad1", "to_gl")]
+
+
+_vp = C.c_void_p
+lib.sipg_setup.argtypes = [C.POINTER(SipgMesh), C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
+                           _vp, C.POINTER(_vp)]
+lib.sipg_destroy.argtypes = [_vp]
+lib.sipg_ndofs.argtypes = [_vp]
+lib.sipg_ndofs.restype = C.c_int64
+lib.sipg_get_info.argtypes = [_vp, C.POINTER(SipgOpInfo)]
+lib.sipg_apply.argtypes = [_vp, _vp, _vp, _vp]
+lib.sipg_basis_change.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
+lib.sipg_compute_gl_diagonal.argtypes = [_vp, _vp, _vp]
+lib.sipg_cg_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
+lib.sipg_last_error.restype = C.c_char_p
+lib.sipg_host_tables.argtypes = [C.c_int, C.c_int, C.POINTER(SipgTables1D)]
+lib.sipg_launch_shape.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
+                                  C.POINTER(C.c_int64)]
+for _f in EXPORTED:
+    if _f not in ("sipg_ndofs", "sipg_last_error"):
+        getattr(lib, _f).restype = C.c_int
+
+
+class SipgError(RuntimeError):
+    def __init__(self, code: int, where: str):
+        self.code = code
+        super().__init__(f"{where} failed ({code}): {lib.sipg_last_error().decode()}")
+
+
+def _check(code: int, where: str):
+    if code != SIPG_OK:
+        raise SipgError(code, where)
+
+
+# ------------------------------------------------------------------ host-only
+def host_tables(degree: int, basis: str = "hermite_like") -> dict:
+    """1D tables computed by the library's host code (no GPU needed)."""
+    n = degree + 1
+    arrays = {k: np.zeros(n * n if k in ("shape", "shape_grad", "colloc_grad", "to_gl") else n)
+              for k, _ in SipgTables1D._fields_}
+    t = SipgTables1D(**{k: v.ctypes.data_as(C.POINTER(C.c_double)) for k, v in arrays.items()})
+    _check(lib.sipg_host_tables(degree, BASIS[basis], C.byref(t)), "sipg_host_tables")
+    for k in ("shape", "shape_grad", "colloc_grad", "to_gl"):
+        arrays[k] = arrays[k].reshape(n, n)
+    return arrays
+
+
+def launch_shape(degree: int, dtype: str = "f64"):
+    """(cells per workgroup, threads per workgroup, dynamic LDS bytes)."""
+    cpb, nt, lds = C.c_int32(), C.c_int32(), C.c_int64()
+    _check(lib.sipg_launch_shape(degree, DTYPE[dtype], C.byref(cpb), C.byref(nt), C.byref(lds)),
+           "sipg_launch_shape")
+    return cpb.value, nt.value, lds.value
+
+
+def make_mesh(mesh) -> SipgMesh:
+    """Convert any object with n, lo, hi, lin, deform_amp attributes."""
+    m = SipgMesh()
+    for d in range(3):
+        m.n[d] = int(mesh.n[d])
+        m.lo[d] = float(mesh.lo[d])
+        m.hi[d] = float(mesh.hi[d])
+    lin = getattr(mesh, "lin", None)
+    if lin is not None:
+        flat = np.asarray(lin, dtype=np.float64).reshape(9)
+        for i in range(9):
+            m.lin[i] = float(flat[i])
+    m.deform_amp = float(getattr(mesh, "deform_amp", 0.0))
+    return m
+
+
+# --------------------------------------------------------------- device side
+def _torch():
+    import torch  # noqa: WPS433 (imported lazily: host-only users need no torch)
+    return torch
+
+
+def _stream_ptr(stream) -> int:
+    torch = _torch()
+    s = stream if stream is not None else torch.cuda.current_stream()
+    return int(s.cuda_stream)
+
+
+@dataclass
+class SolveInfo:
+    iterations: int
+    initial_residual: float
+    final_residual: float
+    true_residual: float
+    status: int
+
+
+class Operator:
+    """The SIPG operator of one mesh, degree and basis on the current device."""
+
+    def __init__(self, mesh, degree: int, penalty: float = 2.0, basis: str = "hermite_like",
+                 dtype: str = "f64", geometry: str = "auto", stream=None):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("Operator needs a GPU (HIP device)")
+        self.degree = int(degree)
+        self.basis = basis
+        self.dtype_name = dtype
+        self.torch_dtype = torch.float64 if dtype == "f64" else torch.float32
+        self._mesh = make_mesh(mesh)
+        h = _vp()
+        _check(lib.sipg_setup(C.byref(self._mesh), self.degree, float(penalty), BASIS[basis],
+                              DTYPE[dtype], GEOMETRY[geometry], _vp(_stream_ptr(stream)), C.byref(h)),
+               "sipg_setup")
+        self._h = h
+        self.ndofs = int(lib.sipg_ndofs(h))
+        info = SipgOpInfo()
+        _check(lib.sipg_get_info(h, C.byref(info)), "sipg_get_info")
+        self.info = info
+
+    @property
+    def handle(self):
+        return self._h
+
+    def _vec(self, t, name):
+        torch = _torch()
+        if not isinstance(t, torch.Tensor) or not t.is_cuda:
+            raise TypeError(f"{name} must be a CUDA/HIP tensor")
+        if t.dtype != self.torch_dtype or t.numel() != self.ndofs or not t.is_contiguous():
+            raise ValueError(f"{name} must be contiguous {self.torch_dtype} with {self.ndofs} elements")
+        return _vp(t.data_ptr())
+
+    def empty(self):
+        return _torch().empty(self.ndofs, dtype=self.torch_dtype, device="cuda")
+
+    def apply(self, x, out=None, stream=None):
+        """out = A x (stream ordered)."""
+        y = self.empty() if out is None else out
+        _check(lib.sipg_apply(self._h, self._vec(x, "x"), self._vec(y, "out"), _vp(_stream_ptr(stream))),
+               "sipg_apply")
+        return y
+
+    def basis_change(self, mode: str, x, out=None, stream=None):
+        y = self.empty() if out is None else out
+        _check(lib.sipg_basis_change(self._h, BC_MODES[mode], self._vec(x, "in"), self._vec(y, "out"),
+                                     _vp(_stream_ptr(stream))), "sipg_basis_change")
+        return y
+
+    def compute_gl_diagonal(self, return_diag: bool = True, stream=None):
+        d = self.empty() if return_diag else None
+        _check(lib.sipg_compute_gl_diagonal(self._h, self._vec(d, "diag") if d is not None else None,
+                                            _vp(_stream_ptr(stream))), "sipg_compute_gl_diagonal")
+        return d
+
+    def cg_solve(self, b, x=None, rel_tol: float = 1e-10, max_iter: int = 10000, stream=None,
+                 raise_on_noconv: bool = True):
+        torch = _torch()
+        if self.dtype_name != "f64":
+            raise ValueError("cg_solve needs an f64 operator")
+        if x is None:
+            x = torch.zeros_like(b)
+        info = SipgSolveInfo()
+        rc = lib.sipg_cg_solve(self._h, self._vec(b, "b"), self._vec(x, "x"), float(rel_tol), int(max_iter),
+                               C.byref(info), _vp(_stream_ptr(stream)))
+        if rc != SIPG_OK and (rc != SIPG_E_NOCONV or raise_on_noconv):
+            raise SipgError(rc, "sipg_cg_solve")
+        return x, SolveInfo(info.iterations, info.initial_residual, info.final_residual,
+                            info.true_residual, rc)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sipg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass

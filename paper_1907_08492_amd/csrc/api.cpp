@@ -1,0 +1,315 @@
+// C ABI front end (include/sipg.h): argument checks, operator set-up on the
+// host side (1D tables), device memory ownership, dispatch to the kernels.
+#include <hip/hip_runtime.h>
+
+#include <cmath>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "basis1d.hpp"
+#include "setup.hpp"
+#include "sipg_common.hpp"
+
+namespace sipg {
+
+static thread_local std::string g_last_error;
+
+void set_error(const std::string& msg) { g_last_error = msg; }
+
+int hip_fail(hipError_t e, const char* what) {
+    g_last_error = std::string(what) + ": " + hipGetErrorString(e);
+    return e == hipErrorOutOfMemory ? SIPG_E_OOM : SIPG_E_HIP;
+}
+
+// Even-odd packing of an n x n row-major matrix (layout in sipg_common.hpp).
+template <typename T>
+static void pack_eo(const std::vector<double>& M, int n, int eps, T* out) {
+    const int h = n / 2;
+    const int oA = 0, oB = h * h, oC = 2 * h * h, oR = 2 * h * h + h, oM = 2 * h * h + 2 * h;
+    for (int i = 0; i < eo_size(n); ++i) out[i] = T(0);
+    for (int q = 0; q < h; ++q)
+        for (int j = 0; j < h; ++j) {
+            out[oA + q * h + j] = T(0.5 * (M[q * n + j] + M[q * n + n - 1 - j]));
+            out[oB + q * h + j] = T(0.5 * (M[q * n + j] - M[q * n + n - 1 - j]));
+        }
+    if (n % 2 == 1) {
+        for (int q = 0; q < h; ++q) out[oC + q] = T(M[q * n + h]);
+        for (int j = 0; j < h; ++j)
+            out[oR + j] = T(eps > 0 ? 0.5 * (M[h * n + j] + M[h * n + n - 1 - j])
+                                    : 0.5 * (M[h * n + j] - M[h * n + n - 1 - j]));
+        out[oM] = T(M[h * n + h]);
+    }
+}
+
+static std::vector<double> transpose(const std::vector<double>& M, int n) {
+    std::vector<double> t(n * n);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) t[j * n + i] = M[i * n + j];
+    return t;
+}
+
+template <typename T>
+static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl) {
+    const int n = t.n;
+    const TableLayout L(n);
+    std::vector<T> tab(L.total + 1, T(0));
+    pack_eo<T>(t.S, n, +1, &tab[L.S]);
+    pack_eo<T>(transpose(t.S, n), n, +1, &tab[L.ST]);
+    pack_eo<T>(t.D, n, -1, &tab[L.D]);
+    pack_eo<T>(transpose(t.D, n), n, -1, &tab[L.DT]);
+    pack_eo<T>(t.Sg, n, -1, &tab[L.SG]);
+    pack_eo<T>(t.T, n, +1, &tab[L.T]);
+    pack_eo<T>(transpose(t.T, n), n, +1, &tab[L.TT]);
+    pack_eo<T>(transpose(t.E, n), n, +1, &tab[L.ET]);
+    for (int j = 0; j < n; ++j) {
+        tab[L.df0 + j] = T(t.g0[j]);
+        tab[L.df1 + j] = T(t.g1[j]);
+        tab[L.w + j] = T(t.weights[j]);
+        tab[L.df0gl + j] = T(gl.g0[j]);
+        tab[L.df1gl + j] = T(gl.g1[j]);
+    }
+    for (int i = 0; i < n * n; ++i) {
+        tab[L.Sgl + i] = T(gl.S[i]);
+        tab[L.SGgl + i] = T(gl.Sg[i]);
+    }
+    return tab;
+}
+
+static int free_op(sipg_op* op) {
+    if (!op) return SIPG_OK;
+    void* ptrs[] = {op->tables, op->cell_geom, op->face_geom[0], op->face_geom[1], op->face_geom[2], op->gl_inv_diag};
+    for (void* p : ptrs)
+        if (p) (void)hipFree(p);
+    delete op;
+    return SIPG_OK;
+}
+
+int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st) {
+    switch (op->n) {
+        case 2: return launch_matvec_n<2>(op, x, y, st);
+        case 3: return launch_matvec_n<3>(op, x, y, st);
+        case 4: return launch_matvec_n<4>(op, x, y, st);
+        case 5: return launch_matvec_n<5>(op, x, y, st);
+        case 6: return launch_matvec_n<6>(op, x, y, st);
+        case 7: return launch_matvec_n<7>(op, x, y, st);
+        case 8: return launch_matvec_n<8>(op, x, y, st);
+        case 9: return launch_matvec_n<9>(op, x, y, st);
+    }
+    set_error("unsupported degree");
+    return SIPG_E_UNSUPPORTED;
+}
+
+static bool ranges_overlap(const void* a, const void* b, size_t bytes) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + bytes && pb < pa + bytes;
+}
+
+}  // namespace sipg
+
+using namespace sipg;
+
+extern "C" {
+
+const char* sipg_last_error(void) { return g_last_error.c_str(); }
+
+int sipg_host_tables(int degree, int basis, sipg_tables1d* out) {
+    if (degree < 1 || degree > 15 || (basis != 0 && basis != 1) || !out) {
+        set_error("sipg_host_tables: degree must be in [1,15], basis 0 or 1, out non-null");
+        return SIPG_E_ARG;
+    }
+    Tables1D t;
+    if (!build_tables(basis, degree, t)) {
+        set_error("sipg_host_tables: singular basis-change matrix");
+        return SIPG_E_ARG;
+    }
+    const int n = degree + 1;
+    auto cp = [](double* dst, const std::vector<double>& src) {
+        if (dst) std::memcpy(dst, src.data(), sizeof(double) * src.size());
+    };
+    cp(out->points, t.points);
+    cp(out->weights, t.weights);
+    cp(out->shape, t.S);
+    cp(out->shape_grad, t.Sg);
+    cp(out->colloc_grad, t.D);
+    cp(out->face_value0, t.v0);
+    cp(out->face_grad0, t.g0);
+    cp(out->face_value1, t.v1);
+    cp(out->face_grad1, t.g1);
+    cp(out->to_gl, t.T);
+    (void)n;
+    return SIPG_OK;
+}
+
+int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int basis, int dtype,
+               int geometry, void* stream, sipg_op** out) {
+    if (!mesh || !out) { set_error("sipg_setup: null mesh or out"); return SIPG_E_ARG; }
+    *out = nullptr;
+    if (degree < 1 || degree > 8) { set_error("sipg_setup: degree must be in [1,8]"); return SIPG_E_ARG; }
+    if (!(penalty_factor > 0.0) || !std::isfinite(penalty_factor)) { set_error("sipg_setup: penalty_factor must be > 0"); return SIPG_E_ARG; }
+    if (basis != SIPG_BASIS_HERMITE_LIKE && basis != SIPG_BASIS_NODAL_GL) { set_error("sipg_setup: bad basis"); return SIPG_E_ARG; }
+    if (dtype != SIPG_F64 && dtype != SIPG_F32) { set_error("sipg_setup: bad dtype"); return SIPG_E_ARG; }
+    if (geometry < SIPG_GEOM_AUTO || geometry > SIPG_GEOM_QPOINT) { set_error("sipg_setup: bad geometry mode"); return SIPG_E_ARG; }
+    for (int d = 0; d < 3; ++d) {
+        if (mesh->n[d] <= 0) { set_error("sipg_setup: cell counts must be positive"); return SIPG_E_ARG; }
+        if (!(mesh->hi[d] > mesh->lo[d])) { set_error("sipg_setup: need hi > lo in every direction"); return SIPG_E_ARG; }
+    }
+    const int64_t ncells = int64_t(mesh->n[0]) * mesh->n[1] * mesh->n[2];
+    const int n = degree + 1;
+    if (ncells * n * n * n > (int64_t(1) << 31) - 1 || ncells > (int64_t(1) << 30)) {
+        set_error("sipg_setup: mesh too large (dofs must fit in 31 bits)");
+        return SIPG_E_ARG;
+    }
+    if (geometry == SIPG_GEOM_CELL && mesh->deform_amp != 0.0) {
+        set_error("sipg_setup: per-cell geometry requires an undeformed (affine) mesh");
+        return SIPG_E_ARG;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    sipg_op* op = new (std::nothrow) sipg_op();
+    if (!op) { set_error("sipg_setup: out of host memory"); return SIPG_E_OOM; }
+    op->degree = degree;
+    op->n = n;
+    op->basis = basis;
+    op->dtype = dtype;
+    op->geom = geometry == SIPG_GEOM_AUTO ? (mesh->deform_amp != 0.0 ? GEOM_QPOINT : GEOM_CELL) : geometry;
+    op->eta = penalty_factor;
+    for (int d = 0; d < 3; ++d) op->nc[d] = mesh->n[d];
+    op->ncells = ncells;
+    op->ndofs = ncells * n * n * n;
+    MeshDev& m = op->mesh;
+    bool lin_zero = true;
+    for (int i = 0; i < 9; ++i) lin_zero = lin_zero && mesh->lin[i] == 0.0;
+    for (int d = 0; d < 3; ++d) {
+        m.n[d] = mesh->n[d];
+        m.lo[d] = mesh->lo[d];
+        m.h[d] = (mesh->hi[d] - mesh->lo[d]) / mesh->n[d];
+    }
+    for (int i = 0; i < 9; ++i) m.L[i] = lin_zero ? (i % 4 == 0 ? 1.0 : 0.0) : mesh->lin[i];
+    m.a = mesh->deform_amp;
+    {
+        const double* L = m.L;
+        const double det = L[0] * (L[4] * L[8] - L[5] * L[7]) - L[1] * (L[3] * L[8] - L[5] * L[6]) +
+                           L[2] * (L[3] * L[7] - L[4] * L[6]);
+        if (!(det > 0.0)) { free_op(op); set_error("sipg_setup: linear map must have a positive determinant"); return SIPG_E_ARG; }
+    }
+    hipError_t e = hipGetDevice(&op->device);
+    if (e != hipSuccess) { free_op(op); return hip_fail(e, "hipGetDevice"); }
+
+    Tables1D t, tgl;
+    if (!build_tables(basis, degree, t) || !build_tables(SIPG_BASIS_NODAL_GL, degree, tgl)) {
+        free_op(op);
+        set_error("sipg_setup: singular basis change");
+        return SIPG_E_ARG;
+    }
+    const size_t esz = dtype == SIPG_F64 ? 8 : 4;
+    const TableLayout L(n);
+    const size_t tab_bytes = esz * (L.total + 1);
+    for (int d = 0; d < 3; ++d) {
+        int64_t nf = 1;
+        for (int k = 0; k < 3; ++k) nf *= (k == d ? mesh->n[k] + 1 : mesh->n[k]);
+        op->nfaces[d] = nf;
+    }
+    const size_t cg_bytes = esz * size_t(ncells) * cell_geom_stride(op->geom, n);
+    auto fail = [&](hipError_t err, const char* what) { free_op(op); return hip_fail(err, what); };
+    if ((e = hipMalloc(&op->tables, tab_bytes)) != hipSuccess) return fail(e, "hipMalloc(tables)");
+    if ((e = hipMalloc(&op->cell_geom, cg_bytes)) != hipSuccess) return fail(e, "hipMalloc(cell geometry)");
+    op->device_bytes = int64_t(tab_bytes + cg_bytes);
+    for (int d = 0; d < 3; ++d) {
+        const size_t fb = esz * size_t(op->nfaces[d]) * face_geom_stride(op->geom, n);
+        if ((e = hipMalloc(&op->face_geom[d], fb)) != hipSuccess) return fail(e, "hipMalloc(face geometry)");
+        op->device_bytes += int64_t(fb);
+    }
+    if (dtype == SIPG_F64) {
+        std::vector<double> tab = make_table<double>(t, tgl);
+        if ((e = hipMemcpyAsync(op->tables, tab.data(), tab_bytes, hipMemcpyHostToDevice, st)) != hipSuccess) return fail(e, "hipMemcpy(tables)");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "hipStreamSynchronize");
+        const int rc = build_geometry<double>(op, t.points, t.weights, st);
+        if (rc != SIPG_OK) { free_op(op); return rc; }
+    } else {
+        std::vector<float> tab = make_table<float>(t, tgl);
+        if ((e = hipMemcpyAsync(op->tables, tab.data(), tab_bytes, hipMemcpyHostToDevice, st)) != hipSuccess) return fail(e, "hipMemcpy(tables)");
+        if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "hipStreamSynchronize");
+        const int rc = build_geometry<float>(op, t.points, t.weights, st);
+        if (rc != SIPG_OK) { free_op(op); return rc; }
+    }
+    *out = op;
+    return SIPG_OK;
+}
+
+int sipg_destroy(sipg_op* op) { return free_op(op); }
+
+int sipg_launch_shape(int degree, int dtype, int32_t* cpb, int32_t* nt, int64_t* lds) {
+    if (degree < 1 || degree > 8 || (dtype != SIPG_F64 && dtype != SIPG_F32)) {
+        set_error("sipg_launch_shape: degree must be in [1,8], dtype SIPG_F64 or SIPG_F32");
+        return SIPG_E_ARG;
+    }
+    const int n = degree + 1;
+    if (cpb) *cpb = cells_per_block(n);
+    if (nt) *nt = threads_per_block(n);
+    if (lds) *lds = int64_t(matvec_lds_bytes_rt(n, dtype == SIPG_F64 ? 8 : 4));
+    return SIPG_OK;
+}
+
+int64_t sipg_ndofs(const sipg_op* op) { return op ? op->ndofs : -1; }
+
+int sipg_get_info(const sipg_op* op, sipg_op_info* info) {
+    if (!op || !info) { set_error("sipg_get_info: null argument"); return SIPG_E_ARG; }
+    info->degree = op->degree;
+    info->basis = op->basis;
+    info->dtype = op->dtype;
+    info->geometry = op->geom;
+    for (int d = 0; d < 3; ++d) info->n[d] = op->nc[d];
+    info->ndofs = op->ndofs;
+    info->device_bytes = op->device_bytes;
+    info->cells_per_block = cells_per_block(op->n);
+    info->threads_per_block = threads_per_block(op->n);
+    return SIPG_OK;
+}
+
+int sipg_apply(const sipg_op* op, const void* x, void* y, void* stream) {
+    if (!op || !x || !y) { set_error("sipg_apply: null argument"); return SIPG_E_ARG; }
+    const size_t bytes = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
+    if (ranges_overlap(x, y, bytes)) { set_error("sipg_apply: x and y overlap"); return SIPG_E_ARG; }
+    return launch_matvec(op, x, y, static_cast<hipStream_t>(stream));
+}
+
+int sipg_basis_change(const sipg_op* op, int mode, const void* in, void* out, void* stream) {
+    if (!op || !in || !out) { set_error("sipg_basis_change: null argument"); return SIPG_E_ARG; }
+    if (mode < SIPG_BC_T || mode > SIPG_BC_PJACOBI) { set_error("sipg_basis_change: bad mode"); return SIPG_E_ARG; }
+    if (mode == SIPG_BC_PJACOBI && !op->gl_inv_diag) {
+        set_error("sipg_basis_change: SIPG_BC_PJACOBI needs sipg_compute_gl_diagonal first");
+        return SIPG_E_ARG;
+    }
+    const size_t bytes = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
+    if (ranges_overlap(in, out, bytes)) { set_error("sipg_basis_change: in and out overlap"); return SIPG_E_ARG; }
+    return launch_basis_change(op, mode, in, out, static_cast<hipStream_t>(stream));
+}
+
+int sipg_compute_gl_diagonal(sipg_op* op, void* diag_out, void* stream) {
+    if (!op) { set_error("sipg_compute_gl_diagonal: null operator"); return SIPG_E_ARG; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const size_t bytes = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
+    if (!op->gl_inv_diag) {
+        hipError_t e = hipMalloc(&op->gl_inv_diag, bytes);
+        if (e != hipSuccess) { op->gl_inv_diag = nullptr; return hip_fail(e, "hipMalloc(gl diagonal)"); }
+        op->device_bytes += int64_t(bytes);
+    }
+    const int rc = launch_gl_diagonal(op, diag_out, st);
+    if (rc != SIPG_OK) return rc;
+    SIPG_HIP(hipStreamSynchronize(st));
+    return SIPG_OK;
+}
+
+int sipg_cg_solve(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
+                  sipg_solve_info* info, void* stream) {
+    if (!op || !b || !x || !info) { set_error("sipg_cg_solve: null argument"); return SIPG_E_ARG; }
+    if (op->dtype != SIPG_F64) { set_error("sipg_cg_solve: needs an SIPG_F64 operator"); return SIPG_E_ARG; }
+    if (!(rel_tol > 0.0) || max_iter < 0) { set_error("sipg_cg_solve: rel_tol must be > 0, max_iter >= 0"); return SIPG_E_ARG; }
+    if (ranges_overlap(b, x, size_t(op->ndofs) * 8)) { set_error("sipg_cg_solve: b and x overlap"); return SIPG_E_ARG; }
+    std::memset(info, 0, sizeof(*info));
+    return cg_solve_device(op, b, x, rel_tol, max_iter, info, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

@@ -1,0 +1,266 @@
+// Host-side 1D polynomial machinery (see basis1d.hpp).
+//
+// Roots are bracketed by sign changes of the three-term recurrence on a fine
+// grid, bisected and polished by Newton steps; every basis function is kept
+// as a scale and a list of roots so that evaluation never goes through
+// monomial coefficients.
+#include "basis1d.hpp"
+
+#include <cmath>
+#include <algorithm>
+
+namespace sipg {
+
+double ProductPoly::value(double x) const {
+    if (mirror) x = 1.0 - x;
+    double v = c;
+    for (double r : roots) v *= (x - r);
+    return v;
+}
+
+double ProductPoly::deriv(double x) const {
+    const double sgn = mirror ? -1.0 : 1.0;
+    if (mirror) x = 1.0 - x;
+    double s = 0.0;
+    for (size_t k = 0; k < roots.size(); ++k) {
+        double t = c;
+        for (size_t l = 0; l < roots.size(); ++l)
+            if (l != k) t *= (x - roots[l]);
+        s += t;
+    }
+    return sgn * s;
+}
+
+// P_m^{(a,b)}(x) and its derivative by the standard recurrence in m.
+static void jacobi_eval(int m, double a, double b, double x, double& p, double& dp) {
+    double p0 = 1.0;
+    if (m == 0) { p = 1.0; dp = 0.0; return; }
+    double p1 = 0.5 * (a - b + (a + b + 2.0) * x);
+    for (int k = 2; k <= m; ++k) {
+        const double kk = k;
+        const double s = 2.0 * kk + a + b;
+        const double c1 = 2.0 * kk * (kk + a + b) * (s - 2.0);
+        const double c2 = (s - 1.0) * (a * a - b * b);
+        const double c3 = (s - 2.0) * (s - 1.0) * s;
+        const double c4 = 2.0 * (kk + a - 1.0) * (kk + b - 1.0) * s;
+        const double p2 = ((c2 + c3 * x) * p1 - c4 * p0) / c1;
+        p0 = p1;
+        p1 = p2;
+    }
+    p = p1;
+    // d/dx P_m^{(a,b)} = (m + a + b + 1)/2 * P_{m-1}^{(a+1,b+1)}
+    double q, dq;
+    jacobi_eval(m - 1, a + 1.0, b + 1.0, x, q, dq);
+    dp = 0.5 * (m + a + b + 1.0) * q;
+}
+
+std::vector<double> jacobi_roots(int m, double a, double b) {
+    std::vector<double> roots;
+    if (m <= 0) return roots;
+    const int grid = 20000;
+    double xl = -1.0, pl, dpl;
+    jacobi_eval(m, a, b, xl, pl, dpl);
+    for (int i = 1; i <= grid && (int)roots.size() < m; ++i) {
+        const double xr = -1.0 + 2.0 * i / grid;
+        double pr, dpr;
+        jacobi_eval(m, a, b, xr, pr, dpr);
+        if (pr == 0.0) { roots.push_back(xr); xl = xr; pl = pr; continue; }
+        if (pl * pr < 0.0) {
+            double lo = xl, hi = xr, flo = pl;
+            for (int it = 0; it < 200 && hi - lo > 1e-15; ++it) {
+                const double mid = 0.5 * (lo + hi);
+                double fm, dfm;
+                jacobi_eval(m, a, b, mid, fm, dfm);
+                if ((fm < 0.0) == (flo < 0.0)) { lo = mid; flo = fm; } else { hi = mid; }
+            }
+            double x = 0.5 * (lo + hi);
+            for (int it = 0; it < 3; ++it) {
+                double f, df;
+                jacobi_eval(m, a, b, x, f, df);
+                if (df != 0.0) x -= f / df;
+            }
+            roots.push_back(x);
+        }
+        xl = xr;
+        pl = pr;
+    }
+    std::sort(roots.begin(), roots.end());
+    // exact symmetry for a == b
+    if (a == b) {
+        for (int i = 0; i < m / 2; ++i) {
+            const double s = 0.5 * (roots[m - 1 - i] - roots[i]);
+            roots[i] = -s;
+            roots[m - 1 - i] = s;
+        }
+        if (m % 2 == 1) roots[m / 2] = 0.0;
+    }
+    return roots;
+}
+
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w) {
+    const std::vector<double> r = jacobi_roots(n, 0.0, 0.0);
+    x.resize(n);
+    w.resize(n);
+    for (int i = 0; i < n; ++i) {
+        double p, dp;
+        jacobi_eval(n, 0.0, 0.0, r[i], p, dp);
+        x[i] = 0.5 * (r[i] + 1.0);
+        w[i] = 0.5 * 2.0 / ((1.0 - r[i] * r[i]) * dp * dp);   // mapped to (0,1)
+    }
+}
+
+std::vector<double> gauss_lobatto_points(int n) {
+    std::vector<double> x(n);
+    x[0] = 0.0;
+    x[n - 1] = 1.0;
+    const std::vector<double> r = jacobi_roots(n - 2, 1.0, 1.0);
+    for (int i = 0; i < n - 2; ++i) x[i + 1] = 0.5 * (r[i] + 1.0);
+    return x;
+}
+
+// Hermite-like basis of degree p (Section 4.1, Appendix A).
+static std::vector<ProductPoly> hermite_like(int p) {
+    std::vector<ProductPoly> f;
+    if (p == 1) {
+        f.push_back({-1.0, {1.0}, false});
+        f.push_back({1.0, {0.0}, false});
+        return f;
+    }
+    if (p == 2) {
+        f.push_back({1.0, {1.0, 1.0}, false});
+        f.push_back({-2.0, {0.0, 1.0}, false});
+        f.push_back({1.0, {0.0, 0.0}, false});
+        return f;
+    }
+    // interior nodes: roots of P^{4,4}_{p-3} mapped to (0,1)
+    std::vector<double> nodes = jacobi_roots(p - 3, 4.0, 4.0);
+    for (double& r : nodes) r = 0.5 * (r + 1.0);
+    // g(xi) = (xi - 1)^2 prod (xi - r_l)
+    ProductPoly g{1.0, {1.0, 1.0}, false};
+    for (double r : nodes) g.roots.push_back(r);
+    // free root of phi_0 from orthogonality of phi_0 = c0 (xi - s) g and
+    // phi_1 = c1 xi g:  s = int xi^2 g^2 / int xi g^2 (exact with p+2 points)
+    std::vector<double> xq, wq;
+    gauss_rule(p + 2, xq, wq);
+    double num = 0.0, den = 0.0;
+    for (size_t q = 0; q < xq.size(); ++q) {
+        const double gv = g.value(xq[q]);
+        num += wq[q] * xq[q] * xq[q] * gv * gv;
+        den += wq[q] * xq[q] * gv * gv;
+    }
+    const double s = num / den;
+    const double g0 = g.value(0.0), dg0 = g.deriv(0.0);
+    const double c0 = 1.0 / (-s * g0);                 // phi_0(0) = 1
+    const double d0 = c0 * (g0 - s * dg0);             // phi_0'(0)
+    const double c1 = -d0 / g0;                        // phi_1'(0) = -phi_0'(0)
+    ProductPoly phi0{c0, {s}, false};
+    ProductPoly phi1{c1, {0.0}, false};
+    for (double r : g.roots) { phi0.roots.push_back(r); phi1.roots.push_back(r); }
+    f.push_back(phi0);
+    f.push_back(phi1);
+    for (size_t m = 0; m < nodes.size(); ++m) {
+        ProductPoly b{1.0, {0.0, 0.0, 1.0, 1.0}, false};
+        for (size_t l = 0; l < nodes.size(); ++l)
+            if (l != m) b.roots.push_back(nodes[l]);
+        b.c = 1.0 / b.value(nodes[m]);
+        f.push_back(b);
+    }
+    ProductPoly m1 = phi1; m1.mirror = true;
+    ProductPoly m0 = phi0; m0.mirror = true;
+    f.push_back(m1);
+    f.push_back(m0);
+    return f;
+}
+
+static std::vector<ProductPoly> nodal_gl(int p) {
+    const std::vector<double> x = gauss_lobatto_points(p + 1);
+    std::vector<ProductPoly> f;
+    for (int j = 0; j <= p; ++j) {
+        ProductPoly l{1.0, {}, false};
+        double den = 1.0;
+        for (int m = 0; m <= p; ++m)
+            if (m != j) { l.roots.push_back(x[m]); den *= (x[j] - x[m]); }
+        l.c = 1.0 / den;
+        f.push_back(l);
+    }
+    return f;
+}
+
+std::vector<ProductPoly> make_basis(int kind, int p) {
+    return kind == 0 ? hermite_like(p) : nodal_gl(p);
+}
+
+// Gauss-Jordan inverse with partial pivoting (n <= 16).
+static bool invert(int n, const std::vector<double>& A, std::vector<double>& Ai) {
+    std::vector<double> M(A);
+    Ai.assign(n * n, 0.0);
+    for (int i = 0; i < n; ++i) Ai[i * n + i] = 1.0;
+    for (int c = 0; c < n; ++c) {
+        int piv = c;
+        for (int r = c + 1; r < n; ++r)
+            if (std::fabs(M[r * n + c]) > std::fabs(M[piv * n + c])) piv = r;
+        if (M[piv * n + c] == 0.0) return false;
+        if (piv != c)
+            for (int k = 0; k < n; ++k) {
+                std::swap(M[c * n + k], M[piv * n + k]);
+                std::swap(Ai[c * n + k], Ai[piv * n + k]);
+            }
+        const double inv = 1.0 / M[c * n + c];
+        for (int k = 0; k < n; ++k) { M[c * n + k] *= inv; Ai[c * n + k] *= inv; }
+        for (int r = 0; r < n; ++r)
+            if (r != c) {
+                const double f = M[r * n + c];
+                if (f == 0.0) continue;
+                for (int k = 0; k < n; ++k) {
+                    M[r * n + k] -= f * M[c * n + k];
+                    Ai[r * n + k] -= f * Ai[c * n + k];
+                }
+            }
+    }
+    return true;
+}
+
+bool build_tables(int kind, int p, Tables1D& t) {
+    const int n = p + 1;
+    t.n = n;
+    gauss_rule(n, t.points, t.weights);
+    const std::vector<ProductPoly> f = make_basis(kind, p);
+    t.S.assign(n * n, 0.0);
+    t.Sg.assign(n * n, 0.0);
+    for (int q = 0; q < n; ++q)
+        for (int j = 0; j < n; ++j) {
+            t.S[q * n + j] = f[j].value(t.points[q]);
+            t.Sg[q * n + j] = f[j].deriv(t.points[q]);
+        }
+    // collocation derivative: Lagrange polynomials in the Gauss points, via
+    // barycentric weights lambda_j = 1 / prod_{m != j} (x_j - x_m)
+    std::vector<double> lam(n, 1.0);
+    for (int j = 0; j < n; ++j)
+        for (int m = 0; m < n; ++m)
+            if (m != j) lam[j] /= (t.points[j] - t.points[m]);
+    t.D.assign(n * n, 0.0);
+    for (int q = 0; q < n; ++q) {
+        double diag = 0.0;
+        for (int j = 0; j < n; ++j)
+            if (j != q) {
+                const double v = (lam[j] / lam[q]) / (t.points[q] - t.points[j]);
+                t.D[q * n + j] = v;
+                diag -= v;
+            }
+        t.D[q * n + q] = diag;
+    }
+    t.v0.resize(n); t.g0.resize(n); t.v1.resize(n); t.g1.resize(n);
+    for (int j = 0; j < n; ++j) {
+        t.v0[j] = f[j].value(0.0);
+        t.g0[j] = f[j].deriv(0.0);
+        t.v1[j] = f[j].value(1.0);
+        t.g1[j] = f[j].deriv(1.0);
+    }
+    const std::vector<double> xgl = gauss_lobatto_points(n);
+    t.E.assign(n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) t.E[i * n + j] = f[i].value(xgl[j]);
+    return invert(n, t.E, t.T);
+}
+
+}  // namespace sipg

@@ -1,0 +1,42 @@
+// Host-side 1D polynomial machinery for the operator set-up: Jacobi roots,
+// Gauss and Gauss-Lobatto rules, the Hermite-like basis of Section 4.1 and
+// the nodal Gauss-Lobatto basis, all in double precision and in product form.
+#pragma once
+
+#include <vector>
+
+namespace sipg {
+
+// p(xi) = c * prod_l (xi - r_l); `mirror` evaluates p(1 - xi) instead.
+struct ProductPoly {
+    double c = 1.0;
+    std::vector<double> roots;
+    bool mirror = false;
+    double value(double x) const;
+    double deriv(double x) const;
+};
+
+// Roots of the Jacobi polynomial P_m^{(a,b)} on (-1,1), ascending.
+std::vector<double> jacobi_roots(int m, double a, double b);
+
+// Gauss-Legendre rule with n points on (0,1).
+void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);
+
+// The n Gauss-Lobatto points on [0,1].
+std::vector<double> gauss_lobatto_points(int n);
+
+// Degree-p 1D basis: 0 = Hermite-like, 1 = nodal Gauss-Lobatto Lagrange.
+std::vector<ProductPoly> make_basis(int kind, int p);
+
+// All 1D tables (see sipg_host_tables in sipg.h), n = p + 1, row major.
+struct Tables1D {
+    int n = 0;
+    std::vector<double> points, weights;
+    std::vector<double> S, Sg, D;          // S[q][j], S'[q][j], D[q][j]
+    std::vector<double> v0, g0, v1, g1;    // face values/derivatives at 0 and 1
+    std::vector<double> T;                 // E^-1, E[i][j] = phi_i(x^GL_j)
+    std::vector<double> E;
+};
+bool build_tables(int kind, int p, Tables1D& t);
+
+}  // namespace sipg

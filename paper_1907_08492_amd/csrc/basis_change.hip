@@ -1,0 +1,143 @@
+// Cell-wise tensor-product basis change and the preconditioner of eq.
+// (jacobi), Section 6.3:  out = (M3 x M2 x M1) in  with the same 1D matrix M
+// in every direction, optionally  (T^T)^{x3} diag^-1 T^{x3}.  One thread per
+// pencil, sweeps through LDS, coalesced loads and stores of whole cells.
+#include "sipg_common.hpp"
+#include "sumfac.hpp"
+#include "setup.hpp"
+
+namespace sipg {
+
+template <int N>
+struct BcShape {
+    static constexpr int RS = (N % 2 == 0) ? N + 1 : N;
+    static constexpr int CS = RS * N * N;
+    static constexpr int CPB = cells_per_block(N);
+    static constexpr int NT = threads_per_block(N);
+    __device__ static constexpr int idx(int i1, int i2, int i3) { return i1 + RS * (i2 + N * i3); }
+};
+
+// MODE: 0 = apply M (table offset moff) in all directions; 1 = P^-1 with
+// T (table TL.T), the inverse diagonal, then T^T (table TL.TT).
+template <int N, typename T, int MODE>
+__global__ void __launch_bounds__(BcShape<N>::NT)
+basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ tab,
+                    int moff, const T* __restrict__ inv_diag, int ncells) {
+    using Sh = BcShape<N>;
+    constexpr int N2 = N * N, N3 = N2 * N, CPB = Sh::CPB, NT = Sh::NT, CS = Sh::CS;
+    constexpr TableLayout TL(N);
+    __shared__ T lds[CPB * CS];
+    const int tid = threadIdx.x;
+    const int cell0 = blockIdx.x * CPB;
+    const int ncb = min(CPB, ncells - cell0);
+    const T* __restrict__ src = in + size_t(cell0) * N3;
+    for (int e = tid; e < ncb * N3; e += NT) {
+        const int c = e / N3, i = e % N3;
+        lds[c * CS + Sh::idx(i % N, (i / N) % N, i / N2)] = src[e];
+    }
+    __syncthreads();
+    const int c = tid / N2, t = tid % N2, ta = t % N, tb = t / N;
+    const bool act = c < ncb;
+    T* A = lds + (act ? c : 0) * CS;
+    const T* M = tab + (MODE == 0 ? moff : TL.T);
+    T v[N];
+    // z
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(ta, tb, k)];
+        eo_apply<N, +1>(M, v, v);
+#pragma unroll
+        for (int k = 0; k < N; ++k) A[Sh::idx(ta, tb, k)] = v[k];
+    }
+    __syncthreads();
+    // y
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(ta, k, tb)];
+        eo_apply<N, +1>(M, v, v);
+#pragma unroll
+        for (int k = 0; k < N; ++k) A[Sh::idx(ta, k, tb)] = v[k];
+    }
+    __syncthreads();
+    // x (and for the preconditioner: diagonal scaling, then T^T along x)
+    if (act) {
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(k, ta, tb)];
+        eo_apply<N, +1>(M, v, v);
+        if constexpr (MODE == 1) {
+            const T* dg = inv_diag + size_t(cell0 + c) * N3 + N * (ta + N * tb);
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] *= dg[k];
+            eo_apply<N, +1>(tab + TL.TT, v, v);
+        }
+#pragma unroll
+        for (int k = 0; k < N; ++k) A[Sh::idx(k, ta, tb)] = v[k];
+    }
+    __syncthreads();
+    if constexpr (MODE == 1) {
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(ta, k, tb)];
+            eo_apply<N, +1>(tab + TL.TT, v, v);
+#pragma unroll
+            for (int k = 0; k < N; ++k) A[Sh::idx(ta, k, tb)] = v[k];
+        }
+        __syncthreads();
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(ta, tb, k)];
+            eo_apply<N, +1>(tab + TL.TT, v, v);
+            T* __restrict__ dst = out + size_t(cell0 + c) * N3 + ta + N * tb;
+#pragma unroll
+            for (int k = 0; k < N; ++k) dst[k * N2] = v[k];
+        }
+        return;
+    }
+    T* __restrict__ dst = out + size_t(cell0) * N3;
+    for (int e = tid; e < ncb * N3; e += NT) {
+        const int cc = e / N3, i = e % N3;
+        dst[e] = lds[cc * CS + Sh::idx(i % N, (i / N) % N, i / N2)];
+    }
+}
+
+template <int N, typename T>
+static int launch_bc_t(const sipg_op* op, int mode, const void* in, void* out, hipStream_t st) {
+    constexpr TableLayout TL(N);
+    const int ncells = int(op->ncells);
+    const unsigned nblk = unsigned((ncells + cells_per_block(N) - 1) / cells_per_block(N));
+    const T* tab = static_cast<const T*>(op->tables);
+    const T* i_ = static_cast<const T*>(in);
+    T* o_ = static_cast<T*>(out);
+    constexpr int NT = threads_per_block(N);
+    if (mode == SIPG_BC_PJACOBI) {
+        basis_change_kernel<N, T, 1><<<nblk, NT, 0, st>>>(i_, o_, tab, 0, static_cast<const T*>(op->gl_inv_diag), ncells);
+    } else {
+        const int off = mode == SIPG_BC_T ? TL.T : mode == SIPG_BC_TT ? TL.TT : TL.ET;
+        basis_change_kernel<N, T, 0><<<nblk, NT, 0, st>>>(i_, o_, tab, off, nullptr, ncells);
+    }
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
+template <int N>
+static int launch_bc_n(const sipg_op* op, int mode, const void* in, void* out, hipStream_t st) {
+    return op->dtype == SIPG_F64 ? launch_bc_t<N, double>(op, mode, in, out, st)
+                                 : launch_bc_t<N, float>(op, mode, in, out, st);
+}
+
+int launch_basis_change(const sipg_op* op, int mode, const void* in, void* out, hipStream_t st) {
+    switch (op->n) {
+        case 2: return launch_bc_n<2>(op, mode, in, out, st);
+        case 3: return launch_bc_n<3>(op, mode, in, out, st);
+        case 4: return launch_bc_n<4>(op, mode, in, out, st);
+        case 5: return launch_bc_n<5>(op, mode, in, out, st);
+        case 6: return launch_bc_n<6>(op, mode, in, out, st);
+        case 7: return launch_bc_n<7>(op, mode, in, out, st);
+        case 8: return launch_bc_n<8>(op, mode, in, out, st);
+        case 9: return launch_bc_n<9>(op, mode, in, out, st);
+    }
+    set_error("basis change: unsupported degree");
+    return SIPG_E_UNSUPPORTED;
+}
+
+}  // namespace sipg

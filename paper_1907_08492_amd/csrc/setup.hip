@@ -1,0 +1,213 @@
+// Operator set-up on the device: metric terms of the cells and the faces
+// (Section 3, eq. integral_laplace; Section 4.2 for the per-point storage),
+// computed in double precision from the analytic mesh map and stored in the
+// operator's precision.
+#include "sipg_common.hpp"
+#include "setup.hpp"
+
+namespace sipg {
+
+// J[a][b] = dx_a / dxi_b of the map of cell (ix, iy, iz) at reference point xi.
+__device__ void map_jacobian(const MeshDev& m, int ix, int iy, int iz, double x0, double x1,
+                             double x2, double J[9]) {
+    const double X[3] = {m.lo[0] + (ix + x0) * m.h[0], m.lo[1] + (iy + x1) * m.h[1],
+                         m.lo[2] + (iz + x2) * m.h[2]};
+    double LH[9], Y[3];
+    for (int i = 0; i < 3; ++i) {
+        Y[i] = m.L[3 * i] * X[0] + m.L[3 * i + 1] * X[1] + m.L[3 * i + 2] * X[2];
+        for (int j = 0; j < 3; ++j) LH[3 * i + j] = m.L[3 * i + j] * m.h[j];
+    }
+    if (m.a == 0.0) {
+        for (int i = 0; i < 9; ++i) J[i] = LH[i];
+        return;
+    }
+    const double pi = 3.14159265358979323846;
+    double sn[3], cs[3];
+    for (int i = 0; i < 3; ++i) sincos(pi * Y[i], &sn[i], &cs[i]);
+    const double gs[3] = {pi * cs[0] * sn[1] * sn[2], pi * sn[0] * cs[1] * sn[2],
+                          pi * sn[0] * sn[1] * cs[2]};
+    // J = (I + a (1,1,1) grad s^T) L diag(h)
+    double t[3];
+    for (int j = 0; j < 3; ++j) t[j] = gs[0] * LH[j] + gs[1] * LH[3 + j] + gs[2] * LH[6 + j];
+    for (int i = 0; i < 3; ++i)
+        for (int j = 0; j < 3; ++j) J[3 * i + j] = LH[3 * i + j] + m.a * t[j];
+}
+
+__device__ double inverse3(const double J[9], double Ji[9]) {
+    const double c00 = J[4] * J[8] - J[5] * J[7];
+    const double c01 = J[5] * J[6] - J[3] * J[8];
+    const double c02 = J[3] * J[7] - J[4] * J[6];
+    const double det = J[0] * c00 + J[1] * c01 + J[2] * c02;
+    const double id = 1.0 / det;
+    Ji[0] = c00 * id;
+    Ji[1] = (J[2] * J[7] - J[1] * J[8]) * id;
+    Ji[2] = (J[1] * J[5] - J[2] * J[4]) * id;
+    Ji[3] = c01 * id;
+    Ji[4] = (J[0] * J[8] - J[2] * J[6]) * id;
+    Ji[5] = (J[2] * J[3] - J[0] * J[5]) * id;
+    Ji[6] = c02 * id;
+    Ji[7] = (J[1] * J[6] - J[0] * J[7]) * id;
+    Ji[8] = (J[0] * J[4] - J[1] * J[3]) * id;
+    return det;
+}
+
+struct Rule {
+    double x[16], w[16];
+    int n;
+};
+
+// Cell metric: G = J^-1 J^-T det J (times w_q for per-point storage), and the
+// cell measure |K| = sum_q det J w_q.  One thread per cell.
+template <typename T, int MODE>
+__global__ void cell_geometry_kernel(MeshDev m, Rule r, T* __restrict__ out,
+                                     double* __restrict__ vol, int* __restrict__ bad, int64_t ncells) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const int ix = c % m.n[0], iy = (c / m.n[0]) % m.n[1], iz = c / (int64_t(m.n[0]) * m.n[1]);
+    const int n = r.n, n3 = n * n * n;
+    double v = 0.0;
+    for (int q = 0; q < n3; ++q) {
+        const int q1 = q % n, q2 = (q / n) % n, q3 = q / (n * n);
+        double J[9], Ji[9];
+        map_jacobian(m, ix, iy, iz, r.x[q1], r.x[q2], r.x[q3], J);
+        const double det = inverse3(J, Ji);
+        if (!(det > 0.0)) atomicOr(bad, 1);
+        const double w = r.w[q1] * r.w[q2] * r.w[q3];
+        v += det * w;
+        if (MODE == GEOM_QPOINT || q == 0) {
+            double G[6];
+            int k = 0;
+            for (int a = 0; a < 3; ++a)
+                for (int b = a; b < 3; ++b)
+                    G[k++] = (Ji[3 * a] * Ji[3 * b] + Ji[3 * a + 1] * Ji[3 * b + 1] + Ji[3 * a + 2] * Ji[3 * b + 2]) * det;
+            if (MODE == GEOM_QPOINT) {
+                for (int k2 = 0; k2 < 6; ++k2) out[c * 6 * n3 + k2 * n3 + q] = T(G[k2] * w);
+            } else {
+                for (int k2 = 0; k2 < 6; ++k2) out[c * 8 + k2] = T(G[k2]);
+                out[c * 8 + 6] = T(0);
+                out[c * 8 + 7] = T(0);
+            }
+        }
+    }
+    vol[c] = v;
+}
+
+// Face records for the faces normal to direction d, one thread per face.
+// Record = {JxW sigma, JxW J_L^-1 n, JxW J_R^-1 n} with n the unit normal
+// pointing from the lower cell L to the upper cell R; on boundary faces the
+// missing side takes the present cell's values (mirror principle).  Per-point
+// storage multiplies by the face quadrature weights; per-face storage keeps
+// the weight-free constant of an affine face.
+template <typename T, int MODE>
+__global__ void face_geometry_kernel(MeshDev m, Rule r, int d, double sigma0, T* __restrict__ out,
+                                     const double* __restrict__ vol, int64_t nfaces) {
+    const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (f >= nfaces) return;
+    int ext[3] = {m.n[0], m.n[1], m.n[2]};
+    ext[d] += 1;
+    int idx[3];
+    idx[0] = f % ext[0];
+    idx[1] = (f / ext[0]) % ext[1];
+    idx[2] = f / (int64_t(ext[0]) * ext[1]);
+    const bool hasL = idx[d] > 0, hasR = idx[d] < m.n[d];
+    int cl[3] = {idx[0], idx[1], idx[2]}, cr[3] = {idx[0], idx[1], idx[2]};
+    cl[d] -= 1;
+    const int64_t cellL = hasL ? cl[0] + int64_t(m.n[0]) * (cl[1] + int64_t(m.n[1]) * cl[2]) : -1;
+    const int64_t cellR = hasR ? cr[0] + int64_t(m.n[0]) * (cr[1] + int64_t(m.n[1]) * cr[2]) : -1;
+    const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
+    const int n = r.n, n2 = n * n;
+    const int npts = MODE == GEOM_QPOINT ? n2 : 1;
+    double area = 0.0;
+    for (int pass = 0; pass < 2; ++pass) {
+        double sigma = 0.0;
+        if (pass == 1) {
+            double ih = 0.0;
+            if (hasL) ih = fmax(ih, area / vol[cellL]);
+            if (hasR) ih = fmax(ih, area / vol[cellR]);
+            sigma = sigma0 * ih;
+        }
+        for (int q = 0; q < npts; ++q) {
+            const int qa = q % n, qb = q / n;
+            double xiL[3], xiR[3];
+            xiL[d] = 1.0;
+            xiR[d] = 0.0;
+            const double xa = MODE == GEOM_QPOINT ? r.x[qa] : 0.5, xb = MODE == GEOM_QPOINT ? r.x[qb] : 0.5;
+            const double wq = MODE == GEOM_QPOINT ? r.w[qa] * r.w[qb] : 1.0;
+            xiL[t1] = xiR[t1] = xa;
+            xiL[t2] = xiR[t2] = xb;
+            double JL[9], JLi[9], JR[9], JRi[9];
+            double detL = 0.0, detR = 0.0;
+            if (hasL) { map_jacobian(m, cl[0], cl[1], cl[2], xiL[0], xiL[1], xiL[2], JL); detL = inverse3(JL, JLi); }
+            if (hasR) { map_jacobian(m, cr[0], cr[1], cr[2], xiR[0], xiR[1], xiR[2], JR); detR = inverse3(JR, JRi); }
+            if (!hasL) { for (int i = 0; i < 9; ++i) JLi[i] = JRi[i]; detL = detR; }
+            if (!hasR) { for (int i = 0; i < 9; ++i) JRi[i] = JLi[i]; detR = detL; }
+            // own side for the measure and the normal: L if present, else R
+            const double* Ji = hasL ? JLi : JRi;
+            const double det = hasL ? detL : detR;
+            // J^-T e_d = column d of J^-1 seen as a row: (J^-T)_{a d} = Ji[d][a]
+            double nv[3] = {Ji[3 * d], Ji[3 * d + 1], Ji[3 * d + 2]};
+            const double nn = sqrt(nv[0] * nv[0] + nv[1] * nv[1] + nv[2] * nv[2]);
+            for (int k = 0; k < 3; ++k) nv[k] /= nn;
+            const double jxw = det * nn * wq;
+            if (pass == 0) { area += jxw; continue; }
+            double rec[7];
+            rec[0] = jxw * sigma;
+            for (int a = 0; a < 3; ++a) {
+                rec[1 + a] = jxw * (JLi[3 * a] * nv[0] + JLi[3 * a + 1] * nv[1] + JLi[3 * a + 2] * nv[2]);
+                rec[4 + a] = jxw * (JRi[3 * a] * nv[0] + JRi[3 * a + 1] * nv[1] + JRi[3 * a + 2] * nv[2]);
+            }
+            if (MODE == GEOM_QPOINT) {
+                for (int k = 0; k < 7; ++k) out[f * 7 * n2 + k * n2 + q] = T(rec[k]);
+            } else {
+                for (int k = 0; k < 7; ++k) out[f * 8 + k] = T(rec[k]);
+                out[f * 8 + 7] = T(0);
+            }
+        }
+    }
+}
+
+template <typename T>
+int build_geometry(sipg_op* op, const std::vector<double>& xq, const std::vector<double>& wq,
+                   hipStream_t st) {
+    Rule r{};
+    r.n = op->n;
+    for (int i = 0; i < op->n; ++i) { r.x[i] = xq[i]; r.w[i] = wq[i]; }
+    double* vol = nullptr;
+    int* bad = nullptr;
+    SIPG_HIP(hipMalloc(&vol, sizeof(double) * op->ncells));
+    SIPG_HIP(hipMalloc(&bad, sizeof(int)));
+    SIPG_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
+    const int bs = 128;
+    const unsigned gc = unsigned((op->ncells + bs - 1) / bs);
+    T* cg = static_cast<T*>(op->cell_geom);
+    if (op->geom == GEOM_QPOINT)
+        cell_geometry_kernel<T, GEOM_QPOINT><<<gc, bs, 0, st>>>(op->mesh, r, cg, vol, bad, op->ncells);
+    else
+        cell_geometry_kernel<T, GEOM_CELL><<<gc, bs, 0, st>>>(op->mesh, r, cg, vol, bad, op->ncells);
+    SIPG_HIP(hipGetLastError());
+    const double sigma0 = op->eta * double(op->degree + 1) * double(op->degree + 1);
+    for (int d = 0; d < 3; ++d) {
+        const unsigned gf = unsigned((op->nfaces[d] + bs - 1) / bs);
+        T* fg = static_cast<T*>(op->face_geom[d]);
+        if (op->geom == GEOM_QPOINT)
+            face_geometry_kernel<T, GEOM_QPOINT><<<gf, bs, 0, st>>>(op->mesh, r, d, sigma0, fg, vol, op->nfaces[d]);
+        else
+            face_geometry_kernel<T, GEOM_CELL><<<gf, bs, 0, st>>>(op->mesh, r, d, sigma0, fg, vol, op->nfaces[d]);
+        SIPG_HIP(hipGetLastError());
+    }
+    int hbad = 0;
+    SIPG_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    SIPG_HIP(hipStreamSynchronize(st));
+    SIPG_HIP(hipFree(vol));
+    SIPG_HIP(hipFree(bad));
+    if (hbad) {
+        set_error("sipg_setup: the mesh map has a non-positive Jacobian determinant");
+        return SIPG_E_ARG;
+    }
+    return SIPG_OK;
+}
+
+template int build_geometry<double>(sipg_op*, const std::vector<double>&, const std::vector<double>&, hipStream_t);
+template int build_geometry<float>(sipg_op*, const std::vector<double>&, const std::vector<double>&, hipStream_t);
+
+}  // namespace sipg

@@ -1,0 +1,30 @@
+// Internal interfaces between the C-ABI front end and the device code.
+#pragma once
+
+#include <vector>
+
+#include "sipg_common.hpp"
+
+namespace sipg {
+
+template <typename T>
+int build_geometry(sipg_op* op, const std::vector<double>& xq, const std::vector<double>& wq,
+                   hipStream_t st);
+
+// y = A x for the operator (dispatch over degree, basis, precision, geometry).
+int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st);
+// Per-degree launchers (one translation unit each).
+template <int N>
+int launch_matvec_n(const sipg_op* op, const void* x, void* y, hipStream_t st);
+
+// Cell-wise basis change / preconditioner (see sipg_basis_change).
+int launch_basis_change(const sipg_op* op, int mode, const void* in, void* out, hipStream_t st);
+
+// diag(A) in the nodal Gauss-Lobatto basis, written to `diag` (operator precision).
+int launch_gl_diagonal(const sipg_op* op, void* diag, hipStream_t st);
+
+// FP64 vector kernels of the conjugate gradient method.
+int cg_solve_device(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
+                    sipg_solve_info* info, hipStream_t st);
+
+}  // namespace sipg

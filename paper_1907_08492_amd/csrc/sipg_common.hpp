@@ -1,0 +1,103 @@
+// Shared definitions of the device code and the host library: operator
+// record, packed 1D tables, launch shapes, error helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+#include <string>
+
+#include "../../include/sipg.h"
+
+namespace sipg {
+
+// ---------------------------------------------------------------------------
+// Launch shape per n = k + 1: cells per workgroup and threads per workgroup.
+// One thread owns one n-long pencil of a cell in every sum-factorization
+// sweep, so a cell uses n^2 threads; cells are packed so that a workgroup is a
+// whole number of 64-wide wavefronts with few idle lanes.
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int cells_per_block(int n) {
+    return n == 2 ? 32 : n == 3 ? 14 : n == 4 ? 8 : n == 5 ? 5 : n == 6 ? 3
+         : n == 7 ? 2 : n == 8 ? 2 : 3;
+}
+__host__ __device__ constexpr int threads_per_block(int n) {
+    return ((cells_per_block(n) * n * n + 63) / 64) * 64;
+}
+
+// Dynamic LDS bytes of the matrix-free kernel (must match Shape<N> in
+// matvec.hpp): per cell the x/work array, 12 persistent face arrays and the
+// larger of 24 face arrays or two cell arrays, plus 12 ints of metadata.
+__host__ __device__ constexpr size_t matvec_lds_bytes_rt(int n, int esz) {
+    const int rs = (n % 2 == 0) ? n + 1 : n;
+    const int cs = rs * n * n, fa = rs * n;
+    const int ws = (24 * fa > 2 * cs) ? 24 * fa : 2 * cs;
+    return size_t(cells_per_block(n)) * (size_t(cs + 12 * fa + ws) * esz + 12 * sizeof(int));
+}
+
+// ---------------------------------------------------------------------------
+// Even-odd packed form of an n x n matrix M with M[n-1-q][n-1-j] = eps M[q][j]
+// (all 1D matrices here have this symmetry because phi_i(xi) =
+// phi_{p-i}(1-xi) and the point sets are symmetric, Section 4.1).
+// Layout, h = n/2:  A[h][h], B[h][h], C[h], R[h], M_center  (2h^2 + 2h + 1).
+//   A[q][j] = (M[q][j] + M[q][n-1-j]) / 2,  B[q][j] = (M[q][j] - M[q][n-1-j]) / 2,
+//   C[q] = M[q][h] (odd n), R = middle row (A-type for eps=+1, B-type for eps=-1).
+// ---------------------------------------------------------------------------
+__host__ __device__ constexpr int eo_size(int n) { return 2 * (n / 2) * (n / 2) + 2 * (n / 2) + 1; }
+
+// Offsets (in elements) of the packed tables of an operator.
+struct TableLayout {
+    int n, es;
+    int S, ST, D, DT, SG, T, TT, ET;   // even-odd packed matrices
+    int df0, df1, w;                   // face derivative rows at 0 and 1, Gauss weights
+    int Sgl, SGgl, df0gl, df1gl;       // plain row-major tables of the nodal GL basis
+    int total;
+    __host__ __device__ constexpr TableLayout(int n_)
+        : n(n_), es(eo_size(n_)), S(0), ST(es), D(2 * es), DT(3 * es), SG(4 * es),
+          T(5 * es), TT(6 * es), ET(7 * es), df0(8 * es), df1(8 * es + n_), w(8 * es + 2 * n_),
+          Sgl(8 * es + 3 * n_), SGgl(8 * es + 3 * n_ + n_ * n_), df0gl(8 * es + 3 * n_ + 2 * n_ * n_),
+          df1gl(8 * es + 4 * n_ + 2 * n_ * n_), total(8 * es + 5 * n_ + 2 * n_ * n_ + 1) {}
+};
+
+enum GeomMode { GEOM_CELL = 1, GEOM_QPOINT = 2 };
+
+// Number of stored values per cell / per face for each geometry mode.
+__host__ __device__ constexpr int cell_geom_stride(int mode, int n) { return mode == GEOM_CELL ? 8 : 6 * n * n * n; }
+__host__ __device__ constexpr int face_geom_stride(int mode, int n) { return mode == GEOM_CELL ? 8 : 7 * n * n; }
+
+// Mesh description in the form the device kernels take it.
+struct MeshDev {
+    int n[3];
+    double lo[3], h[3];
+    double L[9];
+    double a;
+};
+
+}  // namespace sipg
+
+// The operator handle (opaque in the C ABI).
+struct sipg_op {
+    int degree = 0, n = 0, basis = 0, dtype = 0, geom = 0;
+    int nc[3] = {0, 0, 0};
+    int64_t ncells = 0, ndofs = 0;
+    double eta = 0.0;
+    sipg::MeshDev mesh{};
+    int device = 0;
+    // device memory owned by the operator
+    void* tables = nullptr;          // packed 1D tables, operator precision
+    void* cell_geom = nullptr;       // [ncells][cell_geom_stride]
+    void* face_geom[3] = {nullptr, nullptr, nullptr};   // [nfaces_d][face_geom_stride]
+    int64_t nfaces[3] = {0, 0, 0};
+    void* gl_inv_diag = nullptr;     // 1 / diag(A_GL) for SIPG_BC_PJACOBI (optional)
+    int64_t device_bytes = 0;
+};
+
+namespace sipg {
+void set_error(const std::string& msg);
+int hip_fail(hipError_t e, const char* what);
+}  // namespace sipg
+
+#define SIPG_HIP(call)                                                 \
+    do {                                                               \
+        hipError_t e_ = (call);                                        \
+        if (e_ != hipSuccess) return sipg::hip_fail(e_, #call);        \
+    } while (0)

@@ -1,0 +1,66 @@
+// Device building blocks for sum factorization on gfx950: even-odd 1D
+// contractions on register pencils and small helpers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+namespace sipg {
+
+// out = M in for an n x n matrix in even-odd packed form (sipg_common.hpp),
+// with M[n-1-q][n-1-j] = EPS M[q][j].  Costs about n^2/2 multiply-adds
+// instead of n^2 (even-odd decomposition, Section 4.1 / Section 5).
+// `in` and `out` may be the same array.  P must be a wavefront-uniform
+// pointer so that the coefficients come through scalar loads.
+template <int N, int EPS, typename T>
+__device__ __forceinline__ void eo_apply(const T* __restrict__ P, const T* in, T* out) {
+    constexpr int H = N / 2;
+    constexpr int oA = 0, oB = H * H, oC = 2 * H * H, oR = 2 * H * H + H, oM = 2 * H * H + 2 * H;
+    T e[H], o[H];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        e[j] = in[j] + in[N - 1 - j];
+        o[j] = in[j] - in[N - 1 - j];
+    }
+    T mid = T(0);
+    if constexpr (N % 2 == 1) mid = in[H];
+#pragma unroll
+    for (int q = 0; q < H; ++q) {
+        T ev = T(0), od = T(0);
+        if constexpr (N % 2 == 1) ev = P[oC + q] * mid;
+#pragma unroll
+        for (int j = 0; j < H; ++j) {
+            ev = fma(P[oA + q * H + j], e[j], ev);
+            od = fma(P[oB + q * H + j], o[j], od);
+        }
+        if constexpr (EPS > 0) {
+            out[q] = ev + od;
+            out[N - 1 - q] = ev - od;
+        } else {
+            out[q] = ev + od;
+            out[N - 1 - q] = od - ev;
+        }
+    }
+    if constexpr (N % 2 == 1) {
+        T m = T(0);
+        if constexpr (EPS > 0) {
+            m = P[oM] * mid;
+#pragma unroll
+            for (int j = 0; j < H; ++j) m = fma(P[oR + j], e[j], m);
+        } else {
+#pragma unroll
+            for (int j = 0; j < H; ++j) m = fma(P[oR + j], o[j], m);
+        }
+        out[H] = m;
+    }
+}
+
+// P[i] for a lane-varying index 0 <= i < N, from uniform (scalar) loads.
+template <int N, typename T>
+__device__ __forceinline__ T pick(const T* __restrict__ P, int i) {
+    T r = P[0];
+#pragma unroll
+    for (int j = 1; j < N; ++j) r = (i == j) ? P[j] : r;
+    return r;
+}
+
+}  // namespace sipg

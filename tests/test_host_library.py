@@ -1,0 +1,96 @@
+"""CPU-only checks of the HIP library's host side: it loads, exports every
+symbol the header declares, its host-computed 1D tables match the oracle, the
+launch shapes respect the gfx950 limits, and argument errors are reported
+without touching a GPU."""
+import ctypes as C
+import os
+import re
+
+import numpy as np
+import pytest
+
+from oracle import basis as b1d
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+P = pytest.importorskip("paper_1907_08492_amd")
+
+
+def declared_functions():
+    text = open(os.path.join(ROOT, "include", "sipg.h")).read()
+    text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+    return sorted(set(re.findall(r"\b(sipg_[a-z0-9_]+)\s*\(", text)))
+
+
+def test_exports_every_declared_symbol():
+    names = declared_functions()
+    assert len(names) >= 10
+    for name in names:
+        assert hasattr(P.lib, name), name
+    assert set(P.EXPORTED) == set(names)
+
+
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+@pytest.mark.parametrize("k", list(range(1, 9)))
+def test_host_tables_match_oracle(basis, k):
+    t = P.host_tables(k, basis)
+    bas = b1d.make_basis(basis, k)
+    x, w = b1d.gauss(k + 1)
+    S, Sg = bas.values(x), bas.derivs(x)
+    assert np.allclose(t["points"], x, atol=1e-15, rtol=0)
+    assert np.allclose(t["weights"], w, atol=1e-15, rtol=0)
+    assert np.max(np.abs(t["shape"] - S)) < 1e-14
+    assert np.max(np.abs(t["shape_grad"] - Sg)) < 1e-14 * np.max(np.abs(Sg))
+    # collocation derivative in the Gauss points reproduces S' = D S
+    assert np.max(np.abs(t["colloc_grad"] @ S - Sg)) < 1e-13 * np.max(np.abs(Sg))
+    s0, d0, s1, d1 = b1d.face_rows(bas)
+    assert np.allclose(t["face_value0"], s0, atol=1e-14)
+    assert np.allclose(t["face_value1"], s1, atol=1e-14)
+    assert np.allclose(t["face_grad0"], d0, atol=1e-13 * np.max(np.abs(d0)))
+    assert np.allclose(t["face_grad1"], d1, atol=1e-13 * np.max(np.abs(d1)))
+    E = bas.values(b1d.gauss_lobatto_points(k + 1)).T
+    assert np.allclose(t["to_gl"] @ E, np.eye(k + 1), atol=1e-12)
+
+
+@pytest.mark.parametrize("k", list(range(1, 9)))
+@pytest.mark.parametrize("dtype", ["f64", "f32"])
+def test_launch_shape_limits(k, dtype):
+    cpb, nt, lds = P.launch_shape(k, dtype)
+    n = k + 1
+    assert nt % 64 == 0 and nt <= 1024
+    assert cpb * n * n <= nt          # one thread per pencil of every cell
+    assert lds <= 160 * 1024          # LDS of one gfx950 compute unit
+    assert cpb >= 1
+
+
+def _xcd_remap(blk, nblk):
+    """Model of the workgroup renumbering in the matrix-free kernel."""
+    per = (nblk + 7) // 8
+    xcd, slot = blk % 8, blk // 8
+    full = 8 if nblk % 8 == 0 else nblk % 8
+    start = xcd * per if xcd < full else full * per + (xcd - full) * (per - 1)
+    return start + slot
+
+
+@pytest.mark.parametrize("nblk", [1, 2, 7, 8, 9, 15, 16, 17, 63, 64, 65, 1000, 52429])
+def test_xcd_remap_is_a_permutation(nblk):
+    m = [_xcd_remap(b, nblk) for b in range(nblk)]
+    assert sorted(m) == list(range(nblk))
+
+
+def test_argument_errors_without_gpu():
+    m = P.make_mesh(type("M", (), dict(n=(2, 2, 2), lo=(0, 0, 0), hi=(1, 1, 1)))())
+    h = C.c_void_p()
+    for deg, pen, basis, dt, geo in ((0, 1.0, 0, 0, 0), (9, 1.0, 0, 0, 0), (2, 0.0, 0, 0, 0),
+                                     (2, 1.0, 5, 0, 0), (2, 1.0, 0, 7, 0), (2, 1.0, 0, 0, 9)):
+        rc = P.lib.sipg_setup(C.byref(m), deg, pen, basis, dt, geo, None, C.byref(h))
+        assert rc == -1, (deg, pen, basis, dt, geo)
+        assert P.lib.sipg_last_error().decode()
+    bad = P.make_mesh(type("M", (), dict(n=(2, 0, 2), lo=(0, 0, 0), hi=(1, 1, 1)))())
+    assert P.lib.sipg_setup(C.byref(bad), 2, 1.0, 0, 0, 0, None, C.byref(h)) == -1
+    deformed = P.make_mesh(type("M", (), dict(n=(2, 2, 2), lo=(0, 0, 0), hi=(1, 1, 1), deform_amp=0.1))())
+    assert P.lib.sipg_setup(C.byref(deformed), 2, 1.0, 0, 0, 1, None, C.byref(h)) == -1
+    assert P.lib.sipg_apply(None, None, None, None) == -1
+    assert P.lib.sipg_basis_change(None, 0, None, None, None) == -1
+    assert P.lib.sipg_ndofs(None) == -1
+    assert P.lib.sipg_destroy(None) == 0
+    assert P.lib.sipg_launch_shape(0, 0, None, None, None) == -1
