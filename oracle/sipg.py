@@ -56,17 +56,24 @@ def _tangential(d):
 
 class SIPG:
     """Discrete SIPG operator on a `workloads.Mesh` with degree k, penalty
-    factor eta and a 1D basis ("hermite_like" or "nodal_gl")."""
+    factor eta and a 1D basis ("hermite_like" or "nodal_gl").
 
-    def __init__(self, mesh, k: int, eta: float = 2.0, basis: str = "hermite_like"):
+    `cells` restricts the rows to a subset of cells (the metric terms are
+    then evaluated for those cells only); apply_naive then takes the full
+    vector and returns the rows of those cells."""
+
+    def __init__(self, mesh, k: int, eta: float = 2.0, basis: str = "hermite_like", cells=None):
         self.mesh = mesh
+        self.all_cells = cells is None
+        self.cells = np.arange(mesh.ncells) if cells is None else np.asarray(cells, dtype=np.int64)
         self.k = int(k)
         self.n = self.k + 1
         self.eta = float(eta)
         self.basis = b1d.make_basis(basis, self.k)
         self.nq = self.k + 1
-        self.ncells = mesh.ncells
+        self.ncells = len(self.cells)
         self.ndofs = self.ncells * self.n ** 3
+        self.ncells_total = mesh.ncells
         xq, wq = b1d.gauss(self.nq)
         self.xq, self.wq = xq, wq
         nq = self.nq
@@ -96,8 +103,8 @@ class SIPG:
 
     # ------------------------------------------------------------------
     def neighbor(self, d: int, s: int) -> np.ndarray:
-        """Cell across face (d, s) of every cell, -1 on the domain boundary."""
-        c = np.arange(self.ncells)
+        """Cell across face (d, s) of every row cell, -1 on the domain boundary."""
+        c = self.cells
         idx = list(cell_coords(self.mesh, c))
         step = 1 if s == 1 else -1
         j = idx[d] + step
@@ -106,8 +113,13 @@ class SIPG:
         nb = idx[0] + self.mesh.n[0] * (idx[1] + self.mesh.n[1] * idx[2])
         return np.where(ok, nb, -1)
 
+    def volumes(self, cells) -> np.ndarray:
+        """|K| = sum_q det J w_q for the given cells."""
+        _, J = map_points(self.mesh, np.asarray(cells), self.cell_pts)
+        return np.sum(np.linalg.det(J) * self.cell_w, axis=1)
+
     def _geometry(self):
-        cells = np.arange(self.ncells)
+        cells = self.cells
         _, J = map_points(self.mesh, cells, self.cell_pts)        # [C, Q, 3, 3]
         detJ = np.linalg.det(J)
         if np.any(detJ <= 0):
@@ -137,7 +149,8 @@ class SIPG:
                 _, Jnb = map_points(self.mesh, np.where(nb >= 0, nb, 0), pts_nb)
                 JnbinvT = np.swapaxes(np.linalg.inv(Jnb), -1, -2)
                 inv_h = area / self.cell_volume
-                inv_h_nb = np.where(nb >= 0, area / self.cell_volume[np.where(nb >= 0, nb, 0)], 0.0)
+                vol_nb = self.volumes(np.where(nb >= 0, nb, 0))
+                inv_h_nb = np.where(nb >= 0, area / vol_nb, 0.0)
                 sigma = self.eta * (self.k + 1) ** 2 * np.maximum(inv_h, inv_h_nb)
                 self.faces[(d, s)] = dict(JxW=JxW, normal=normal, JinvT=JinvT,
                                           JinvT_nb=JnbinvT, nb=nb, sigma=sigma)
@@ -180,6 +193,8 @@ class SIPG:
 
     def assemble(self) -> sp.csr_matrix:
         """A_ij = a_h(phi_j, phi_i) as a CSR matrix, float64."""
+        if not self.all_cells:
+            raise ValueError("assemble() needs the operator on all cells")
         C, n3 = self.ncells, self.n ** 3
         Akk, offdiag = self.local_blocks()
         rows = [np.arange(C)]
@@ -206,7 +221,8 @@ class SIPG:
         """y = A x evaluated matrix-free at the quadrature points, with dense
         per-cell evaluation matrices (no sum factorization)."""
         C, n3 = self.ncells, self.n ** 3
-        U = np.asarray(x, dtype=np.float64).reshape(C, n3)
+        Uall = np.asarray(x, dtype=np.float64).reshape(self.ncells_total, n3)
+        U = Uall if self.all_cells else Uall[self.cells]
         Gr = self.cell_grad
         gu = np.stack([U @ Gr[a].T for a in range(3)], axis=-1)          # [C, Q, 3]
         t = np.einsum("cqab,cqb->cqa", self.cell_G, gu)
@@ -216,7 +232,7 @@ class SIPG:
             val_nb, grad_nb = self.face_eval[(d, 1 - s)]
             nb = f["nb"]
             interior = nb >= 0
-            Unb = U[np.where(interior, nb, 0)]
+            Unb = Uall[np.where(interior, nb, 0)]
             um = U @ val.T                                                 # [C, Qf]
             gm = np.einsum("cqab,cqb->cqa", f["JinvT"],
                            np.stack([U @ grad[a].T for a in range(3)], axis=-1))
