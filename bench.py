@@ -1,0 +1,252 @@
+#!/usr/bin/env python3
+"""Benchmark of the hot path on one MI355X.
+
+A step is one pass of the whole hot path over one synthetic input vector:
+y = A x (matrix-free SIPG product: gather, cell and face sum factorization,
+flux, integration, one write per cell) followed by z = P^-1 y (the basis-change
+preconditioner of eq. (jacobi)).  The headline workload is the Hermite-like
+operator of degree 4 on 64^3 cells of the sine-deformed unit cube in FP64
+(32.8 M unknowns, metric terms stored per quadrature point).  Throughput
+follows eq. (throughput): unknowns times steps over the wall time of the
+timed steps, with the inputs resident in HBM.
+
+The JSON line also carries the roofline of the dominant kernel (the matvec:
+algorithmic bytes per launch over its average duration from HIP events), the
+other matvec variants of the same study (affine/deformed, k = 4 and 7,
+Hermite-like and nodal Gauss-Lobatto, FP64 and FP32), and the FP64 CPU oracle
+timed on a bounded sample on the host.
+"""
+from __future__ import annotations
+
+import argparse
+import json
+import os
+import sys
+import time
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
+FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
+# FLOP per unknown of the matrix-free product, Table 4 (Hermite-like / nodal GL)
+TABLE4_FLOP = {"hermite_like": {1: 244, 2: 191, 3: 218, 4: 206, 5: 225, 7: 241},
+               "nodal_gl": {1: 258, 2: 210, 3: 240, 4: 229, 5: 250, 7: 267}}
+
+
+def alg_bytes_per_dof(mesh, k: int, esz: int, per_point: bool) -> float:
+    """Algorithmic bytes per unknown of one matvec: read x, write y, read the
+    metric terms once (6 values per cell or per cell point, 7 per face or per
+    face point).  Neighbour layers are cache reuse and not counted again."""
+    n = k + 1
+    nx, ny, nz = mesh.n
+    ncells = nx * ny * nz
+    nfaces = (nx + 1) * ny * nz + nx * (ny + 1) * nz + nx * ny * (nz + 1)
+    ndofs = ncells * n ** 3
+    cell = 6 * (n ** 3 if per_point else 1) * ncells
+    face = 7 * (n ** 2 if per_point else 1) * nfaces
+    return esz * (2.0 + (cell + face) / ndofs)
+
+
+def make_inputs(torch, ndofs, dtype, nrot, seed0=0):
+    from workloads import uniform_vector
+    return [torch.from_numpy(uniform_vector(ndofs, seed0 + i)).to("cuda", dtype=dtype) for i in range(nrot)]
+
+
+def time_matvec(torch, op, xs, ys, launches: int, warmup: int):
+    """Average duration (s) of one matvec launch from HIP events on the stream
+    the library launches on (the current stream)."""
+    st = torch.cuda.current_stream()
+    for i in range(warmup):
+        op.apply(xs[i % len(xs)], ys[i % len(ys)])
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
+    for i in range(launches):
+        ev[i][0].record(st)
+        op.apply(xs[i % len(xs)], ys[i % len(ys)])
+        ev[i][1].record(st)
+    torch.cuda.synchronize()
+    ms = [a.elapsed_time(b) for a, b in ev]
+    return float(np.mean(ms)) * 1e-3, float(np.min(ms)) * 1e-3
+
+
+def cpu_baseline(mesh, k, eta, target_s: float):
+    """The FP64 oracle (naive matrix-free product, then the preconditioner of
+    eq. (jacobi)) on a bounded sample of cells of the same mesh."""
+    from threadpoolctl import threadpool_info
+    from oracle import precond
+    from oracle.sipg import SIPG
+    from workloads import uniform_vector
+    rng = np.random.default_rng(0)
+    nsample = min(mesh.ncells, 2048)
+    cells = np.sort(rng.choice(mesh.ncells, nsample, replace=False))
+    op = SIPG(mesh, k, eta, "hermite_like", cells=cells)
+    opg = SIPG(mesh, k, eta, "nodal_gl", cells=cells)
+    akk, _ = opg.local_blocks()
+    dgl = np.einsum("cii->ci", akk).reshape(-1)
+    del akk, opg
+    x = uniform_vector(mesh.ncells * (k + 1) ** 3, 0)
+    reps = 0
+    t0 = time.perf_counter()
+    while True:
+        y = op.apply_naive(x)
+        precond.pjacobi_hl(k, dgl, y, nsample)
+        reps += 1
+        el = time.perf_counter() - t0
+        if el >= target_s:
+            break
+    threads = max([d.get("num_threads", 1) for d in threadpool_info()] + [1])
+    return {"value": reps * nsample * (k + 1) ** 3 / el, "unit": "DoF/s", "cores": int(threads),
+            "kind": "oracle",
+            "sample": (f"{nsample} random cells of the {mesh.n[0]}^3 deformed mesh, k={k}: "
+                       f"naive matrix-free y = A x + P^-1 y in float64 NumPy, {reps} repetitions "
+                       f"in {el:.1f} s (metric terms precomputed, not timed); host os.cpu_count()="
+                       f"{os.cpu_count()}, BLAS threads={threads}")}
+
+
+def main():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=50)
+    ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--no-variants", action="store_true", help="headline workload only")
+    ap.add_argument("--no-cpu", action="store_true", help="skip the CPU oracle baseline")
+    ap.add_argument("--cpu-seconds", type=float, default=12.0)
+    ap.add_argument("--copy-probe", action="store_true",
+                    help="also run one plain 1 GiB device copy (counter calibration)")
+    args = ap.parse_args()
+    if args.gpus != 1:
+        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+              "the multi-GPU sharding is a design in DESIGN.md, not a measured path.", file=sys.stderr)
+        sys.exit(2)
+
+    import torch
+    import paper_1907_08492_amd as P
+    from workloads import CONFIGS, with_basis
+
+    assert torch.cuda.is_available(), "bench.py needs a GPU"
+    torch.cuda.set_device(0)
+    cfg = CONFIGS["scale_k4_64c_deformed"]
+    mesh, k, eta = cfg.mesh, cfg.degree, cfg.eta
+    print(f"[bench] setup {cfg.mesh.n} k={k} deformed HL f64", file=sys.stderr, flush=True)
+    op = P.Operator(mesh, k, eta, "hermite_like", "f64")
+    op.compute_gl_diagonal(return_diag=False)
+    nrot = 3
+    xs = make_inputs(torch, op.ndofs, torch.float64, nrot)
+    ys = [torch.empty_like(xs[0]) for _ in range(nrot)]
+    zs = [torch.empty_like(xs[0]) for _ in range(nrot)]
+    if args.copy_probe:
+        a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
+        b = torch.empty_like(a)
+        b.copy_(a)
+        torch.cuda.synchronize()
+        del a, b
+
+    st = torch.cuda.current_stream()
+    ev_mv = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(args.steps)]
+    ev_pj = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+             for _ in range(args.steps)]
+
+    def step(i, timed):
+        x, y, z = xs[i % nrot], ys[i % nrot], zs[i % nrot]
+        if timed:
+            ev_mv[i][0].record(st)
+        op.apply(x, y)
+        if timed:
+            ev_mv[i][1].record(st)
+            ev_pj[i][0].record(st)
+        op.basis_change("PJACOBI", y, z)
+        if timed:
+            ev_pj[i][1].record(st)
+
+    print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
+    for i in range(args.warmup):
+        step(i, False)
+    torch.cuda.synchronize()
+    print(f"[bench] timing {args.steps} steps", file=sys.stderr, flush=True)
+    t0 = time.perf_counter()
+    for i in range(args.steps):
+        step(i, True)
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    T = t1 - t0
+    mv_ms = np.array([a.elapsed_time(b) for a, b in ev_mv])
+    pj_ms = np.array([a.elapsed_time(b) for a, b in ev_pj])
+    ndofs = op.ndofs
+    value = ndofs * args.steps / T
+    bpd = alg_bytes_per_dof(mesh, k, 8, per_point=True)
+    mv_s = float(mv_ms.mean()) * 1e-3
+    achieved = bpd * ndofs / mv_s / 1e9
+    pj_bpd = 8.0 * 3          # read y, read 1/diag, write z
+    pj_s = float(pj_ms.mean()) * 1e-3
+
+    out = {
+        "metric": "SIPG matvec DoF/s (% HBM roofline)",
+        "value": value,
+        "unit": "DoF/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": T / args.steps * 1e3,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic: x ~ U[-1,1] (numpy default_rng seeds 0,1,2, rotated), metric terms of the analytic map",
+        "config": {"workload": "SIPG Hermite-like matvec + P^-1, k=4, 64^3 cells of the sine-deformed unit cube "
+                               "(amplitude 0.1), per-point metric terms, penalty 2(k+1)^2/h",
+                   "ndofs": ndofs, "degree": k, "cells": list(mesh.n), "basis": "hermite_like",
+                   "geometry": "per quadrature point", "parallelism": "1 GPU"},
+        "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "kernel": "sipg_matvec_kernel<5,0,double,2>",
+                     "alg_bytes_per_dof": bpd, "avg_launch_ms": mv_s * 1e3},
+        "matvec": {"dof_per_s": ndofs / mv_s, "avg_ms": mv_s * 1e3, "min_ms": float(mv_ms.min()),
+                   "alg_GBs": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
+                   "valu_frac_table4": TABLE4_FLOP["hermite_like"][k] * ndofs / mv_s / (FP64_PEAK_TFLOPS * 1e12)},
+        "pjacobi": {"dof_per_s": ndofs / pj_s, "avg_ms": pj_s * 1e3, "alg_GBs": pj_bpd * ndofs / pj_s / 1e9,
+                    "hbm_frac": pj_bpd * ndofs / pj_s / 1e9 / HBM_PEAK_GBS},
+    }
+    del op, xs, ys, zs
+    torch.cuda.empty_cache()
+
+    if not args.no_variants:
+        variants = []
+        plan = [("scale_k4_64c_affine", "hermite_like", "f64"), ("scale_k4_64c_affine", "nodal_gl", "f64"),
+                ("scale_k4_64c_deformed", "nodal_gl", "f64"),
+                ("scale_k7_32c_affine", "hermite_like", "f64"), ("scale_k7_32c_affine", "nodal_gl", "f64"),
+                ("scale_k7_32c_deformed", "hermite_like", "f64"), ("scale_k7_32c_deformed", "nodal_gl", "f64"),
+                ("scale_k4_64c_deformed", "hermite_like", "f32"), ("mixed_k5_48c_deformed", "hermite_like", "f32")]
+        for name, basis, dt in plan:
+            c = with_basis(CONFIGS[name], basis)
+            print(f"[bench] variant {name} {basis} {dt}", file=sys.stderr, flush=True)
+            o = P.Operator(c.mesh, c.degree, c.eta, basis, dt)
+            tdt = torch.float64 if dt == "f64" else torch.float32
+            vx = make_inputs(torch, o.ndofs, tdt, nrot)
+            vy = [torch.empty_like(vx[0]) for _ in range(nrot)]
+            avg, mn = time_matvec(torch, o, vx, vy, launches=max(10, args.steps // 2), warmup=3)
+            per_point = c.mesh.deformed
+            b = alg_bytes_per_dof(c.mesh, c.degree, 8 if dt == "f64" else 4, per_point)
+            gbs = b * o.ndofs / avg / 1e9
+            variants.append({"workload": name, "basis": basis, "dtype": dt, "ndofs": o.ndofs,
+                             "dof_per_s": o.ndofs / avg, "avg_ms": avg * 1e3, "min_ms": mn * 1e3,
+                             "alg_bytes_per_dof": b, "alg_GBs": gbs, "hbm_frac": gbs / HBM_PEAK_GBS,
+                             "table4_flop_per_dof": TABLE4_FLOP[basis].get(c.degree)})
+            o.close()
+            del vx, vy
+            torch.cuda.empty_cache()
+        out["variants"] = variants
+
+    if not args.no_cpu:
+        print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)
+        out["cpu_baseline"] = cpu_baseline(mesh, k, eta, args.cpu_seconds)
+    else:
+        out["cpu_baseline"] = None
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -19,6 +19,13 @@ LIB_PATH = os.path.join(_HERE, "libsipg.so")
 
 if not os.path.exists(LIB_PATH):
     raise ImportError(f"{LIB_PATH} is missing: build it with paper_1907_08492_amd/build.py")
+# PyTorch ships its own HIP runtime.  Load it first so that libsipg.so binds
+# to that same runtime (one HIP runtime per process; torch allocates the
+# buffers and streams the library works on).
+try:
+    import torch as _torch_first  # noqa: F401
+except ImportError:  # host-only use (tables, launch shapes) without torch
+    _torch_first = None
 lib = C.CDLL(LIB_PATH)
 
 # ----------------------------------------------------------------- constants

@@ -94,3 +94,11 @@ def test_argument_errors_without_gpu():
     assert P.lib.sipg_ndofs(None) == -1
     assert P.lib.sipg_destroy(None) == 0
     assert P.lib.sipg_launch_shape(0, 0, None, None, None) == -1
+
+
+def test_single_hip_runtime_in_process():
+    """The library binds to the HIP runtime PyTorch loaded (a second runtime in
+    the same process does not see the device)."""
+    maps = open("/proc/self/maps").read().splitlines()
+    hip = {line.split()[-1] for line in maps if "libamdhip64" in line}
+    assert len(hip) == 1, hip
