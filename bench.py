@@ -50,6 +50,34 @@ def alg_bytes_per_dof(mesh, k: int, esz: int, per_point: bool) -> float:
     return esz * (2.0 + (cell + face) / ndofs)
 
 
+KERNEL_SOURCES = ["paper_1907_08492_amd/csrc/matvec.hpp", "paper_1907_08492_amd/csrc/sumfac.hpp",
+                  "paper_1907_08492_amd/csrc/sipg_common.hpp", "paper_1907_08492_amd/csrc/matvec_n5.hip"]
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sipg_matvec_k4_64c_deformed_f64.traffic.json")
+
+
+def kernel_source_hash() -> str:
+    import hashlib
+    h = hashlib.sha256()
+    for s in KERNEL_SOURCES:
+        h.update(open(os.path.join(ROOT, s), "rb").read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(avg_launch_s: float):
+    """HBM bytes per launch from the committed rocprofv3 counter summary
+    (FETCH_SIZE and WRITE_SIZE, each scaled by what the same counter reads for
+    a plain 1 GiB device copy), as GB/s over this run's launch duration; None
+    when the kernel sources changed since the counters were taken."""
+    try:
+        t = json.load(open(TRAFFIC_FILE))
+    except (OSError, ValueError):
+        return None, None
+    if t.get("source_hash") != kernel_source_hash():
+        return None, None
+    b = t["bytes_per_launch"]
+    return b / avg_launch_s / 1e9, b
+
+
 def make_inputs(torch, ndofs, dtype, nrot, seed0=0):
     from workloads import uniform_vector
     return [torch.from_numpy(uniform_vector(ndofs, seed0 + i)).to("cuda", dtype=dtype) for i in range(nrot)]
@@ -181,6 +209,7 @@ def main():
     mv_s = float(mv_ms.mean()) * 1e-3
     achieved = bpd * ndofs / mv_s / 1e9
     pj_bpd = 8.0 * 3          # read y, read 1/diag, write z
+    traffic, traffic_bytes = measured_traffic(mv_s)
     pj_s = float(pj_ms.mean()) * 1e-3
 
     out = {
@@ -201,7 +230,8 @@ def main():
                    "ndofs": ndofs, "degree": k, "cells": list(mesh.n), "basis": "hermite_like",
                    "geometry": "per quadrature point", "parallelism": "1 GPU"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-                     "frac": achieved / HBM_PEAK_GBS, "traffic": None,
+                     "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
+                     "traffic_bytes_per_launch": traffic_bytes,
                      "kernel": "sipg_matvec_kernel<5,0,double,2>",
                      "alg_bytes_per_dof": bpd, "avg_launch_ms": mv_s * 1e3},
         "matvec": {"dof_per_s": ndofs / mv_s, "avg_ms": mv_s * 1e3, "min_ms": float(mv_ms.min()),

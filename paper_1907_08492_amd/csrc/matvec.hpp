@@ -49,6 +49,8 @@ struct Shape {
     static constexpr int CPB = cells_per_block(N);
     static constexpr int NT = threads_per_block(N);
     static constexpr int WS = (24 * FA > 2 * CS) ? 24 * FA : 2 * CS;
+    static constexpr int F1_ITEMS = (CPB * 6 * N2 + NT - 1) / NT;   // gather items per thread
+    static constexpr int F3_ITEMS = (CPB * 6 * N + NT - 1) / NT;    // flux columns per thread
     static constexpr int PER_CELL = CS + 12 * FA + WS;     // words of T per cell
     __host__ __device__ static constexpr int lds_idx(int i1, int i2, int i3) { return i1 + RS * (i2 + N * i3); }
 };
@@ -65,6 +67,33 @@ constexpr size_t matvec_lds_bytes() {
 
 // basis: 0 Hermite-like (derivative rows touch layers {0,1} / {n-2,n-1}),
 //        1 nodal Gauss-Lobatto (derivative rows touch every layer).
+// Coordinates of cell0 + c from those of cell0 (cells of a workgroup are
+// consecutive in the lexicographic order; c is small).
+__device__ __forceinline__ void cell_coords(int bx, int by, int bz, int c, int nx, int ny, int& ix, int& iy, int& iz) {
+    ix = bx + c;
+    iy = by;
+    iz = bz;
+    while (ix >= nx) {
+        ix -= nx;
+        if (++iy == ny) { iy = 0; ++iz; }
+    }
+}
+
+// Neighbour cell across face f = 2d+s of the cell (ix,iy,iz) (-1 on the
+// boundary) and the index of that face in the face arrays of direction d.
+__device__ __forceinline__ void face_topology(int ix, int iy, int iz, int f, int nx, int ny, int nz, int& nb, int& fi) {
+    const int d = f >> 1, s = f & 1;
+    const int cell = ix + nx * (iy + ny * iz);
+    int idx[3] = {ix, iy, iz};
+    const int nd[3] = {nx, ny, nz};
+    const int j = idx[d] + (s ? 1 : -1);
+    nb = (j >= 0 && j < nd[d]) ? cell + (s ? 1 : -1) * (d == 0 ? 1 : d == 1 ? nx : nx * ny) : -1;
+    idx[d] += s;
+    if (d == 0) fi = idx[0] + (nx + 1) * (idx[1] + ny * idx[2]);
+    else if (d == 1) fi = idx[0] + nx * (idx[1] + (ny + 1) * idx[2]);
+    else fi = idx[0] + nx * (idx[1] + ny * idx[2]);
+}
+
 template <int N, int BASIS>
 struct Layers {
     static constexpr int NL = (BASIS == 0) ? 2 : N;
@@ -106,24 +135,65 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     }
     const int cell0 = blk * CPB;
     const int ncb = min(CPB, p.ncells - cell0);      // cells in this workgroup
+    const int bx = cell0 % p.nx, by = (cell0 / p.nx) % p.ny, bz = cell0 / (p.nx * p.ny);
+    auto topo = [&](int c, int f, int& nb, int& fi) {
+        int ix, iy, iz;
+        cell_coords(bx, by, bz, c, p.nx, p.ny, ix, iy, iz);
+        face_topology(ix, iy, iz, f, p.nx, p.ny, p.nz, nb, fi);
+    };
 
     // ---------------------------------------------------------------- meta
     for (int it = tid; it < ncb * 6; it += NT) {
-        const int c = it / 6, f = it % 6, d = f >> 1, s = f & 1;
-        const int cell = cell0 + c;
-        const int ix = cell % p.nx, iy = (cell / p.nx) % p.ny, iz = cell / (p.nx * p.ny);
-        int idx[3] = {ix, iy, iz};
-        const int nd[3] = {p.nx, p.ny, p.nz};
-        const int j = idx[d] + (s ? 1 : -1);
-        int nb = -1;
-        if (j >= 0 && j < nd[d]) nb = cell + (s ? 1 : -1) * (d == 0 ? 1 : d == 1 ? p.nx : p.nx * p.ny);
-        int fi;
-        idx[d] += s;
-        if (d == 0) fi = idx[0] + (p.nx + 1) * (idx[1] + p.ny * idx[2]);
-        else if (d == 1) fi = idx[0] + p.nx * (idx[1] + (p.ny + 1) * idx[2]);
-        else fi = idx[0] + p.nx * (idx[1] + p.ny * idx[2]);
-        meta[c * 12 + f] = nb;
-        meta[c * 12 + 6 + f] = fi;
+        int nb, fi;
+        topo(it / 6, it % 6, nb, fi);
+        meta[(it / 6) * 12 + it % 6] = nb;
+        meta[(it / 6) * 12 + 6 + it % 6] = fi;
+    }
+
+    // Prefetch into registers, before any LDS work and without waiting for
+    // the metadata: the metric terms of this thread's first face-flux column
+    // (used in F3) and the neighbour value/derivative layers of the gather (F1).
+    constexpr int NREC = GEOM == GEOM_CELL ? 7 : 7 * N;
+    T frec[NREC];
+    if (tid < ncb * 6 * N) {
+        const int a = tid % N, f = (tid / N) % 6, c = tid / (6 * N);
+        const int d = f >> 1;
+        int nb, fidx;
+        topo(c, f, nb, fidx);
+        const T* __restrict__ fg = d == 0 ? p.fgeom0 : d == 1 ? p.fgeom1 : p.fgeom2;
+        if constexpr (GEOM == GEOM_CELL) {
+#pragma unroll
+            for (int k = 0; k < 7; ++k) frec[k] = fg[size_t(fidx) * 8 + k];
+        } else {
+#pragma unroll
+            for (int k = 0; k < 7; ++k)
+#pragma unroll
+                for (int b = 0; b < N; ++b) frec[k * N + b] = fg[size_t(fidx) * (7 * N2) + k * N2 + a + N * b];
+        }
+    }
+    const int c = tid / N2;                 // cell of this thread in the cell phases
+    const int t = tid % N2;                 // pencil of this thread
+    const int ta = t % N, tb = t / N;
+    const bool act = c < ncb;
+    T nbv[Sh::F1_ITEMS][Ly::NL];
+#pragma unroll
+    for (int r = 0; r < Sh::F1_ITEMS; ++r) {
+        const int it = tid + r * NT;
+        if (it < ncb * 6 * N2) {
+            const int a = it % N, b = (it / N) % N, f = (it / N2) % 6, c = it / (6 * N2);
+            const int d = f >> 1, s = f & 1;
+            int nb, fi;
+            topo(c, f, nb, fi);
+            if (nb >= 0) {
+                const T* __restrict__ xn = p.x + size_t(nb) * N3;
+#pragma unroll
+                for (int j = 0; j < Ly::NL; ++j) {
+                    const int l = Ly::layer(1 - s, j);
+                    const int g = d == 0 ? l + N * (a + N * b) : d == 1 ? a + N * (l + N * b) : a + N * (b + N * l);
+                    nbv[r][j] = xn[g];
+                }
+            }
+        }
     }
     // ---------------------------------------------------------------- load x
     {
@@ -141,40 +211,41 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     };
 
     // ------------------------------------------------ F1: face layer gather
-    for (int it = tid; it < ncb * 6 * N2; it += NT) {
-        const int a = it % N, b = (it / N) % N, f = (it / N2) % 6, c = it / (6 * N2);
-        const int d = f >> 1, s = f & 1;
-        const T* Xc = ldsX + c * CS;
-        auto lidx = [&](int j) {
-            return d == 0 ? Sh::lds_idx(j, a, b) : d == 1 ? Sh::lds_idx(a, j, b) : Sh::lds_idx(a, b, j);
-        };
-        auto gidx = [&](int j) {
-            return d == 0 ? j + N * (a + N * b) : d == 1 ? a + N * (j + N * b) : a + N * (b + N * j);
-        };
-        const T* dfs = tab + (s ? TL.df1 : TL.df0);
-        const T* dfn = tab + (s ? TL.df0 : TL.df1);
-        const T vm = Xc[lidx(s ? N - 1 : 0)];
-        T nm = T(0);
 #pragma unroll
-        for (int j = 0; j < Ly::NL; ++j) {
-            const int l = Ly::layer(s, j);
-            nm = fma(dfs[l], Xc[lidx(l)], nm);
-        }
-        const int row = b * RS + a;
-        slot(c, f, 0)[row] = vm;
-        slot(c, f, 1)[row] = nm;
-        const int nb = meta[c * 12 + f];
-        if (nb >= 0) {
-            const T* __restrict__ xn = p.x + size_t(nb) * N3;
-            const T vp = xn[gidx(s ? 0 : N - 1)];
-            T np = T(0);
+    for (int r = 0; r < Sh::F1_ITEMS; ++r) {
+        const int it = tid + r * NT;
+        if (it < ncb * 6 * N2) {
+            const int a = it % N, b = (it / N) % N, f = (it / N2) % 6, c = it / (6 * N2);
+            const int d = f >> 1, s = f & 1;
+            const T* Xc = ldsX + c * CS;
+            auto lidx = [&](int j) {
+                return d == 0 ? Sh::lds_idx(j, a, b) : d == 1 ? Sh::lds_idx(a, j, b) : Sh::lds_idx(a, b, j);
+            };
+            const T* dfs = tab + (s ? TL.df1 : TL.df0);
+            const T* dfn = tab + (s ? TL.df0 : TL.df1);
+            const T vm = Xc[lidx(s ? N - 1 : 0)];
+            T nm = T(0);
 #pragma unroll
             for (int j = 0; j < Ly::NL; ++j) {
-                const int l = Ly::layer(1 - s, j);
-                np = fma(dfn[l], xn[gidx(l)], np);
+                const int l = Ly::layer(s, j);
+                nm = fma(dfs[l], Xc[lidx(l)], nm);
             }
-            slot(c, f, 2)[row] = vp;
-            slot(c, f, 3)[row] = np;
+            const int row = b * RS + a;
+            slot(c, f, 0)[row] = vm;
+            slot(c, f, 1)[row] = nm;
+            if (meta[c * 12 + f] >= 0) {
+                // neighbour side: its value layer touches the face, its
+                // derivative row combines the registers loaded above
+                T vp = T(0), np = T(0);
+#pragma unroll
+                for (int j = 0; j < Ly::NL; ++j) {
+                    const int l = Ly::layer(1 - s, j);
+                    if (l == (s ? 0 : N - 1)) vp = nbv[r][j];
+                    np = fma(dfn[l], nbv[r][j], np);
+                }
+                slot(c, f, 2)[row] = vp;
+                slot(c, f, 3)[row] = np;
+            }
         }
     }
     __syncthreads();
@@ -228,6 +299,17 @@ sipg_matvec_kernel(MatvecParams<T> p) {
             for (int b = 0; b < N; ++b) { up[b] = -um[b]; gdp[b] = gdm[b]; g1p[b] = g1m[b]; g2p[b] = g2m[b]; }
         }
         const T* __restrict__ fg = d == 0 ? p.fgeom0 : d == 1 ? p.fgeom1 : p.fgeom2;
+        if (it != tid) {   // later columns of this thread: load now
+            if constexpr (GEOM == GEOM_CELL) {
+#pragma unroll
+                for (int k = 0; k < 7; ++k) frec[k] = fg[size_t(fidx) * 8 + k];
+            } else {
+#pragma unroll
+                for (int k = 0; k < 7; ++k)
+#pragma unroll
+                    for (int b = 0; b < N; ++b) frec[k * N + b] = fg[size_t(fidx) * (7 * N2) + k * N2 + a + N * b];
+            }
+        }
         T wa = T(1);
         if constexpr (GEOM == GEOM_CELL) wa = pick<N>(tab + TL.w, a);
         T vv[N], wd[N], w1[N], w2[N];
@@ -235,14 +317,12 @@ sipg_matvec_kernel(MatvecParams<T> p) {
         for (int b = 0; b < N; ++b) {
             T rec[7];
             if constexpr (GEOM == GEOM_CELL) {
-                const T* r = fg + size_t(fidx) * 8;
                 const T jw = wa * tab[TL.w + b];
 #pragma unroll
-                for (int k = 0; k < 7; ++k) rec[k] = r[k] * jw;
+                for (int k = 0; k < 7; ++k) rec[k] = frec[k] * jw;
             } else {
-                const T* r = fg + size_t(fidx) * (7 * N2) + a + N * b;
 #pragma unroll
-                for (int k = 0; k < 7; ++k) rec[k] = r[k * N2];
+                for (int k = 0; k < 7; ++k) rec[k] = frec[k * N + b];
             }
             // own-side (g-) and neighbour-side (g+) scaled normals in the
             // cell's reference coordinates; the stored record uses the normal
@@ -280,6 +360,23 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     }
     __syncthreads();
 
+    // Cell metric terms of this thread's z pencil (used in C5).
+    constexpr int NG = GEOM == GEOM_CELL ? 6 : 6 * N;
+    T gpre[NG];
+    if (act) {
+        const int cell = cell0 + c;
+        if constexpr (GEOM == GEOM_CELL) {
+#pragma unroll
+            for (int m = 0; m < 6; ++m) gpre[m] = p.cgeom[size_t(cell) * 8 + m];
+        } else {
+            const T* gq = p.cgeom + size_t(cell) * (6 * N3) + ta + N * tb;
+#pragma unroll
+            for (int m = 0; m < 6; ++m)
+#pragma unroll
+                for (int k = 0; k < N; ++k) gpre[m * N + k] = __builtin_nontemporal_load(gq + m * N3 + N2 * k);
+        }
+    }
+
     // ----------------- F4: transposed sweeps along t1 -> P (slot 0), Q (slot 1)
     for (int it = tid; it < ncb * 6 * N; it += NT) {
         const int b = it % N, f = (it / N) % 6, c = it / (6 * N);
@@ -300,10 +397,6 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     __syncthreads();
 
     // ================================================================ cell
-    const int c = tid / N2;                 // cell of this thread
-    const int t = tid % N2;                 // pencil of this thread
-    const int ta = t % N, tb = t / N;
-    const bool act = c < ncb;
     T* A = ldsX + (act ? c : 0) * CS;
     T* B = ldsW + (act ? c : 0) * Sh::WS;
     T* C = B + CS;
@@ -348,7 +441,6 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     __syncthreads();
     // C5: z pencils (thread (q1, q2)) : D along z -> du/dxi3, metric, D^T along z
     if (act) {
-        const int cell = cell0 + c;
         T g1[N], g2[N], g3[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) {
@@ -363,14 +455,12 @@ sipg_matvec_kernel(MatvecParams<T> p) {
         for (int k = 0; k < N; ++k) {
             T G[6];
             if constexpr (GEOM == GEOM_CELL) {
-                const T* gc = p.cgeom + size_t(cell) * 8;
                 const T w = w12 * tab[TL.w + k];
 #pragma unroll
-                for (int m = 0; m < 6; ++m) G[m] = gc[m] * w;
+                for (int m = 0; m < 6; ++m) G[m] = gpre[m] * w;
             } else {
-                const T* gq = p.cgeom + size_t(cell) * (6 * N3) + ta + N * tb + N2 * k;
 #pragma unroll
-                for (int m = 0; m < 6; ++m) G[m] = gq[m * N3];
+                for (int m = 0; m < 6; ++m) G[m] = gpre[m * N + k];
             }
             const T a1 = G[0] * g1[k] + G[1] * g2[k] + G[2] * g3[k];
             const T a2 = G[1] * g1[k] + G[3] * g2[k] + G[4] * g3[k];

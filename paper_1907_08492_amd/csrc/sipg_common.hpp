@@ -14,10 +14,11 @@ namespace sipg {
 // Launch shape per n = k + 1: cells per workgroup and threads per workgroup.
 // One thread owns one n-long pencil of a cell in every sum-factorization
 // sweep, so a cell uses n^2 threads; cells are packed so that a workgroup is a
-// whole number of 64-wide wavefronts with few idle lanes.
+// whole number of 64-wide wavefronts and, for n >= 4, so that the 6 n face
+// flux columns of every cell fit one per thread.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int cells_per_block(int n) {
-    return n == 2 ? 32 : n == 3 ? 14 : n == 4 ? 8 : n == 5 ? 5 : n == 6 ? 3
+    return n == 2 ? 32 : n == 3 ? 14 : n == 4 ? 5 : n == 5 ? 4 : n == 6 ? 3
          : n == 7 ? 2 : n == 8 ? 2 : 3;
 }
 __host__ __device__ constexpr int threads_per_block(int n) {
