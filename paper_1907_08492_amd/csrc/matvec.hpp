@@ -1,26 +1,30 @@
 // Element-wise matrix-free SIPG product y = A x on gfx950 (Section 3).
 //
-// One workgroup handles CPB consecutive cells.  Every phase below maps one
-// thread to one n-long pencil of a cell (or of a face array) held in
-// registers; the 1D contraction along the pencil is an even-odd
+// One workgroup of three wavefronts handles CPB consecutive cells.  Every
+// step maps one thread to one n-long pencil (of a cell or of a face array)
+// held in registers; the 1D contraction along the pencil is an even-odd
 // multiply-add sweep with coefficients in scalar registers, and the change of
-// pencil direction between sweeps goes through LDS.  Per cell:
+// pencil direction between sweeps goes through LDS.
 //
-//   gather  x of the cell (coalesced) into LDS; for each of the six faces the
-//           own value/derivative layers (from LDS) and the neighbour's value
-//           and derivative layers (from HBM: two layers for the Hermite-like
-//           basis, all n for the nodal basis), combined with S_f and D_f
-//           (eq. tensor_face) into face arrays
-//   faces   2D interpolation to the face Gauss points (S along t1, then S and
-//           D along t2), flux at the points, and the transposed sweeps back
-//           to two coefficient arrays P (value test) and Q (normal-derivative
-//           test) per face
-//   cell    S along z, y, x, collocation D along x, y, z (eq. tensor_cell),
-//           merged metric at the points (eq. integral_laplace), transposed
-//           sweeps back
-//   write   y_K = cell part + sum over faces of e_layer (x) P + D_f (x) Q,
-//           one coalesced write per cell (element-wise face evaluation).
+// Face integrals (eq. tensor_face, element-wise arrangement): wavefront d
+// works on the two faces of normal direction d of every cell, so the
+// direction is a compile-time constant inside its code, and each lane owns
+// one row (t1 direction) and one column (t2 direction) of one face:
+//   G   gather the own value/derivative layers (LDS) and the neighbour's value
+//       and derivative layers (registers, loaded at kernel start; two layers
+//       for the Hermite-like basis, all n for the nodal basis), combine them
+//       with S_f and D_f, and interpolate along t1 (S, and S' for values)
+//   F   interpolate along t2 (S, and D for the tangential derivative), flux
+//       at the face Gauss points, transposed sweeps along t2
+//   I   transposed sweeps along t1 -> P (value test) and Q (normal-derivative
+//       test) coefficient arrays of the face
+// Cell integral: S along z, y, x, collocation D along x, y, z (eq.
+// tensor_cell), merged metric at the points (eq. integral_laplace),
+// transposed sweeps back; the last sweep adds e_layer (x) P + D_f (x) Q of
+// the six faces and writes y_K once.
 #pragma once
+
+#include <type_traits>
 
 #include "sipg_common.hpp"
 #include "sumfac.hpp"
@@ -49,24 +53,22 @@ struct Shape {
     static constexpr int CPB = cells_per_block(N);
     static constexpr int NT = threads_per_block(N);
     static constexpr int WS = (24 * FA > 2 * CS) ? 24 * FA : 2 * CS;
-    static constexpr int F1_ITEMS = (CPB * 6 * N2 + NT - 1) / NT;   // gather items per thread
-    static constexpr int F3_ITEMS = (CPB * 6 * N + NT - 1) / NT;    // flux columns per thread
     static constexpr int PER_CELL = CS + 12 * FA + WS;     // words of T per cell
+    static constexpr int FROWS = CPB * 2 * N;              // face rows (= columns) per direction
     __host__ __device__ static constexpr int lds_idx(int i1, int i2, int i3) { return i1 + RS * (i2 + N * i3); }
 };
 
 template <int N, typename T>
 constexpr size_t matvec_lds_bytes() {
     using S = Shape<N>;
-    constexpr size_t b = size_t(S::CPB) * S::PER_CELL * sizeof(T) + size_t(S::CPB) * 12 * sizeof(int);
+    constexpr size_t b = size_t(S::CPB) * S::PER_CELL * sizeof(T);
     static_assert(b == matvec_lds_bytes_rt(N, sizeof(T)), "LDS size formula mismatch");
     static_assert(b <= 160 * 1024, "LDS budget of a gfx950 CU exceeded");
-    static_assert(S::CPB * N * N <= S::NT && S::NT % 64 == 0 && S::NT <= 1024, "launch shape");
+    static_assert(S::NT == 192 && S::CPB * N * N <= S::NT, "three wavefronts, one pencil per thread");
+    static_assert(S::FROWS <= 64, "one face row per lane of a direction wavefront");
     return b;
 }
 
-// basis: 0 Hermite-like (derivative rows touch layers {0,1} / {n-2,n-1}),
-//        1 nodal Gauss-Lobatto (derivative rows touch every layer).
 // Coordinates of cell0 + c from those of cell0 (cells of a workgroup are
 // consecutive in the lexicographic order; c is small).
 __device__ __forceinline__ void cell_coords(int bx, int by, int bz, int c, int nx, int ny, int& ix, int& iy, int& iz) {
@@ -94,12 +96,36 @@ __device__ __forceinline__ void face_topology(int ix, int iy, int iz, int f, int
     else fi = idx[0] + nx * (idx[1] + ny * idx[2]);
 }
 
+// basis: 0 Hermite-like (derivative rows touch layers {0,1} / {n-2,n-1}),
+//        1 nodal Gauss-Lobatto (derivative rows touch every layer).
 template <int N, int BASIS>
 struct Layers {
     static constexpr int NL = (BASIS == 0) ? 2 : N;
     // j-th layer of the derivative support at side s
     __host__ __device__ static constexpr int layer(int s, int j) { return BASIS == 0 ? (s ? N - 2 + j : j) : j; }
 };
+
+// Index in a cell array of (layer l along direction D, tangential t1 = a, t2 = b).
+template <int N, int D>
+__device__ __forceinline__ constexpr int face_lidx(int l, int a, int b) {
+    using Sh = Shape<N>;
+    return D == 0 ? Sh::lds_idx(l, a, b) : D == 1 ? Sh::lds_idx(a, l, b) : Sh::lds_idx(a, b, l);
+}
+template <int N, int D>
+__device__ __forceinline__ constexpr int face_gidx(int l, int a, int b) {
+    return D == 0 ? l + N * (a + N * b) : D == 1 ? a + N * (l + N * b) : a + N * (b + N * l);
+}
+
+template <int D>
+using DirC = std::integral_constant<int, D>;
+
+// Calls fn(DirC<d>) with d the (wavefront-uniform) direction of this wave.
+template <typename F>
+__device__ __forceinline__ void by_direction(int wave, F&& fn) {
+    if (wave == 0) fn(DirC<0>{});
+    else if (wave == 1) fn(DirC<1>{});
+    else fn(DirC<2>{});
+}
 
 template <int N, int BASIS, typename T, int GEOM>
 __global__ void __launch_bounds__(Shape<N>::NT)
@@ -113,170 +139,157 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     T* ldsX = lds;                                   // [CPB][CS]   x, later the cell work array A
-    T* ldsPQ = lds + CPB * CS;                       // [CPB][6][2][FA]   face slots 0,1
-    T* ldsW = ldsPQ + CPB * 12 * FA;                 // [CPB][WS]  face slots 2..5, later cell arrays B, C
-    int* meta = reinterpret_cast<int*>(ldsW + CPB * Sh::WS);   // [CPB][12]: neighbour, face index
+    T* ldsPQ = lds + CPB * CS;                       // [CPB][6][2][FA]   face arrays 0,1
+    T* ldsW = ldsPQ + CPB * 12 * FA;                 // [CPB][WS]  face arrays 2..5, later cell arrays B, C
 
     const T* __restrict__ tab = p.tab;
     const int tid = threadIdx.x;
+    const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // = face direction in the face steps
+    const int lane = tid & 63;
     // XCD-aware order: consecutive workgroups are dispatched round-robin over
     // the 8 XCDs, so give each XCD a contiguous range of cells (shared L2).
     const int nblk = gridDim.x;
     int blk = blockIdx.x;
     {
         const int per = (nblk + 7) / 8;
-        const int xcd = blk % 8, slot = blk / 8;
+        const int xcd = blk % 8, sl = blk / 8;
         const int full = nblk % 8 == 0 ? 8 : nblk % 8;   // XCDs that get `per` blocks
-        const int rem_per = per - 1;
-        int start;
-        if (xcd < full) start = xcd * per;
-        else start = full * per + (xcd - full) * rem_per;
-        blk = start + slot;
+        blk = (xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1)) + sl;
     }
     const int cell0 = blk * CPB;
     const int ncb = min(CPB, p.ncells - cell0);      // cells in this workgroup
     const int bx = cell0 % p.nx, by = (cell0 / p.nx) % p.ny, bz = cell0 / (p.nx * p.ny);
-    auto topo = [&](int c, int f, int& nb, int& fi) {
-        int ix, iy, iz;
-        cell_coords(bx, by, bz, c, p.nx, p.ny, ix, iy, iz);
-        face_topology(ix, iy, iz, f, p.nx, p.ny, p.nz, nb, fi);
-    };
-
-    // ---------------------------------------------------------------- meta
-    for (int it = tid; it < ncb * 6; it += NT) {
-        int nb, fi;
-        topo(it / 6, it % 6, nb, fi);
-        meta[(it / 6) * 12 + it % 6] = nb;
-        meta[(it / 6) * 12 + 6 + it % 6] = fi;
-    }
-
-    // Prefetch into registers, before any LDS work and without waiting for
-    // the metadata: the metric terms of this thread's first face-flux column
-    // (used in F3) and the neighbour value/derivative layers of the gather (F1).
-    constexpr int NREC = GEOM == GEOM_CELL ? 7 : 7 * N;
-    T frec[NREC];
-    if (tid < ncb * 6 * N) {
-        const int a = tid % N, f = (tid / N) % 6, c = tid / (6 * N);
-        const int d = f >> 1;
-        int nb, fidx;
-        topo(c, f, nb, fidx);
-        const T* __restrict__ fg = d == 0 ? p.fgeom0 : d == 1 ? p.fgeom1 : p.fgeom2;
-        if constexpr (GEOM == GEOM_CELL) {
-#pragma unroll
-            for (int k = 0; k < 7; ++k) frec[k] = fg[size_t(fidx) * 8 + k];
-        } else {
-#pragma unroll
-            for (int k = 0; k < 7; ++k)
-#pragma unroll
-                for (int b = 0; b < N; ++b) frec[k * N + b] = fg[size_t(fidx) * (7 * N2) + k * N2 + a + N * b];
-        }
-    }
-    const int c = tid / N2;                 // cell of this thread in the cell phases
-    const int t = tid % N2;                 // pencil of this thread
-    const int ta = t % N, tb = t / N;
-    const bool act = c < ncb;
-    T nbv[Sh::F1_ITEMS][Ly::NL];
-#pragma unroll
-    for (int r = 0; r < Sh::F1_ITEMS; ++r) {
-        const int it = tid + r * NT;
-        if (it < ncb * 6 * N2) {
-            const int a = it % N, b = (it / N) % N, f = (it / N2) % 6, c = it / (6 * N2);
-            const int d = f >> 1, s = f & 1;
-            int nb, fi;
-            topo(c, f, nb, fi);
-            if (nb >= 0) {
-                const T* __restrict__ xn = p.x + size_t(nb) * N3;
-#pragma unroll
-                for (int j = 0; j < Ly::NL; ++j) {
-                    const int l = Ly::layer(1 - s, j);
-                    const int g = d == 0 ? l + N * (a + N * b) : d == 1 ? a + N * (l + N * b) : a + N * (b + N * l);
-                    nbv[r][j] = xn[g];
-                }
-            }
-        }
-    }
-    // ---------------------------------------------------------------- load x
-    {
-        const T* __restrict__ xs = p.x + size_t(cell0) * N3;
-        for (int e = tid; e < ncb * N3; e += NT) {
-            const int c = e / N3, i = e % N3;
-            const int i1 = i % N, i2 = (i / N) % N, i3 = i / N2;
-            ldsX[c * CS + Sh::lds_idx(i1, i2, i3)] = xs[e];
-        }
-    }
-    __syncthreads();
 
     auto slot = [&](int c, int f, int s) -> T* {
         return s < 2 ? ldsPQ + ((c * 6 + f) * 2 + s) * FA : ldsW + c * Sh::WS + (f * 4 + (s - 2)) * FA;
     };
 
-    // ------------------------------------------------ F1: face layer gather
+    // Face item of this lane (the same in the three face steps): cell fc,
+    // side fs (face f = 2 wave + fs), row / column index fab.
+    const int fc = lane / (2 * N), fs = (lane / N) & 1, fab = lane % N;
+    const bool fact = lane < ncb * 2 * N;
+    int fnb = -1, fidx = 0;
+    if (fact) {
+        int ix, iy, iz;
+        cell_coords(bx, by, bz, fc, p.nx, p.ny, ix, iy, iz);
+        face_topology(ix, iy, iz, 2 * wave + fs, p.nx, p.ny, p.nz, fnb, fidx);
+    }
+
+    // ------------------------------------------------------------ prefetch
+    // Registers, before any LDS work: the metric terms of this lane's flux
+    // column (used in F) and the neighbour layers of this lane's row (used
+    // in G).
+    constexpr int NREC = GEOM == GEOM_CELL ? 7 : 7 * N;
+    T frec[NREC];
+    T nbv[Ly::NL][N];
+    by_direction(wave, [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        if (!fact) return;
+        const T* __restrict__ fg = D == 0 ? p.fgeom0 : D == 1 ? p.fgeom1 : p.fgeom2;
+        if constexpr (GEOM == GEOM_CELL) {
 #pragma unroll
-    for (int r = 0; r < Sh::F1_ITEMS; ++r) {
-        const int it = tid + r * NT;
-        if (it < ncb * 6 * N2) {
-            const int a = it % N, b = (it / N) % N, f = (it / N2) % 6, c = it / (6 * N2);
-            const int d = f >> 1, s = f & 1;
-            const T* Xc = ldsX + c * CS;
-            auto lidx = [&](int j) {
-                return d == 0 ? Sh::lds_idx(j, a, b) : d == 1 ? Sh::lds_idx(a, j, b) : Sh::lds_idx(a, b, j);
-            };
-            const T* dfs = tab + (s ? TL.df1 : TL.df0);
-            const T* dfn = tab + (s ? TL.df0 : TL.df1);
-            const T vm = Xc[lidx(s ? N - 1 : 0)];
-            T nm = T(0);
+            for (int k = 0; k < 7; ++k) frec[k] = fg[size_t(fidx) * 8 + k];
+        } else {
+            const T* __restrict__ r = fg + size_t(fidx) * (7 * N2) + fab;
+#pragma unroll
+            for (int k = 0; k < 7; ++k)
+#pragma unroll
+                for (int b = 0; b < N; ++b) frec[k * N + b] = r[k * N2 + N * b];
+        }
+        if (fnb >= 0) {
+            const T* __restrict__ xn = p.x + size_t(fnb) * N3;
+#pragma unroll
+            for (int j = 0; j < Ly::NL; ++j) {
+                const int l = Ly::layer(1 - fs, j);
+#pragma unroll
+                for (int a = 0; a < N; ++a) nbv[j][a] = xn[face_gidx<N, D>(l, a, fab)];
+            }
+        }
+    });
+    // --------------------------------------------------------------- x tile
+    {
+        const T* __restrict__ xs = p.x + size_t(cell0) * N3;
+        for (int e = tid; e < ncb * N3; e += NT) {
+            const int c = e / N3, i = e % N3;
+            ldsX[c * CS + Sh::lds_idx(i % N, (i / N) % N, i / N2)] = xs[e];
+        }
+    }
+    __syncthreads();
+
+    // ------------------------ G: gather face layers, interpolate along t1
+    by_direction(wave, [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        if (!fact) return;
+        const int b = fab;                 // this lane's row
+        const int s = fs, c = fc;
+        const T* Xc = ldsX + c * CS;
+        const T* dfs = tab + (s ? TL.df1 : TL.df0);
+        const T* dfn = tab + (s ? TL.df0 : TL.df1);
+        T vm[N], nm[N];
+#pragma unroll
+        for (int a = 0; a < N; ++a) {
+            vm[a] = Xc[face_lidx<N, D>(s ? N - 1 : 0, a, b)];
+            T acc = T(0);
 #pragma unroll
             for (int j = 0; j < Ly::NL; ++j) {
                 const int l = Ly::layer(s, j);
-                nm = fma(dfs[l], Xc[lidx(l)], nm);
+                acc = fma(dfs[l], Xc[face_lidx<N, D>(l, a, b)], acc);
             }
-            const int row = b * RS + a;
-            slot(c, f, 0)[row] = vm;
-            slot(c, f, 1)[row] = nm;
-            if (meta[c * 12 + f] >= 0) {
-                // neighbour side: its value layer touches the face, its
-                // derivative row combines the registers loaded above
-                T vp = T(0), np = T(0);
+            nm[a] = acc;
+        }
+        T r[N];
+        const int row = b * RS;
+        eo_apply<N, +1>(tab + TL.S, vm, r);
+        T* o = slot(c, 2 * D + s, 0) + row;
+#pragma unroll
+        for (int a = 0; a < N; ++a) o[a] = r[a];
+        eo_apply<N, -1>(tab + TL.SG, vm, r);
+        o = slot(c, 2 * D + s, 4) + row;
+#pragma unroll
+        for (int a = 0; a < N; ++a) o[a] = r[a];
+        eo_apply<N, +1>(tab + TL.S, nm, r);
+        o = slot(c, 2 * D + s, 1) + row;
+#pragma unroll
+        for (int a = 0; a < N; ++a) o[a] = r[a];
+        if (fnb >= 0) {
+            // neighbour side: its value layer touches the face; its
+            // derivative row combines the layers loaded at kernel start
+            T vp[N], np[N];
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                T acc = T(0), val = T(0);
 #pragma unroll
                 for (int j = 0; j < Ly::NL; ++j) {
                     const int l = Ly::layer(1 - s, j);
-                    if (l == (s ? 0 : N - 1)) vp = nbv[r][j];
-                    np = fma(dfn[l], nbv[r][j], np);
+                    acc = fma(dfn[l], nbv[j][a], acc);
+                    if (l == (s ? 0 : N - 1)) val = nbv[j][a];
                 }
-                slot(c, f, 2)[row] = vp;
-                slot(c, f, 3)[row] = np;
+                vp[a] = val;
+                np[a] = acc;
             }
+            eo_apply<N, +1>(tab + TL.S, vp, r);
+            o = slot(c, 2 * D + s, 2) + row;
+#pragma unroll
+            for (int a = 0; a < N; ++a) o[a] = r[a];
+            eo_apply<N, -1>(tab + TL.SG, vp, r);
+            o = slot(c, 2 * D + s, 5) + row;
+#pragma unroll
+            for (int a = 0; a < N; ++a) o[a] = r[a];
+            eo_apply<N, +1>(tab + TL.S, np, r);
+            o = slot(c, 2 * D + s, 3) + row;
+#pragma unroll
+            for (int a = 0; a < N; ++a) o[a] = r[a];
         }
-    }
+    });
     __syncthreads();
 
-    // ------------------------------------ F2: S (and S') along t1 (rows)
-    for (int it = tid; it < ncb * 6 * 4 * N; it += NT) {
-        const int b = it % N, m = (it / N) % 4, f = (it / (4 * N)) % 6, c = it / (24 * N);
-        if (m >= 2 && meta[c * 12 + f] < 0) continue;
-        T* src = slot(c, f, m) + b * RS;
-        T v[N], r[N];
-#pragma unroll
-        for (int a = 0; a < N; ++a) v[a] = src[a];
-        eo_apply<N, +1>(tab + TL.S, v, r);
-#pragma unroll
-        for (int a = 0; a < N; ++a) src[a] = r[a];
-        if (m == 0 || m == 2) {
-            eo_apply<N, -1>(tab + TL.SG, v, r);
-            T* dst = slot(c, f, 4 + (m >> 1)) + b * RS;
-#pragma unroll
-            for (int a = 0; a < N; ++a) dst[a] = r[a];
-        }
-    }
-    __syncthreads();
-
-    // ------------------- F3: S, D along t2 (columns), flux, transposed sweeps
-    for (int it = tid; it < ncb * 6 * N; it += NT) {
-        const int a = it % N, f = (it / N) % 6, c = it / (6 * N);
-        const int d = f >> 1, s = f & 1;
-        const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        const bool interior = meta[c * 12 + f] >= 0;
-        const int fidx = meta[c * 12 + 6 + f];
+    // ----------------- F: along t2: S, D, flux at the points, S^T / D^T
+    by_direction(wave, [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
+        if (!fact) return;
+        const int a = fab;                 // this lane's column
+        const int s = fs, c = fc, f = 2 * D + s;
         auto col = [&](int sl, T* v) {
             const T* src = slot(c, f, sl) + a;
 #pragma unroll
@@ -288,6 +301,7 @@ sipg_matvec_kernel(MatvecParams<T> p) {
         col(4, g1m); eo_apply<N, +1>(tab + TL.S, g1m, g1m);
         eo_apply<N, -1>(tab + TL.D, um, g2m);
         T up[N], gdp[N], g1p[N], g2p[N];
+        const bool interior = fnb >= 0;
         if (interior) {
             col(2, up);  eo_apply<N, +1>(tab + TL.S, up, up);
             col(3, gdp); eo_apply<N, +1>(tab + TL.S, gdp, gdp);
@@ -298,20 +312,12 @@ sipg_matvec_kernel(MatvecParams<T> p) {
 #pragma unroll
             for (int b = 0; b < N; ++b) { up[b] = -um[b]; gdp[b] = gdm[b]; g1p[b] = g1m[b]; g2p[b] = g2m[b]; }
         }
-        const T* __restrict__ fg = d == 0 ? p.fgeom0 : d == 1 ? p.fgeom1 : p.fgeom2;
-        if (it != tid) {   // later columns of this thread: load now
-            if constexpr (GEOM == GEOM_CELL) {
-#pragma unroll
-                for (int k = 0; k < 7; ++k) frec[k] = fg[size_t(fidx) * 8 + k];
-            } else {
-#pragma unroll
-                for (int k = 0; k < 7; ++k)
-#pragma unroll
-                    for (int b = 0; b < N; ++b) frec[k * N + b] = fg[size_t(fidx) * (7 * N2) + k * N2 + a + N * b];
-            }
-        }
         T wa = T(1);
         if constexpr (GEOM == GEOM_CELL) wa = pick<N>(tab + TL.w, a);
+        // own side (g-) and neighbour side (g+) scaled normals in the cell's
+        // reference coordinates; the stored record uses the normal pointing
+        // from the lower to the upper cell of the face.
+        const T sg = s ? T(1) : T(-1);
         T vv[N], wd[N], w1[N], w2[N];
 #pragma unroll
         for (int b = 0; b < N; ++b) {
@@ -324,23 +330,18 @@ sipg_matvec_kernel(MatvecParams<T> p) {
 #pragma unroll
                 for (int k = 0; k < 7; ++k) rec[k] = frec[k * N + b];
             }
-            // own-side (g-) and neighbour-side (g+) scaled normals in the
-            // cell's reference coordinates; the stored record uses the normal
-            // pointing from the lower to the upper cell of the face.
             T gm[3], gp[3];
-            if (s == 1) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) { gm[k] = rec[1 + k]; gp[k] = rec[4 + k]; }
-            } else {
-#pragma unroll
-                for (int k = 0; k < 3; ++k) { gm[k] = -rec[4 + k]; gp[k] = -rec[1 + k]; }
+            for (int k = 0; k < 3; ++k) {
+                gm[k] = sg * (s ? rec[1 + k] : rec[4 + k]);
+                gp[k] = sg * (s ? rec[4 + k] : rec[1 + k]);
             }
             const T jump = um[b] - up[b];
-            const T dm = gm[d] * gdm[b] + gm[t1] * g1m[b] + gm[t2] * g2m[b];
-            const T dp = gp[d] * gdp[b] + gp[t1] * g1p[b] + gp[t2] * g2p[b];
+            const T dm = gm[D] * gdm[b] + gm[t1] * g1m[b] + gm[t2] * g2m[b];
+            const T dp = gp[D] * gdp[b] + gp[t1] * g1p[b] + gp[t2] * g2p[b];
             vv[b] = rec[0] * jump - T(0.5) * (dm + dp);
             const T hj = T(-0.5) * jump;
-            wd[b] = hj * gm[d];
+            wd[b] = hj * gm[D];
             w1[b] = hj * gm[t1];
             w2[b] = hj * gm[t2];
         }
@@ -357,10 +358,13 @@ sipg_matvec_kernel(MatvecParams<T> p) {
         T* s2 = slot(c, f, 2) + a;
 #pragma unroll
         for (int b = 0; b < N; ++b) { s0[b * RS] = vv[b]; s1[b * RS] = w1[b]; s2[b * RS] = wd[b]; }
-    }
-    __syncthreads();
+    });
 
     // Cell metric terms of this thread's z pencil (used in C5).
+    const int c = tid / N2;                 // cell of this thread in the cell phases
+    const int t = tid % N2;                 // pencil of this thread
+    const int ta = t % N, tb = t / N;
+    const bool act = c < ncb;
     constexpr int NG = GEOM == GEOM_CELL ? 6 : 6 * N;
     T gpre[NG];
     if (act) {
@@ -376,13 +380,15 @@ sipg_matvec_kernel(MatvecParams<T> p) {
                 for (int k = 0; k < N; ++k) gpre[m * N + k] = __builtin_nontemporal_load(gq + m * N3 + N2 * k);
         }
     }
+    __syncthreads();
 
-    // ----------------- F4: transposed sweeps along t1 -> P (slot 0), Q (slot 1)
-    for (int it = tid; it < ncb * 6 * N; it += NT) {
-        const int b = it % N, f = (it / N) % 6, c = it / (6 * N);
-        T* s0 = slot(c, f, 0) + b * RS;
-        T* s1 = slot(c, f, 1) + b * RS;
-        const T* s2 = slot(c, f, 2) + b * RS;
+    // ----------------------- I: along t1: S^T / D^T -> P (array 0), Q (array 1)
+    if (fact) {
+        const int b = fab;
+        const int f = 2 * wave + fs;
+        T* s0 = slot(fc, f, 0) + b * RS;
+        T* s1 = slot(fc, f, 1) + b * RS;
+        const T* s2 = slot(fc, f, 2) + b * RS;
         T av[N], cv[N], bv[N];
 #pragma unroll
         for (int a = 0; a < N; ++a) { av[a] = s0[a]; cv[a] = s1[a]; bv[a] = s2[a]; }

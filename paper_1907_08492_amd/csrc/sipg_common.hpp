@@ -12,27 +12,24 @@ namespace sipg {
 
 // ---------------------------------------------------------------------------
 // Launch shape per n = k + 1: cells per workgroup and threads per workgroup.
-// One thread owns one n-long pencil of a cell in every sum-factorization
-// sweep, so a cell uses n^2 threads; cells are packed so that a workgroup is a
-// whole number of 64-wide wavefronts and, for n >= 4, so that the 6 n face
-// flux columns of every cell fit one per thread.
+// Three 64-wide wavefronts per workgroup.  In the cell steps one thread owns
+// one n-long pencil of a cell (n^2 threads per cell); in the face steps
+// wavefront d owns the faces of normal direction d, one lane per face row,
+// so cells_per_block * 2n <= 64 and cells_per_block * n^2 <= 192.
 // ---------------------------------------------------------------------------
 __host__ __device__ constexpr int cells_per_block(int n) {
-    return n == 2 ? 32 : n == 3 ? 14 : n == 4 ? 5 : n == 5 ? 4 : n == 6 ? 3
-         : n == 7 ? 2 : n == 8 ? 2 : 3;
+    return n == 2 ? 16 : n == 3 ? 10 : n == 4 ? 8 : n == 5 ? 6 : n == 6 ? 5 : n == 7 ? 3 : n == 8 ? 3 : 2;
 }
-__host__ __device__ constexpr int threads_per_block(int n) {
-    return ((cells_per_block(n) * n * n + 63) / 64) * 64;
-}
+__host__ __device__ constexpr int threads_per_block(int) { return 192; }
 
 // Dynamic LDS bytes of the matrix-free kernel (must match Shape<N> in
 // matvec.hpp): per cell the x/work array, 12 persistent face arrays and the
-// larger of 24 face arrays or two cell arrays, plus 12 ints of metadata.
+// larger of 24 face arrays or two cell arrays.
 __host__ __device__ constexpr size_t matvec_lds_bytes_rt(int n, int esz) {
     const int rs = (n % 2 == 0) ? n + 1 : n;
     const int cs = rs * n * n, fa = rs * n;
     const int ws = (24 * fa > 2 * cs) ? 24 * fa : 2 * cs;
-    return size_t(cells_per_block(n)) * (size_t(cs + 12 * fa + ws) * esz + 12 * sizeof(int));
+    return size_t(cells_per_block(n)) * size_t(cs + 12 * fa + ws) * esz;
 }
 
 // ---------------------------------------------------------------------------
