@@ -127,8 +127,16 @@ __device__ __forceinline__ void by_direction(int wave, F&& fn) {
     else fn(DirC<2>{});
 }
 
+// Minimum wavefronts per SIMD requested from the register allocator: two for
+// n >= 7 with per-cell metric terms, so that two workgroups share a compute
+// unit (the few spilled registers cost less than the idle SIMD); with
+// per-point metric terms the spill traffic would compete with the HBM
+// stream, so those keep one.
+template <int N, int GEOM>
+constexpr int matvec_min_waves() { return (N >= 7 && GEOM == GEOM_CELL) ? 2 : 1; }
+
 template <int N, int BASIS, typename T, int GEOM>
-__global__ void __launch_bounds__(Shape<N>::NT)
+__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
 sipg_matvec_kernel(MatvecParams<T> p) {
     using Sh = Shape<N>;
     using Ly = Layers<N, BASIS>;
@@ -179,12 +187,15 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     // Registers, before any LDS work: the metric terms of this lane's flux
     // column (used in F) and the neighbour layers of this lane's row (used
     // in G).
+    // For n >= 7 (FP64) the registers are needed by the sweeps: the face
+    // records are then loaded at the start of step F and the cell metric
+    // terms at the start of C4.
+    constexpr bool EARLY = N <= 6 || sizeof(T) == 4;
     constexpr int NREC = GEOM == GEOM_CELL ? 7 : 7 * N;
     T frec[NREC];
     T nbv[Ly::NL][N];
-    by_direction(wave, [&](auto dc) {
+    auto load_frec = [&](auto dc) {
         constexpr int D = decltype(dc)::value;
-        if (!fact) return;
         const T* __restrict__ fg = D == 0 ? p.fgeom0 : D == 1 ? p.fgeom1 : p.fgeom2;
         if constexpr (GEOM == GEOM_CELL) {
 #pragma unroll
@@ -196,6 +207,11 @@ sipg_matvec_kernel(MatvecParams<T> p) {
 #pragma unroll
                 for (int b = 0; b < N; ++b) frec[k * N + b] = r[k * N2 + N * b];
         }
+    };
+    by_direction(wave, [&](auto dc) {
+        constexpr int D = decltype(dc)::value;
+        if (!fact) return;
+        if constexpr (EARLY) load_frec(dc);
         if (fnb >= 0) {
             const T* __restrict__ xn = p.x + size_t(fnb) * N3;
 #pragma unroll
@@ -290,6 +306,7 @@ sipg_matvec_kernel(MatvecParams<T> p) {
         if (!fact) return;
         const int a = fab;                 // this lane's column
         const int s = fs, c = fc, f = 2 * D + s;
+        if constexpr (!EARLY) load_frec(dc);
         auto col = [&](int sl, T* v) {
             const T* src = slot(c, f, sl) + a;
 #pragma unroll
@@ -367,7 +384,7 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     const bool act = c < ncb;
     constexpr int NG = GEOM == GEOM_CELL ? 6 : 6 * N;
     T gpre[NG];
-    if (act) {
+    auto load_gpre = [&]() {
         const int cell = cell0 + c;
         if constexpr (GEOM == GEOM_CELL) {
 #pragma unroll
@@ -379,6 +396,9 @@ sipg_matvec_kernel(MatvecParams<T> p) {
 #pragma unroll
                 for (int k = 0; k < N; ++k) gpre[m * N + k] = __builtin_nontemporal_load(gq + m * N3 + N2 * k);
         }
+    };
+    if constexpr (EARLY) {
+        if (act) load_gpre();
     }
     __syncthreads();
 
@@ -438,6 +458,7 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     __syncthreads();
     // C4: y pencils : D along y -> du/dxi2
     if (act) {
+        if constexpr (!EARLY) load_gpre();
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, k, tb)];
         eo_apply<N, -1>(tab + TL.D, v, v);
