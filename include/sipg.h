@@ -173,6 +173,74 @@ int sipg_cg_solve(const sipg_op* op, const double* b, double* x, double rel_tol,
 int sipg_launch_shape(int degree, int dtype, int32_t* cells_per_block, int32_t* threads_per_block,
                       int64_t* lds_bytes);
 
+/*
+ * Geometric multigrid solver of Section 6: FP64 conjugate gradient
+ * preconditioned by one V-cycle per iteration.  On every level of the brick
+ * coarsened by two in each direction (while all cell counts are even and at
+ * least min_coarse_cells coarse cells remain) the V-cycle smooths with a
+ * Chebyshev iteration (eq. chebyshev) around P^-1 of eq. (jacobi) (point
+ * Jacobi in the nodal Gauss-Lobatto basis through the basis change).  The
+ * smoothing range is [range_lo, range_hi] times the largest eigenvalue of
+ * P^-1 A estimated by lanczos_steps conjugate-gradient (Lanczos) steps from
+ * [-5.5, -4.5, ..., 5.5, -5.5, ...] (Section 6.2); the coarsest level is
+ * solved by a Chebyshev iteration whose degree guarantees a residual
+ * reduction of coarse_reduction.  Grid transfer: exact embedding of the
+ * coarse space and its transpose.
+ *   precision 0: the V-cycle runs in FP32 (mixed precision, Section 6.2);
+ *   precision 1: everything in FP64.
+ */
+typedef struct {
+    int32_t smoother_degree;     /* Chebyshev degree per smoothing (5) */
+    int32_t lanczos_steps;       /* eigenvalue estimate steps (15) */
+    double range_lo, range_hi;   /* smoothing range factors (0.06, 1.2) */
+    double coarse_reduction;     /* coarse solve residual reduction (1e5) */
+    int32_t min_coarse_cells;    /* stop coarsening below this many cells (1) */
+    int32_t precision;           /* 0 mixed, 1 FP64 */
+} sipg_mg_opts;
+typedef struct {
+    int32_t levels;
+    int64_t ndofs;
+    int32_t precision;
+    double lambda_max_fine;      /* estimated largest eigenvalue of P^-1 A, finest level */
+    double lambda_min_coarse, lambda_max_coarse;
+    int32_t coarse_steps;        /* Chebyshev degree of the coarse solve */
+} sipg_mg_info;
+typedef struct sipg_mg sipg_mg;
+
+/* Fill *opts with the defaults above. */
+int sipg_mg_default_opts(sipg_mg_opts* opts);
+/* Build the hierarchy (operators, diagonals, eigenvalue estimates) for the
+ * same problem as sipg_setup; opts may be NULL (defaults).  Synchronises
+ * `stream`.  The solver owns all its device memory. */
+int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int basis,
+                  const sipg_mg_opts* opts, void* stream, sipg_mg** out);
+int sipg_mg_destroy(sipg_mg* mg);
+int sipg_mg_get_info(const sipg_mg* mg, sipg_mg_info* info);
+/* z = V-cycle(r): one application of the preconditioner (device, double, ndofs). */
+int sipg_mg_apply_vcycle(sipg_mg* mg, const double* r, double* z, void* stream);
+/* Solve A x = b (device, double) to ||b - A x|| <= rel_tol ||b|| with the
+ * preconditioned CG; x holds the initial guess.  Blocks the host (one scalar
+ * read per dot product).  Allocates its 4 FP64 work vectors per call.
+ * SIPG_E_NOCONV after max_iter iterations (info still filled). */
+int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int max_iter,
+                  sipg_solve_info* info, void* stream);
+
+/* Grid transfer between level `level` and level+1 of the hierarchy (0 =
+ * finest), in the V-cycle's precision (float for precision 0, double for 1):
+ * mode 0 prolongation out_fine = P in_coarse, mode 1 restriction
+ * out_coarse = P^T in_fine.  Device pointers, stream ordered. */
+int sipg_mg_transfer(sipg_mg* mg, int level, int mode, const void* in, void* out, void* stream);
+/* Unknowns and cell counts of a level. */
+int sipg_mg_level_ndofs(const sipg_mg* mg, int level, int64_t* ndofs, int32_t cells[3]);
+
+/* b_i = sum_K sum_q f(F_K(xi_q)) phi_i(xi_q) det J w_q for
+ * f(x) = sum_m amps[m] sin(w[3m] pi x1) sin(w[3m+1] pi x2) sin(w[3m+2] pi x3),
+ * 1 <= nmodes <= 16 (amps, waves in host memory; b device, operator
+ * precision).  Stream ordered.  The manufactured solution sin sin sin is the
+ * single mode (1,1,1) with amplitude 3 pi^2. */
+int sipg_assemble_rhs_sines(const sipg_op* op, int nmodes, const double* amps, const int* waves,
+                            void* b, void* stream);
+
 /* Text of the calling thread's last error ("" if none). */
 const char* sipg_last_error(void);
 

@@ -1,0 +1,59 @@
+"""Nested-mesh embedding used to check the multigrid transfer.
+
+Test infrastructure (see oracle/__init__.py).  A coarse cell of a brick is
+split into 2 x 2 x 2 children; on child side s of a direction the coarse 1D
+function phi_j((s + xi) / 2) is again a polynomial of degree k in xi, so it
+has exact coefficients in the fine basis.  The prolongation of a coarse
+vector is this change of representation on every child, and the restriction
+is its transpose.
+"""
+from __future__ import annotations
+
+import numpy as np
+
+from . import basis as b1d
+
+
+def child_embedding(kind: str, k: int):
+    """M_s[i, j] with phi_j((s + xi)/2) = sum_i M_s[i, j] phi_i(xi), s = 0, 1.
+    Computed by least squares on k + 4 Gauss points (exact: polynomials)."""
+    bas = b1d.make_basis(kind, k)
+    x, _ = b1d.gauss(k + 4)
+    V = bas.values(x)                                   # [m, i]
+    out = []
+    for s in (0, 1):
+        C = bas.values(0.5 * (s + x))                   # [m, j]
+        M, *_ = np.linalg.lstsq(V, C, rcond=None)
+        out.append(M)
+    return out
+
+
+def prolongate(coarse: np.ndarray, nc_fine, kind: str, k: int) -> np.ndarray:
+    """Fine-mesh coefficients of a coarse-mesh function (cell-wise layout)."""
+    n = k + 1
+    M = child_embedding(kind, k)
+    fx, fy, fz = nc_fine
+    cx, cy, cz = fx // 2, fy // 2, fz // 2
+    C = np.asarray(coarse, dtype=np.float64).reshape(cz, cy, cx, n ** 3)
+    F = np.zeros((fz, fy, fx, n ** 3))
+    for s3 in (0, 1):
+        for s2 in (0, 1):
+            for s1 in (0, 1):
+                P = np.kron(M[s3], np.kron(M[s2], M[s1]))
+                F[s3::2, s2::2, s1::2] = C @ P.T
+    return F.reshape(-1)
+
+
+def restrict(fine: np.ndarray, nc_fine, kind: str, k: int) -> np.ndarray:
+    n = k + 1
+    M = child_embedding(kind, k)
+    fx, fy, fz = nc_fine
+    cx, cy, cz = fx // 2, fy // 2, fz // 2
+    F = np.asarray(fine, dtype=np.float64).reshape(fz, fy, fx, n ** 3)
+    C = np.zeros((cz, cy, cx, n ** 3))
+    for s3 in (0, 1):
+        for s2 in (0, 1):
+            for s1 in (0, 1):
+                P = np.kron(M[s3], np.kron(M[s2], M[s1]))
+                C += F[s3::2, s2::2, s1::2] @ P
+    return C.reshape(-1)

@@ -40,6 +40,9 @@ EXPORTED = [
     "sipg_setup", "sipg_destroy", "sipg_ndofs", "sipg_get_info", "sipg_apply",
     "sipg_basis_change", "sipg_compute_gl_diagonal", "sipg_cg_solve",
     "sipg_last_error", "sipg_host_tables", "sipg_launch_shape",
+    "sipg_mg_default_opts", "sipg_mg_setup", "sipg_mg_destroy", "sipg_mg_get_info",
+    "sipg_mg_apply_vcycle", "sipg_mg_solve", "sipg_mg_transfer", "sipg_mg_level_ndofs",
+    "sipg_assemble_rhs_sines",
 ]
 
 
@@ -58,6 +61,18 @@ class SipgOpInfo(C.Structure):
 class SipgSolveInfo(C.Structure):
     _fields_ = [("iterations", C.c_int32), ("initial_residual", C.c_double),
                 ("final_residual", C.c_double), ("true_residual", C.c_double)]
+
+
+class SipgMgOpts(C.Structure):
+    _fields_ = [("smoother_degree", C.c_int32), ("lanczos_steps", C.c_int32), ("range_lo", C.c_double),
+                ("range_hi", C.c_double), ("coarse_reduction", C.c_double), ("min_coarse_cells", C.c_int32),
+                ("precision", C.c_int32)]
+
+
+class SipgMgInfo(C.Structure):
+    _fields_ = [("levels", C.c_int32), ("ndofs", C.c_int64), ("precision", C.c_int32),
+                ("lambda_max_fine", C.c_double), ("lambda_min_coarse", C.c_double),
+                ("lambda_max_coarse", C.c_double), ("coarse_steps", C.c_int32)]
 
 
 class SipgTables1D(C.Structure):
@@ -81,6 +96,16 @@ lib.sipg_last_error.restype = C.c_char_p
 lib.sipg_host_tables.argtypes = [C.c_int, C.c_int, C.POINTER(SipgTables1D)]
 lib.sipg_launch_shape.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int64)]
+lib.sipg_mg_default_opts.argtypes = [C.POINTER(SipgMgOpts)]
+lib.sipg_mg_setup.argtypes = [C.POINTER(SipgMesh), C.c_int, C.c_double, C.c_int, C.POINTER(SipgMgOpts), _vp,
+                              C.POINTER(_vp)]
+lib.sipg_mg_destroy.argtypes = [_vp]
+lib.sipg_mg_get_info.argtypes = [_vp, C.POINTER(SipgMgInfo)]
+lib.sipg_mg_apply_vcycle.argtypes = [_vp, _vp, _vp, _vp]
+lib.sipg_mg_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
+lib.sipg_mg_transfer.argtypes = [_vp, C.c_int, C.c_int, _vp, _vp, _vp]
+lib.sipg_mg_level_ndofs.argtypes = [_vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+lib.sipg_assemble_rhs_sines.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), _vp, _vp]
 for _f in EXPORTED:
     if _f not in ("sipg_ndofs", "sipg_last_error"):
         getattr(lib, _f).restype = C.c_int
@@ -227,9 +252,93 @@ class Operator:
         return x, SolveInfo(info.iterations, info.initial_residual, info.final_residual,
                             info.true_residual, rc)
 
+    def assemble_rhs(self, amps, waves, out=None, stream=None):
+        """b for f = sum_m amps[m] sin(w0 pi x) sin(w1 pi y) sin(w2 pi z)."""
+        amps = np.ascontiguousarray(amps, dtype=np.float64).reshape(-1)
+        waves = np.ascontiguousarray(waves, dtype=np.int32).reshape(-1, 3)
+        b = self.empty() if out is None else out
+        _check(lib.sipg_assemble_rhs_sines(self._h, len(amps), amps.ctypes.data_as(C.POINTER(C.c_double)),
+                                           waves.ctypes.data_as(C.POINTER(C.c_int)), self._vec(b, "out"),
+                                           _vp(_stream_ptr(stream))), "sipg_assemble_rhs_sines")
+        return b
+
     def close(self):
         if getattr(self, "_h", None):
             lib.sipg_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Multigrid:
+    """FP64 CG preconditioned by a V-cycle (FP32 for precision="mixed")."""
+
+    def __init__(self, mesh, degree: int, penalty: float = 2.0, basis: str = "hermite_like",
+                 precision: str = "mixed", stream=None, **opts):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("Multigrid needs a GPU (HIP device)")
+        o = SipgMgOpts()
+        _check(lib.sipg_mg_default_opts(C.byref(o)), "sipg_mg_default_opts")
+        o.precision = {"mixed": 0, "f64": 1}[precision]
+        for k, v in opts.items():
+            setattr(o, k, v)
+        self._mesh = make_mesh(mesh)
+        h = _vp()
+        _check(lib.sipg_mg_setup(C.byref(self._mesh), int(degree), float(penalty), BASIS[basis], C.byref(o),
+                                 _vp(_stream_ptr(stream)), C.byref(h)), "sipg_mg_setup")
+        self._h = h
+        self.precision = precision
+        info = SipgMgInfo()
+        _check(lib.sipg_mg_get_info(h, C.byref(info)), "sipg_mg_get_info")
+        self.info = info
+        self.ndofs = int(info.ndofs)
+
+    def _vec(self, t, name, dtype=None):
+        torch = _torch()
+        dtype = torch.float64 if dtype is None else dtype
+        if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != dtype or not t.is_contiguous():
+            raise TypeError(f"{name} must be a contiguous CUDA/HIP tensor of {dtype}")
+        return _vp(t.data_ptr())
+
+    def level(self, level: int):
+        n = C.c_int64()
+        cells = (C.c_int32 * 3)()
+        _check(lib.sipg_mg_level_ndofs(self._h, level, C.byref(n), cells), "sipg_mg_level_ndofs")
+        return int(n.value), tuple(cells)
+
+    def transfer(self, level: int, mode: str, x, out, stream=None):
+        dt = _torch().float32 if self.precision == "mixed" else _torch().float64
+        _check(lib.sipg_mg_transfer(self._h, level, {"prolongate": 0, "restrict": 1}[mode],
+                                    self._vec(x, "in", dt), self._vec(out, "out", dt), _vp(_stream_ptr(stream))),
+               "sipg_mg_transfer")
+        return out
+
+    def vcycle(self, r, out=None, stream=None):
+        z = _torch().empty_like(r) if out is None else out
+        _check(lib.sipg_mg_apply_vcycle(self._h, self._vec(r, "r"), self._vec(z, "z"), _vp(_stream_ptr(stream))),
+               "sipg_mg_apply_vcycle")
+        return z
+
+    def solve(self, b, x=None, rel_tol: float = 1e-10, max_iter: int = 200, stream=None,
+              raise_on_noconv: bool = True):
+        if x is None:
+            x = _torch().zeros_like(b)
+        info = SipgSolveInfo()
+        rc = lib.sipg_mg_solve(self._h, self._vec(b, "b"), self._vec(x, "x"), float(rel_tol), int(max_iter),
+                               C.byref(info), _vp(_stream_ptr(stream)))
+        if rc != SIPG_OK and (rc != SIPG_E_NOCONV or raise_on_noconv):
+            raise SipgError(rc, "sipg_mg_solve")
+        return x, SolveInfo(info.iterations, info.initial_residual, info.final_residual,
+                            info.true_residual, rc)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sipg_mg_destroy(self._h)
             self._h = None
 
     def __del__(self):

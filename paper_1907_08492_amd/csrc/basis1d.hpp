@@ -39,4 +39,9 @@ struct Tables1D {
 };
 bool build_tables(int kind, int p, Tables1D& t);
 
+// Embedding of the coarse 1D space into the two halves of a coarse interval:
+// phi_j((s + xi) / 2) = sum_i M_s[i][j] phi_i(xi) for child side s = 0, 1
+// (row major, n x n).  Exact: both sides are polynomials of degree p.
+bool child_embedding(int kind, int p, std::vector<double>& M0, std::vector<double>& M1);
+
 }  // namespace sipg

@@ -1,0 +1,463 @@
+// Geometric multigrid solver of Section 6: conjugate gradient in FP64
+// preconditioned by one V-cycle per iteration.  The V-cycle runs in FP32
+// (mixed precision, Section 6.2) or FP64; on every level it smooths with a
+// Chebyshev iteration (eq. chebyshev, degree 5 by default) around the
+// preconditioner of eq. (jacobi): point Jacobi in the nodal Gauss-Lobatto
+// basis reached by the tensor-product basis change.  The smoothing range is
+// [0.06, 1.2] times the largest eigenvalue of P^-1 A estimated by 15 Lanczos
+// steps from the vector [-5.5, -4.5, ..., 5.5, -5.5, ...]; the coarsest level
+// is solved by a Chebyshev iteration whose degree guarantees a residual
+// reduction of 1e5 by the a-priori Chebyshev bound.  Levels coarsen the brick
+// by two in every direction while all cell counts are even; the transfer is
+// the exact embedding of the coarse space (the coarse map differs from the
+// fine one by an affine map per child).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <chrono>
+#include <cmath>
+#include <cstring>
+#include <memory>
+#include <new>
+#include <type_traits>
+#include <vector>
+
+#include "basis1d.hpp"
+#include "setup.hpp"
+#include "sipg_common.hpp"
+#include "vecops.hpp"
+
+namespace sipg {
+
+// Largest and smallest eigenvalue of the symmetric tridiagonal matrix
+// (diag d, off-diagonal e) by Sturm-sequence bisection.
+static void tridiag_extremes(const std::vector<double>& d, const std::vector<double>& e, double& lmin, double& lmax) {
+    const int n = int(d.size());
+    double lo = 1e300, hi = -1e300;
+    for (int i = 0; i < n; ++i) {
+        const double r = (i > 0 ? std::fabs(e[i - 1]) : 0.0) + (i + 1 < n ? std::fabs(e[i]) : 0.0);
+        lo = std::min(lo, d[i] - r);
+        hi = std::max(hi, d[i] + r);
+    }
+    auto count_below = [&](double x) {   // eigenvalues < x
+        int c = 0;
+        double q = d[0] - x;
+        if (q < 0) ++c;
+        for (int i = 1; i < n; ++i) {
+            const double qq = q != 0.0 ? q : 1e-300;
+            q = d[i] - x - e[i - 1] * e[i - 1] / qq;
+            if (q < 0) ++c;
+        }
+        return c;
+    };
+    auto kth = [&](int k) {   // k-th smallest (0-based)
+        double a = lo, b = hi;
+        for (int it = 0; it < 200; ++it) {
+            const double m = 0.5 * (a + b);
+            if (count_below(m) > k) b = m; else a = m;
+        }
+        return 0.5 * (a + b);
+    };
+    lmin = kth(0);
+    lmax = kth(n - 1);
+}
+
+template <typename T>
+struct DevBuf {
+    T* p = nullptr;
+    ~DevBuf() { if (p) (void)hipFree(p); }
+    int alloc(int64_t n) {
+        hipError_t e = hipMalloc(&p, sizeof(T) * size_t(std::max<int64_t>(n, 1)));
+        if (e != hipSuccess) { p = nullptr; return hip_fail(e, "hipMalloc(multigrid)"); }
+        return SIPG_OK;
+    }
+};
+
+template <typename T>
+struct Level {
+    sipg_op* op = nullptr;
+    int nc[3] = {0, 0, 0};
+    int64_t n = 0;
+    DevBuf<T> b, u, uo, r, z;
+    double lmin = 0.0, lmax = 0.0;
+    std::vector<double> sigma, theta;   // Chebyshev coefficients per step
+    ~Level() { if (op) sipg_destroy(op); }
+};
+
+struct Scratch {
+    DevBuf<double> partial, scal;
+    double* host = nullptr;
+    ~Scratch() { if (host) (void)hipHostFree(host); }
+    int init() {
+        int rc;
+        if ((rc = partial.alloc(kVecPartials)) != SIPG_OK) return rc;
+        if ((rc = scal.alloc(8)) != SIPG_OK) return rc;
+        SIPG_HIP(hipHostMalloc(&host, sizeof(double) * 8, hipHostMallocDefault));
+        return SIPG_OK;
+    }
+    template <typename T>
+    int dot(const T* a, const T* b, int64_t n, double& out, hipStream_t st) {
+        int rc = vec_dot_async<T>(a, b, partial.p, scal.p, n, st);
+        if (rc != SIPG_OK) return rc;
+        SIPG_HIP(hipMemcpyAsync(host, scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
+        SIPG_HIP(hipStreamSynchronize(st));
+        out = host[0];
+        return SIPG_OK;
+    }
+};
+
+// Chebyshev coefficients (Saad, Chebyshev acceleration, written in the
+// three-term form of eq. chebyshev) for eigenvalues in [a, b], m steps.
+static void chebyshev_coefficients(double a, double b, int m, std::vector<double>& sig, std::vector<double>& th) {
+    const double theta = 0.5 * (b + a), delta = 0.5 * (b - a);
+    const double s1 = theta / delta;
+    sig.assign(m, 0.0);
+    th.assign(m, 0.0);
+    double rho_old = 1.0 / s1;
+    th[0] = 1.0 / theta;
+    for (int j = 1; j < m; ++j) {
+        const double rho = 1.0 / (2.0 * s1 - rho_old);
+        sig[j] = rho * rho_old;
+        th[j] = 2.0 * rho / delta;
+        rho_old = rho;
+    }
+}
+
+template <typename T>
+struct Hierarchy {
+    std::vector<std::unique_ptr<Level<T>>> lv;
+    DevBuf<T> emb;   // M_0, M_1 of the child embedding (n x n each)
+    int n = 0;
+    int smooth_steps = 5;
+    int coarse_steps = 1;
+
+    // u = S^m(b; u) on level l (u = 0 on entry when zero_init).
+    int smooth(int l, bool zero_init, int steps, const std::vector<double>& sig, const std::vector<double>& th,
+               hipStream_t st) {
+        Level<T>& L = *lv[l];
+        int rc;
+        for (int j = 0; j < steps; ++j) {
+            if (j == 0 && zero_init) {
+                // u_0 = 0 (kept in uo for the next step), u_1 = theta_0 P^-1 b
+                SIPG_HIP(hipMemsetAsync(L.uo.p, 0, sizeof(T) * size_t(L.n), st));
+                if ((rc = launch_basis_change(L.op, SIPG_BC_PJACOBI, L.b.p, L.z.p, st)) != SIPG_OK) return rc;
+                if ((rc = vec_scale<T>(th[0], L.z.p, L.u.p, L.n, st)) != SIPG_OK) return rc;
+                continue;
+            }
+            if ((rc = launch_matvec(L.op, L.u.p, L.r.p, st)) != SIPG_OK) return rc;
+            if ((rc = vec_sub<T>(L.b.p, L.r.p, L.r.p, L.n, st)) != SIPG_OK) return rc;
+            if ((rc = launch_basis_change(L.op, SIPG_BC_PJACOBI, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
+            // u_{j+1} = u_j + sigma_j (u_j - u_{j-1}) + theta_j z into uo, then swap
+            if ((rc = vec_cheb<T>(L.u.p, L.uo.p, L.z.p, j == 0 ? 0.0 : sig[j], th[j], L.n, st)) != SIPG_OK) return rc;
+            std::swap(L.u.p, L.uo.p);
+        }
+        return SIPG_OK;
+    }
+
+    // u_l = V-cycle(b_l) with zero initial guess.
+    int vcycle(int l, hipStream_t st) {
+        Level<T>& L = *lv[l];
+        int rc;
+        if (l + 1 == int(lv.size())) return smooth(l, true, coarse_steps, L.sigma, L.theta, st);
+        if ((rc = smooth(l, true, smooth_steps, L.sigma, L.theta, st)) != SIPG_OK) return rc;
+        if ((rc = launch_matvec(L.op, L.u.p, L.r.p, st)) != SIPG_OK) return rc;
+        if ((rc = vec_sub<T>(L.b.p, L.r.p, L.r.p, L.n, st)) != SIPG_OK) return rc;
+        Level<T>& C = *lv[l + 1];
+        if ((rc = transfer_restrict<T>(n, L.nc, L.r.p, C.b.p, emb.p, st)) != SIPG_OK) return rc;
+        if ((rc = vcycle(l + 1, st)) != SIPG_OK) return rc;
+        if ((rc = transfer_prolongate_add<T>(n, L.nc, C.u.p, L.u.p, emb.p, st)) != SIPG_OK) return rc;
+        return smooth(l, false, smooth_steps, L.sigma, L.theta, st);
+    }
+
+    // Extreme eigenvalues of P^-1 A on level l from `steps` conjugate gradient
+    // (Lanczos) steps started from the vector [-5.5, -4.5, ..., 5.5, ...].
+    int lanczos(int l, int steps, Scratch& sc, hipStream_t st) {
+        Level<T>& L = *lv[l];
+        std::vector<T> h(L.n);
+        for (int64_t i = 0; i < L.n; ++i) h[i] = T(-5.5 + double(i % 12));
+        SIPG_HIP(hipMemcpyAsync(L.r.p, h.data(), sizeof(T) * L.n, hipMemcpyHostToDevice, st));
+        // x = 0, r = b; z = P^-1 r; p = z  (p in uo, Ap in b)
+        int rc;
+        if ((rc = launch_basis_change(L.op, SIPG_BC_PJACOBI, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
+        SIPG_HIP(hipMemcpyAsync(L.uo.p, L.z.p, sizeof(T) * L.n, hipMemcpyDeviceToDevice, st));
+        double rz;
+        if ((rc = sc.dot<T>(L.r.p, L.z.p, L.n, rz, st)) != SIPG_OK) return rc;
+        std::vector<double> alpha, beta;
+        for (int k = 0; k < steps && rz > 0.0; ++k) {
+            if ((rc = launch_matvec(L.op, L.uo.p, L.b.p, st)) != SIPG_OK) return rc;
+            double pap;
+            if ((rc = sc.dot<T>(L.uo.p, L.b.p, L.n, pap, st)) != SIPG_OK) return rc;
+            if (!(pap > 0.0)) break;
+            const double a = rz / pap;
+            if ((rc = vec_axpby<T>(-a, L.b.p, 1.0, L.r.p, L.n, st)) != SIPG_OK) return rc;
+            if ((rc = launch_basis_change(L.op, SIPG_BC_PJACOBI, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
+            double rz_new;
+            if ((rc = sc.dot<T>(L.r.p, L.z.p, L.n, rz_new, st)) != SIPG_OK) return rc;
+            const double bta = rz_new / rz;
+            alpha.push_back(a);
+            beta.push_back(bta);
+            if ((rc = vec_axpby<T>(1.0, L.z.p, bta, L.uo.p, L.n, st)) != SIPG_OK) return rc;
+            rz = rz_new;
+        }
+        const int m = int(alpha.size());
+        if (m == 0) { set_error("multigrid: Lanczos breakdown"); return SIPG_E_NOCONV; }
+        std::vector<double> d(m), e(std::max(m - 1, 1), 0.0);
+        for (int k = 0; k < m; ++k) {
+            d[k] = 1.0 / alpha[k] + (k > 0 ? beta[k - 1] / alpha[k - 1] : 0.0);
+            if (k + 1 < m) e[k] = std::sqrt(beta[k]) / alpha[k];
+        }
+        tridiag_extremes(d, e, L.lmin, L.lmax);
+        return SIPG_OK;
+    }
+};
+
+}  // namespace sipg
+
+using namespace sipg;
+
+struct sipg_mg {
+    int precision = 0;                   // 0: FP32 V-cycle, 1: FP64 V-cycle
+    sipg_op* fine64 = nullptr;           // FP64 operator of the outer iteration
+    Hierarchy<float> h32;
+    Hierarchy<double> h64;
+    Scratch sc;
+    int64_t ndofs = 0;
+    int levels = 0;
+    double lmax0 = 0.0, lmin_coarse = 0.0, lmax_coarse = 0.0;
+    int coarse_steps = 0;
+    ~sipg_mg() { if (fine64) sipg_destroy(fine64); }
+};
+
+template <typename T>
+static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, int degree, double penalty,
+                           int basis, const sipg_mg_opts& o, hipStream_t st) {
+    const int dt = std::is_same<T, double>::value ? SIPG_F64 : SIPG_F32;
+    int nc[3] = {mesh->n[0], mesh->n[1], mesh->n[2]};
+    H.n = degree + 1;
+    H.smooth_steps = o.smoother_degree;
+    for (;;) {
+        auto L = std::make_unique<Level<T>>();
+        sipg_mesh m = *mesh;
+        for (int d = 0; d < 3; ++d) { m.n[d] = nc[d]; L->nc[d] = nc[d]; }
+        int rc = sipg_setup(&m, degree, penalty, basis, dt, SIPG_GEOM_AUTO, st, &L->op);
+        if (rc != SIPG_OK) return rc;
+        if ((rc = sipg_compute_gl_diagonal(L->op, nullptr, st)) != SIPG_OK) return rc;
+        L->n = L->op->ndofs;
+        if ((rc = L->b.alloc(L->n)) || (rc = L->u.alloc(L->n)) || (rc = L->uo.alloc(L->n)) ||
+            (rc = L->r.alloc(L->n)) || (rc = L->z.alloc(L->n)))
+            return rc;
+        H.lv.push_back(std::move(L));
+        const bool can = nc[0] % 2 == 0 && nc[1] % 2 == 0 && nc[2] % 2 == 0 &&
+                         int64_t(nc[0] / 2) * (nc[1] / 2) * (nc[2] / 2) >= o.min_coarse_cells;
+        if (!can || int(H.lv.size()) >= 16) break;
+        for (int d = 0; d < 3; ++d) nc[d] /= 2;
+    }
+    // embedding matrices
+    std::vector<double> M0, M1;
+    if (!child_embedding(basis, degree, M0, M1)) { set_error("multigrid: singular embedding"); return SIPG_E_ARG; }
+    std::vector<T> e(2 * H.n * H.n);
+    for (int i = 0; i < H.n * H.n; ++i) { e[i] = T(M0[i]); e[H.n * H.n + i] = T(M1[i]); }
+    int rc;
+    if ((rc = H.emb.alloc(int64_t(e.size()))) != SIPG_OK) return rc;
+    SIPG_HIP(hipMemcpyAsync(H.emb.p, e.data(), sizeof(T) * e.size(), hipMemcpyHostToDevice, st));
+    // eigenvalue estimates and Chebyshev coefficients
+    for (size_t l = 0; l < H.lv.size(); ++l) {
+        const bool coarsest = l + 1 == H.lv.size();
+        Level<T>& L = *H.lv[l];
+        const int steps = coarsest ? int(std::min<int64_t>(L.n, 300)) : o.lanczos_steps;
+        if ((rc = H.lanczos(int(l), steps, mg->sc, st)) != SIPG_OK) return rc;
+        if (!coarsest) {
+            chebyshev_coefficients(o.range_lo * L.lmax, o.range_hi * L.lmax, H.smooth_steps, L.sigma, L.theta);
+        } else {
+            // degree with 2 c^m / (1 + c^2m) <= 1 / coarse_reduction
+            const double a = 0.9 * L.lmin, b = 1.1 * L.lmax;
+            const double kap = b / a, c = (std::sqrt(kap) - 1.0) / (std::sqrt(kap) + 1.0);
+            int m = 1;
+            while (m < 2000) {
+                const double cm = std::pow(c, m);
+                if (2.0 * cm / (1.0 + cm * cm) <= 1.0 / o.coarse_reduction) break;
+                ++m;
+            }
+            H.coarse_steps = m;
+            chebyshev_coefficients(a, b, m, L.sigma, L.theta);
+            mg->lmin_coarse = L.lmin;
+            mg->lmax_coarse = L.lmax;
+            mg->coarse_steps = m;
+        }
+    }
+    mg->lmax0 = H.lv[0]->lmax;
+    mg->levels = int(H.lv.size());
+    return SIPG_OK;
+}
+
+extern "C" {
+
+int sipg_mg_default_opts(sipg_mg_opts* o) {
+    if (!o) { set_error("sipg_mg_default_opts: null"); return SIPG_E_ARG; }
+    o->smoother_degree = 5;
+    o->lanczos_steps = 15;
+    o->range_lo = 0.06;
+    o->range_hi = 1.2;
+    o->coarse_reduction = 1e5;
+    o->min_coarse_cells = 1;
+    o->precision = 0;
+    return SIPG_OK;
+}
+
+int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, const sipg_mg_opts* opts,
+                  void* stream, sipg_mg** out) {
+    if (!mesh || !out) { set_error("sipg_mg_setup: null argument"); return SIPG_E_ARG; }
+    *out = nullptr;
+    sipg_mg_opts o;
+    sipg_mg_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.smoother_degree < 1 || o.smoother_degree > 64 || o.lanczos_steps < 2 || !(o.range_lo > 0.0) ||
+        !(o.range_hi > o.range_lo) || !(o.coarse_reduction > 1.0) || (o.precision != 0 && o.precision != 1) ||
+        o.min_coarse_cells < 1) {
+        set_error("sipg_mg_setup: invalid options");
+        return SIPG_E_ARG;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    std::unique_ptr<sipg_mg> mg(new (std::nothrow) sipg_mg());
+    if (!mg) { set_error("sipg_mg_setup: out of host memory"); return SIPG_E_OOM; }
+    mg->precision = o.precision;
+    int rc = sipg_setup(mesh, degree, penalty, basis, SIPG_F64, SIPG_GEOM_AUTO, stream, &mg->fine64);
+    if (rc != SIPG_OK) return rc;
+    mg->ndofs = mg->fine64->ndofs;
+    if ((rc = mg->sc.init()) != SIPG_OK) return rc;
+    rc = o.precision == 0 ? build_hierarchy<float>(mg.get(), mg->h32, mesh, degree, penalty, basis, o, st)
+                          : build_hierarchy<double>(mg.get(), mg->h64, mesh, degree, penalty, basis, o, st);
+    if (rc != SIPG_OK) return rc;
+    SIPG_HIP(hipStreamSynchronize(st));
+    *out = mg.release();
+    return SIPG_OK;
+}
+
+int sipg_mg_destroy(sipg_mg* mg) {
+    delete mg;
+    return SIPG_OK;
+}
+
+int sipg_mg_get_info(const sipg_mg* mg, sipg_mg_info* info) {
+    if (!mg || !info) { set_error("sipg_mg_get_info: null argument"); return SIPG_E_ARG; }
+    info->levels = mg->levels;
+    info->ndofs = mg->ndofs;
+    info->precision = mg->precision;
+    info->lambda_max_fine = mg->lmax0;
+    info->lambda_min_coarse = mg->lmin_coarse;
+    info->lambda_max_coarse = mg->lmax_coarse;
+    info->coarse_steps = mg->coarse_steps;
+    return SIPG_OK;
+}
+
+int sipg_mg_apply_vcycle(sipg_mg* mg, const double* r, double* z, void* stream) {
+    if (!mg || !r || !z) { set_error("sipg_mg_apply_vcycle: null argument"); return SIPG_E_ARG; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    int rc;
+    if (mg->precision == 0) {
+        auto& L = *mg->h32.lv[0];
+        if ((rc = vec_convert<float, double>(r, L.b.p, L.n, st)) != SIPG_OK) return rc;
+        if ((rc = mg->h32.vcycle(0, st)) != SIPG_OK) return rc;
+        return vec_convert<double, float>(L.u.p, z, L.n, st);
+    }
+    auto& L = *mg->h64.lv[0];
+    SIPG_HIP(hipMemcpyAsync(L.b.p, r, sizeof(double) * L.n, hipMemcpyDeviceToDevice, st));
+    if ((rc = mg->h64.vcycle(0, st)) != SIPG_OK) return rc;
+    SIPG_HIP(hipMemcpyAsync(z, L.u.p, sizeof(double) * L.n, hipMemcpyDeviceToDevice, st));
+    return SIPG_OK;
+}
+
+// FP64 preconditioned conjugate gradient with one V-cycle per iteration.
+int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int max_iter, sipg_solve_info* info,
+                  void* stream) {
+    if (!mg || !b || !x || !info) { set_error("sipg_mg_solve: null argument"); return SIPG_E_ARG; }
+    if (!(rel_tol > 0.0) || max_iter < 0) { set_error("sipg_mg_solve: rel_tol must be > 0, max_iter >= 0"); return SIPG_E_ARG; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    const int64_t n = mg->ndofs;
+    std::memset(info, 0, sizeof(*info));
+    DevBuf<double> r, z, p, ap;
+    int rc;
+    if ((rc = r.alloc(n)) || (rc = z.alloc(n)) || (rc = p.alloc(n)) || (rc = ap.alloc(n))) return rc;
+    Scratch& sc = mg->sc;
+    double bb;
+    if ((rc = sc.dot<double>(b, b, n, bb, st)) != SIPG_OK) return rc;
+    const double target = rel_tol * (bb > 0.0 ? std::sqrt(bb) : 1.0);
+    if ((rc = launch_matvec(mg->fine64, x, ap.p, st)) != SIPG_OK) return rc;
+    if ((rc = vec_sub<double>(b, ap.p, r.p, n, st)) != SIPG_OK) return rc;
+    double rr;
+    if ((rc = sc.dot<double>(r.p, r.p, n, rr, st)) != SIPG_OK) return rc;
+    info->initial_residual = std::sqrt(rr);
+    int it = 0;
+    double rz = 0.0;
+    while (std::sqrt(rr) > target && it < max_iter) {
+        if ((rc = sipg_mg_apply_vcycle(mg, r.p, z.p, stream)) != SIPG_OK) return rc;
+        double rz_new;
+        if ((rc = sc.dot<double>(r.p, z.p, n, rz_new, st)) != SIPG_OK) return rc;
+        if (it == 0) {
+            SIPG_HIP(hipMemcpyAsync(p.p, z.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+        } else {
+            if ((rc = vec_axpby<double>(1.0, z.p, rz_new / rz, p.p, n, st)) != SIPG_OK) return rc;
+        }
+        rz = rz_new;
+        if ((rc = launch_matvec(mg->fine64, p.p, ap.p, st)) != SIPG_OK) return rc;
+        double pap;
+        if ((rc = sc.dot<double>(p.p, ap.p, n, pap, st)) != SIPG_OK) return rc;
+        const double alpha = rz / pap;
+        if ((rc = vec_axpby<double>(alpha, p.p, 1.0, x, n, st)) != SIPG_OK) return rc;
+        if ((rc = vec_axpby<double>(-alpha, ap.p, 1.0, r.p, n, st)) != SIPG_OK) return rc;
+        if ((rc = sc.dot<double>(r.p, r.p, n, rr, st)) != SIPG_OK) return rc;
+        ++it;
+    }
+    info->iterations = it;
+    info->final_residual = std::sqrt(rr);
+    if ((rc = launch_matvec(mg->fine64, x, ap.p, st)) != SIPG_OK) return rc;
+    if ((rc = vec_sub<double>(b, ap.p, r.p, n, st)) != SIPG_OK) return rc;
+    double tr;
+    if ((rc = sc.dot<double>(r.p, r.p, n, tr, st)) != SIPG_OK) return rc;
+    info->true_residual = std::sqrt(tr);
+    if (std::sqrt(rr) > target) {
+        set_error("sipg_mg_solve: no convergence within max_iter");
+        return SIPG_E_NOCONV;
+    }
+    return SIPG_OK;
+}
+
+int sipg_mg_transfer(sipg_mg* mg, int level, int mode, const void* in, void* out, void* stream) {
+    if (!mg || !in || !out || level < 0 || level + 1 >= mg->levels || (mode != 0 && mode != 1)) {
+        set_error("sipg_mg_transfer: bad argument (level must have a coarser level, mode 0 or 1)");
+        return SIPG_E_ARG;
+    }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    auto run = [&](auto& H) -> int {
+        using T = typename std::remove_reference<decltype(*H.emb.p)>::type;
+        auto& L = *H.lv[level];
+        auto& C = *H.lv[level + 1];
+        if (mode == 1) return transfer_restrict<T>(H.n, L.nc, static_cast<const T*>(in), static_cast<T*>(out), H.emb.p, st);
+        SIPG_HIP(hipMemsetAsync(out, 0, sizeof(T) * size_t(L.n), st));
+        (void)C;
+        return transfer_prolongate_add<T>(H.n, L.nc, static_cast<const T*>(in), static_cast<T*>(out), H.emb.p, st);
+    };
+    return mg->precision == 0 ? run(mg->h32) : run(mg->h64);
+}
+
+int sipg_mg_level_ndofs(const sipg_mg* mg, int level, int64_t* ndofs, int32_t cells[3]) {
+    if (!mg || level < 0 || level >= mg->levels) { set_error("sipg_mg_level_ndofs: bad level"); return SIPG_E_ARG; }
+    auto get = [&](const auto& H) {
+        const auto& L = *H.lv[level];
+        if (ndofs) *ndofs = L.n;
+        if (cells) for (int d = 0; d < 3; ++d) cells[d] = L.nc[d];
+    };
+    if (mg->precision == 0) get(mg->h32); else get(mg->h64);
+    return SIPG_OK;
+}
+
+int sipg_assemble_rhs_sines(const sipg_op* op, int nmodes, const double* amps, const int* waves, void* b,
+                            void* stream) {
+    if (!op || !amps || !waves || !b || nmodes < 1 || nmodes > 16) {
+        set_error("sipg_assemble_rhs_sines: null argument or nmodes outside [1,16]");
+        return SIPG_E_ARG;
+    }
+    return launch_rhs_sines(op, nmodes, amps, waves, b, static_cast<hipStream_t>(stream));
+}
+
+}  // extern "C"

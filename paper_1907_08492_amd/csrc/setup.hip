@@ -3,7 +3,9 @@
 // computed in double precision from the analytic mesh map and stored in the
 // operator's precision.
 #include "sipg_common.hpp"
+#include "sumfac.hpp"
 #include "setup.hpp"
+#include "basis1d.hpp"
 
 namespace sipg {
 
@@ -31,6 +33,21 @@ __device__ void map_jacobian(const MeshDev& m, int ix, int iy, int iz, double x0
     for (int j = 0; j < 3; ++j) t[j] = gs[0] * LH[j] + gs[1] * LH[3 + j] + gs[2] * LH[6 + j];
     for (int i = 0; i < 3; ++i)
         for (int j = 0; j < 3; ++j) J[3 * i + j] = LH[3 * i + j] + m.a * t[j];
+}
+
+// Physical point of cell (ix, iy, iz) at reference point xi (same map).
+__device__ void map_point(const MeshDev& m, int ix, int iy, int iz, double x0, double x1, double x2,
+                          double x[3]) {
+    const double X[3] = {m.lo[0] + (ix + x0) * m.h[0], m.lo[1] + (iy + x1) * m.h[1],
+                         m.lo[2] + (iz + x2) * m.h[2]};
+    double Y[3];
+    for (int i = 0; i < 3; ++i) Y[i] = m.L[3 * i] * X[0] + m.L[3 * i + 1] * X[1] + m.L[3 * i + 2] * X[2];
+    double s = 0.0;
+    if (m.a != 0.0) {
+        const double pi = 3.14159265358979323846;
+        s = m.a * sin(pi * Y[0]) * sin(pi * Y[1]) * sin(pi * Y[2]);
+    }
+    for (int i = 0; i < 3; ++i) x[i] = Y[i] + s;
 }
 
 __device__ double inverse3(const double J[9], double Ji[9]) {
@@ -164,6 +181,90 @@ __global__ void face_geometry_kernel(MeshDev m, Rule r, int d, double sigma0, T*
             }
         }
     }
+}
+
+// Right-hand side for f = sum_m a_m sin(p_m pi x1) sin(q_m pi x2) sin(r_m pi x3):
+// b_i = sum_q f(F_K(xi_q)) phi_i(xi_q) det J w_q on every cell, the source at
+// the mapped Gauss points followed by the transposed sweeps S^T x S^T x S^T.
+struct Modes {
+    int count;
+    double a[16];
+    int w[16][3];
+};
+
+template <int N, typename T>
+__global__ void __launch_bounds__(128) rhs_kernel(MeshDev m, Rule r, Modes md, const T* __restrict__ tab,
+                                                  T* __restrict__ b) {
+    constexpr int N2 = N * N, N3 = N2 * N;
+    constexpr TableLayout TL(N);
+    __shared__ T F[N3];
+    const int cell = blockIdx.x;
+    const int ix = cell % m.n[0], iy = (cell / m.n[0]) % m.n[1], iz = cell / (m.n[0] * m.n[1]);
+    const double pi = 3.14159265358979323846;
+    for (int q = threadIdx.x; q < N3; q += blockDim.x) {
+        const int q1 = q % N, q2 = (q / N) % N, q3 = q / N2;
+        double x[3], J[9], Ji[9];
+        map_point(m, ix, iy, iz, r.x[q1], r.x[q2], r.x[q3], x);
+        map_jacobian(m, ix, iy, iz, r.x[q1], r.x[q2], r.x[q3], J);
+        const double det = inverse3(J, Ji);
+        double f = 0.0;
+        for (int k = 0; k < md.count; ++k)
+            f += md.a[k] * sin(md.w[k][0] * pi * x[0]) * sin(md.w[k][1] * pi * x[1]) * sin(md.w[k][2] * pi * x[2]);
+        F[q] = T(f * det * r.w[q1] * r.w[q2] * r.w[q3]);
+    }
+    __syncthreads();
+    const int t = threadIdx.x;
+    const bool act = t < N2;
+    const int ta = t % N, tb = t / N;
+    T v[N];
+    auto sweep = [&](int dir) {
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < N; ++k)
+                v[k] = F[dir == 0 ? k + N * (ta + N * tb) : dir == 1 ? ta + N * (k + N * tb) : ta + N * (tb + N * k)];
+            eo_apply<N, +1>(tab + TL.ST, v, v);
+#pragma unroll
+            for (int k = 0; k < N; ++k)
+                F[dir == 0 ? k + N * (ta + N * tb) : dir == 1 ? ta + N * (k + N * tb) : ta + N * (tb + N * k)] = v[k];
+        }
+        __syncthreads();
+    };
+    sweep(0);
+    sweep(1);
+    sweep(2);
+    for (int e = threadIdx.x; e < N3; e += blockDim.x) b[size_t(cell) * N3 + e] = F[e];
+}
+
+template <typename T>
+static int launch_rhs_t(const sipg_op* op, const Modes& md, void* b, hipStream_t st) {
+    std::vector<double> xq, wq;
+    gauss_rule(op->n, xq, wq);
+    Rule r{};
+    r.n = op->n;
+    for (int i = 0; i < op->n; ++i) { r.x[i] = xq[i]; r.w[i] = wq[i]; }
+    const T* tab = static_cast<const T*>(op->tables);
+    T* bp = static_cast<T*>(b);
+    const unsigned nb = unsigned(op->ncells);
+    switch (op->n) {
+#define SIPG_RHS_CASE(NN) \
+    case NN: rhs_kernel<NN, T><<<nb, 128, 0, st>>>(op->mesh, r, md, tab, bp); break;
+        SIPG_RHS_CASE(2) SIPG_RHS_CASE(3) SIPG_RHS_CASE(4) SIPG_RHS_CASE(5)
+        SIPG_RHS_CASE(6) SIPG_RHS_CASE(7) SIPG_RHS_CASE(8) SIPG_RHS_CASE(9)
+#undef SIPG_RHS_CASE
+        default: set_error("rhs: unsupported degree"); return SIPG_E_UNSUPPORTED;
+    }
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
+int launch_rhs_sines(const sipg_op* op, int nmodes, const double* amps, const int* waves, void* b, hipStream_t st) {
+    Modes md{};
+    md.count = nmodes;
+    for (int k = 0; k < nmodes; ++k) {
+        md.a[k] = amps[k];
+        for (int d = 0; d < 3; ++d) md.w[k][d] = waves[3 * k + d];
+    }
+    return op->dtype == SIPG_F64 ? launch_rhs_t<double>(op, md, b, st) : launch_rhs_t<float>(op, md, b, st);
 }
 
 template <typename T>

@@ -20,6 +20,9 @@ int launch_matvec_n(const sipg_op* op, const void* x, void* y, hipStream_t st);
 // Cell-wise basis change / preconditioner (see sipg_basis_change).
 int launch_basis_change(const sipg_op* op, int mode, const void* in, void* out, hipStream_t st);
 
+// Right-hand side of a sum of sine modes (see sipg_assemble_rhs_sines).
+int launch_rhs_sines(const sipg_op* op, int nmodes, const double* amps, const int* waves, void* b, hipStream_t st);
+
 // diag(A) in the nodal Gauss-Lobatto basis, written to `diag` (operator precision).
 int launch_gl_diagonal(const sipg_op* op, void* diag, hipStream_t st);
 

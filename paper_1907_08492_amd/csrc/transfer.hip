@@ -1,0 +1,202 @@
+// Geometric multigrid transfer between a brick of cells and its coarsening
+// by two in every direction.  The coarse and fine maps differ by an affine
+// map per child, so the coarse space is a subspace of the fine one and the
+// prolongation is the exact embedding: on child (s1,s2,s3) the fine
+// coefficients are (M_s3 x M_s2 x M_s1) times the coarse ones, with the 1D
+// matrices M_0, M_1 of the two halves of the coarse interval.  Restriction is
+// the transpose.  One workgroup per coarse cell, one thread per pencil; the
+// 1D contractions are shared between children with the same sides.
+#include "sipg_common.hpp"
+#include "vecops.hpp"
+
+namespace sipg {
+
+template <int N>
+struct TrShape {
+    static constexpr int N2 = N * N, N3 = N2 * N;
+    static constexpr int NT = ((N2 + 63) / 64) * 64;
+    __device__ static constexpr int idx(int i1, int i2, int i3) { return i1 + N * (i2 + N * i3); }
+};
+
+// out[i] = sum_j M[i][j] in[j]  (TRANS: out[j] = sum_i M[i][j] in[i])
+template <int N, bool TRANS, typename T>
+__device__ __forceinline__ void mat1d(const T* __restrict__ M, const T* in, T* out) {
+#pragma unroll
+    for (int i = 0; i < N; ++i) {
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < N; ++j) acc = fma(TRANS ? M[j * N + i] : M[i * N + j], in[j], acc);
+        out[i] = acc;
+    }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(TrShape<N>::NT)
+prolongate_kernel(const T* __restrict__ coarse, T* __restrict__ fine, const T* __restrict__ emb, int fx, int fy, int fz) {
+    using S = TrShape<N>;
+    constexpr int N2 = S::N2, N3 = S::N3;
+    __shared__ T C[N3];
+    __shared__ T Z[2][N3];
+    __shared__ T Y[4][N3];
+    const int cx = fx / 2, cy = fy / 2;
+    const int cc = blockIdx.x;
+    const int ix = cc % cx, iy = (cc / cx) % cy, iz = cc / (cx * cy);
+    const int tid = threadIdx.x;
+    const bool act = tid < N2;
+    const int ta = tid % N, tb = tid / N;
+    for (int e = tid; e < N3; e += S::NT) C[e] = coarse[size_t(cc) * N3 + e];
+    __syncthreads();
+    T v[N], r[N];
+    if (act) {   // z: thread (j1, j2)
+#pragma unroll
+        for (int k = 0; k < N; ++k) v[k] = C[S::idx(ta, tb, k)];
+#pragma unroll
+        for (int s3 = 0; s3 < 2; ++s3) {
+            mat1d<N, false>(emb + s3 * N2, v, r);
+#pragma unroll
+            for (int k = 0; k < N; ++k) Z[s3][S::idx(ta, tb, k)] = r[k];
+        }
+    }
+    __syncthreads();
+    if (act) {   // y: thread (j1, i3)
+#pragma unroll
+        for (int s3 = 0; s3 < 2; ++s3) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = Z[s3][S::idx(ta, k, tb)];
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+                mat1d<N, false>(emb + s2 * N2, v, r);
+#pragma unroll
+                for (int k = 0; k < N; ++k) Y[s2 + 2 * s3][S::idx(ta, k, tb)] = r[k];
+            }
+        }
+    }
+    __syncthreads();
+    if (act) {   // x: thread (i2, i3), add into the 8 children
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int s2 = q & 1, s3 = q >> 1;
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = Y[q][S::idx(k, ta, tb)];
+#pragma unroll
+            for (int s1 = 0; s1 < 2; ++s1) {
+                mat1d<N, false>(emb + s1 * N2, v, r);
+                const size_t child = size_t(2 * ix + s1) + size_t(fx) * (size_t(2 * iy + s2) + size_t(fy) * size_t(2 * iz + s3));
+                T* __restrict__ dst = fine + child * N3 + N * (ta + N * tb);
+#pragma unroll
+                for (int k = 0; k < N; ++k) dst[k] += r[k];
+            }
+        }
+    }
+}
+
+template <int N, typename T>
+__global__ void __launch_bounds__(TrShape<N>::NT)
+restrict_kernel(const T* __restrict__ fine, T* __restrict__ coarse, const T* __restrict__ emb, int fx, int fy, int fz) {
+    using S = TrShape<N>;
+    constexpr int N2 = S::N2, N3 = S::N3;
+    __shared__ T X[4][N3];
+    __shared__ T Y[2][N3];
+    const int cx = fx / 2, cy = fy / 2;
+    const int cc = blockIdx.x;
+    const int ix = cc % cx, iy = (cc / cx) % cy, iz = cc / (cx * cy);
+    const int tid = threadIdx.x;
+    const bool act = tid < N2;
+    const int ta = tid % N, tb = tid / N;
+    T v[N], r[N], acc[N];
+    if (act) {   // x: thread (i2, i3); sum the two children along x
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int s2 = q & 1, s3 = q >> 1;
+#pragma unroll
+            for (int k = 0; k < N; ++k) acc[k] = T(0);
+#pragma unroll
+            for (int s1 = 0; s1 < 2; ++s1) {
+                const size_t child = size_t(2 * ix + s1) + size_t(fx) * (size_t(2 * iy + s2) + size_t(fy) * size_t(2 * iz + s3));
+                const T* __restrict__ src = fine + child * N3 + N * (ta + N * tb);
+#pragma unroll
+                for (int k = 0; k < N; ++k) v[k] = src[k];
+                mat1d<N, true>(emb + s1 * N2, v, r);
+#pragma unroll
+                for (int k = 0; k < N; ++k) acc[k] += r[k];
+            }
+#pragma unroll
+            for (int k = 0; k < N; ++k) X[q][S::idx(k, ta, tb)] = acc[k];
+        }
+    }
+    __syncthreads();
+    if (act) {   // y: thread (j1, i3)
+#pragma unroll
+        for (int s3 = 0; s3 < 2; ++s3) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) acc[k] = T(0);
+#pragma unroll
+            for (int s2 = 0; s2 < 2; ++s2) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) v[k] = X[s2 + 2 * s3][S::idx(ta, k, tb)];
+                mat1d<N, true>(emb + s2 * N2, v, r);
+#pragma unroll
+                for (int k = 0; k < N; ++k) acc[k] += r[k];
+            }
+#pragma unroll
+            for (int k = 0; k < N; ++k) Y[s3][S::idx(ta, k, tb)] = acc[k];
+        }
+    }
+    __syncthreads();
+    if (act) {   // z: thread (j1, j2)
+#pragma unroll
+        for (int k = 0; k < N; ++k) acc[k] = T(0);
+#pragma unroll
+        for (int s3 = 0; s3 < 2; ++s3) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = Y[s3][S::idx(ta, tb, k)];
+            mat1d<N, true>(emb + s3 * N2, v, r);
+#pragma unroll
+            for (int k = 0; k < N; ++k) acc[k] += r[k];
+        }
+        T* __restrict__ dst = coarse + size_t(cc) * N3 + ta + N * tb;
+#pragma unroll
+        for (int k = 0; k < N; ++k) dst[k * N2] = acc[k];
+    }
+}
+
+template <typename T>
+int transfer_prolongate_add(int n, const int nf[3], const T* coarse, T* fine, const T* emb, hipStream_t st) {
+    const unsigned ncoarse = unsigned((nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2));
+    switch (n) {
+#define SIPG_TR_CASE(NN)                                                                                      \
+    case NN:                                                                                                  \
+        prolongate_kernel<NN, T><<<ncoarse, TrShape<NN>::NT, 0, st>>>(coarse, fine, emb, nf[0], nf[1], nf[2]); \
+        break;
+        SIPG_TR_CASE(2) SIPG_TR_CASE(3) SIPG_TR_CASE(4) SIPG_TR_CASE(5)
+        SIPG_TR_CASE(6) SIPG_TR_CASE(7) SIPG_TR_CASE(8) SIPG_TR_CASE(9)
+#undef SIPG_TR_CASE
+        default: set_error("transfer: unsupported degree"); return SIPG_E_UNSUPPORTED;
+    }
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
+template <typename T>
+int transfer_restrict(int n, const int nf[3], const T* fine, T* coarse, const T* emb, hipStream_t st) {
+    const unsigned ncoarse = unsigned((nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2));
+    switch (n) {
+#define SIPG_TR_CASE(NN)                                                                                    \
+    case NN:                                                                                                \
+        restrict_kernel<NN, T><<<ncoarse, TrShape<NN>::NT, 0, st>>>(fine, coarse, emb, nf[0], nf[1], nf[2]); \
+        break;
+        SIPG_TR_CASE(2) SIPG_TR_CASE(3) SIPG_TR_CASE(4) SIPG_TR_CASE(5)
+        SIPG_TR_CASE(6) SIPG_TR_CASE(7) SIPG_TR_CASE(8) SIPG_TR_CASE(9)
+#undef SIPG_TR_CASE
+        default: set_error("transfer: unsupported degree"); return SIPG_E_UNSUPPORTED;
+    }
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
+template int transfer_prolongate_add<float>(int, const int[3], const float*, float*, const float*, hipStream_t);
+template int transfer_prolongate_add<double>(int, const int[3], const double*, double*, const double*, hipStream_t);
+template int transfer_restrict<float>(int, const int[3], const float*, float*, const float*, hipStream_t);
+template int transfer_restrict<double>(int, const int[3], const double*, double*, const double*, hipStream_t);
+
+}  // namespace sipg

@@ -1,0 +1,27 @@
+// Vector kernels (FP32 / FP64) used by the solvers.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace sipg {
+
+constexpr int kVecPartials = 2048;   // size of the partial-sum buffer of vec_dot_async
+
+template <typename T> int vec_cheb(const T* u, T* u_old, const T* z, double sigma, double theta, int64_t n, hipStream_t st);
+template <typename T> int vec_sub(const T* b, const T* a, T* r, int64_t n, hipStream_t st);
+template <typename T> int vec_axpby(double alpha, const T* x, double beta, T* y, int64_t n, hipStream_t st);
+template <typename T> int vec_scale(double alpha, const T* x, T* y, int64_t n, hipStream_t st);
+template <typename TO, typename TI> int vec_convert(const TI* x, TO* y, int64_t n, hipStream_t st);
+// *out = sum a_i b_i (device scalar, double); partial holds kVecPartials doubles
+template <typename T> int vec_dot_async(const T* a, const T* b, double* partial, double* out, int64_t n, hipStream_t st);
+
+// Grid transfer between a mesh and its coarsening by two in every direction
+// (tensor-product embedding of the coarse cell into its 8 children).
+// Prolongation: fine += P coarse.  Restriction: coarse = P^T fine.
+template <typename T>
+int transfer_prolongate_add(int n, const int nc_fine[3], const T* coarse, T* fine, const T* emb, hipStream_t st);
+template <typename T>
+int transfer_restrict(int n, const int nc_fine[3], const T* fine, T* coarse, const T* emb, hipStream_t st);
+
+}  // namespace sipg

@@ -1,0 +1,128 @@
+"""GPU parity of the right-hand side, the multigrid transfer and the
+multigrid-preconditioned solves against the oracle."""
+import numpy as np
+import pytest
+import scipy.sparse.linalg as spla
+
+from oracle import mms
+from oracle import multigrid as omg
+from oracle.sipg import SIPG
+from workloads import unit_cube, paper_affine_brick
+from tests.gpu_util import banner, rel_errors, require_gpu
+
+pytestmark = pytest.mark.gpu
+
+
+@pytest.mark.parametrize("k", [1, 3, 5, 8])
+@pytest.mark.parametrize("deform", [0.0, 0.1])
+def test_rhs_sines(k, deform):
+    torch, P = require_gpu()
+    banner(f"rhs k={k} deform={deform}")
+    mesh = unit_cube((3, 2, 4), deform)
+    ref = SIPG(mesh, k, 2.0)
+    amps = [3 * np.pi ** 2, -0.7, 1.3]
+    waves = [(1, 1, 1), (2, 1, 3), (4, 2, 1)]
+    b_ref = mms.rhs(ref, mms.modes_rhs(amps, waves))
+    op = P.Operator(mesh, k, 2.0)
+    b = op.assemble_rhs(amps, waves).cpu().numpy()
+    e2, emax = rel_errors(b, b_ref)
+    assert e2 <= 1e-12 and emax <= 1e-12, (e2, emax)
+    op.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 4, 7])
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+def test_transfer_matches_oracle(k, basis):
+    torch, P = require_gpu()
+    banner(f"transfer k={k} {basis}")
+    mesh = unit_cube((4, 2, 6), 0.1)
+    mg = P.Multigrid(mesh, k, 2.0, basis, precision="f64", lanczos_steps=4)
+    nf, cf = mg.level(0)
+    nc, cc = mg.level(1)
+    assert cf == (4, 2, 6) and cc == (2, 1, 3)
+    rng = np.random.default_rng(k)
+    c = rng.uniform(-1, 1, nc)
+    f = rng.uniform(-1, 1, nf)
+    dc = torch.from_numpy(c).cuda()
+    df = torch.from_numpy(f).cuda()
+    out_f = torch.empty(nf, dtype=torch.float64, device="cuda")
+    out_c = torch.empty(nc, dtype=torch.float64, device="cuda")
+    pf = mg.transfer(0, "prolongate", dc, out_f).cpu().numpy()
+    rc = mg.transfer(0, "restrict", df, out_c).cpu().numpy()
+    e = rel_errors(pf, omg.prolongate(c, cf, basis, k))
+    assert e[0] < 1e-12 and e[1] < 1e-12, e
+    e = rel_errors(rc, omg.restrict(f, cf, basis, k))
+    assert e[0] < 1e-12 and e[1] < 1e-12, e
+    mg.close()
+
+
+def test_vcycle_is_symmetric_in_fp64():
+    """The V-cycle (Chebyshev pre/post smoothing, transposed transfers) is a
+    symmetric operator, as CG requires."""
+    torch, P = require_gpu()
+    banner("vcycle symmetry")
+    mesh = unit_cube((4, 4, 4), 0.1)
+    mg = P.Multigrid(mesh, 3, 2.0, precision="f64")
+    rng = np.random.default_rng(2)
+    a = torch.from_numpy(rng.uniform(-1, 1, mg.ndofs)).cuda()
+    b = torch.from_numpy(rng.uniform(-1, 1, mg.ndofs)).cuda()
+    va = mg.vcycle(a)
+    vb = mg.vcycle(b)
+    lhs = float(torch.dot(b, va))
+    rhs = float(torch.dot(a, vb))
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs), (lhs, rhs)
+    assert float(torch.dot(a, va)) > 0
+    mg.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "f64"])
+def test_mg_solve_small_config(precision):
+    """8^3 Cartesian unit cube, k=3, eta=2, manufactured sine solution:
+    residual 1e-10 in FP64 and the same discrete solution as the oracle."""
+    torch, P = require_gpu()
+    banner(f"mg solve small {precision}")
+    mesh = unit_cube(8)
+    ref = SIPG(mesh, 3, 2.0)
+    A = ref.assemble()
+    b = mms.rhs(ref, mms.sine_rhs)
+    mg = P.Multigrid(mesh, 3, 2.0, precision=precision)
+    assert mg.info.levels == 4
+    x, info = mg.solve(torch.from_numpy(b).cuda(), rel_tol=1e-10)
+    xs = x.cpu().numpy()
+    res = np.linalg.norm(b - A @ xs) / np.linalg.norm(b)
+    assert res <= 1.5e-10, res
+    assert info.iterations <= 20, info.iterations
+    xr, _ = spla.cg(A, b, rtol=1e-13, maxiter=20000)
+    assert rel_errors(xs, xr)[0] < 1e-8
+    mg.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "f64"])
+def test_mg_solve_deformed_k5(precision):
+    torch, P = require_gpu()
+    banner(f"mg solve deformed k=5 {precision}")
+    mesh = unit_cube(6, 0.1)
+    ref = SIPG(mesh, 5, 2.0)
+    b = mms.rhs(ref, mms.sine_rhs)
+    mg = P.Multigrid(mesh, 5, 2.0, precision=precision)
+    x, info = mg.solve(torch.from_numpy(b).cuda(), rel_tol=1e-10)
+    xs = x.cpu().numpy()
+    r = b - ref.apply_naive(xs)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-10
+    assert info.iterations <= 25, info.iterations
+    assert mms.l2_error(ref, xs, mms.sine) < 1e-4
+    mg.close()
+
+
+def test_mg_solve_gl_basis_and_affine_brick():
+    torch, P = require_gpu()
+    banner("mg solve GL basis, paper brick")
+    mesh = paper_affine_brick((4, 4, 2))
+    ref = SIPG(mesh, 4, 2.0, "nodal_gl")
+    rng = np.random.default_rng(0)
+    b = rng.uniform(-1, 1, ref.ndofs)
+    mg = P.Multigrid(mesh, 4, 2.0, "nodal_gl", precision="mixed")
+    x, info = mg.solve(torch.from_numpy(b).cuda(), rel_tol=1e-10)
+    r = b - ref.apply_naive(x.cpu().numpy())
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-10
+    mg.close()

@@ -1,0 +1,36 @@
+"""Pin of the oracle's nested-mesh embedding: the fine representation of a
+coarse function takes the same values at every point (CPU only)."""
+import numpy as np
+import pytest
+
+from oracle import multigrid as omg
+from oracle.sipg import tensor_eval
+from oracle import basis as b1d
+from workloads import unit_cube
+
+
+@pytest.mark.parametrize("kind", ["hermite_like", "nodal_gl"])
+@pytest.mark.parametrize("k", [1, 2, 3, 5, 8])
+def test_embedding_reproduces_coarse_function(kind, k):
+    n = k + 1
+    rng = np.random.default_rng(k)
+    coarse = rng.uniform(-1, 1, n ** 3)                 # one coarse cell
+    fine = omg.prolongate(coarse, (2, 2, 2), kind, k).reshape(8, n ** 3)
+    bas = b1d.make_basis(kind, k)
+    pts = rng.uniform(0, 1, (50, 3))                    # child reference points
+    vf, _ = tensor_eval(bas, pts)
+    for child in range(8):
+        s = np.array([child % 2, (child // 2) % 2, child // 4])
+        vc, _ = tensor_eval(bas, 0.5 * (s + pts))       # same points in the coarse cell
+        assert np.max(np.abs(vf @ fine[child] - vc @ coarse)) < 1e-12
+
+
+def test_restriction_is_transpose():
+    k, nc = 2, (4, 2, 2)
+    n3 = (k + 1) ** 3
+    rng = np.random.default_rng(0)
+    c = rng.uniform(-1, 1, (nc[0] // 2) * (nc[1] // 2) * (nc[2] // 2) * n3)
+    f = rng.uniform(-1, 1, nc[0] * nc[1] * nc[2] * n3)
+    lhs = omg.prolongate(c, nc, "hermite_like", k) @ f
+    rhs = c @ omg.restrict(f, nc, "hermite_like", k)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
