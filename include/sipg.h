@@ -204,6 +204,7 @@ typedef struct {
     double lambda_max_fine;      /* estimated largest eigenvalue of P^-1 A, finest level */
     double lambda_min_coarse, lambda_max_coarse;
     int32_t coarse_steps;        /* Chebyshev degree of the coarse solve */
+    int64_t device_bytes;        /* device memory owned by the solver */
 } sipg_mg_info;
 typedef struct sipg_mg sipg_mg;
 
@@ -240,6 +241,68 @@ int sipg_mg_level_ndofs(const sipg_mg* mg, int level, int64_t* ndofs, int32_t ce
  * single mode (1,1,1) with amplitude 3 pi^2. */
 int sipg_assemble_rhs_sines(const sipg_op* op, int nmodes, const double* amps, const int* waves,
                             void* b, void* stream);
+
+/*
+ * Request loop for Poisson solves on one GPU (continuous batching).
+ * A request names the problem (mesh, degree, penalty, basis), a smooth source
+ * f = sum of sine modes (as for sipg_assemble_rhs_sines) and a tolerance; the
+ * server assembles b on the device and solves A x = b with the multigrid
+ * solver (precision of the server).  Requests wait in a FIFO; `workers`
+ * threads with one HIP stream each take the oldest request whose memory fits
+ * the budget, so solves of different requests overlap on the device and new
+ * arrivals are admitted as soon as a worker and memory are free.  Solver
+ * hierarchies stay resident in a cache keyed by the problem (reused by later
+ * requests, evicted least-recently-used when memory is needed).
+ */
+typedef struct {
+    int64_t hbm_budget_bytes;    /* device memory the server may hold (64 GiB) */
+    int32_t workers;             /* concurrent solves, 1..16 (4) */
+    int32_t precision;           /* 0 mixed FP32 V-cycle, 1 FP64 (0) */
+} sipg_server_opts;
+typedef struct {
+    sipg_mesh mesh;
+    int32_t degree;
+    double penalty_factor;
+    int32_t basis;
+    int32_t nmodes;              /* 1..16 */
+    double amps[16];
+    int32_t waves[16][3];
+    double rel_tol;
+    int32_t max_iter;
+    double* x_out;               /* device buffer (ndofs doubles) for the solution, or NULL:
+                                    the server then owns it until sipg_release */
+} sipg_request;
+typedef struct {
+    int32_t status;              /* SIPG_OK, SIPG_E_NOCONV, ... of the solve */
+    int32_t iterations;
+    double true_residual;        /* ||b - A x||_2 */
+    double rel_residual;         /* true_residual / ||b||_2 */
+    double queue_s, solve_s, total_s;   /* wait, run, submit-to-done (seconds) */
+    int64_t ndofs;
+    const double* x;             /* device pointer of the solution */
+} sipg_result;
+typedef struct {
+    int64_t queued, completed, cached_hierarchies, used_bytes, peak_bytes;
+} sipg_server_stats_t;
+typedef struct sipg_server sipg_server;
+
+int sipg_server_default_opts(sipg_server_opts* opts);
+int sipg_server_create(const sipg_server_opts* opts, sipg_server** out);
+/* Non-blocking.  *ticket identifies the request.  SIPG_E_BUDGET if the
+ * request alone can never fit the budget, SIPG_E_ARG for an invalid one. */
+int sipg_submit(sipg_server* s, const sipg_request* req, uint64_t* ticket);
+/* SIPG_E_NOTREADY until the request finished; then fills *res. */
+int sipg_poll(sipg_server* s, uint64_t ticket, sipg_result* res);
+/* Blocks until the request finished, then fills *res. */
+int sipg_wait(sipg_server* s, uint64_t ticket, sipg_result* res);
+/* Forget a finished request (frees a server-owned solution buffer). */
+int sipg_release(sipg_server* s, uint64_t ticket);
+int sipg_server_stats(sipg_server* s, sipg_server_stats_t* stats);
+/* Finishes every submitted request, then frees the server. */
+int sipg_server_destroy(sipg_server* s);
+
+/* Stream-ordered device-to-device copy of `bytes` bytes (e.g. a result's solution). */
+int sipg_copy_device(void* dst, const void* src, size_t bytes, void* stream);
 
 /* Text of the calling thread's last error ("" if none). */
 const char* sipg_last_error(void);

@@ -43,6 +43,8 @@ EXPORTED = [
     "sipg_mg_default_opts", "sipg_mg_setup", "sipg_mg_destroy", "sipg_mg_get_info",
     "sipg_mg_apply_vcycle", "sipg_mg_solve", "sipg_mg_transfer", "sipg_mg_level_ndofs",
     "sipg_assemble_rhs_sines",
+    "sipg_server_default_opts", "sipg_server_create", "sipg_submit", "sipg_poll", "sipg_wait",
+    "sipg_release", "sipg_server_stats", "sipg_server_destroy", "sipg_copy_device",
 ]
 
 
@@ -72,7 +74,29 @@ class SipgMgOpts(C.Structure):
 class SipgMgInfo(C.Structure):
     _fields_ = [("levels", C.c_int32), ("ndofs", C.c_int64), ("precision", C.c_int32),
                 ("lambda_max_fine", C.c_double), ("lambda_min_coarse", C.c_double),
-                ("lambda_max_coarse", C.c_double), ("coarse_steps", C.c_int32)]
+                ("lambda_max_coarse", C.c_double), ("coarse_steps", C.c_int32), ("device_bytes", C.c_int64)]
+
+
+class SipgServerOpts(C.Structure):
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("workers", C.c_int32), ("precision", C.c_int32)]
+
+
+class SipgRequest(C.Structure):
+    _fields_ = [("mesh", SipgMesh), ("degree", C.c_int32), ("penalty_factor", C.c_double),
+                ("basis", C.c_int32), ("nmodes", C.c_int32), ("amps", C.c_double * 16),
+                ("waves", (C.c_int32 * 3) * 16), ("rel_tol", C.c_double), ("max_iter", C.c_int32),
+                ("x_out", C.c_void_p)]
+
+
+class SipgResult(C.Structure):
+    _fields_ = [("status", C.c_int32), ("iterations", C.c_int32), ("true_residual", C.c_double),
+                ("rel_residual", C.c_double), ("queue_s", C.c_double), ("solve_s", C.c_double),
+                ("total_s", C.c_double), ("ndofs", C.c_int64), ("x", C.c_void_p)]
+
+
+class SipgServerStats(C.Structure):
+    _fields_ = [("queued", C.c_int64), ("completed", C.c_int64), ("cached_hierarchies", C.c_int64),
+                ("used_bytes", C.c_int64), ("peak_bytes", C.c_int64)]
 
 
 class SipgTables1D(C.Structure):
@@ -106,6 +130,15 @@ lib.sipg_mg_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(Sipg
 lib.sipg_mg_transfer.argtypes = [_vp, C.c_int, C.c_int, _vp, _vp, _vp]
 lib.sipg_mg_level_ndofs.argtypes = [_vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
 lib.sipg_assemble_rhs_sines.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), _vp, _vp]
+lib.sipg_server_default_opts.argtypes = [C.POINTER(SipgServerOpts)]
+lib.sipg_server_create.argtypes = [C.POINTER(SipgServerOpts), C.POINTER(_vp)]
+lib.sipg_submit.argtypes = [_vp, C.POINTER(SipgRequest), C.POINTER(C.c_uint64)]
+lib.sipg_poll.argtypes = [_vp, C.c_uint64, C.POINTER(SipgResult)]
+lib.sipg_wait.argtypes = [_vp, C.c_uint64, C.POINTER(SipgResult)]
+lib.sipg_release.argtypes = [_vp, C.c_uint64]
+lib.sipg_server_stats.argtypes = [_vp, C.POINTER(SipgServerStats)]
+lib.sipg_server_destroy.argtypes = [_vp]
+lib.sipg_copy_device.argtypes = [_vp, _vp, C.c_size_t, _vp]
 for _f in EXPORTED:
     if _f not in ("sipg_ndofs", "sipg_last_error"):
         getattr(lib, _f).restype = C.c_int
@@ -346,3 +379,87 @@ class Multigrid:
             self.close()
         except Exception:
             pass
+
+
+def _result_dict(r: SipgResult) -> dict:
+    return {k: getattr(r, k) for k, _ in SipgResult._fields_}
+
+
+class Server:
+    """Continuous-batching request loop of multigrid Poisson solves."""
+
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 4, precision: str = "mixed"):
+        torch = _torch()
+        if not torch.cuda.is_available():
+            raise RuntimeError("Server needs a GPU (HIP device)")
+        torch.cuda.init()
+        o = SipgServerOpts(int(hbm_budget_bytes), int(workers), {"mixed": 0, "f64": 1}[precision])
+        h = _vp()
+        _check(lib.sipg_server_create(C.byref(o), C.byref(h)), "sipg_server_create")
+        self._h = h
+
+    @staticmethod
+    def make_request(mesh, degree: int, amps, waves, penalty: float = 2.0, basis: str = "hermite_like",
+                     rel_tol: float = 1e-8, max_iter: int = 200, x_out=None) -> SipgRequest:
+        r = SipgRequest()
+        r.mesh = make_mesh(mesh)
+        r.degree = int(degree)
+        r.penalty_factor = float(penalty)
+        r.basis = BASIS[basis]
+        amps = list(amps)
+        waves = [tuple(w) for w in waves]
+        r.nmodes = len(amps)
+        for i, (a, w) in enumerate(zip(amps, waves)):
+            r.amps[i] = float(a)
+            for d in range(3):
+                r.waves[i][d] = int(w[d])
+        r.rel_tol = float(rel_tol)
+        r.max_iter = int(max_iter)
+        r.x_out = None if x_out is None else int(x_out.data_ptr())
+        return r
+
+    def submit(self, req: SipgRequest) -> int:
+        t = C.c_uint64()
+        _check(lib.sipg_submit(self._h, C.byref(req), C.byref(t)), "sipg_submit")
+        return int(t.value)
+
+    def poll(self, ticket: int):
+        r = SipgResult()
+        rc = lib.sipg_poll(self._h, ticket, C.byref(r))
+        if rc == SIPG_E_NOTREADY:
+            return None
+        _check(rc, "sipg_poll")
+        return _result_dict(r)
+
+    def wait(self, ticket: int) -> dict:
+        r = SipgResult()
+        _check(lib.sipg_wait(self._h, ticket, C.byref(r)), "sipg_wait")
+        return _result_dict(r)
+
+    def solution(self, result: dict, stream=None):
+        """Copy of a result's device solution as a torch tensor."""
+        torch = _torch()
+        out = torch.empty(int(result["ndofs"]), dtype=torch.float64, device="cuda")
+        _check(lib.sipg_copy_device(_vp(out.data_ptr()), _vp(result["x"]), C.c_size_t(out.numel() * 8),
+                                    _vp(_stream_ptr(stream))), "sipg_copy_device")
+        return out
+
+    def release(self, ticket: int):
+        _check(lib.sipg_release(self._h, ticket), "sipg_release")
+
+    def stats(self) -> dict:
+        st = SipgServerStats()
+        _check(lib.sipg_server_stats(self._h, C.byref(st)), "sipg_server_stats")
+        return {k: getattr(st, k) for k, _ in SipgServerStats._fields_}
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sipg_server_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+

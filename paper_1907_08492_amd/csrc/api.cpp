@@ -240,6 +240,12 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
 
 int sipg_destroy(sipg_op* op) { return free_op(op); }
 
+int sipg_copy_device(void* dst, const void* src, size_t bytes, void* stream) {
+    if (!dst || !src) { set_error("sipg_copy_device: null pointer"); return SIPG_E_ARG; }
+    SIPG_HIP(hipMemcpyAsync(dst, src, bytes, hipMemcpyDeviceToDevice, static_cast<hipStream_t>(stream)));
+    return SIPG_OK;
+}
+
 int sipg_launch_shape(int degree, int dtype, int32_t* cpb, int32_t* nt, int64_t* lds) {
     if (degree < 1 || degree > 8 || (dtype != SIPG_F64 && dtype != SIPG_F32)) {
         set_error("sipg_launch_shape: degree must be in [1,8], dtype SIPG_F64 or SIPG_F32");

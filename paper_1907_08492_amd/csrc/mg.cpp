@@ -215,6 +215,13 @@ struct Hierarchy {
 
 using namespace sipg;
 
+struct sipg_mg;
+namespace sipg {
+sipg_op* mg_fine_operator(sipg_mg* mg);
+double* mg_rhs_buffer(sipg_mg* mg);
+double mg_last_rhs_norm(const sipg_mg* mg);
+}  // namespace sipg
+
 struct sipg_mg {
     int precision = 0;                   // 0: FP32 V-cycle, 1: FP64 V-cycle
     sipg_op* fine64 = nullptr;           // FP64 operator of the outer iteration
@@ -222,11 +229,20 @@ struct sipg_mg {
     Hierarchy<double> h64;
     Scratch sc;
     int64_t ndofs = 0;
+    DevBuf<double> wb, wr, wz, wp, wap;  // right-hand side and CG work vectors (FP64)
+    double last_bnorm = 0.0;
+    int64_t device_bytes = 0;            // operators, diagonals and level vectors
     int levels = 0;
     double lmax0 = 0.0, lmin_coarse = 0.0, lmax_coarse = 0.0;
     int coarse_steps = 0;
     ~sipg_mg() { if (fine64) sipg_destroy(fine64); }
 };
+
+namespace sipg {
+sipg_op* mg_fine_operator(sipg_mg* mg) { return mg->fine64; }
+double* mg_rhs_buffer(sipg_mg* mg) { return mg->wb.p; }
+double mg_last_rhs_norm(const sipg_mg* mg) { return mg->last_bnorm; }
+}  // namespace sipg
 
 template <typename T>
 static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, int degree, double penalty,
@@ -264,7 +280,10 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
     for (size_t l = 0; l < H.lv.size(); ++l) {
         const bool coarsest = l + 1 == H.lv.size();
         Level<T>& L = *H.lv[l];
-        const int steps = coarsest ? int(std::min<int64_t>(L.n, 300)) : o.lanczos_steps;
+        // the coarse solve needs both ends of the spectrum: more Lanczos steps,
+        // bounded well below the level size so that the FP32 recurrence does
+        // not lose orthogonality into spurious extreme values
+        const int steps = coarsest ? int(std::min<int64_t>(L.n / 4 + 2, 120)) : o.lanczos_steps;
         if ((rc = H.lanczos(int(l), steps, mg->sc, st)) != SIPG_OK) return rc;
         if (!coarsest) {
             chebyshev_coefficients(o.range_lo * L.lmax, o.range_hi * L.lmax, H.smooth_steps, L.sigma, L.theta);
@@ -287,6 +306,9 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
     }
     mg->lmax0 = H.lv[0]->lmax;
     mg->levels = int(H.lv.size());
+    int64_t bytes = mg->fine64 ? mg->fine64->device_bytes : 0;
+    for (auto& L : H.lv) bytes += L->op->device_bytes + int64_t(5 * sizeof(T)) * L->n;
+    mg->device_bytes = bytes + int64_t(sizeof(double)) * (kVecPartials + 8 + 5 * mg->ndofs);
     return SIPG_OK;
 }
 
@@ -325,6 +347,9 @@ int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, 
     if (rc != SIPG_OK) return rc;
     mg->ndofs = mg->fine64->ndofs;
     if ((rc = mg->sc.init()) != SIPG_OK) return rc;
+    if ((rc = mg->wb.alloc(mg->ndofs)) || (rc = mg->wr.alloc(mg->ndofs)) || (rc = mg->wz.alloc(mg->ndofs)) ||
+        (rc = mg->wp.alloc(mg->ndofs)) || (rc = mg->wap.alloc(mg->ndofs)))
+        return rc;
     rc = o.precision == 0 ? build_hierarchy<float>(mg.get(), mg->h32, mesh, degree, penalty, basis, o, st)
                           : build_hierarchy<double>(mg.get(), mg->h64, mesh, degree, penalty, basis, o, st);
     if (rc != SIPG_OK) return rc;
@@ -347,6 +372,7 @@ int sipg_mg_get_info(const sipg_mg* mg, sipg_mg_info* info) {
     info->lambda_min_coarse = mg->lmin_coarse;
     info->lambda_max_coarse = mg->lmax_coarse;
     info->coarse_steps = mg->coarse_steps;
+    info->device_bytes = mg->device_bytes;
     return SIPG_OK;
 }
 
@@ -375,12 +401,15 @@ int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int m
     hipStream_t st = static_cast<hipStream_t>(stream);
     const int64_t n = mg->ndofs;
     std::memset(info, 0, sizeof(*info));
-    DevBuf<double> r, z, p, ap;
+    DevBuf<double>& r = mg->wr;
+    DevBuf<double>& z = mg->wz;
+    DevBuf<double>& p = mg->wp;
+    DevBuf<double>& ap = mg->wap;
     int rc;
-    if ((rc = r.alloc(n)) || (rc = z.alloc(n)) || (rc = p.alloc(n)) || (rc = ap.alloc(n))) return rc;
     Scratch& sc = mg->sc;
     double bb;
     if ((rc = sc.dot<double>(b, b, n, bb, st)) != SIPG_OK) return rc;
+    mg->last_bnorm = std::sqrt(bb);
     const double target = rel_tol * (bb > 0.0 ? std::sqrt(bb) : 1.0);
     if ((rc = launch_matvec(mg->fine64, x, ap.p, st)) != SIPG_OK) return rc;
     if ((rc = vec_sub<double>(b, ap.p, r.p, n, st)) != SIPG_OK) return rc;

@@ -1,0 +1,379 @@
+// Request loop for Poisson solves (sipg_submit / sipg_poll): continuous
+// batching of multigrid solves on one GPU.
+//
+// Requests wait in a FIFO queue.  A pool of worker threads, each with its own
+// HIP stream (default priority), takes the oldest request whose memory fits:
+// a worker checks out an idle multigrid hierarchy of the request's problem
+// from a cache (or builds one), assembles the right-hand side on the device,
+// runs the FP64-CG / multigrid solve and returns the hierarchy to the cache.
+// Solves of different requests therefore run concurrently on the device;
+// requests that arrive while others run are admitted as soon as a worker and
+// enough of the HBM budget are free.  The budget counts the cached
+// hierarchies and the per-request vectors; idle hierarchies are evicted in
+// least-recently-used order when a request needs the memory.
+#include <hip/hip_runtime.h>
+
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <list>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <new>
+#include <string>
+#include <thread>
+#include <vector>
+
+#include "setup.hpp"
+#include "sipg_common.hpp"
+
+using Clock = std::chrono::steady_clock;
+
+namespace {
+
+struct Key {
+    int32_t n[3];
+    double lo[3], hi[3], lin[9], a;
+    int degree, basis, precision;
+    double penalty;
+    bool operator<(const Key& o) const { return std::memcmp(this, &o, sizeof(Key)) < 0; }
+};
+
+struct CacheEntry {
+    sipg_mg* mg = nullptr;
+    bool busy = false;
+    int64_t bytes = 0;
+    Clock::time_point last_used;
+};
+
+struct Job {
+    uint64_t ticket = 0;
+    sipg_request req{};
+    Key key{};
+    int64_t ndofs = 0;
+    int64_t est_bytes = 0;           // hierarchy estimate + request vectors
+    Clock::time_point t_submit, t_start, t_end;
+    bool done = false;
+    sipg_result res{};
+    double* x_owned = nullptr;       // server-owned solution buffer
+};
+
+}  // namespace
+
+struct sipg_server {
+    sipg_server_opts opts{};
+    std::mutex mu;
+    std::condition_variable cv_work, cv_done;
+    std::deque<Job*> queue;
+    std::map<uint64_t, std::unique_ptr<Job>> jobs;
+    std::multimap<Key, CacheEntry> cache;
+    int64_t used_bytes = 0;          // cached hierarchies + running requests' vectors
+    uint64_t next_ticket = 1;
+    bool stop = false;
+    std::vector<std::thread> workers;
+    hipStream_t house = nullptr;     // stream for releasing result buffers
+    int64_t peak_bytes = 0;
+    int64_t completed = 0;
+};
+
+namespace sipg {
+
+static Key make_key(const sipg_request& r, int precision) {
+    Key k;
+    std::memset(&k, 0, sizeof(k));
+    for (int d = 0; d < 3; ++d) { k.n[d] = r.mesh.n[d]; k.lo[d] = r.mesh.lo[d]; k.hi[d] = r.mesh.hi[d]; }
+    for (int i = 0; i < 9; ++i) k.lin[i] = r.mesh.lin[i];
+    k.a = r.mesh.deform_amp;
+    k.degree = r.degree;
+    k.basis = r.basis;
+    k.precision = precision;
+    k.penalty = r.penalty_factor;
+    return k;
+}
+
+// Upper estimate of a hierarchy's device memory before it exists: the FP64
+// fine operator, the V-cycle levels (8/7 of the fine size) with five vectors
+// each, and the metric terms (per point on deformed meshes).
+static int64_t estimate_hierarchy_bytes(const sipg_request& r, int precision) {
+    const int n = r.degree + 1;
+    const int64_t cells = int64_t(r.mesh.n[0]) * r.mesh.n[1] * r.mesh.n[2];
+    const int64_t dofs = cells * n * n * n;
+    const bool deformed = r.mesh.deform_amp != 0.0;
+    const int esz = precision == 0 ? 4 : 8;
+    const int64_t geo_per_cell = deformed ? int64_t(6 * n * n * n + 3 * 7 * n * n) : 32;
+    const int64_t fine64 = 8 * (geo_per_cell * cells + 6 * dofs);        // geometry, rhs and CG vectors
+    const int64_t levels = (esz * (geo_per_cell * cells + 6 * dofs)) * 8 / 7 + 4096 * 8;
+    return fine64 + levels + (int64_t(1) << 20);
+}
+
+static void finish_job(sipg_server* s, Job* j, int status) {
+    j->t_end = Clock::now();
+    j->res.status = status;
+    j->res.queue_s = std::chrono::duration<double>(j->t_start - j->t_submit).count();
+    j->res.solve_s = std::chrono::duration<double>(j->t_end - j->t_start).count();
+    j->res.total_s = std::chrono::duration<double>(j->t_end - j->t_submit).count();
+    j->res.ndofs = j->ndofs;
+    j->done = true;
+    s->completed++;
+}
+
+// Pick the oldest queued job that fits the budget (evicting idle cached
+// hierarchies if needed); called with the lock held.
+static Job* admit(sipg_server* s) {
+    for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
+        Job* j = *it;
+        // an idle cached hierarchy of this problem?
+        bool cached = false;
+        auto range = s->cache.equal_range(j->key);
+        for (auto c = range.first; c != range.second; ++c)
+            if (!c->second.busy) { cached = true; break; }
+        const int64_t vec_bytes = j->req.x_out ? 0 : 8 * j->ndofs;   // server-owned solution
+        const int64_t need = vec_bytes + (cached ? 0 : estimate_hierarchy_bytes(j->req, s->opts.precision));
+        // evict idle hierarchies (least recently used first) until it fits
+        while (s->used_bytes + need > s->opts.hbm_budget_bytes) {
+            auto victim = s->cache.end();
+            for (auto c = s->cache.begin(); c != s->cache.end(); ++c) {
+                if (c->second.busy) continue;
+                if (cached && !(c->first < j->key) && !(j->key < c->first)) continue;   // keep ours
+                if (victim == s->cache.end() || c->second.last_used < victim->second.last_used) victim = c;
+            }
+            if (victim == s->cache.end()) break;
+            sipg_mg_destroy(victim->second.mg);
+            s->used_bytes -= victim->second.bytes;
+            s->cache.erase(victim);
+        }
+        if (s->used_bytes + need > s->opts.hbm_budget_bytes) continue;   // try a smaller request
+        j->est_bytes = need;
+        s->used_bytes += need;
+        s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
+        s->queue.erase(it);
+        return j;
+    }
+    return nullptr;
+}
+
+static void worker_main(sipg_server* s) {
+    hipStream_t st = nullptr;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
+    std::unique_lock<std::mutex> lk(s->mu);
+    for (;;) {
+        Job* j = nullptr;
+        s->cv_work.wait(lk, [&] { return s->stop || (j = admit(s)) != nullptr; });
+        if (!j) break;   // stop requested and nothing admissible
+        j->t_start = Clock::now();
+        // check out a cached hierarchy
+        sipg_mg* mg = nullptr;
+        CacheEntry* ce = nullptr;
+        auto range = s->cache.equal_range(j->key);
+        for (auto c = range.first; c != range.second; ++c)
+            if (!c->second.busy) { ce = &c->second; break; }
+        if (ce) { ce->busy = true; mg = ce->mg; }
+        lk.unlock();
+
+        int status = SIPG_OK;
+        int64_t built_bytes = 0;
+        if (!mg) {
+            sipg_mg_opts o;
+            sipg_mg_default_opts(&o);
+            o.precision = s->opts.precision;
+            status = sipg_mg_setup(&j->req.mesh, j->req.degree, j->req.penalty_factor, j->req.basis, &o, st, &mg);
+            if (status == SIPG_OK) {
+                sipg_mg_info info;
+                sipg_mg_get_info(mg, &info);
+                built_bytes = info.device_bytes;
+            }
+        }
+        double* b = status == SIPG_OK ? mg_rhs_buffer(mg) : nullptr;
+        double* x = j->req.x_out;
+        if (status == SIPG_OK && !x) {
+            // stream-ordered: no device-wide synchronisation between workers
+            if (hipMallocAsync(reinterpret_cast<void**>(&j->x_owned), sizeof(double) * size_t(j->ndofs), st) != hipSuccess)
+                status = SIPG_E_OOM;
+            x = j->x_owned;
+        }
+        sipg_solve_info info{};
+        if (status == SIPG_OK) {
+            status = launch_rhs_sines(mg_fine_operator(mg), j->req.nmodes, j->req.amps, &j->req.waves[0][0], b, st);
+            if (status == SIPG_OK && hipMemsetAsync(x, 0, sizeof(double) * size_t(j->ndofs), st) != hipSuccess)
+                status = SIPG_E_HIP;
+            if (status == SIPG_OK)
+                status = sipg_mg_solve(mg, b, x, j->req.rel_tol, j->req.max_iter, &info, st);
+            double bn = 0.0;
+            if (status == SIPG_OK || status == SIPG_E_NOCONV) bn = mg_last_rhs_norm(mg);
+            j->res.iterations = info.iterations;
+            j->res.true_residual = info.true_residual;
+            j->res.rel_residual = bn > 0.0 ? info.true_residual / bn : info.true_residual;
+            (void)hipStreamSynchronize(st);
+        }
+        j->res.x = x;
+
+        lk.lock();
+        // return or insert the hierarchy into the cache, settle the budget
+        s->used_bytes -= j->est_bytes;
+        if (ce) {
+            ce->busy = false;
+            ce->last_used = Clock::now();
+            s->used_bytes += (j->req.x_out ? 0 : 8 * j->ndofs);   // result buffer stays until released
+        } else if (mg) {
+            CacheEntry e;
+            e.mg = mg;
+            e.bytes = built_bytes;
+            e.last_used = Clock::now();
+            s->cache.emplace(j->key, e);
+            s->used_bytes += built_bytes + (j->req.x_out ? 0 : 8 * j->ndofs);
+        }
+        s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
+        finish_job(s, j, status);
+        s->cv_done.notify_all();
+        s->cv_work.notify_all();
+    }
+    lk.unlock();
+    (void)hipStreamDestroy(st);
+}
+
+}  // namespace sipg
+
+using namespace sipg;
+
+extern "C" {
+
+int sipg_server_default_opts(sipg_server_opts* o) {
+    if (!o) { set_error("sipg_server_default_opts: null"); return SIPG_E_ARG; }
+    o->hbm_budget_bytes = int64_t(64) << 30;
+    o->workers = 4;
+    o->precision = 0;
+    return SIPG_OK;
+}
+
+int sipg_server_create(const sipg_server_opts* opts, sipg_server** out) {
+    if (!out) { set_error("sipg_server_create: null out"); return SIPG_E_ARG; }
+    *out = nullptr;
+    sipg_server_opts o;
+    sipg_server_default_opts(&o);
+    if (opts) o = *opts;
+    if (o.workers < 1 || o.workers > 16 || o.hbm_budget_bytes <= 0 || (o.precision != 0 && o.precision != 1)) {
+        set_error("sipg_server_create: workers in [1,16], budget > 0, precision 0 or 1");
+        return SIPG_E_ARG;
+    }
+    sipg_server* s = new (std::nothrow) sipg_server();
+    if (!s) { set_error("sipg_server_create: out of host memory"); return SIPG_E_OOM; }
+    s->opts = o;
+    int dev = 0;
+    if (hipGetDevice(&dev) != hipSuccess) { delete s; set_error("sipg_server_create: no device"); return SIPG_E_HIP; }
+    if (hipStreamCreateWithFlags(&s->house, hipStreamNonBlocking) != hipSuccess) {
+        delete s;
+        set_error("sipg_server_create: stream creation failed");
+        return SIPG_E_HIP;
+    }
+    for (int w = 0; w < o.workers; ++w)
+        s->workers.emplace_back([s, dev] {
+            (void)hipSetDevice(dev);
+            worker_main(s);
+        });
+    *out = s;
+    return SIPG_OK;
+}
+
+int sipg_submit(sipg_server* s, const sipg_request* r, uint64_t* ticket) {
+    if (!s || !r || !ticket) { set_error("sipg_submit: null argument"); return SIPG_E_ARG; }
+    if (r->degree < 1 || r->degree > 8 || r->nmodes < 1 || r->nmodes > 16 || !(r->rel_tol > 0.0) ||
+        r->max_iter < 0 || !(r->penalty_factor > 0.0) || (r->basis != 0 && r->basis != 1)) {
+        set_error("sipg_submit: invalid request");
+        return SIPG_E_ARG;
+    }
+    for (int d = 0; d < 3; ++d)
+        if (r->mesh.n[d] <= 0) { set_error("sipg_submit: cell counts must be positive"); return SIPG_E_ARG; }
+    auto j = std::make_unique<Job>();
+    j->req = *r;
+    j->key = make_key(*r, s->opts.precision);
+    const int n = r->degree + 1;
+    j->ndofs = int64_t(r->mesh.n[0]) * r->mesh.n[1] * r->mesh.n[2] * n * n * n;
+    const int64_t need = estimate_hierarchy_bytes(*r, s->opts.precision) + 3 * 8 * j->ndofs;
+    if (need > s->opts.hbm_budget_bytes) {
+        set_error("sipg_submit: the request alone exceeds the memory budget");
+        return SIPG_E_BUDGET;
+    }
+    j->t_submit = Clock::now();
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stop) { set_error("sipg_submit: server is shutting down"); return SIPG_E_ARG; }
+    j->ticket = s->next_ticket++;
+    *ticket = j->ticket;
+    s->queue.push_back(j.get());
+    s->jobs.emplace(j->ticket, std::move(j));
+    s->cv_work.notify_one();
+    return SIPG_OK;
+}
+
+int sipg_poll(sipg_server* s, uint64_t ticket, sipg_result* res) {
+    if (!s || !res) { set_error("sipg_poll: null argument"); return SIPG_E_ARG; }
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) { set_error("sipg_poll: unknown ticket"); return SIPG_E_ARG; }
+    if (!it->second->done) return SIPG_E_NOTREADY;
+    *res = it->second->res;
+    return SIPG_OK;
+}
+
+int sipg_wait(sipg_server* s, uint64_t ticket, sipg_result* res) {
+    if (!s || !res) { set_error("sipg_wait: null argument"); return SIPG_E_ARG; }
+    std::unique_lock<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) { set_error("sipg_wait: unknown ticket"); return SIPG_E_ARG; }
+    Job* j = it->second.get();
+    s->cv_done.wait(lk, [&] { return j->done; });
+    *res = j->res;
+    return SIPG_OK;
+}
+
+int sipg_release(sipg_server* s, uint64_t ticket) {
+    if (!s) { set_error("sipg_release: null server"); return SIPG_E_ARG; }
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) { set_error("sipg_release: unknown ticket"); return SIPG_E_ARG; }
+    if (!it->second->done) { set_error("sipg_release: request still running"); return SIPG_E_NOTREADY; }
+    if (it->second->x_owned) {
+        (void)hipFreeAsync(it->second->x_owned, s->house);
+        s->used_bytes -= 8 * it->second->ndofs;
+    }
+    s->jobs.erase(it);
+    s->cv_work.notify_all();
+    return SIPG_OK;
+}
+
+int sipg_server_stats(sipg_server* s, sipg_server_stats_t* st) {
+    if (!s || !st) { set_error("sipg_server_stats: null argument"); return SIPG_E_ARG; }
+    std::lock_guard<std::mutex> lk(s->mu);
+    st->queued = int64_t(s->queue.size());
+    st->completed = s->completed;
+    st->cached_hierarchies = int64_t(s->cache.size());
+    st->used_bytes = s->used_bytes;
+    st->peak_bytes = s->peak_bytes;
+    return SIPG_OK;
+}
+
+int sipg_server_destroy(sipg_server* s) {
+    if (!s) return SIPG_OK;
+    {
+        std::unique_lock<std::mutex> lk(s->mu);
+        // finish everything queued, then stop the workers
+        s->cv_done.wait(lk, [&] {
+            for (auto& kv : s->jobs)
+                if (!kv.second->done) return false;
+            return true;
+        });
+        s->stop = true;
+    }
+    s->cv_work.notify_all();
+    for (auto& t : s->workers) t.join();
+    for (auto& kv : s->jobs)
+        if (kv.second->x_owned) (void)hipFreeAsync(kv.second->x_owned, s->house);
+    (void)hipStreamSynchronize(s->house);
+    (void)hipStreamDestroy(s->house);
+    for (auto& kv : s->cache) sipg_mg_destroy(kv.second.mg);
+    delete s;
+    return SIPG_OK;
+}
+
+}  // extern "C"

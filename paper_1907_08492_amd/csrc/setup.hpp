@@ -30,4 +30,9 @@ int launch_gl_diagonal(const sipg_op* op, void* diag, hipStream_t st);
 int cg_solve_device(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
                     sipg_solve_info* info, hipStream_t st);
 
+// Accessors of the multigrid solver used by the request loop.
+sipg_op* mg_fine_operator(sipg_mg* mg);
+double* mg_rhs_buffer(sipg_mg* mg);
+double mg_last_rhs_norm(const sipg_mg* mg);
+
 }  // namespace sipg
