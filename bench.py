@@ -134,6 +134,63 @@ def cpu_baseline(mesh, k, eta, target_s: float):
                        f"{os.cpu_count()}, BLAS threads={threads}")}
 
 
+def serve_benchmark(P, precision: str, seconds: float, rate: float, workers: int = 4,
+                    budget_bytes: int = 96 << 30, tol: float = 1e-8):
+    """Poisson arrivals of multigrid Poisson solves (unit cube n^3, n log-uniform
+    in [8, 48], k in {3, 4, 5}, 8 random sine modes, tolerance 1e-8) served by
+    the request loop; solves/s, latency percentiles and unknowns/s."""
+    import threading
+    from workloads import serving_requests, unit_cube
+    reqs = serving_requests(rate, seconds, 0)
+    srv = P.Server(hbm_budget_bytes=budget_bytes, workers=workers, precision=precision)
+    tickets = []
+    lock = threading.Condition()
+    results = []
+
+    def waiter():
+        i = 0
+        while True:
+            with lock:
+                while i >= len(tickets):
+                    lock.wait()
+                t = tickets[i]
+            if t is None:
+                return
+            r = srv.wait(t)
+            srv.release(t)
+            results.append(r)
+            i += 1
+
+    th = threading.Thread(target=waiter)
+    th.start()
+    t0 = time.perf_counter()
+    for arrival, n, k, amps, waves in reqs:
+        now = time.perf_counter() - t0
+        if arrival > now:
+            time.sleep(arrival - now)
+        t = srv.submit(P.Server.make_request(unit_cube(n), k, amps, waves, rel_tol=tol))
+        with lock:
+            tickets.append(t)
+            lock.notify()
+    with lock:
+        tickets.append(None)
+        lock.notify()
+    th.join()
+    wall = time.perf_counter() - t0
+    st = srv.stats()
+    srv.close()
+    lat = np.array([r["total_s"] for r in results])
+    ok = sum(1 for r in results if r["status"] == 0 and r["rel_residual"] <= tol)
+    return {"precision": precision, "requests": len(results), "converged": ok, "offered_rate": rate,
+            "arrival_seconds": seconds, "wall_s": wall, "solves_per_s": len(results) / wall,
+            "dof_per_s": float(sum(r["ndofs"] for r in results)) / wall,
+            "p50_s": float(np.percentile(lat, 50)), "p99_s": float(np.percentile(lat, 99)),
+            "mean_queue_s": float(np.mean([r["queue_s"] for r in results])),
+            "mean_iterations": float(np.mean([r["iterations"] for r in results])),
+            "max_rel_residual": float(max(r["rel_residual"] for r in results)),
+            "cached_hierarchies": st["cached_hierarchies"], "peak_bytes": st["peak_bytes"], "workers": workers}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,6 +201,10 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
+    ap.add_argument("--serve-seconds", type=float, default=5.0,
+                    help="arrival window of the serving leg (0 skips it; 60 is the full stream)")
+    ap.add_argument("--serve-rate", type=float, default=200.0)
+    ap.add_argument("--serve-workers", type=int, default=4)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -269,6 +330,16 @@ def main():
             del vx, vy
             torch.cuda.empty_cache()
         out["variants"] = variants
+
+    if args.serve_seconds > 0:
+        serve = {}
+        for prec in ("mixed", "f64"):
+            print(f"[bench] serving {prec}: {args.serve_rate}/s for {args.serve_seconds} s",
+                  file=sys.stderr, flush=True)
+            serve[prec] = serve_benchmark(P, prec, args.serve_seconds, args.serve_rate, args.serve_workers)
+            torch.cuda.empty_cache()
+        serve["mixed_over_f64_solves_per_s"] = serve["mixed"]["solves_per_s"] / serve["f64"]["solves_per_s"]
+        out["serving"] = serve
 
     if not args.no_cpu:
         print("[bench] cpu oracle baseline", file=sys.stderr, flush=True)

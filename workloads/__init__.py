@@ -107,3 +107,24 @@ CONFIGS = {
 
 def with_basis(op: Operator, basis: str) -> Operator:
     return Operator(op.mesh, op.degree, op.eta, basis)
+
+
+def serving_requests(rate_per_s: float = 200.0, seconds: float = 60.0, seed: int = 0):
+    """Poisson arrivals of Poisson solves: unit cube with n^3 cells,
+    n = round(exp(U[ln 8, ln 48])), degree k ~ U{3, 4, 5}, source
+    f = sum_{m<8} a_m sin(p_m pi x) sin(q_m pi y) sin(r_m pi z) with
+    a_m ~ N(0, 1) and (p, q, r)_m ~ U{1..4}^3.  Returns a list of
+    (arrival_time_s, n, k, amps[8], waves[8][3])."""
+    rng = np.random.default_rng(seed)
+    out = []
+    t = 0.0
+    while True:
+        t += rng.exponential(1.0 / rate_per_s)
+        if t >= seconds:
+            break
+        n = int(round(np.exp(rng.uniform(np.log(8.0), np.log(48.0)))))
+        k = int(rng.integers(3, 6))
+        amps = rng.normal(size=8)
+        waves = rng.integers(1, 5, size=(8, 3))
+        out.append((t, n, k, amps, waves))
+    return out
