@@ -49,20 +49,22 @@ struct Shape {
     static constexpr int N2 = N * N, N3 = N * N * N;
     static constexpr int RS = (N % 2 == 0) ? N + 1 : N;   // LDS row stride (odd: no bank aliasing)
     static constexpr int CS = RS * N * N;                  // one cell array in LDS
-    static constexpr int FA = RS * N;                      // one face array in LDS
     static constexpr int CPB = cells_per_block(N);
     static constexpr int NT = threads_per_block(N);
-    static constexpr int WS = (24 * FA > 2 * CS) ? 24 * FA : 2 * CS;
-    static constexpr int PER_CELL = CS + 12 * FA + WS;     // words of T per cell
     static constexpr int FROWS = CPB * 2 * N;              // face rows (= columns) per direction
+    static constexpr int FR = face_row_stride(N);          // row stride of a face array
+    static constexpr int FARR = N * FR;                    // one face array (all faces of a direction)
+    static constexpr int WORDS = CPB * CS + 18 * FARR;     // words of T per workgroup
     __host__ __device__ static constexpr int lds_idx(int i1, int i2, int i3) { return i1 + RS * (i2 + N * i3); }
 };
 
 template <int N, typename T>
 constexpr size_t matvec_lds_bytes() {
     using S = Shape<N>;
-    constexpr size_t b = size_t(S::CPB) * S::PER_CELL * sizeof(T);
+    constexpr size_t b = size_t(S::WORDS) * sizeof(T);
     static_assert(b == matvec_lds_bytes_rt(N, sizeof(T)), "LDS size formula mismatch");
+    static_assert(S::FR >= S::FROWS, "face row holds every face of a direction");
+    static_assert(2 * S::CPB * S::CS <= 12 * S::FARR, "cell arrays B, C fit the face work arrays");
     static_assert(b <= 160 * 1024, "LDS budget of a gfx950 CU exceeded");
     static_assert(S::NT == 192 && S::CPB * N * N <= S::NT, "three wavefronts, one pencil per thread");
     static_assert(S::FROWS <= 64, "one face row per lane of a direction wavefront");
@@ -140,15 +142,18 @@ __global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
 sipg_matvec_kernel(MatvecParams<T> p) {
     using Sh = Shape<N>;
     using Ly = Layers<N, BASIS>;
-    constexpr int N2 = Sh::N2, N3 = Sh::N3, RS = Sh::RS, CS = Sh::CS, FA = Sh::FA;
+    constexpr int N2 = Sh::N2, N3 = Sh::N3, RS = Sh::RS, CS = Sh::CS, FR = Sh::FR;
     constexpr int CPB = Sh::CPB, NT = Sh::NT;
     constexpr TableLayout TL(N);
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     T* ldsX = lds;                                   // [CPB][CS]   x, later the cell work array A
-    T* ldsPQ = lds + CPB * CS;                       // [CPB][6][2][FA]   face arrays 0,1
-    T* ldsW = ldsPQ + CPB * 12 * FA;                 // [CPB][WS]  face arrays 2..5, later cell arrays B, C
+    // Face arrays [6 arrays][3 directions][n rows][FR]: a row holds that row
+    // of every (cell, side) face of the direction, (2 cell + side) n + column.
+    // Arrays 0, 1 (P, Q at the end of the face steps) persist; arrays 2..5
+    // are reused by the cell arrays B, C.
+    T* ldsF = lds + CPB * CS;
 
     const T* __restrict__ tab = p.tab;
     const int tid = threadIdx.x;
@@ -168,9 +173,7 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     const int ncb = min(CPB, p.ncells - cell0);      // cells in this workgroup
     const int bx = cell0 % p.nx, by = (cell0 / p.nx) % p.ny, bz = cell0 / (p.nx * p.ny);
 
-    auto slot = [&](int c, int f, int s) -> T* {
-        return s < 2 ? ldsPQ + ((c * 6 + f) * 2 + s) * FA : ldsW + c * Sh::WS + (f * 4 + (s - 2)) * FA;
-    };
+    auto fel = [&](int m, int d, int c, int s) -> T* { return ldsF + (m * 3 + d) * Sh::FARR + (2 * c + s) * N; };
 
     // Face item of this lane (the same in the three face steps): cell fc,
     // side fs (face f = 2 wave + fs), row / column index fab.
@@ -254,17 +257,17 @@ sipg_matvec_kernel(MatvecParams<T> p) {
             nm[a] = acc;
         }
         T r[N];
-        const int row = b * RS;
+        const int row = b * FR;
         eo_apply<N, +1>(tab + TL.S, vm, r);
-        T* o = slot(c, 2 * D + s, 0) + row;
+        T* o = fel(0, D, c, s) + row;
 #pragma unroll
         for (int a = 0; a < N; ++a) o[a] = r[a];
         eo_apply<N, -1>(tab + TL.SG, vm, r);
-        o = slot(c, 2 * D + s, 4) + row;
+        o = fel(4, D, c, s) + row;
 #pragma unroll
         for (int a = 0; a < N; ++a) o[a] = r[a];
         eo_apply<N, +1>(tab + TL.S, nm, r);
-        o = slot(c, 2 * D + s, 1) + row;
+        o = fel(1, D, c, s) + row;
 #pragma unroll
         for (int a = 0; a < N; ++a) o[a] = r[a];
         if (fnb >= 0) {
@@ -284,15 +287,15 @@ sipg_matvec_kernel(MatvecParams<T> p) {
                 np[a] = acc;
             }
             eo_apply<N, +1>(tab + TL.S, vp, r);
-            o = slot(c, 2 * D + s, 2) + row;
+            o = fel(2, D, c, s) + row;
 #pragma unroll
             for (int a = 0; a < N; ++a) o[a] = r[a];
             eo_apply<N, -1>(tab + TL.SG, vp, r);
-            o = slot(c, 2 * D + s, 5) + row;
+            o = fel(5, D, c, s) + row;
 #pragma unroll
             for (int a = 0; a < N; ++a) o[a] = r[a];
             eo_apply<N, +1>(tab + TL.S, np, r);
-            o = slot(c, 2 * D + s, 3) + row;
+            o = fel(3, D, c, s) + row;
 #pragma unroll
             for (int a = 0; a < N; ++a) o[a] = r[a];
         }
@@ -308,9 +311,9 @@ sipg_matvec_kernel(MatvecParams<T> p) {
         const int s = fs, c = fc, f = 2 * D + s;
         if constexpr (!EARLY) load_frec(dc);
         auto col = [&](int sl, T* v) {
-            const T* src = slot(c, f, sl) + a;
+            const T* src = fel(sl, D, c, s) + a;
 #pragma unroll
-            for (int b = 0; b < N; ++b) v[b] = src[b * RS];
+            for (int b = 0; b < N; ++b) v[b] = src[b * FR];
         };
         T um[N], gdm[N], g1m[N], g2m[N];
         col(0, um);  eo_apply<N, +1>(tab + TL.S, um, um);
@@ -370,11 +373,11 @@ sipg_matvec_kernel(MatvecParams<T> p) {
         eo_apply<N, +1>(tab + TL.ST, vv, vv);
         eo_apply<N, +1>(tab + TL.ST, w1, w1);
         eo_apply<N, +1>(tab + TL.ST, wd, wd);
-        T* s0 = slot(c, f, 0) + a;
-        T* s1 = slot(c, f, 1) + a;
-        T* s2 = slot(c, f, 2) + a;
+        T* s0 = fel(0, D, c, s) + a;
+        T* s1 = fel(1, D, c, s) + a;
+        T* s2 = fel(2, D, c, s) + a;
 #pragma unroll
-        for (int b = 0; b < N; ++b) { s0[b * RS] = vv[b]; s1[b * RS] = w1[b]; s2[b * RS] = wd[b]; }
+        for (int b = 0; b < N; ++b) { s0[b * FR] = vv[b]; s1[b * FR] = w1[b]; s2[b * FR] = wd[b]; }
     });
 
     // Cell metric terms of this thread's z pencil (used in C5).
@@ -405,10 +408,9 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     // ----------------------- I: along t1: S^T / D^T -> P (array 0), Q (array 1)
     if (fact) {
         const int b = fab;
-        const int f = 2 * wave + fs;
-        T* s0 = slot(fc, f, 0) + b * RS;
-        T* s1 = slot(fc, f, 1) + b * RS;
-        const T* s2 = slot(fc, f, 2) + b * RS;
+        T* s0 = fel(0, wave, fc, fs) + b * FR;
+        T* s1 = fel(1, wave, fc, fs) + b * FR;
+        const T* s2 = fel(2, wave, fc, fs) + b * FR;
         T av[N], cv[N], bv[N];
 #pragma unroll
         for (int a = 0; a < N; ++a) { av[a] = s0[a]; cv[a] = s1[a]; bv[a] = s2[a]; }
@@ -424,8 +426,8 @@ sipg_matvec_kernel(MatvecParams<T> p) {
 
     // ================================================================ cell
     T* A = ldsX + (act ? c : 0) * CS;
-    T* B = ldsW + (act ? c : 0) * Sh::WS;
-    T* C = B + CS;
+    T* B = ldsF + 6 * Sh::FARR + (act ? c : 0) * CS;
+    T* C = B + CPB * CS;
     T v[N];
     // C1: z pencils (thread (i1, i2)) : S along z
     if (act) {
@@ -547,30 +549,30 @@ sipg_matvec_kernel(MatvecParams<T> p) {
         const T cy0 = pick<N>(df0, i2), cy1 = pick<N>(df1, i2);
         const bool hx0 = BASIS != 0 || i1 <= 1, hx1 = BASIS != 0 || i1 >= N - 2;
         const bool hy0 = BASIS != 0 || i2 <= 1, hy1 = BASIS != 0 || i2 >= N - 2;
-        const T* P0 = slot(c, 0, 0); const T* Q0 = slot(c, 0, 1);
-        const T* P1 = slot(c, 1, 0); const T* Q1 = slot(c, 1, 1);
-        const T* P2 = slot(c, 2, 0); const T* Q2 = slot(c, 2, 1);
-        const T* P3 = slot(c, 3, 0); const T* Q3 = slot(c, 3, 1);
-        const T* P4 = slot(c, 4, 0); const T* Q4 = slot(c, 4, 1);
-        const T* P5 = slot(c, 5, 0); const T* Q5 = slot(c, 5, 1);
+        const T* P0 = fel(0, 0, c, 0); const T* Q0 = fel(1, 0, c, 0);
+        const T* P1 = fel(0, 0, c, 1); const T* Q1 = fel(1, 0, c, 1);
+        const T* P2 = fel(0, 1, c, 0); const T* Q2 = fel(1, 1, c, 0);
+        const T* P3 = fel(0, 1, c, 1); const T* Q3 = fel(1, 1, c, 1);
+        const T* P4 = fel(0, 2, c, 0); const T* Q4 = fel(1, 2, c, 0);
+        const T* P5 = fel(0, 2, c, 1); const T* Q5 = fel(1, 2, c, 1);
         T* __restrict__ yc = p.y + size_t(cell0 + c) * N3 + i1 + N * i2;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             T r = v[k];
             // x faces: tangential (t1, t2) = (i2, k), layer i1
-            if (hx0) r += (i1 == 0 ? P0[k * RS + i2] : T(0)) + cx0 * Q0[k * RS + i2];
-            if (hx1) r += (i1 == N - 1 ? P1[k * RS + i2] : T(0)) + cx1 * Q1[k * RS + i2];
+            if (hx0) r += (i1 == 0 ? P0[k * FR + i2] : T(0)) + cx0 * Q0[k * FR + i2];
+            if (hx1) r += (i1 == N - 1 ? P1[k * FR + i2] : T(0)) + cx1 * Q1[k * FR + i2];
             // y faces: tangential (i1, k), layer i2
-            if (hy0) r += (i2 == 0 ? P2[k * RS + i1] : T(0)) + cy0 * Q2[k * RS + i1];
-            if (hy1) r += (i2 == N - 1 ? P3[k * RS + i1] : T(0)) + cy1 * Q3[k * RS + i1];
+            if (hy0) r += (i2 == 0 ? P2[k * FR + i1] : T(0)) + cy0 * Q2[k * FR + i1];
+            if (hy1) r += (i2 == N - 1 ? P3[k * FR + i1] : T(0)) + cy1 * Q3[k * FR + i1];
             // z faces: tangential (i1, i2), layer k (compile time)
             if (BASIS != 0 || k <= 1) {
-                if (k == 0) r += P4[i2 * RS + i1];
-                r += df0[k] * Q4[i2 * RS + i1];
+                if (k == 0) r += P4[i2 * FR + i1];
+                r += df0[k] * Q4[i2 * FR + i1];
             }
             if (BASIS != 0 || k >= N - 2) {
-                if (k == N - 1) r += P5[i2 * RS + i1];
-                r += df1[k] * Q5[i2 * RS + i1];
+                if (k == N - 1) r += P5[i2 * FR + i1];
+                r += df1[k] * Q5[i2 * FR + i1];
             }
             yc[k * N2] = r;
         }

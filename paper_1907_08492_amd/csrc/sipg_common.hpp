@@ -22,14 +22,20 @@ __host__ __device__ constexpr int cells_per_block(int n) {
 }
 __host__ __device__ constexpr int threads_per_block(int) { return 192; }
 
+// Row stride of the face arrays in LDS.  A face array row holds the same row
+// of every (cell, side) face of one direction, 2 n cells_per_block words,
+// padded so that row-wise accesses of a wavefront hit distinct banks.
+__host__ __device__ constexpr int face_row_stride(int n) {
+    return n == 2 ? 65 : n == 3 ? 61 : n == 4 ? 65 : n == 5 ? 65 : n == 6 ? 65 : n == 7 ? 49 : n == 8 ? 49 : 37;
+}
+
 // Dynamic LDS bytes of the matrix-free kernel (must match Shape<N> in
-// matvec.hpp): per cell the x/work array, 12 persistent face arrays and the
-// larger of 24 face arrays or two cell arrays.
+// matvec.hpp): the x/work array of every cell plus 18 face arrays (6 per
+// direction) of n rows; the cell arrays B, C alias 12 of the face arrays.
 __host__ __device__ constexpr size_t matvec_lds_bytes_rt(int n, int esz) {
     const int rs = (n % 2 == 0) ? n + 1 : n;
-    const int cs = rs * n * n, fa = rs * n;
-    const int ws = (24 * fa > 2 * cs) ? 24 * fa : 2 * cs;
-    return size_t(cells_per_block(n)) * size_t(cs + 12 * fa + ws) * esz;
+    const int cs = rs * n * n;
+    return size_t(cells_per_block(n) * cs + 18 * n * face_row_stride(n)) * esz;
 }
 
 // ---------------------------------------------------------------------------
