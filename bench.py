@@ -51,7 +51,8 @@ def alg_bytes_per_dof(mesh, k: int, esz: int, per_point: bool) -> float:
 
 
 KERNEL_SOURCES = ["paper_1907_08492_amd/csrc/matvec.hpp", "paper_1907_08492_amd/csrc/sumfac.hpp",
-                  "paper_1907_08492_amd/csrc/sipg_common.hpp", "paper_1907_08492_amd/csrc/matvec_n5.hip"]
+                  "paper_1907_08492_amd/csrc/sipg_common.hpp", "paper_1907_08492_amd/csrc/matvec_launch.hpp",
+                  "paper_1907_08492_amd/csrc/matvec_n5.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sipg_matvec_k4_64c_deformed_f64.traffic.json")
 
 
@@ -134,6 +135,63 @@ def cpu_baseline(mesh, k, eta, target_s: float):
                        f"{os.cpu_count()}, BLAS threads={threads}")}
 
 
+def batch_benchmark(torch, P, dtype: str, reps: int = 10, count: int = 256):
+    """256 independent operators (n^3 cells, n ~ U{4..24}, k ~ U{2..7}, half
+    affine with one metric record per cell/face, half deformed with metric
+    terms per point) applied by one sipg_batch_apply (one grid per degree and
+    geometry mode), against the same products launched one by one."""
+    from workloads import batch_operators, uniform_vector
+    specs = batch_operators(count, 0)
+    tdt = torch.float64 if dtype == "f64" else torch.float32
+    esz = 8 if dtype == "f64" else 4
+    ops, xs, ys = [], [], []
+    alg = 0.0
+    for i, c in enumerate(specs):
+        op = P.Operator(c.mesh, c.degree, c.eta, "hermite_like", dtype)
+        ops.append(op)
+        xs.append(torch.from_numpy(uniform_vector(op.ndofs, i)).to("cuda", dtype=tdt))
+        ys.append(torch.empty_like(xs[-1]))
+        alg += alg_bytes_per_dof(c.mesh, c.degree, esz, c.mesh.deformed) * op.ndofs
+    ndofs = sum(op.ndofs for op in ops)
+    b = P.Batch(ops, xs, ys)
+    st = torch.cuda.current_stream()
+
+    def timed(fn, r):
+        ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(r)]
+        for i in range(r):
+            ev[i][0].record(st)
+            fn()
+            ev[i][1].record(st)
+        torch.cuda.synchronize()
+        return np.array([a.elapsed_time(e) for a, e in ev]) * 1e-3
+
+    def serial():
+        for op, x, y in zip(ops, xs, ys):
+            op.apply(x, y)
+
+    b.apply()
+    serial()
+    torch.cuda.synchronize()
+    tb = timed(b.apply, reps)
+    ts = timed(serial, reps)
+    alone = []
+    for op, x, y in zip(ops, xs, ys):
+        alone.append(float(timed(lambda: op.apply(x, y), 3).min()))
+    alone = np.array(alone)
+    out = {"dtype": dtype, "operators": count, "ndofs": ndofs, "launches": int(b.info.launches),
+           "batched": {"dof_per_s": ndofs / tb.mean(), "avg_ms": tb.mean() * 1e3, "min_ms": tb.min() * 1e3,
+                       "alg_GBs": alg / tb.mean() / 1e9, "hbm_frac": alg / tb.mean() / 1e9 / HBM_PEAK_GBS},
+           "one_by_one": {"dof_per_s": ndofs / ts.mean(), "avg_ms": ts.mean() * 1e3,
+                          "alg_GBs": alg / ts.mean() / 1e9, "hbm_frac": alg / ts.mean() / 1e9 / HBM_PEAK_GBS},
+           "alone_ms": {"p50": float(np.percentile(alone, 50)) * 1e3, "p90": float(np.percentile(alone, 90)) * 1e3,
+                        "max": float(alone.max()) * 1e3, "sum": float(alone.sum()) * 1e3},
+           "alg_bytes": alg}
+    b.close()
+    for op in ops:
+        op.close()
+    return out
+
+
 def serve_benchmark(P, precision: str, seconds: float, rate: float, workers: int = 4,
                     budget_bytes: int = 96 << 30, tol: float = 1e-8):
     """Poisson arrivals of multigrid Poisson solves (unit cube n^3, n log-uniform
@@ -201,7 +259,8 @@ def main():
     ap.add_argument("--cpu-seconds", type=float, default=12.0)
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
-    ap.add_argument("--serve-seconds", type=float, default=5.0,
+    ap.add_argument("--no-batch", action="store_true", help="skip the 256-operator batched leg")
+    ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="arrival window of the serving leg (0 skips it; 60 is the full stream)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-workers", type=int, default=4)
@@ -330,6 +389,13 @@ def main():
             del vx, vy
             torch.cuda.empty_cache()
         out["variants"] = variants
+
+    if not args.no_batch:
+        out["batch"] = []
+        for dt in ("f64", "f32"):
+            print(f"[bench] batch of 256 operators {dt}", file=sys.stderr, flush=True)
+            out["batch"].append(batch_benchmark(torch, P, dt))
+            torch.cuda.empty_cache()
 
     if args.serve_seconds > 0:
         serve = {}

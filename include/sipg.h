@@ -126,6 +126,38 @@ int sipg_get_info(const sipg_op* op, sipg_op_info* info);
 int sipg_apply(const sipg_op* op, const void* x, void* y, void* stream);
 
 /*
+ * Batched product y_i = A_i x_i of nops independent operators (the same
+ * element-wise evaluation as sipg_apply, Section 3), for many small problems
+ * at once.  Operators of equal degree, basis, precision and geometry mode
+ * share one grid, so a batch runs as one launch per such group.
+ *   sipg_batch_create  ops[i], x[i], y[i] (host arrays of nops entries; x, y
+ *                      device pointers of ops[i]'s size and precision) are
+ *                      bound at creation.  The batch stores device pointers
+ *                      only: operators and vectors must outlive it.  All
+ *                      operators on one device.  Inputs may be shared; an
+ *                      output that overlaps any input or other output ->
+ *                      SIPG_E_ARG.  Allocates one small device table
+ *                      (kernel parameters, workgroup -> operator map) and
+ *                      copies it synchronously.
+ *   sipg_batch_apply   launches the groups on `stream`; allocates nothing,
+ *                      stream ordered.  Each y_i is bit-identical to
+ *                      sipg_apply(ops[i], x[i], y[i]).
+ *   sipg_batch_destroy frees the table (NULL accepted); no queued work may
+ *                      still use it.
+ */
+typedef struct sipg_batch sipg_batch;
+typedef struct {
+    int32_t nops, launches;
+    int64_t ndofs, ncells, workgroups;
+    int64_t device_bytes;
+} sipg_batch_info;
+int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x, void* const* y,
+                      sipg_batch** out);
+int sipg_batch_apply(const sipg_batch* batch, void* stream);
+int sipg_batch_get_info(const sipg_batch* batch, sipg_batch_info* info);
+int sipg_batch_destroy(sipg_batch* batch);
+
+/*
  * Cell-wise tensor-product basis change between the operator's basis and the
  * nodal Gauss-Lobatto basis, and the preconditioner of eq. (jacobi)
  * (Section 6.3).  With E_ij = phi_i(x^GL_j), T = E^-1:

@@ -7,6 +7,6 @@ this package is a thin ctypes binding over it.  Build the library with
 `python -m paper_1907_08492_amd.build` (or `__graft_entry__.build()`).
 """
 from .binding import (  # noqa: F401
-    BASIS, BC_MODES, DTYPE, EXPORTED, GEOMETRY, LIB_PATH, Multigrid, Operator, Server, SipgError,
+    BASIS, BC_MODES, DTYPE, EXPORTED, GEOMETRY, LIB_PATH, Batch, Multigrid, Operator, Server, SipgError,
     SolveInfo, host_tables, launch_shape, lib, make_mesh,
 )

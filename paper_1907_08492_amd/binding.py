@@ -45,6 +45,7 @@ EXPORTED = [
     "sipg_assemble_rhs_sines",
     "sipg_server_default_opts", "sipg_server_create", "sipg_submit", "sipg_poll", "sipg_wait",
     "sipg_release", "sipg_server_stats", "sipg_server_destroy", "sipg_copy_device",
+    "sipg_batch_create", "sipg_batch_apply", "sipg_batch_get_info", "sipg_batch_destroy",
 ]
 
 
@@ -99,6 +100,11 @@ class SipgServerStats(C.Structure):
                 ("used_bytes", C.c_int64), ("peak_bytes", C.c_int64)]
 
 
+class SipgBatchInfo(C.Structure):
+    _fields_ = [("nops", C.c_int32), ("launches", C.c_int32), ("ndofs", C.c_int64),
+                ("ncells", C.c_int64), ("workgroups", C.c_int64), ("device_bytes", C.c_int64)]
+
+
 class SipgTables1D(C.Structure):
     _fields_ = [(name, C.POINTER(C.c_double)) for name in (
         "points", "weights", "shape", "shape_grad", "colloc_grad", "face_value0",
@@ -139,6 +145,10 @@ lib.sipg_release.argtypes = [_vp, C.c_uint64]
 lib.sipg_server_stats.argtypes = [_vp, C.POINTER(SipgServerStats)]
 lib.sipg_server_destroy.argtypes = [_vp]
 lib.sipg_copy_device.argtypes = [_vp, _vp, C.c_size_t, _vp]
+lib.sipg_batch_create.argtypes = [C.c_int, C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp), C.POINTER(_vp)]
+lib.sipg_batch_apply.argtypes = [_vp, _vp]
+lib.sipg_batch_get_info.argtypes = [_vp, C.POINTER(SipgBatchInfo)]
+lib.sipg_batch_destroy.argtypes = [_vp]
 for _f in EXPORTED:
     if _f not in ("sipg_ndofs", "sipg_last_error"):
         getattr(lib, _f).restype = C.c_int
@@ -299,6 +309,42 @@ class Operator:
         if getattr(self, "_h", None):
             lib.sipg_destroy(self._h)
             self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+
+class Batch:
+    """y_i = A_i x_i for many operators at once (sipg_batch_*).  The vectors
+    are bound at construction; the batch keeps references to the operators
+    and tensors so that they outlive it."""
+
+    def __init__(self, ops, xs, ys):
+        if not (len(ops) == len(xs) == len(ys)) or len(ops) == 0:
+            raise ValueError("ops, xs and ys must be non-empty lists of equal length")
+        n = len(ops)
+        hops = (_vp * n)(*[op.handle for op in ops])
+        hx = (_vp * n)(*[op._vec(x, f"xs[{i}]") for i, (op, x) in enumerate(zip(ops, xs))])
+        hy = (_vp * n)(*[op._vec(y, f"ys[{i}]") for i, (op, y) in enumerate(zip(ops, ys))])
+        h = _vp()
+        _check(lib.sipg_batch_create(n, hops, hx, hy, C.byref(h)), "sipg_batch_create")
+        self._h = h
+        self._keep = (list(ops), list(xs), list(ys))
+        info = SipgBatchInfo()
+        _check(lib.sipg_batch_get_info(h, C.byref(info)), "sipg_batch_get_info")
+        self.info = info
+
+    def apply(self, stream=None):
+        _check(lib.sipg_batch_apply(self._h, _vp(_stream_ptr(stream))), "sipg_batch_apply")
+
+    def close(self):
+        if getattr(self, "_h", None):
+            lib.sipg_batch_destroy(self._h)
+            self._h = None
+            self._keep = None
 
     def __del__(self):
         try:

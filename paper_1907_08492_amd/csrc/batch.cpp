@@ -1,0 +1,230 @@
+// Batched application of many independent SIPG operators (sipg_batch_*).
+//
+// Operators are grouped by (degree, basis, precision, geometry mode); each
+// group becomes one grid over the concatenated workgroup lists of its
+// operators, so a batch of small operators fills the 256 compute units that
+// each of them alone would leave mostly idle.  The per-operator kernel
+// parameters and the workgroup -> operator table live in one device buffer
+// made at creation; sipg_batch_apply only launches (one kernel per group).
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cstring>
+#include <map>
+#include <new>
+#include <string>
+#include <tuple>
+#include <vector>
+
+#include "matvec.hpp"
+#include "setup.hpp"
+#include "sipg_common.hpp"
+
+struct sipg_batch {
+    int device = 0;
+    int nops = 0;
+    int64_t ndofs = 0, ncells = 0, nblocks = 0;
+    std::vector<sipg::BatchGroup> groups;
+    void* mem = nullptr;
+    size_t bytes = 0;
+};
+
+namespace sipg {
+
+int launch_matvec_batched(const BatchGroup& g, hipStream_t st) {
+    switch (g.n) {
+        case 2: return launch_matvec_batched_n<2>(g, st);
+        case 3: return launch_matvec_batched_n<3>(g, st);
+        case 4: return launch_matvec_batched_n<4>(g, st);
+        case 5: return launch_matvec_batched_n<5>(g, st);
+        case 6: return launch_matvec_batched_n<6>(g, st);
+        case 7: return launch_matvec_batched_n<7>(g, st);
+        case 8: return launch_matvec_batched_n<8>(g, st);
+        case 9: return launch_matvec_batched_n<9>(g, st);
+    }
+    set_error("unsupported degree");
+    return SIPG_E_UNSUPPORTED;
+}
+
+namespace {
+
+struct Range {
+    const char* lo;
+    const char* hi;
+    int op;
+    bool write;
+};
+
+// Any written range that meets another range (read or written) of a
+// different role is a race inside one launch.
+bool ranges_conflict(std::vector<Range> r, std::string& why) {
+    std::sort(r.begin(), r.end(), [](const Range& a, const Range& b) { return a.lo < b.lo; });
+    // sweep: keep the range with the largest end seen so far among writes and
+    // among reads
+    const Range* last_w = nullptr;
+    const Range* last_any = nullptr;
+    for (const Range& c : r) {
+        if (last_w && c.lo < last_w->hi) {
+            why = "the output of operator " + std::to_string(last_w->op) + " overlaps " +
+                  (c.write ? "the output" : "the input") + " of operator " + std::to_string(c.op);
+            return true;
+        }
+        if (c.write && last_any && c.lo < last_any->hi) {
+            why = "the output of operator " + std::to_string(c.op) + " overlaps " +
+                  (last_any->write ? "the output" : "the input") + " of operator " + std::to_string(last_any->op);
+            return true;
+        }
+        if (c.write && (!last_w || c.hi > last_w->hi)) last_w = &c;
+        if (!last_any || c.hi > last_any->hi) last_any = &c;
+    }
+    return false;
+}
+
+size_t align_up(size_t v) { return (v + 255) & ~size_t(255); }
+
+}  // namespace
+}  // namespace sipg
+
+using namespace sipg;
+
+extern "C" {
+
+int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x, void* const* y,
+                      sipg_batch** out) {
+    if (!out) { set_error("sipg_batch_create: null output handle"); return SIPG_E_ARG; }
+    *out = nullptr;
+    if (nops <= 0 || !ops || !x || !y) { set_error("sipg_batch_create: empty batch or null array"); return SIPG_E_ARG; }
+    std::vector<Range> ranges;
+    ranges.reserve(2 * size_t(nops));
+    int device = -1;
+    for (int i = 0; i < nops; ++i) {
+        if (!ops[i] || !x[i] || !y[i]) {
+            set_error("sipg_batch_create: null operator or vector at entry " + std::to_string(i));
+            return SIPG_E_ARG;
+        }
+        if (device >= 0 && ops[i]->device != device) {
+            set_error("sipg_batch_create: operators live on different devices");
+            return SIPG_E_ARG;
+        }
+        device = ops[i]->device;
+        const size_t bytes = size_t(ops[i]->ndofs) * (ops[i]->dtype == SIPG_F64 ? 8 : 4);
+        const char* px = static_cast<const char*>(x[i]);
+        const char* py = static_cast<const char*>(y[i]);
+        ranges.push_back({px, px + bytes, i, false});
+        ranges.push_back({py, py + bytes, i, true});
+    }
+    std::string why;
+    if (ranges_conflict(ranges, why)) { set_error("sipg_batch_create: " + why); return SIPG_E_ARG; }
+
+    // group by (n, basis, dtype, geometry); std::map gives a fixed order
+    std::map<std::tuple<int, int, int, int>, std::vector<int>> by_key;
+    for (int i = 0; i < nops; ++i)
+        by_key[{ops[i]->n, ops[i]->basis, ops[i]->dtype, ops[i]->geom}].push_back(i);
+
+    auto* b = new (std::nothrow) sipg_batch;
+    if (!b) { set_error("sipg_batch_create: out of host memory"); return SIPG_E_OOM; }
+    b->device = device;
+    b->nops = nops;
+    // host images of the device arrays, laid out group after group
+    std::vector<char> host;
+    struct Off { size_t params, blk_op, blk_first; };
+    std::vector<Off> offs;
+    for (const auto& kv : by_key) {
+        const auto [n, basis, dtype, geom] = kv.first;
+        const std::vector<int>& idx = kv.second;
+        const int cpb = cells_per_block(n);
+        BatchGroup g;
+        g.n = n; g.basis = basis; g.dtype = dtype; g.geom = geom;
+        g.nops = int(idx.size());
+        std::vector<int> first(idx.size());
+        int64_t nblk = 0;
+        for (size_t j = 0; j < idx.size(); ++j) {
+            first[j] = int(nblk);
+            nblk += (ops[idx[j]]->ncells + cpb - 1) / cpb;
+            g.ndofs += ops[idx[j]]->ndofs;
+            b->ncells += ops[idx[j]]->ncells;
+        }
+        if (nblk >= (int64_t(1) << 31)) {
+            delete b;
+            set_error("sipg_batch_create: a group exceeds 2^31 workgroups");
+            return SIPG_E_ARG;
+        }
+        g.nblocks = nblk;
+        std::vector<int> blk_op(static_cast<size_t>(nblk), 0);
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const int64_t e = j + 1 < idx.size() ? first[j + 1] : nblk;
+            std::fill(blk_op.begin() + first[j], blk_op.begin() + e, int(j));
+        }
+        const size_t psz = sizeof(MatvecParams<double>) * idx.size();
+        static_assert(sizeof(MatvecParams<double>) == sizeof(MatvecParams<float>), "same parameter layout");
+        Off o;
+        o.params = align_up(host.size());
+        o.blk_first = align_up(o.params + psz);
+        o.blk_op = align_up(o.blk_first + sizeof(int) * first.size());
+        host.resize(align_up(o.blk_op + sizeof(int) * blk_op.size()));
+        for (size_t j = 0; j < idx.size(); ++j) {
+            const int i = idx[j];
+            if (dtype == SIPG_F64) {
+                const MatvecParams<double> p = matvec_params<double>(ops[i], x[i], y[i]);
+                std::memcpy(host.data() + o.params + j * sizeof(p), &p, sizeof(p));
+            } else {
+                const MatvecParams<float> p = matvec_params<float>(ops[i], x[i], y[i]);
+                std::memcpy(host.data() + o.params + j * sizeof(p), &p, sizeof(p));
+            }
+        }
+        std::memcpy(host.data() + o.blk_first, first.data(), sizeof(int) * first.size());
+        std::memcpy(host.data() + o.blk_op, blk_op.data(), sizeof(int) * blk_op.size());
+        offs.push_back(o);
+        b->ndofs += g.ndofs;
+        b->nblocks += nblk;
+        b->groups.push_back(g);
+    }
+    int prev = 0;
+    (void)hipGetDevice(&prev);
+    hipError_t e = hipSetDevice(device);
+    if (e == hipSuccess) e = hipMalloc(&b->mem, host.size());
+    if (e == hipSuccess) e = hipMemcpy(b->mem, host.data(), host.size(), hipMemcpyHostToDevice);
+    (void)hipSetDevice(prev);
+    if (e != hipSuccess) {
+        if (b->mem) (void)hipFree(b->mem);
+        delete b;
+        return hip_fail(e, "sipg_batch_create: device tables");
+    }
+    b->bytes = host.size();
+    char* base = static_cast<char*>(b->mem);
+    for (size_t gi = 0; gi < b->groups.size(); ++gi) {
+        b->groups[gi].params = base + offs[gi].params;
+        b->groups[gi].blk_first = reinterpret_cast<const int*>(base + offs[gi].blk_first);
+        b->groups[gi].blk_op = reinterpret_cast<const int*>(base + offs[gi].blk_op);
+    }
+    *out = b;
+    return SIPG_OK;
+}
+
+int sipg_batch_apply(const sipg_batch* b, void* stream) {
+    if (!b) { set_error("sipg_batch_apply: null batch"); return SIPG_E_ARG; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    for (const BatchGroup& g : b->groups)
+        if (int rc = launch_matvec_batched(g, st)) return rc;
+    return SIPG_OK;
+}
+
+int sipg_batch_get_info(const sipg_batch* b, sipg_batch_info* info) {
+    if (!b || !info) { set_error("sipg_batch_get_info: null argument"); return SIPG_E_ARG; }
+    info->nops = b->nops;
+    info->launches = int(b->groups.size());
+    info->ndofs = b->ndofs;
+    info->ncells = b->ncells;
+    info->workgroups = b->nblocks;
+    info->device_bytes = int64_t(b->bytes);
+    return SIPG_OK;
+}
+
+int sipg_batch_destroy(sipg_batch* b) {
+    if (!b) return SIPG_OK;
+    if (b->mem) (void)hipFree(b->mem);
+    delete b;
+    return SIPG_OK;
+}
+
+}  // extern "C"

@@ -44,6 +44,24 @@ struct MatvecParams {
     int ncells;
 };
 
+// Kernel parameters of operator `op` for the product y = A x.
+template <typename T>
+inline MatvecParams<T> matvec_params(const sipg_op* op, const void* x, void* y) {
+    MatvecParams<T> p;
+    p.x = static_cast<const T*>(x);
+    p.y = static_cast<T*>(y);
+    p.tab = static_cast<const T*>(op->tables);
+    p.cgeom = static_cast<const T*>(op->cell_geom);
+    p.fgeom0 = static_cast<const T*>(op->face_geom[0]);
+    p.fgeom1 = static_cast<const T*>(op->face_geom[1]);
+    p.fgeom2 = static_cast<const T*>(op->face_geom[2]);
+    p.nx = op->nc[0];
+    p.ny = op->nc[1];
+    p.nz = op->nc[2];
+    p.ncells = int(op->ncells);
+    return p;
+}
+
 template <int N>
 struct Shape {
     static constexpr int N2 = N * N, N3 = N * N * N;
@@ -137,9 +155,19 @@ __device__ __forceinline__ void by_direction(int wave, F&& fn) {
 template <int N, int GEOM>
 constexpr int matvec_min_waves() { return (N >= 7 && GEOM == GEOM_CELL) ? 2 : 1; }
 
+// XCD-aware order: consecutive workgroups are dispatched round-robin over
+// the 8 XCDs, so give each XCD a contiguous range of block indices (a range
+// of consecutive cells, whose x- and y-neighbours then meet in that XCD's L2).
+__device__ __forceinline__ int xcd_block(int blk, int nblk) {
+    const int per = (nblk + 7) / 8;
+    const int xcd = blk % 8, sl = blk / 8;
+    const int full = nblk % 8 == 0 ? 8 : nblk % 8;   // XCDs that get `per` blocks
+    return (xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1)) + sl;
+}
+
+// The product on workgroup `blk` of the operator `p`: cells blk*CPB ...
 template <int N, int BASIS, typename T, int GEOM>
-__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
-sipg_matvec_kernel(MatvecParams<T> p) {
+__device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int blk) {
     using Sh = Shape<N>;
     using Ly = Layers<N, BASIS>;
     constexpr int N2 = Sh::N2, N3 = Sh::N3, RS = Sh::RS, CS = Sh::CS, FR = Sh::FR;
@@ -159,16 +187,6 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // = face direction in the face steps
     const int lane = tid & 63;
-    // XCD-aware order: consecutive workgroups are dispatched round-robin over
-    // the 8 XCDs, so give each XCD a contiguous range of cells (shared L2).
-    const int nblk = gridDim.x;
-    int blk = blockIdx.x;
-    {
-        const int per = (nblk + 7) / 8;
-        const int xcd = blk % 8, sl = blk / 8;
-        const int full = nblk % 8 == 0 ? 8 : nblk % 8;   // XCDs that get `per` blocks
-        blk = (xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1)) + sl;
-    }
     const int cell0 = blk * CPB;
     const int ncb = min(CPB, p.ncells - cell0);      // cells in this workgroup
     const int bx = cell0 % p.nx, by = (cell0 / p.nx) % p.ny, bz = cell0 / (p.nx * p.ny);
@@ -577,6 +595,27 @@ sipg_matvec_kernel(MatvecParams<T> p) {
             yc[k * N2] = r;
         }
     }
+}
+
+// One operator: workgroup b handles cells b*CPB ... of it.
+template <int N, int BASIS, typename T, int GEOM>
+__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
+sipg_matvec_kernel(MatvecParams<T> p) {
+    matvec_block<N, BASIS, T, GEOM>(p, xcd_block(blockIdx.x, gridDim.x));
+}
+
+// Many independent operators of the same degree, basis, precision and
+// geometry mode in one grid: the workgroups of operator o are the block
+// indices blk_first[o] ... blk_first[o+1]-1 of the concatenated list, and
+// blk_op[b] names the operator of block b.
+template <int N, int BASIS, typename T, int GEOM>
+__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
+sipg_matvec_batched_kernel(const MatvecParams<T>* __restrict__ ops, const int* __restrict__ blk_op,
+                           const int* __restrict__ blk_first) {
+    const int b = xcd_block(blockIdx.x, gridDim.x);
+    const int o = __builtin_amdgcn_readfirstlane(blk_op[b]);
+    const MatvecParams<T> p = ops[o];
+    matvec_block<N, BASIS, T, GEOM>(p, b - __builtin_amdgcn_readfirstlane(blk_first[o]));
 }
 
 }  // namespace sipg

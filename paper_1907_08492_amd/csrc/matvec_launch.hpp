@@ -1,0 +1,76 @@
+// Launchers of the matrix-free product for one degree (included by the
+// per-degree translation units matvec_n<N>.hip).
+#pragma once
+
+#include "matvec.hpp"
+#include "setup.hpp"
+
+namespace sipg {
+
+template <int N, int BASIS, typename T, int GEOM, typename K>
+static int set_lds_limit(K kernel) {
+    // Raising the dynamic LDS limit is idempotent; racing first calls from
+    // several threads are harmless.
+    static bool done = false;
+    if (!done) {
+        SIPG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
+                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(matvec_lds_bytes<N, T>())));
+        done = true;
+    }
+    return SIPG_OK;
+}
+
+template <int N, int BASIS, typename T, int GEOM>
+static int launch_one(const sipg_op* op, const void* x, void* y, hipStream_t st) {
+    auto kern = &sipg_matvec_kernel<N, BASIS, T, GEOM>;
+    if (int rc = set_lds_limit<N, BASIS, T, GEOM>(kern)) return rc;
+    const unsigned nblk = unsigned((op->ncells + cells_per_block(N) - 1) / cells_per_block(N));
+    kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(matvec_params<T>(op, x, y));
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
+template <int N, int BASIS, typename T, int GEOM>
+static int launch_group(const BatchGroup& g, hipStream_t st) {
+    auto kern = &sipg_matvec_batched_kernel<N, BASIS, T, GEOM>;
+    if (int rc = set_lds_limit<N, BASIS, T, GEOM>(kern)) return rc;
+    kern<<<unsigned(g.nblocks), threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(
+        static_cast<const MatvecParams<T>*>(g.params), g.blk_op, g.blk_first);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
+// Calls launch<N, BASIS, T, GEOM>() for the run-time (basis, dtype, geometry).
+template <int N, typename F>
+static int dispatch(int basis, int dtype, int geom, F&& launch) {
+    using I0 = std::integral_constant<int, 0>;
+    using I1 = std::integral_constant<int, 1>;
+    using GC = std::integral_constant<int, GEOM_CELL>;
+    using GQ = std::integral_constant<int, GEOM_QPOINT>;
+    const bool hl = basis == SIPG_BASIS_HERMITE_LIKE, cell = geom == GEOM_CELL;
+    if (dtype == SIPG_F64) {
+        if (hl) return cell ? launch(I0{}, double{}, GC{}) : launch(I0{}, double{}, GQ{});
+        return cell ? launch(I1{}, double{}, GC{}) : launch(I1{}, double{}, GQ{});
+    }
+    if (hl) return cell ? launch(I0{}, float{}, GC{}) : launch(I0{}, float{}, GQ{});
+    return cell ? launch(I1{}, float{}, GC{}) : launch(I1{}, float{}, GQ{});
+}
+
+}  // namespace sipg
+
+// Defines the two per-degree entry points of setup.hpp for degree NV - 1.
+#define SIPG_MATVEC_DEGREE(NV)                                                                          \
+    namespace sipg {                                                                                    \
+    template <>                                                                                         \
+    int launch_matvec_n<NV>(const sipg_op* op, const void* x, void* y, hipStream_t st) {                \
+        return dispatch<NV>(op->basis, op->dtype, op->geom, [&](auto b, auto t, auto g) {               \
+            return launch_one<NV, decltype(b)::value, decltype(t), decltype(g)::value>(op, x, y, st);   \
+        });                                                                                             \
+    }                                                                                                   \
+    template <>                                                                                         \
+    int launch_matvec_batched_n<NV>(const BatchGroup& grp, hipStream_t st) {                            \
+        return dispatch<NV>(grp.basis, grp.dtype, grp.geom, [&](auto b, auto t, auto g) {               \
+            return launch_group<NV, decltype(b)::value, decltype(t), decltype(g)::value>(grp, st);      \
+        });                                                                                             \
+    }                                                                                                   \
+    }

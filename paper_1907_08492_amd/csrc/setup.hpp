@@ -17,6 +17,23 @@ int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st);
 template <int N>
 int launch_matvec_n(const sipg_op* op, const void* x, void* y, hipStream_t st);
 
+// Operators of one degree, basis, precision and geometry mode applied by one
+// grid (sipg_batch_apply).  Device arrays: `params` holds one kernel
+// parameter block per operator, `blk_first[o]` the first workgroup of
+// operator o, `blk_op[b]` the operator of workgroup b.
+struct BatchGroup {
+    int n = 0, basis = 0, dtype = 0, geom = 0;
+    int nops = 0;
+    int64_t nblocks = 0;
+    int64_t ndofs = 0;
+    const void* params = nullptr;
+    const int* blk_op = nullptr;
+    const int* blk_first = nullptr;
+};
+int launch_matvec_batched(const BatchGroup& g, hipStream_t st);
+template <int N>
+int launch_matvec_batched_n(const BatchGroup& g, hipStream_t st);
+
 // Cell-wise basis change / preconditioner (see sipg_basis_change).
 int launch_basis_change(const sipg_op* op, int mode, const void* in, void* out, hipStream_t st);
 

@@ -94,6 +94,14 @@ def test_argument_errors_without_gpu():
     assert P.lib.sipg_ndofs(None) == -1
     assert P.lib.sipg_destroy(None) == 0
     assert P.lib.sipg_launch_shape(0, 0, None, None, None) == -1
+    assert P.lib.sipg_batch_create(0, None, None, None, C.byref(h)) == -1
+    assert P.lib.sipg_batch_create(1, None, None, None, None) == -1
+    null3 = (C.c_void_p * 1)(None)
+    assert P.lib.sipg_batch_create(1, null3, null3, null3, C.byref(h)) == -1
+    assert "entry 0" in P.lib.sipg_last_error().decode()
+    assert P.lib.sipg_batch_apply(None, None) == -1
+    assert P.lib.sipg_batch_get_info(None, None) == -1
+    assert P.lib.sipg_batch_destroy(None) == 0
 
 
 def test_single_hip_runtime_in_process():

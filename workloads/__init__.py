@@ -109,6 +109,22 @@ def with_basis(op: Operator, basis: str) -> Operator:
     return Operator(op.mesh, op.degree, op.eta, basis)
 
 
+def batch_operators(count: int = 256, seed: int = 0):
+    """Independent operators applied together: cube of n^3 cells with
+    n ~ U{4..24} and degree k ~ U{2..7} (numpy default_rng(seed)); the first
+    half on the affine benchmark brick, the second half on the sine-deformed
+    unit cube (amplitude 0.1).  Operator i takes x = uniform_vector(., i)."""
+    rng = np.random.default_rng(seed)
+    ns = rng.integers(4, 25, size=count)
+    ks = rng.integers(2, 8, size=count)
+    out = []
+    for i in range(count):
+        n, k = int(ns[i]), int(ks[i])
+        mesh = paper_affine_brick(n) if i < count // 2 else unit_cube(n, 0.1)
+        out.append(Operator(mesh, k, 2.0))
+    return out
+
+
 def serving_requests(rate_per_s: float = 200.0, seconds: float = 60.0, seed: int = 0):
     """Poisson arrivals of Poisson solves: unit cube with n^3 cells,
     n = round(exp(U[ln 8, ln 48])), degree k ~ U{3, 4, 5}, source
