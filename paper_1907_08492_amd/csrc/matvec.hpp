@@ -204,6 +204,19 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         face_topology(ix, iy, iz, 2 * wave + fs, p.nx, p.ny, p.nz, fnb, fidx);
     }
 
+    // The workgroup's x tile, one contiguous range, as XPER loads per thread
+    // issued back to back.
+    constexpr int XPER = (CPB * N3 + NT - 1) / NT;
+    T xv[XPER];
+    {
+        const T* __restrict__ xs = p.x + size_t(cell0) * N3;
+#pragma unroll
+        for (int j = 0; j < XPER; ++j) {
+            const int e = tid + j * NT;
+            xv[j] = e < ncb * N3 ? xs[e] : T(0);
+        }
+    }
+
     // ------------------------------------------------------------ prefetch
     // Registers, before any LDS work: the metric terms of this lane's flux
     // column (used in F) and the neighbour layers of this lane's row (used
@@ -233,7 +246,8 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         constexpr int D = decltype(dc)::value;
         if (!fact) return;
         if constexpr (EARLY) load_frec(dc);
-        if (fnb >= 0) {
+        // x-neighbours inside the workgroup are read from the x tile in G
+        if (fnb >= 0 && !(D == 0 && (fs ? fc + 1 < ncb : fc > 0))) {
             const T* __restrict__ xn = p.x + size_t(fnb) * N3;
 #pragma unroll
             for (int j = 0; j < Ly::NL; ++j) {
@@ -244,11 +258,14 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         }
     });
     // --------------------------------------------------------------- x tile
-    {
-        const T* __restrict__ xs = p.x + size_t(cell0) * N3;
-        for (int e = tid; e < ncb * N3; e += NT) {
+    // (loaded into registers at kernel start, with every other load of the
+    // workgroup in flight; written to LDS here)
+#pragma unroll
+    for (int j = 0; j < XPER; ++j) {
+        const int e = tid + j * NT;
+        if (e < ncb * N3) {
             const int c = e / N3, i = e % N3;
-            ldsX[c * CS + Sh::lds_idx(i % N, (i / N) % N, i / N2)] = xs[e];
+            ldsX[c * CS + Sh::lds_idx(i % N, (i / N) % N, i / N2)] = xv[j];
         }
     }
     __syncthreads();
@@ -292,6 +309,16 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
             // neighbour side: its value layer touches the face; its
             // derivative row combines the layers loaded at kernel start
             T vp[N], np[N];
+            if (D == 0 && (s ? c + 1 < ncb : c > 0)) {
+                // the x-neighbour is the adjacent cell of this workgroup
+                const T* Xn = ldsX + (s ? c + 1 : c - 1) * CS;
+#pragma unroll
+                for (int j = 0; j < Ly::NL; ++j) {
+                    const int l = Ly::layer(1 - s, j);
+#pragma unroll
+                    for (int a = 0; a < N; ++a) nbv[j][a] = Xn[face_lidx<N, 0>(l, a, b)];
+                }
+            }
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 T acc = T(0), val = T(0);
