@@ -159,18 +159,28 @@ int sipg_batch_destroy(sipg_batch* batch);
 
 /*
  * Cell-wise tensor-product basis change between the operator's basis and the
- * nodal Gauss-Lobatto basis, and the preconditioner of eq. (jacobi)
- * (Section 6.3).  With E_ij = phi_i(x^GL_j), T = E^-1:
+ * nodal Gauss-Lobatto basis, and the element-wise preconditioners of the
+ * form of eq. (jacobi) (Sections 6.3, 6.4).  With E_ij = phi_i(x^GL_j),
+ * T = E^-1:
  *   SIPG_BC_T        out = (T x T x T) in        : HL residual -> GL residual
  *   SIPG_BC_TT       out = (T^T x T^T x T^T) in  : GL coefficients -> HL coefficients
  *   SIPG_BC_VALUES   out = (E^T x E^T x E^T) in  : HL coefficients -> values at GL nodes
  *   SIPG_BC_PJACOBI  out = (T^T)^{x3} diag(A_GL)^-1 T^{x3} in, the point-Jacobi
  *                    preconditioner of the nodal GL basis expressed in the
- *                    operator's basis (needs sipg_set_gl_diagonal first).
+ *                    operator's basis (needs sipg_compute_gl_diagonal first).
+ *   SIPG_BC_FDM      out = P_K^-1 in per cell, the block-Jacobi preconditioner
+ *                    of Section 6.4: P_K = M (x) M (x) L + M (x) L (x) M +
+ *                    L (x) M (x) M (eq. KDlaplace_dg) with the 1D SIPG matrix
+ *                    L of an interior element and the mass matrix M on
+ *                    intervals of lengths h_d = |J(cell centre) e_d| (exact
+ *                    for interior cells of Cartesian meshes; interior-element
+ *                    matrices also at the boundary, as in the paper), inverted
+ *                    by fast diagonalization: Z^{x3} (vol Lambda_sum)^-1
+ *                    (Z^T)^{x3} with L z = lambda M z on the unit interval.
  * in, out: device pointers, ndofs elements, must not overlap.  Allocates
  * nothing; stream ordered.  SIPG_E_ARG for a bad mode or missing diagonal.
  */
-enum { SIPG_BC_T = 0, SIPG_BC_TT = 1, SIPG_BC_VALUES = 2, SIPG_BC_PJACOBI = 3 };
+enum { SIPG_BC_T = 0, SIPG_BC_TT = 1, SIPG_BC_VALUES = 2, SIPG_BC_PJACOBI = 3, SIPG_BC_FDM = 4 };
 int sipg_basis_change(const sipg_op* op, int mode, const void* in, void* out, void* stream);
 
 /*
@@ -210,8 +220,9 @@ int sipg_launch_shape(int degree, int dtype, int32_t* cells_per_block, int32_t* 
  * preconditioned by one V-cycle per iteration.  On every level of the brick
  * coarsened by two in each direction (while all cell counts are even and at
  * least min_coarse_cells coarse cells remain) the V-cycle smooths with a
- * Chebyshev iteration (eq. chebyshev) around P^-1 of eq. (jacobi) (point
- * Jacobi in the nodal Gauss-Lobatto basis through the basis change).  The
+ * Chebyshev iteration (eq. chebyshev) around P^-1 of the form of eq. (jacobi)
+ * (point Jacobi in the nodal Gauss-Lobatto basis through the basis change,
+ * or the block Jacobi of Section 6.4 by fast diagonalization).  The
  * smoothing range is [range_lo, range_hi] times the largest eigenvalue of
  * P^-1 A estimated by lanczos_steps conjugate-gradient (Lanczos) steps from
  * [-5.5, -4.5, ..., 5.5, -5.5, ...] (Section 6.2); the coarsest level is
@@ -228,6 +239,9 @@ typedef struct {
     double coarse_reduction;     /* coarse solve residual reduction (1e5) */
     int32_t min_coarse_cells;    /* stop coarsening below this many cells (1) */
     int32_t precision;           /* 0 mixed, 1 FP64 */
+    int32_t smoother;            /* P^-1 inside the Chebyshev smoother: 0 point Jacobi in the
+                                    nodal Gauss-Lobatto basis (SIPG_BC_PJACOBI), 1 the block
+                                    Jacobi of Section 6.4 (SIPG_BC_FDM) */
 } sipg_mg_opts;
 typedef struct {
     int32_t levels;
@@ -290,6 +304,7 @@ typedef struct {
     int64_t hbm_budget_bytes;    /* device memory the server may hold (64 GiB) */
     int32_t workers;             /* concurrent solves, 1..16 (4) */
     int32_t precision;           /* 0 mixed FP32 V-cycle, 1 FP64 (0) */
+    int32_t smoother;            /* sipg_mg_opts.smoother of every solve (0) */
 } sipg_server_opts;
 typedef struct {
     sipg_mesh mesh;
@@ -364,6 +379,14 @@ typedef struct {
     double* to_gl;
 } sipg_tables1d;
 int sipg_host_tables(int degree, int basis, sipg_tables1d* out);
+
+/* Host-only: the 1D tables of SIPG_BC_FDM (Section 6.4) that the library
+ * builds for (degree, basis, penalty_factor): zt[m*n + j] = z_m[j], the
+ * generalized eigenvectors of L z = lambda M z on the unit interval (L the
+ * interior-element SIPG matrix with penalty penalty_factor (degree+1)^2, M the
+ * mass matrix), normalised to Z^T M Z = I, and lam[m].  zt: n*n doubles, lam:
+ * n doubles, n = degree + 1 (caller-owned host memory). */
+int sipg_host_fdm_tables(int degree, int basis, double penalty_factor, double* zt, double* lam);
 
 #ifdef __cplusplus
 }

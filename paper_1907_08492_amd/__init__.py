@@ -8,5 +8,5 @@ this package is a thin ctypes binding over it.  Build the library with
 """
 from .binding import (  # noqa: F401
     BASIS, BC_MODES, DTYPE, EXPORTED, GEOMETRY, LIB_PATH, Batch, Multigrid, Operator, Server, SipgError,
-    SolveInfo, host_tables, launch_shape, lib, make_mesh,
+    SolveInfo, host_fdm_tables, host_tables, launch_shape, lib, make_mesh,
 )

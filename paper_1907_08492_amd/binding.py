@@ -34,7 +34,8 @@ SIPG_E_NOTREADY, SIPG_E_NOCONV, SIPG_E_BUDGET = -5, -6, -7
 BASIS = {"hermite_like": 0, "nodal_gl": 1}
 DTYPE = {"f64": 0, "f32": 1}
 GEOMETRY = {"auto": 0, "cell": 1, "qpoint": 2}
-BC_MODES = {"T": 0, "TT": 1, "VALUES": 2, "PJACOBI": 3}
+BC_MODES = {"T": 0, "TT": 1, "VALUES": 2, "PJACOBI": 3, "FDM": 4}
+SMOOTHERS = {"pjacobi": 0, "fdm": 1}
 
 EXPORTED = [
     "sipg_setup", "sipg_destroy", "sipg_ndofs", "sipg_get_info", "sipg_apply",
@@ -46,6 +47,7 @@ EXPORTED = [
     "sipg_server_default_opts", "sipg_server_create", "sipg_submit", "sipg_poll", "sipg_wait",
     "sipg_release", "sipg_server_stats", "sipg_server_destroy", "sipg_copy_device",
     "sipg_batch_create", "sipg_batch_apply", "sipg_batch_get_info", "sipg_batch_destroy",
+    "sipg_host_fdm_tables",
 ]
 
 
@@ -69,7 +71,7 @@ class SipgSolveInfo(C.Structure):
 class SipgMgOpts(C.Structure):
     _fields_ = [("smoother_degree", C.c_int32), ("lanczos_steps", C.c_int32), ("range_lo", C.c_double),
                 ("range_hi", C.c_double), ("coarse_reduction", C.c_double), ("min_coarse_cells", C.c_int32),
-                ("precision", C.c_int32)]
+                ("precision", C.c_int32), ("smoother", C.c_int32)]
 
 
 class SipgMgInfo(C.Structure):
@@ -79,7 +81,8 @@ class SipgMgInfo(C.Structure):
 
 
 class SipgServerOpts(C.Structure):
-    _fields_ = [("hbm_budget_bytes", C.c_int64), ("workers", C.c_int32), ("precision", C.c_int32)]
+    _fields_ = [("hbm_budget_bytes", C.c_int64), ("workers", C.c_int32), ("precision", C.c_int32),
+                ("smoother", C.c_int32)]
 
 
 class SipgRequest(C.Structure):
@@ -149,6 +152,7 @@ lib.sipg_batch_create.argtypes = [C.c_int, C.POINTER(_vp), C.POINTER(_vp), C.POI
 lib.sipg_batch_apply.argtypes = [_vp, _vp]
 lib.sipg_batch_get_info.argtypes = [_vp, C.POINTER(SipgBatchInfo)]
 lib.sipg_batch_destroy.argtypes = [_vp]
+lib.sipg_host_fdm_tables.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
 for _f in EXPORTED:
     if _f not in ("sipg_ndofs", "sipg_last_error"):
         getattr(lib, _f).restype = C.c_int
@@ -176,6 +180,17 @@ def host_tables(degree: int, basis: str = "hermite_like") -> dict:
     for k in ("shape", "shape_grad", "colloc_grad", "to_gl"):
         arrays[k] = arrays[k].reshape(n, n)
     return arrays
+
+
+def host_fdm_tables(degree: int, basis: str = "hermite_like", penalty: float = 2.0):
+    """(Z^T, lambda) of the block preconditioner, from the library's host code."""
+    n = degree + 1
+    zt = np.zeros(n * n)
+    lam = np.zeros(n)
+    _check(lib.sipg_host_fdm_tables(degree, BASIS[basis], float(penalty),
+                                    zt.ctypes.data_as(C.POINTER(C.c_double)),
+                                    lam.ctypes.data_as(C.POINTER(C.c_double))), "sipg_host_fdm_tables")
+    return zt.reshape(n, n), lam
 
 
 def launch_shape(degree: int, dtype: str = "f64"):
@@ -365,7 +380,7 @@ class Multigrid:
         _check(lib.sipg_mg_default_opts(C.byref(o)), "sipg_mg_default_opts")
         o.precision = {"mixed": 0, "f64": 1}[precision]
         for k, v in opts.items():
-            setattr(o, k, v)
+            setattr(o, k, SMOOTHERS[v] if k == "smoother" and isinstance(v, str) else v)
         self._mesh = make_mesh(mesh)
         h = _vp()
         _check(lib.sipg_mg_setup(C.byref(self._mesh), int(degree), float(penalty), BASIS[basis], C.byref(o),
@@ -434,12 +449,14 @@ def _result_dict(r: SipgResult) -> dict:
 class Server:
     """Continuous-batching request loop of multigrid Poisson solves."""
 
-    def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 4, precision: str = "mixed"):
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 4, precision: str = "mixed",
+                 smoother: str = "pjacobi"):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Server needs a GPU (HIP device)")
         torch.cuda.init()
-        o = SipgServerOpts(int(hbm_budget_bytes), int(workers), {"mixed": 0, "f64": 1}[precision])
+        o = SipgServerOpts(int(hbm_budget_bytes), int(workers), {"mixed": 0, "f64": 1}[precision],
+                           SMOOTHERS[smoother])
         h = _vp()
         _check(lib.sipg_server_create(C.byref(o), C.byref(h)), "sipg_server_create")
         self._h = h

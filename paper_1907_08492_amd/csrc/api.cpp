@@ -51,7 +51,8 @@ static std::vector<double> transpose(const std::vector<double>& M, int n) {
 }
 
 template <typename T>
-static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl) {
+static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl, const std::vector<double>& zt,
+                                 const std::vector<double>& lam) {
     const int n = t.n;
     const TableLayout L(n);
     std::vector<T> tab(L.total + 1, T(0));
@@ -74,12 +75,20 @@ static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl) {
         tab[L.Sgl + i] = T(gl.S[i]);
         tab[L.SGgl + i] = T(gl.Sg[i]);
     }
+    for (int i = 0; i < n; ++i) {
+        tab[L.FLAM + i] = T(lam[i]);
+        for (int j = 0; j < n; ++j) {
+            tab[L.FZT + i * n + j] = T(zt[i * n + j]);
+            tab[L.FZ + i * n + j] = T(zt[j * n + i]);
+        }
+    }
     return tab;
 }
 
 static int free_op(sipg_op* op) {
     if (!op) return SIPG_OK;
-    void* ptrs[] = {op->tables, op->cell_geom, op->face_geom[0], op->face_geom[1], op->face_geom[2], op->gl_inv_diag};
+    void* ptrs[] = {op->tables, op->cell_geom, op->face_geom[0], op->face_geom[1], op->face_geom[2], op->gl_inv_diag,
+                    op->fdm_cell};
     for (void* p : ptrs)
         if (p) (void)hipFree(p);
     delete op;
@@ -143,6 +152,21 @@ int sipg_host_tables(int degree, int basis, sipg_tables1d* out) {
     return SIPG_OK;
 }
 
+int sipg_host_fdm_tables(int degree, int basis, double penalty_factor, double* zt, double* lam) {
+    if (degree < 1 || degree > 15 || (basis != 0 && basis != 1) || !zt || !lam || !(penalty_factor > 0.0)) {
+        set_error("sipg_host_fdm_tables: degree in [1,15], basis 0 or 1, penalty > 0, non-null outputs");
+        return SIPG_E_ARG;
+    }
+    std::vector<double> z, l;
+    if (!fdm_1d(basis, degree, penalty_factor, z, l)) {
+        set_error("sipg_host_fdm_tables: 1D eigenproblem failed");
+        return SIPG_E_ARG;
+    }
+    std::memcpy(zt, z.data(), sizeof(double) * z.size());
+    std::memcpy(lam, l.data(), sizeof(double) * l.size());
+    return SIPG_OK;
+}
+
 int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int basis, int dtype,
                int geometry, void* stream, sipg_op** out) {
     if (!mesh || !out) { set_error("sipg_setup: null mesh or out"); return SIPG_E_ARG; }
@@ -198,9 +222,11 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
     if (e != hipSuccess) { free_op(op); return hip_fail(e, "hipGetDevice"); }
 
     Tables1D t, tgl;
-    if (!build_tables(basis, degree, t) || !build_tables(SIPG_BASIS_NODAL_GL, degree, tgl)) {
+    std::vector<double> fzt, flam;
+    if (!build_tables(basis, degree, t) || !build_tables(SIPG_BASIS_NODAL_GL, degree, tgl) ||
+        !fdm_1d(basis, degree, penalty_factor, fzt, flam)) {
         free_op(op);
-        set_error("sipg_setup: singular basis change");
+        set_error("sipg_setup: singular basis change or 1D eigenproblem");
         return SIPG_E_ARG;
     }
     const size_t esz = dtype == SIPG_F64 ? 8 : 4;
@@ -215,20 +241,22 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
     auto fail = [&](hipError_t err, const char* what) { free_op(op); return hip_fail(err, what); };
     if ((e = hipMalloc(&op->tables, tab_bytes)) != hipSuccess) return fail(e, "hipMalloc(tables)");
     if ((e = hipMalloc(&op->cell_geom, cg_bytes)) != hipSuccess) return fail(e, "hipMalloc(cell geometry)");
-    op->device_bytes = int64_t(tab_bytes + cg_bytes);
+    const size_t fdm_bytes = esz * size_t(ncells) * 4;
+    if ((e = hipMalloc(&op->fdm_cell, fdm_bytes)) != hipSuccess) return fail(e, "hipMalloc(block preconditioner)");
+    op->device_bytes = int64_t(tab_bytes + cg_bytes + fdm_bytes);
     for (int d = 0; d < 3; ++d) {
         const size_t fb = esz * size_t(op->nfaces[d]) * face_geom_stride(op->geom, n);
         if ((e = hipMalloc(&op->face_geom[d], fb)) != hipSuccess) return fail(e, "hipMalloc(face geometry)");
         op->device_bytes += int64_t(fb);
     }
     if (dtype == SIPG_F64) {
-        std::vector<double> tab = make_table<double>(t, tgl);
+        std::vector<double> tab = make_table<double>(t, tgl, fzt, flam);
         if ((e = hipMemcpyAsync(op->tables, tab.data(), tab_bytes, hipMemcpyHostToDevice, st)) != hipSuccess) return fail(e, "hipMemcpy(tables)");
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "hipStreamSynchronize");
         const int rc = build_geometry<double>(op, t.points, t.weights, st);
         if (rc != SIPG_OK) { free_op(op); return rc; }
     } else {
-        std::vector<float> tab = make_table<float>(t, tgl);
+        std::vector<float> tab = make_table<float>(t, tgl, fzt, flam);
         if ((e = hipMemcpyAsync(op->tables, tab.data(), tab_bytes, hipMemcpyHostToDevice, st)) != hipSuccess) return fail(e, "hipMemcpy(tables)");
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "hipStreamSynchronize");
         const int rc = build_geometry<float>(op, t.points, t.weights, st);
@@ -283,7 +311,7 @@ int sipg_apply(const sipg_op* op, const void* x, void* y, void* stream) {
 
 int sipg_basis_change(const sipg_op* op, int mode, const void* in, void* out, void* stream) {
     if (!op || !in || !out) { set_error("sipg_basis_change: null argument"); return SIPG_E_ARG; }
-    if (mode < SIPG_BC_T || mode > SIPG_BC_PJACOBI) { set_error("sipg_basis_change: bad mode"); return SIPG_E_ARG; }
+    if (mode < SIPG_BC_T || mode > SIPG_BC_FDM) { set_error("sipg_basis_change: bad mode"); return SIPG_E_ARG; }
     if (mode == SIPG_BC_PJACOBI && !op->gl_inv_diag) {
         set_error("sipg_basis_change: SIPG_BC_PJACOBI needs sipg_compute_gl_diagonal first");
         return SIPG_E_ARG;

@@ -285,4 +285,112 @@ bool child_embedding(int kind, int p, std::vector<double>& M0, std::vector<doubl
     return true;
 }
 
+// Separable block-Jacobi preconditioner (Section 6.4): the 1D SIPG stiffness
+// matrix L of an element with two interior faces and the 1D mass matrix M on
+// the unit interval (Gauss quadrature with n points is exact for both),
+// penalty eta (p+1)^2; the generalized eigenproblem L z = lambda M z is
+// reduced with the Cholesky factor M = C C^T to the symmetric matrix
+// C^-1 L C^-T and solved by cyclic Jacobi rotations.  Z (columns z,
+// Z^T M Z = I, Z^T L Z = diag(lambda)) is returned transposed: Zt[m][j] =
+// z_m[j].
+bool fdm_1d(int kind, int p, double eta, std::vector<double>& Zt, std::vector<double>& lam) {
+    Tables1D t;
+    if (!build_tables(kind, p, t)) return false;
+    const int n = p + 1;
+    const double sigma = eta * double(n) * double(n);
+    std::vector<double> L(n * n, 0.0), M(n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double l = 0.0, m = 0.0;
+            for (int q = 0; q < n; ++q) {
+                l += t.weights[q] * t.Sg[q * n + i] * t.Sg[q * n + j];
+                m += t.weights[q] * t.S[q * n + i] * t.S[q * n + j];
+            }
+            // face at 0 (outward normal -1) and at 1 (outward normal +1):
+            // sigma u v - 1/2 v (n u') - 1/2 (n v') u
+            l += sigma * t.v0[i] * t.v0[j] + 0.5 * (t.v0[i] * t.g0[j] + t.g0[i] * t.v0[j]);
+            l += sigma * t.v1[i] * t.v1[j] - 0.5 * (t.v1[i] * t.g1[j] + t.g1[i] * t.v1[j]);
+            L[i * n + j] = l;
+            M[i * n + j] = m;
+        }
+    // Cholesky M = C C^T (C lower triangular)
+    std::vector<double> C(n * n, 0.0);
+    for (int j = 0; j < n; ++j) {
+        double d = M[j * n + j];
+        for (int k = 0; k < j; ++k) d -= C[j * n + k] * C[j * n + k];
+        if (!(d > 0.0)) return false;
+        C[j * n + j] = std::sqrt(d);
+        for (int i = j + 1; i < n; ++i) {
+            double v = M[i * n + j];
+            for (int k = 0; k < j; ++k) v -= C[i * n + k] * C[j * n + k];
+            C[i * n + j] = v / C[j * n + j];
+        }
+    }
+    std::vector<double> Ci;
+    if (!invert(n, C, Ci)) return false;
+    // B = C^-1 L C^-T
+    std::vector<double> B(n * n, 0.0), W(n * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < n; ++k) v += Ci[i * n + k] * L[k * n + j];
+            W[i * n + j] = v;
+        }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < n; ++k) v += W[i * n + k] * Ci[j * n + k];
+            B[i * n + j] = v;
+        }
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < i; ++j) B[i * n + j] = B[j * n + i] = 0.5 * (B[i * n + j] + B[j * n + i]);
+    // cyclic Jacobi: B = Y diag Y^T
+    std::vector<double> Y(n * n, 0.0);
+    for (int i = 0; i < n; ++i) Y[i * n + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < n; ++i)
+            for (int j = 0; j < n; ++j) {
+                tot += B[i * n + j] * B[i * n + j];
+                if (i != j) off += B[i * n + j] * B[i * n + j];
+            }
+        if (off <= 1e-32 * tot) break;
+        for (int pp = 0; pp < n - 1; ++pp)
+            for (int qq = pp + 1; qq < n; ++qq) {
+                const double apq = B[pp * n + qq];
+                if (apq == 0.0) continue;
+                const double theta = (B[qq * n + qq] - B[pp * n + pp]) / (2.0 * apq);
+                const double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(tt * tt + 1.0), sn = tt * c;
+                for (int k = 0; k < n; ++k) {   // B <- B R (columns p, q)
+                    const double bkp = B[k * n + pp], bkq = B[k * n + qq];
+                    B[k * n + pp] = c * bkp - sn * bkq;
+                    B[k * n + qq] = sn * bkp + c * bkq;
+                }
+                for (int k = 0; k < n; ++k) {   // B <- R^T B (rows p, q)
+                    const double bpk = B[pp * n + k], bqk = B[qq * n + k];
+                    B[pp * n + k] = c * bpk - sn * bqk;
+                    B[qq * n + k] = sn * bpk + c * bqk;
+                }
+                for (int k = 0; k < n; ++k) {   // Y <- Y R
+                    const double ykp = Y[k * n + pp], ykq = Y[k * n + qq];
+                    Y[k * n + pp] = c * ykp - sn * ykq;
+                    Y[k * n + qq] = sn * ykp + c * ykq;
+                }
+            }
+    }
+    // Z = C^-T Y; Zt[m][j] = Z[j][m] = sum_k Ci[k][j] Y[k][m]
+    Zt.assign(n * n, 0.0);
+    lam.assign(n, 0.0);
+    for (int m = 0; m < n; ++m) {
+        lam[m] = B[m * n + m];
+        for (int j = 0; j < n; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < n; ++k) v += Ci[k * n + j] * Y[k * n + m];
+            Zt[m * n + j] = v;
+        }
+    }
+    return true;
+}
+
 }  // namespace sipg

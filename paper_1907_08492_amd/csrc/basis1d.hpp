@@ -44,4 +44,10 @@ bool build_tables(int kind, int p, Tables1D& t);
 // (row major, n x n).  Exact: both sides are polynomials of degree p.
 bool child_embedding(int kind, int p, std::vector<double>& M0, std::vector<double>& M1);
 
+// 1D matrices of the separable block preconditioner of Section 6.4 (eq.
+// KDlaplace_dg) on the unit interval, penalty eta (p+1)^2, interior element:
+// generalized eigenvectors (rows of Zt) and eigenvalues of L z = lambda M z,
+// with Z^T M Z = I.
+bool fdm_1d(int kind, int p, double eta, std::vector<double>& Zt, std::vector<double>& lam);
+
 }  // namespace sipg

@@ -1,7 +1,10 @@
-// Cell-wise tensor-product basis change and the preconditioner of eq.
-// (jacobi), Section 6.3:  out = (M3 x M2 x M1) in  with the same 1D matrix M
-// in every direction, optionally  (T^T)^{x3} diag^-1 T^{x3}.  One thread per
-// pencil, sweeps through LDS, coalesced loads and stores of whole cells.
+// Cell-wise tensor-product basis change and the preconditioners of the form
+// of eq. (jacobi), Sections 6.3 and 6.4:  out = (M3 x M2 x M1) in  with the
+// same 1D matrix M in every direction, or  (T^T)^{x3} P_d^-1 T^{x3} in  with
+// P_d the Gauss-Lobatto point-Jacobi diagonal (T = E^-1) or the diagonal of
+// the fast diagonalization (T = Z^T, generalized eigenvectors of the 1D
+// SIPG and mass matrices).  One thread per pencil, sweeps through LDS,
+// coalesced loads and stores of whole cells.
 #include "sipg_common.hpp"
 #include "sumfac.hpp"
 #include "setup.hpp"
@@ -18,7 +21,11 @@ struct BcShape {
 };
 
 // MODE: 0 = apply M (table offset moff) in all directions; 1 = P^-1 with
-// T (table TL.T), the inverse diagonal, then T^T (table TL.TT).
+// T (table TL.T), the inverse diagonal inv_diag (one value per unknown),
+// then T^T (table TL.TT); 2 = block preconditioner of Section 6.4 with Z^T
+// (TL.FZT), 1 / (vol (lambda_i/h_1^2 + lambda_j/h_2^2 + lambda_k/h_3^2)) from
+// the eigenvalues TL.FLAM and the four cell scalars in inv_diag, then Z
+// (TL.FZ).
 template <int N, typename T, int MODE>
 __global__ void __launch_bounds__(BcShape<N>::NT)
 basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ tab,
@@ -39,13 +46,22 @@ basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __re
     const int c = tid / N2, t = tid % N2, ta = t % N, tb = t / N;
     const bool act = c < ncb;
     T* A = lds + (act ? c : 0) * CS;
-    const T* M = tab + (MODE == 0 ? moff : TL.T);
+    const T* M = tab + (MODE == 0 ? moff : MODE == 1 ? TL.T : TL.FZT);
+    // forward sweeps (M, T or Z^T) and backward sweeps (T^T or Z)
+    auto fwd = [&](T* v) {
+        if constexpr (MODE == 2) dense_apply<N>(M, v, v);
+        else eo_apply<N, +1>(M, v, v);
+    };
+    auto bwd = [&](T* v) {
+        if constexpr (MODE == 2) dense_apply<N>(tab + TL.FZ, v, v);
+        else eo_apply<N, +1>(tab + TL.TT, v, v);
+    };
     T v[N];
     // z
     if (act) {
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(ta, tb, k)];
-        eo_apply<N, +1>(M, v, v);
+        fwd(v);
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::idx(ta, tb, k)] = v[k];
     }
@@ -54,31 +70,39 @@ basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __re
     if (act) {
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(ta, k, tb)];
-        eo_apply<N, +1>(M, v, v);
+        fwd(v);
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::idx(ta, k, tb)] = v[k];
     }
     __syncthreads();
-    // x (and for the preconditioner: diagonal scaling, then T^T along x)
+    // x (and for the preconditioners: diagonal scaling, then the backward
+    // sweep along x)
     if (act) {
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(k, ta, tb)];
-        eo_apply<N, +1>(M, v, v);
+        fwd(v);
         if constexpr (MODE == 1) {
             const T* dg = inv_diag + size_t(cell0 + c) * N3 + N * (ta + N * tb);
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] *= dg[k];
-            eo_apply<N, +1>(tab + TL.TT, v, v);
         }
+        if constexpr (MODE == 2) {
+            const T* cs = inv_diag + size_t(cell0 + c) * 4;
+            const T* lam = tab + TL.FLAM;
+            const T yz = pick<N>(lam, ta) * cs[1] + pick<N>(lam, tb) * cs[2];
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = v[k] * cs[3] / (lam[k] * cs[0] + yz);
+        }
+        if constexpr (MODE != 0) bwd(v);
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::idx(k, ta, tb)] = v[k];
     }
     __syncthreads();
-    if constexpr (MODE == 1) {
+    if constexpr (MODE != 0) {
         if (act) {
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(ta, k, tb)];
-            eo_apply<N, +1>(tab + TL.TT, v, v);
+            bwd(v);
 #pragma unroll
             for (int k = 0; k < N; ++k) A[Sh::idx(ta, k, tb)] = v[k];
         }
@@ -86,7 +110,7 @@ basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __re
         if (act) {
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(ta, tb, k)];
-            eo_apply<N, +1>(tab + TL.TT, v, v);
+            bwd(v);
             T* __restrict__ dst = out + size_t(cell0 + c) * N3 + ta + N * tb;
 #pragma unroll
             for (int k = 0; k < N; ++k) dst[k * N2] = v[k];
@@ -111,6 +135,8 @@ static int launch_bc_t(const sipg_op* op, int mode, const void* in, void* out, h
     constexpr int NT = threads_per_block(N);
     if (mode == SIPG_BC_PJACOBI) {
         basis_change_kernel<N, T, 1><<<nblk, NT, 0, st>>>(i_, o_, tab, 0, static_cast<const T*>(op->gl_inv_diag), ncells);
+    } else if (mode == SIPG_BC_FDM) {
+        basis_change_kernel<N, T, 2><<<nblk, NT, 0, st>>>(i_, o_, tab, 0, static_cast<const T*>(op->fdm_cell), ncells);
     } else {
         const int off = mode == SIPG_BC_T ? TL.T : mode == SIPG_BC_TT ? TL.TT : TL.ET;
         basis_change_kernel<N, T, 0><<<nblk, NT, 0, st>>>(i_, o_, tab, off, nullptr, ncells);

@@ -130,6 +130,7 @@ struct Hierarchy {
     int n = 0;
     int smooth_steps = 5;
     int coarse_steps = 1;
+    int pmode = SIPG_BC_PJACOBI;   // P^-1 of the smoother: SIPG_BC_PJACOBI or SIPG_BC_FDM
 
     // u = S^m(b; u) on level l (u = 0 on entry when zero_init).
     int smooth(int l, bool zero_init, int steps, const std::vector<double>& sig, const std::vector<double>& th,
@@ -140,13 +141,13 @@ struct Hierarchy {
             if (j == 0 && zero_init) {
                 // u_0 = 0 (kept in uo for the next step), u_1 = theta_0 P^-1 b
                 SIPG_HIP(hipMemsetAsync(L.uo.p, 0, sizeof(T) * size_t(L.n), st));
-                if ((rc = launch_basis_change(L.op, SIPG_BC_PJACOBI, L.b.p, L.z.p, st)) != SIPG_OK) return rc;
+                if ((rc = launch_basis_change(L.op, pmode, L.b.p, L.z.p, st)) != SIPG_OK) return rc;
                 if ((rc = vec_scale<T>(th[0], L.z.p, L.u.p, L.n, st)) != SIPG_OK) return rc;
                 continue;
             }
             if ((rc = launch_matvec(L.op, L.u.p, L.r.p, st)) != SIPG_OK) return rc;
             if ((rc = vec_sub<T>(L.b.p, L.r.p, L.r.p, L.n, st)) != SIPG_OK) return rc;
-            if ((rc = launch_basis_change(L.op, SIPG_BC_PJACOBI, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
+            if ((rc = launch_basis_change(L.op, pmode, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
             // u_{j+1} = u_j + sigma_j (u_j - u_{j-1}) + theta_j z into uo, then swap
             if ((rc = vec_cheb<T>(L.u.p, L.uo.p, L.z.p, j == 0 ? 0.0 : sig[j], th[j], L.n, st)) != SIPG_OK) return rc;
             std::swap(L.u.p, L.uo.p);
@@ -178,7 +179,7 @@ struct Hierarchy {
         SIPG_HIP(hipMemcpyAsync(L.r.p, h.data(), sizeof(T) * L.n, hipMemcpyHostToDevice, st));
         // x = 0, r = b; z = P^-1 r; p = z  (p in uo, Ap in b)
         int rc;
-        if ((rc = launch_basis_change(L.op, SIPG_BC_PJACOBI, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
+        if ((rc = launch_basis_change(L.op, pmode, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
         SIPG_HIP(hipMemcpyAsync(L.uo.p, L.z.p, sizeof(T) * L.n, hipMemcpyDeviceToDevice, st));
         double rz;
         if ((rc = sc.dot<T>(L.r.p, L.z.p, L.n, rz, st)) != SIPG_OK) return rc;
@@ -190,7 +191,7 @@ struct Hierarchy {
             if (!(pap > 0.0)) break;
             const double a = rz / pap;
             if ((rc = vec_axpby<T>(-a, L.b.p, 1.0, L.r.p, L.n, st)) != SIPG_OK) return rc;
-            if ((rc = launch_basis_change(L.op, SIPG_BC_PJACOBI, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
+            if ((rc = launch_basis_change(L.op, pmode, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
             double rz_new;
             if ((rc = sc.dot<T>(L.r.p, L.z.p, L.n, rz_new, st)) != SIPG_OK) return rc;
             const double bta = rz_new / rz;
@@ -251,13 +252,14 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
     int nc[3] = {mesh->n[0], mesh->n[1], mesh->n[2]};
     H.n = degree + 1;
     H.smooth_steps = o.smoother_degree;
+    H.pmode = o.smoother == 1 ? SIPG_BC_FDM : SIPG_BC_PJACOBI;
     for (;;) {
         auto L = std::make_unique<Level<T>>();
         sipg_mesh m = *mesh;
         for (int d = 0; d < 3; ++d) { m.n[d] = nc[d]; L->nc[d] = nc[d]; }
         int rc = sipg_setup(&m, degree, penalty, basis, dt, SIPG_GEOM_AUTO, st, &L->op);
         if (rc != SIPG_OK) return rc;
-        if ((rc = sipg_compute_gl_diagonal(L->op, nullptr, st)) != SIPG_OK) return rc;
+        if (H.pmode == SIPG_BC_PJACOBI && (rc = sipg_compute_gl_diagonal(L->op, nullptr, st)) != SIPG_OK) return rc;
         L->n = L->op->ndofs;
         if ((rc = L->b.alloc(L->n)) || (rc = L->u.alloc(L->n)) || (rc = L->uo.alloc(L->n)) ||
             (rc = L->r.alloc(L->n)) || (rc = L->z.alloc(L->n)))
@@ -323,6 +325,7 @@ int sipg_mg_default_opts(sipg_mg_opts* o) {
     o->coarse_reduction = 1e5;
     o->min_coarse_cells = 1;
     o->precision = 0;
+    o->smoother = 0;
     return SIPG_OK;
 }
 
@@ -335,7 +338,7 @@ int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, 
     if (opts) o = *opts;
     if (o.smoother_degree < 1 || o.smoother_degree > 64 || o.lanczos_steps < 2 || !(o.range_lo > 0.0) ||
         !(o.range_hi > o.range_lo) || !(o.coarse_reduction > 1.0) || (o.precision != 0 && o.precision != 1) ||
-        o.min_coarse_cells < 1) {
+        o.min_coarse_cells < 1 || (o.smoother != 0 && o.smoother != 1)) {
         set_error("sipg_mg_setup: invalid options");
         return SIPG_E_ARG;
     }

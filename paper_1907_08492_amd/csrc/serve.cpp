@@ -102,7 +102,8 @@ static int64_t estimate_hierarchy_bytes(const sipg_request& r, int precision) {
     const int64_t dofs = cells * n * n * n;
     const bool deformed = r.mesh.deform_amp != 0.0;
     const int esz = precision == 0 ? 4 : 8;
-    const int64_t geo_per_cell = deformed ? int64_t(6 * n * n * n + 3 * 7 * n * n) : 32;
+    // metric terms plus the four cell scalars of the block preconditioner
+    const int64_t geo_per_cell = (deformed ? int64_t(6 * n * n * n + 3 * 7 * n * n) : 32) + 4;
     const int64_t fine64 = 8 * (geo_per_cell * cells + 6 * dofs);        // geometry, rhs and CG vectors
     const int64_t levels = (esz * (geo_per_cell * cells + 6 * dofs)) * 8 / 7 + 4096 * 8;
     return fine64 + levels + (int64_t(1) << 20);
@@ -178,6 +179,7 @@ static void worker_main(sipg_server* s) {
             sipg_mg_opts o;
             sipg_mg_default_opts(&o);
             o.precision = s->opts.precision;
+            o.smoother = s->opts.smoother;
             status = sipg_mg_setup(&j->req.mesh, j->req.degree, j->req.penalty_factor, j->req.basis, &o, st, &mg);
             if (status == SIPG_OK) {
                 sipg_mg_info info;
@@ -244,6 +246,7 @@ int sipg_server_default_opts(sipg_server_opts* o) {
     o->hbm_budget_bytes = int64_t(64) << 30;
     o->workers = 4;
     o->precision = 0;
+    o->smoother = 0;
     return SIPG_OK;
 }
 
@@ -253,8 +256,9 @@ int sipg_server_create(const sipg_server_opts* opts, sipg_server** out) {
     sipg_server_opts o;
     sipg_server_default_opts(&o);
     if (opts) o = *opts;
-    if (o.workers < 1 || o.workers > 16 || o.hbm_budget_bytes <= 0 || (o.precision != 0 && o.precision != 1)) {
-        set_error("sipg_server_create: workers in [1,16], budget > 0, precision 0 or 1");
+    if (o.workers < 1 || o.workers > 16 || o.hbm_budget_bytes <= 0 || (o.precision != 0 && o.precision != 1) ||
+        (o.smoother != 0 && o.smoother != 1)) {
+        set_error("sipg_server_create: workers in [1,16], budget > 0, precision and smoother 0 or 1");
         return SIPG_E_ARG;
     }
     sipg_server* s = new (std::nothrow) sipg_server();

@@ -267,6 +267,22 @@ int launch_rhs_sines(const sipg_op* op, int nmodes, const double* amps, const in
     return op->dtype == SIPG_F64 ? launch_rhs_t<double>(op, md, b, st) : launch_rhs_t<float>(op, md, b, st);
 }
 
+// Cell scalars of the separable block preconditioner (Section 6.4): with
+// h_d = |J(1/2,1/2,1/2) e_d| (the cell extents on a Cartesian mesh) the
+// values 1/h_1^2, 1/h_2^2, 1/h_3^2 and 1/(h_1 h_2 h_3).  One thread per cell.
+template <typename T>
+__global__ void fdm_cell_kernel(MeshDev m, T* __restrict__ out, int64_t ncells) {
+    const int64_t c = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (c >= ncells) return;
+    const int ix = c % m.n[0], iy = (c / m.n[0]) % m.n[1], iz = c / (int64_t(m.n[0]) * m.n[1]);
+    double J[9];
+    map_jacobian(m, ix, iy, iz, 0.5, 0.5, 0.5, J);
+    double h[3];
+    for (int d = 0; d < 3; ++d) h[d] = sqrt(J[d] * J[d] + J[3 + d] * J[3 + d] + J[6 + d] * J[6 + d]);
+    for (int d = 0; d < 3; ++d) out[c * 4 + d] = T(1.0 / (h[d] * h[d]));
+    out[c * 4 + 3] = T(1.0 / (h[0] * h[1] * h[2]));
+}
+
 template <typename T>
 int build_geometry(sipg_op* op, const std::vector<double>& xq, const std::vector<double>& wq,
                    hipStream_t st) {
@@ -285,6 +301,8 @@ int build_geometry(sipg_op* op, const std::vector<double>& xq, const std::vector
         cell_geometry_kernel<T, GEOM_QPOINT><<<gc, bs, 0, st>>>(op->mesh, r, cg, vol, bad, op->ncells);
     else
         cell_geometry_kernel<T, GEOM_CELL><<<gc, bs, 0, st>>>(op->mesh, r, cg, vol, bad, op->ncells);
+    SIPG_HIP(hipGetLastError());
+    fdm_cell_kernel<T><<<gc, bs, 0, st>>>(op->mesh, static_cast<T*>(op->fdm_cell), op->ncells);
     SIPG_HIP(hipGetLastError());
     const double sigma0 = op->eta * double(op->degree + 1) * double(op->degree + 1);
     for (int d = 0; d < 3; ++d) {

@@ -54,6 +54,22 @@ __device__ __forceinline__ void eo_apply(const T* __restrict__ P, const T* in, T
     }
 }
 
+// out = M in for a general n x n matrix M (row major, uniform pointer).
+// `in` and `out` may be the same array.
+template <int N, typename T>
+__device__ __forceinline__ void dense_apply(const T* __restrict__ M, const T* in, T* out) {
+    T r[N];
+#pragma unroll
+    for (int q = 0; q < N; ++q) {
+        T acc = M[q * N] * in[0];
+#pragma unroll
+        for (int j = 1; j < N; ++j) acc = fma(M[q * N + j], in[j], acc);
+        r[q] = acc;
+    }
+#pragma unroll
+    for (int q = 0; q < N; ++q) out[q] = r[q];
+}
+
 // P[i] for a lane-varying index 0 <= i < N, from uniform (scalar) loads.
 template <int N, typename T>
 __device__ __forceinline__ T pick(const T* __restrict__ P, int i) {

@@ -78,3 +78,28 @@ def test_pjacobi_requires_diagonal():
     with pytest.raises(P.SipgError):
         op.basis_change("PJACOBI", x)
     op.close()
+
+
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("mesh_name", ["brick", "deformed", "affine"])
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+def test_fdm_block_preconditioner(k, mesh_name, basis):
+    """SIPG_BC_FDM (fast diagonalization on the device) equals the oracle's
+    explicit solve with the Kronecker-sum block of eq. (KDlaplace_dg)."""
+    from oracle import fdm
+    from workloads import Mesh
+    torch, P = require_gpu()
+    banner(f"fdm k={k} {mesh_name} {basis}")
+    mesh = {"brick": Mesh(n=(3, 2, 4), lo=(0.0, -0.5, 0.0), hi=(0.75, 1.0, 0.8)),
+            "deformed": unit_cube((2, 3, 2), 0.1),
+            "affine": paper_affine_brick((2, 2, 3))}[mesh_name]
+    r = uniform_vector(mesh.ncells * (k + 1) ** 3, seed=40 + k)
+    ref = fdm.apply(mesh, k, 2.0, basis, r)
+    for dtype, tol in (("f64", 1e-12), ("f32", 1e-5)):
+        op = P.Operator(mesh, k, 2.0, basis, dtype)
+        rr = r if dtype == "f64" else r.astype(np.float32).astype(np.float64)
+        z = op.basis_change("FDM", _dev(torch, rr, dtype)).cpu().numpy().astype(np.float64)
+        ref_d = ref if dtype == "f64" else fdm.apply(mesh, k, 2.0, basis, rr)
+        e2, emax = rel_errors(z, ref_d)
+        assert e2 <= tol and emax <= tol * 10, (dtype, e2, emax)
+        op.close()

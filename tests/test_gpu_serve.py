@@ -113,3 +113,25 @@ def test_budget_rejects_and_evicts():
     st = srv.stats()
     assert st["peak_bytes"] <= 64 << 20
     srv.close()
+
+
+def test_server_with_block_jacobi_smoother_matches_direct_solve():
+    torch, P = require_gpu()
+    banner("serve fdm smoother")
+    mesh = unit_cube(8, 0.1)
+    amps, waves = [1.0, -0.5], [(1, 1, 1), (2, 3, 1)]
+    srv = P.Server(workers=2, precision="mixed", smoother="fdm")
+    t = srv.submit(P.Server.make_request(mesh, 4, amps, waves, rel_tol=1e-9))
+    res = srv.wait(t)
+    assert res["status"] == 0 and res["rel_residual"] <= 1e-9
+    op = P.Operator(mesh, 4, 2.0)
+    b = op.assemble_rhs(amps, waves)
+    mg = P.Multigrid(mesh, 4, 2.0, precision="mixed", smoother="fdm")
+    xd, info = mg.solve(b, rel_tol=1e-9)
+    torch.cuda.synchronize()
+    assert info.iterations == res["iterations"]
+    assert torch.equal(srv.solution(res), xd)
+    srv.release(t)
+    srv.close()
+    mg.close()
+    op.close()

@@ -110,3 +110,19 @@ def test_single_hip_runtime_in_process():
     maps = open("/proc/self/maps").read().splitlines()
     hip = {line.split()[-1] for line in maps if "libamdhip64" in line}
     assert len(hip) == 1, hip
+
+
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+@pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 7, 8])
+def test_host_fdm_tables_diagonalize_the_oracle_1d_matrices(basis, k):
+    """The library's own 1D eigen-decomposition (Cholesky + Jacobi rotations)
+    diagonalizes the oracle's interior-element SIPG and mass matrices:
+    Z^T M Z = I, Z^T L Z = diag(lambda)."""
+    from oracle import fdm
+    for eta in (1.0, 2.0):
+        zt, lam = P.host_fdm_tables(k, basis, eta)
+        L, M = fdm.interior_1d(basis, k, 1.0, eta)
+        Z = zt.T
+        assert np.allclose(Z.T @ M @ Z, np.eye(k + 1), atol=1e-12)
+        assert np.allclose(Z.T @ L @ Z, np.diag(lam), atol=1e-10 * np.max(np.abs(lam)))
+        assert np.all(lam > 0)
