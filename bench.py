@@ -192,6 +192,41 @@ def batch_benchmark(torch, P, dtype: str, reps: int = 10, count: int = 256):
     return out
 
 
+def solver_benchmark(torch, P, reps: int = 3):
+    """Multigrid-preconditioned CG (Section 6) on 48^3 cells of the deformed
+    unit cube, k = 5, manufactured sine solution, residual 1e-10: mixed
+    precision (FP32 V-cycle) against FP64, point-Jacobi (GL basis) against
+    block-Jacobi (fast diagonalization) smoothing."""
+    from workloads import CONFIGS
+    cfg = CONFIGS["mixed_k5_48c_deformed"]
+    out = []
+    op = P.Operator(cfg.mesh, cfg.degree, cfg.eta)
+    b = op.assemble_rhs([3 * np.pi ** 2], [(1, 1, 1)])
+    bn = float(torch.linalg.norm(b))
+    for smoother in ("pjacobi", "fdm"):
+        for prec in ("mixed", "f64"):
+            t0 = time.perf_counter()
+            mg = P.Multigrid(cfg.mesh, cfg.degree, cfg.eta, precision=prec, smoother=smoother)
+            torch.cuda.synchronize()
+            setup = time.perf_counter() - t0
+            mg.solve(b, rel_tol=1e-10)
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                t0 = time.perf_counter()
+                x, info = mg.solve(b, rel_tol=1e-10)
+                torch.cuda.synchronize()
+                ts.append(time.perf_counter() - t0)
+            t = float(np.median(ts))
+            out.append({"smoother": smoother, "precision": prec, "ndofs": mg.ndofs, "levels": mg.info.levels,
+                        "iterations": info.iterations, "rel_residual": info.true_residual / bn,
+                        "solve_s": t, "dof_per_s": mg.ndofs / t, "setup_s": setup})
+            mg.close()
+            del x
+    op.close()
+    return out
+
+
 def serve_benchmark(P, precision: str, seconds: float, rate: float, workers: int = 4,
                     budget_bytes: int = 96 << 30, tol: float = 1e-8):
     """Poisson arrivals of multigrid Poisson solves (unit cube n^3, n log-uniform
@@ -260,6 +295,7 @@ def main():
     ap.add_argument("--copy-probe", action="store_true",
                     help="also run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-operator batched leg")
+    ap.add_argument("--no-solver", action="store_true", help="skip the multigrid solver leg")
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="arrival window of the serving leg (0 skips it; 60 is the full stream)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -285,6 +321,18 @@ def main():
     xs = make_inputs(torch, op.ndofs, torch.float64, nrot)
     ys = [torch.empty_like(xs[0]) for _ in range(nrot)]
     zs = [torch.empty_like(xs[0]) for _ in range(nrot)]
+    zf = torch.empty_like(xs[0])
+    for _ in range(3):
+        op.basis_change("FDM", xs[0], zf)
+    torch.cuda.synchronize()
+    ev_fdm = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(20)]
+    for a, e in ev_fdm:
+        a.record()
+        op.basis_change("FDM", xs[0], zf)
+        e.record()
+    torch.cuda.synchronize()
+    fdm_s = float(np.mean([a.elapsed_time(e) for a, e in ev_fdm])) * 1e-3
+    del zf
     if args.copy_probe:
         a = torch.empty(1 << 27, dtype=torch.float64, device="cuda")
         b = torch.empty_like(a)
@@ -359,6 +407,10 @@ def main():
                    "valu_frac_table4": TABLE4_FLOP["hermite_like"][k] * ndofs / mv_s / (FP64_PEAK_TFLOPS * 1e12)},
         "pjacobi": {"dof_per_s": ndofs / pj_s, "avg_ms": pj_s * 1e3, "alg_GBs": pj_bpd * ndofs / pj_s / 1e9,
                     "hbm_frac": pj_bpd * ndofs / pj_s / 1e9 / HBM_PEAK_GBS},
+        # block-Jacobi of Section 6.4: read r, write z (+ 4 scalars per cell)
+        "fdm": {"dof_per_s": ndofs / fdm_s, "avg_ms": fdm_s * 1e3,
+                "alg_GBs": (16.0 + 32.0 / (k + 1) ** 3) * ndofs / fdm_s / 1e9,
+                "hbm_frac": (16.0 + 32.0 / (k + 1) ** 3) * ndofs / fdm_s / 1e9 / HBM_PEAK_GBS},
     }
     del op, xs, ys, zs
     torch.cuda.empty_cache()
@@ -389,6 +441,11 @@ def main():
             del vx, vy
             torch.cuda.empty_cache()
         out["variants"] = variants
+
+    if not args.no_solver:
+        print("[bench] multigrid solver 48^3 k=5", file=sys.stderr, flush=True)
+        out["solver"] = solver_benchmark(torch, P)
+        torch.cuda.empty_cache()
 
     if not args.no_batch:
         out["batch"] = []

@@ -51,7 +51,7 @@ static std::vector<double> transpose(const std::vector<double>& M, int n) {
 }
 
 template <typename T>
-static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl, const std::vector<double>& zt,
+static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl, const std::vector<double>& fzp,
                                  const std::vector<double>& lam) {
     const int n = t.n;
     const TableLayout L(n);
@@ -75,13 +75,8 @@ static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl, const st
         tab[L.Sgl + i] = T(gl.S[i]);
         tab[L.SGgl + i] = T(gl.Sg[i]);
     }
-    for (int i = 0; i < n; ++i) {
-        tab[L.FLAM + i] = T(lam[i]);
-        for (int j = 0; j < n; ++j) {
-            tab[L.FZT + i * n + j] = T(zt[i * n + j]);
-            tab[L.FZ + i * n + j] = T(zt[j * n + i]);
-        }
-    }
+    for (int i = 0; i < n; ++i) tab[L.FLAM + i] = T(lam[i]);
+    for (size_t i = 0; i < fzp.size(); ++i) tab[L.FZP + i] = T(fzp[i]);
     return tab;
 }
 
@@ -222,9 +217,9 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
     if (e != hipSuccess) { free_op(op); return hip_fail(e, "hipGetDevice"); }
 
     Tables1D t, tgl;
-    std::vector<double> fzt, flam;
+    std::vector<double> fzt, flam, fzp;
     if (!build_tables(basis, degree, t) || !build_tables(SIPG_BASIS_NODAL_GL, degree, tgl) ||
-        !fdm_1d(basis, degree, penalty_factor, fzt, flam)) {
+        !fdm_1d(basis, degree, penalty_factor, fzt, flam, &fzp)) {
         free_op(op);
         set_error("sipg_setup: singular basis change or 1D eigenproblem");
         return SIPG_E_ARG;
@@ -250,13 +245,13 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
         op->device_bytes += int64_t(fb);
     }
     if (dtype == SIPG_F64) {
-        std::vector<double> tab = make_table<double>(t, tgl, fzt, flam);
+        std::vector<double> tab = make_table<double>(t, tgl, fzp, flam);
         if ((e = hipMemcpyAsync(op->tables, tab.data(), tab_bytes, hipMemcpyHostToDevice, st)) != hipSuccess) return fail(e, "hipMemcpy(tables)");
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "hipStreamSynchronize");
         const int rc = build_geometry<double>(op, t.points, t.weights, st);
         if (rc != SIPG_OK) { free_op(op); return rc; }
     } else {
-        std::vector<float> tab = make_table<float>(t, tgl, fzt, flam);
+        std::vector<float> tab = make_table<float>(t, tgl, fzp, flam);
         if ((e = hipMemcpyAsync(op->tables, tab.data(), tab_bytes, hipMemcpyHostToDevice, st)) != hipSuccess) return fail(e, "hipMemcpy(tables)");
         if ((e = hipStreamSynchronize(st)) != hipSuccess) return fail(e, "hipStreamSynchronize");
         const int rc = build_geometry<float>(op, t.points, t.weights, st);

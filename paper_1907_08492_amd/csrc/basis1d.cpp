@@ -285,18 +285,101 @@ bool child_embedding(int kind, int p, std::vector<double>& M0, std::vector<doubl
     return true;
 }
 
+// Generalized symmetric-definite eigenproblem L y = lambda M y of size m
+// (row major): Cholesky M = C C^T, the symmetric C^-1 L C^-T diagonalized by
+// cyclic Jacobi rotations, y = C^-T (rotations).  Columns of Y are the
+// eigenvectors, Y^T M Y = I.
+static bool sym_gen_eig(int m, const std::vector<double>& L, const std::vector<double>& M,
+                        std::vector<double>& Y, std::vector<double>& lam) {
+    std::vector<double> C(m * m, 0.0);
+    for (int j = 0; j < m; ++j) {
+        double d = M[j * m + j];
+        for (int k = 0; k < j; ++k) d -= C[j * m + k] * C[j * m + k];
+        if (!(d > 0.0)) return false;
+        C[j * m + j] = std::sqrt(d);
+        for (int i = j + 1; i < m; ++i) {
+            double v = M[i * m + j];
+            for (int k = 0; k < j; ++k) v -= C[i * m + k] * C[j * m + k];
+            C[i * m + j] = v / C[j * m + j];
+        }
+    }
+    std::vector<double> Ci;
+    if (!invert(m, C, Ci)) return false;
+    std::vector<double> B(m * m, 0.0), W(m * m, 0.0), R(m * m, 0.0);
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < m; ++k) v += Ci[i * m + k] * L[k * m + j];
+            W[i * m + j] = v;
+        }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < m; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < m; ++k) v += W[i * m + k] * Ci[j * m + k];
+            B[i * m + j] = v;
+        }
+    for (int i = 0; i < m; ++i)
+        for (int j = 0; j < i; ++j) B[i * m + j] = B[j * m + i] = 0.5 * (B[i * m + j] + B[j * m + i]);
+    for (int i = 0; i < m; ++i) R[i * m + i] = 1.0;
+    for (int sweep = 0; sweep < 100; ++sweep) {
+        double off = 0.0, tot = 0.0;
+        for (int i = 0; i < m; ++i)
+            for (int j = 0; j < m; ++j) {
+                tot += B[i * m + j] * B[i * m + j];
+                if (i != j) off += B[i * m + j] * B[i * m + j];
+            }
+        if (off <= 1e-32 * tot) break;
+        for (int pp = 0; pp < m - 1; ++pp)
+            for (int qq = pp + 1; qq < m; ++qq) {
+                const double apq = B[pp * m + qq];
+                if (apq == 0.0) continue;
+                const double theta = (B[qq * m + qq] - B[pp * m + pp]) / (2.0 * apq);
+                const double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
+                const double c = 1.0 / std::sqrt(tt * tt + 1.0), sn = tt * c;
+                for (int k = 0; k < m; ++k) {   // B <- B G (columns p, q)
+                    const double bkp = B[k * m + pp], bkq = B[k * m + qq];
+                    B[k * m + pp] = c * bkp - sn * bkq;
+                    B[k * m + qq] = sn * bkp + c * bkq;
+                }
+                for (int k = 0; k < m; ++k) {   // B <- G^T B (rows p, q)
+                    const double bpk = B[pp * m + k], bqk = B[qq * m + k];
+                    B[pp * m + k] = c * bpk - sn * bqk;
+                    B[qq * m + k] = sn * bpk + c * bqk;
+                }
+                for (int k = 0; k < m; ++k) {   // R <- R G
+                    const double rkp = R[k * m + pp], rkq = R[k * m + qq];
+                    R[k * m + pp] = c * rkp - sn * rkq;
+                    R[k * m + qq] = sn * rkp + c * rkq;
+                }
+            }
+    }
+    Y.assign(m * m, 0.0);
+    lam.assign(m, 0.0);
+    for (int e = 0; e < m; ++e) {
+        lam[e] = B[e * m + e];
+        for (int j = 0; j < m; ++j) {
+            double v = 0.0;
+            for (int k = 0; k < m; ++k) v += Ci[k * m + j] * R[k * m + e];
+            Y[j * m + e] = v;
+        }
+    }
+    return true;
+}
+
 // Separable block-Jacobi preconditioner (Section 6.4): the 1D SIPG stiffness
 // matrix L of an element with two interior faces and the 1D mass matrix M on
 // the unit interval (Gauss quadrature with n points is exact for both),
-// penalty eta (p+1)^2; the generalized eigenproblem L z = lambda M z is
-// reduced with the Cholesky factor M = C C^T to the symmetric matrix
-// C^-1 L C^-T and solved by cyclic Jacobi rotations.  Z (columns z,
-// Z^T M Z = I, Z^T L Z = diag(lambda)) is returned transposed: Zt[m][j] =
-// z_m[j].
-bool fdm_1d(int kind, int p, double eta, std::vector<double>& Zt, std::vector<double>& lam) {
+// penalty eta (p+1)^2.  Both commute with the reflection xi -> 1 - xi (the
+// bases are symmetric, phi_{p-i}(xi) = phi_i(1 - xi)), so the eigenvectors
+// of L z = lambda M z are solved for separately on the reflection-even
+// vectors (h = n/2 pairs u_j = u_{n-1-j}, plus the middle entry for odd n)
+// and the reflection-odd ones (u_j = -u_{n-1-j}).  Output order: the
+// ceil(n/2) even eigenvectors, then the floor(n/2) odd ones.
+bool fdm_1d(int kind, int p, double eta, std::vector<double>& Zt, std::vector<double>& lam,
+            std::vector<double>* packed) {
     Tables1D t;
     if (!build_tables(kind, p, t)) return false;
-    const int n = p + 1;
+    const int n = p + 1, h = n / 2, ne = n - h, no = h;
     const double sigma = eta * double(n) * double(n);
     std::vector<double> L(n * n, 0.0), M(n * n, 0.0);
     for (int i = 0; i < n; ++i)
@@ -313,81 +396,49 @@ bool fdm_1d(int kind, int p, double eta, std::vector<double>& Zt, std::vector<do
             L[i * n + j] = l;
             M[i * n + j] = m;
         }
-    // Cholesky M = C C^T (C lower triangular)
-    std::vector<double> C(n * n, 0.0);
-    for (int j = 0; j < n; ++j) {
-        double d = M[j * n + j];
-        for (int k = 0; k < j; ++k) d -= C[j * n + k] * C[j * n + k];
-        if (!(d > 0.0)) return false;
-        C[j * n + j] = std::sqrt(d);
-        for (int i = j + 1; i < n; ++i) {
-            double v = M[i * n + j];
-            for (int k = 0; k < j; ++k) v -= C[i * n + k] * C[j * n + k];
-            C[i * n + j] = v / C[j * n + j];
-        }
-    }
-    std::vector<double> Ci;
-    if (!invert(n, C, Ci)) return false;
-    // B = C^-1 L C^-T
-    std::vector<double> B(n * n, 0.0), W(n * n, 0.0);
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-            double v = 0.0;
-            for (int k = 0; k < n; ++k) v += Ci[i * n + k] * L[k * n + j];
-            W[i * n + j] = v;
-        }
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < n; ++j) {
-            double v = 0.0;
-            for (int k = 0; k < n; ++k) v += W[i * n + k] * Ci[j * n + k];
-            B[i * n + j] = v;
-        }
-    for (int i = 0; i < n; ++i)
-        for (int j = 0; j < i; ++j) B[i * n + j] = B[j * n + i] = 0.5 * (B[i * n + j] + B[j * n + i]);
-    // cyclic Jacobi: B = Y diag Y^T
-    std::vector<double> Y(n * n, 0.0);
-    for (int i = 0; i < n; ++i) Y[i * n + i] = 1.0;
-    for (int sweep = 0; sweep < 100; ++sweep) {
-        double off = 0.0, tot = 0.0;
-        for (int i = 0; i < n; ++i)
-            for (int j = 0; j < n; ++j) {
-                tot += B[i * n + j] * B[i * n + j];
-                if (i != j) off += B[i * n + j] * B[i * n + j];
-            }
-        if (off <= 1e-32 * tot) break;
-        for (int pp = 0; pp < n - 1; ++pp)
-            for (int qq = pp + 1; qq < n; ++qq) {
-                const double apq = B[pp * n + qq];
-                if (apq == 0.0) continue;
-                const double theta = (B[qq * n + qq] - B[pp * n + pp]) / (2.0 * apq);
-                const double tt = (theta >= 0 ? 1.0 : -1.0) / (std::fabs(theta) + std::sqrt(theta * theta + 1.0));
-                const double c = 1.0 / std::sqrt(tt * tt + 1.0), sn = tt * c;
-                for (int k = 0; k < n; ++k) {   // B <- B R (columns p, q)
-                    const double bkp = B[k * n + pp], bkq = B[k * n + qq];
-                    B[k * n + pp] = c * bkp - sn * bkq;
-                    B[k * n + qq] = sn * bkp + c * bkq;
-                }
-                for (int k = 0; k < n; ++k) {   // B <- R^T B (rows p, q)
-                    const double bpk = B[pp * n + k], bqk = B[qq * n + k];
-                    B[pp * n + k] = c * bpk - sn * bqk;
-                    B[qq * n + k] = sn * bpk + c * bqk;
-                }
-                for (int k = 0; k < n; ++k) {   // Y <- Y R
-                    const double ykp = Y[k * n + pp], ykq = Y[k * n + qq];
-                    Y[k * n + pp] = c * ykp - sn * ykq;
-                    Y[k * n + qq] = sn * ykp + c * ykq;
-                }
-            }
-    }
-    // Z = C^-T Y; Zt[m][j] = Z[j][m] = sum_k Ci[k][j] Y[k][m]
+    // parity bases: even column e (e < h: unit vectors j and n-1-j; e = h for
+    // odd n: the middle), odd column o (unit j minus unit n-1-j)
+    auto basis_vec = [&](bool even, int e, std::vector<double>& v) {
+        v.assign(n, 0.0);
+        if (even && e == h) { v[h] = 1.0; return; }
+        v[e] = 1.0;
+        v[n - 1 - e] = even ? 1.0 : -1.0;
+    };
     Zt.assign(n * n, 0.0);
     lam.assign(n, 0.0);
-    for (int m = 0; m < n; ++m) {
-        lam[m] = B[m * n + m];
-        for (int j = 0; j < n; ++j) {
-            double v = 0.0;
-            for (int k = 0; k < n; ++k) v += Ci[k * n + j] * Y[k * n + m];
-            Zt[m * n + j] = v;
+    if (packed) packed->assign(ne * (h + 1) + no * h, 0.0);
+    int row = 0;
+    for (int par = 0; par < 2; ++par) {
+        const bool even = par == 0;
+        const int m = even ? ne : no;
+        if (m == 0) continue;
+        std::vector<std::vector<double>> P(m);
+        for (int e = 0; e < m; ++e) basis_vec(even, e, P[e]);
+        std::vector<double> Lr(m * m), Mr(m * m), Y, lr;
+        for (int a = 0; a < m; ++a)
+            for (int b2 = 0; b2 < m; ++b2) {
+                double l = 0.0, mm = 0.0;
+                for (int i = 0; i < n; ++i)
+                    for (int j = 0; j < n; ++j) {
+                        l += P[a][i] * L[i * n + j] * P[b2][j];
+                        mm += P[a][i] * M[i * n + j] * P[b2][j];
+                    }
+                Lr[a * m + b2] = l;
+                Mr[a * m + b2] = mm;
+            }
+        if (!sym_gen_eig(m, Lr, Mr, Y, lr)) return false;
+        for (int e = 0; e < m; ++e, ++row) {
+            lam[row] = lr[e];
+            for (int j = 0; j < n; ++j) {
+                double v = 0.0;
+                for (int a = 0; a < m; ++a) v += P[a][j] * Y[a * m + e];
+                Zt[row * n + j] = v;
+            }
+            if (packed) {
+                // coefficients of the reduced basis: y[j] for j < h, middle y[h]
+                if (even) for (int a = 0; a < m; ++a) (*packed)[e * (h + 1) + a] = Y[a * m + e];
+                else for (int a = 0; a < m; ++a) (*packed)[ne * (h + 1) + e * h + a] = Y[a * m + e];
+            }
         }
     }
     return true;

@@ -47,7 +47,12 @@ bool child_embedding(int kind, int p, std::vector<double>& M0, std::vector<doubl
 // 1D matrices of the separable block preconditioner of Section 6.4 (eq.
 // KDlaplace_dg) on the unit interval, penalty eta (p+1)^2, interior element:
 // generalized eigenvectors (rows of Zt) and eigenvalues of L z = lambda M z,
-// with Z^T M Z = I.
-bool fdm_1d(int kind, int p, double eta, std::vector<double>& Zt, std::vector<double>& lam);
+// with Z^T M Z = I; the ceil(n/2) reflection-even eigenvectors first, then
+// the reflection-odd ones.  `packed` (optional) receives the parity-split
+// form the device uses: for each even vector its entries 0..h (h = n/2; entry
+// h is the middle one, zero for even n), then for each odd vector its
+// entries 0..h-1.
+bool fdm_1d(int kind, int p, double eta, std::vector<double>& Zt, std::vector<double>& lam,
+            std::vector<double>* packed = nullptr);
 
 }  // namespace sipg

@@ -23,9 +23,9 @@ struct BcShape {
 // MODE: 0 = apply M (table offset moff) in all directions; 1 = P^-1 with
 // T (table TL.T), the inverse diagonal inv_diag (one value per unknown),
 // then T^T (table TL.TT); 2 = block preconditioner of Section 6.4 with Z^T
-// (TL.FZT), 1 / (vol (lambda_i/h_1^2 + lambda_j/h_2^2 + lambda_k/h_3^2)) from
-// the eigenvalues TL.FLAM and the four cell scalars in inv_diag, then Z
-// (TL.FZ).
+// (TL.FZP, parity-split), 1 / (vol (lambda_i/h_1^2 + lambda_j/h_2^2 +
+// lambda_k/h_3^2)) from the eigenvalues TL.FLAM and the four cell scalars in
+// inv_diag, then Z.
 template <int N, typename T, int MODE>
 __global__ void __launch_bounds__(BcShape<N>::NT)
 basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ tab,
@@ -38,22 +38,42 @@ basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __re
     const int cell0 = blockIdx.x * CPB;
     const int ncb = min(CPB, ncells - cell0);
     const T* __restrict__ src = in + size_t(cell0) * N3;
-    for (int e = tid; e < ncb * N3; e += NT) {
-        const int c = e / N3, i = e % N3;
-        lds[c * CS + Sh::idx(i % N, (i / N) % N, i / N2)] = src[e];
+    // all loads of the workgroup's input tile issued back to back
+    constexpr int XPER = (CPB * N3 + NT - 1) / NT;
+    T xv[XPER];
+#pragma unroll
+    for (int j = 0; j < XPER; ++j) {
+        const int e = tid + j * NT;
+        xv[j] = e < ncb * N3 ? src[e] : T(0);
     }
-    __syncthreads();
     const int c = tid / N2, t = tid % N2, ta = t % N, tb = t / N;
     const bool act = c < ncb;
+    // the block preconditioner's four cell scalars, loaded with the tile
+    T cs[4] = {T(0), T(0), T(0), T(0)};
+    if constexpr (MODE == 2) {
+        if (act) {
+#pragma unroll
+            for (int m = 0; m < 4; ++m) cs[m] = inv_diag[size_t(cell0 + c) * 4 + m];
+        }
+    }
+#pragma unroll
+    for (int j = 0; j < XPER; ++j) {
+        const int e = tid + j * NT;
+        if (e < ncb * N3) {
+            const int cc = e / N3, i = e % N3;
+            lds[cc * CS + Sh::idx(i % N, (i / N) % N, i / N2)] = xv[j];
+        }
+    }
+    __syncthreads();
     T* A = lds + (act ? c : 0) * CS;
-    const T* M = tab + (MODE == 0 ? moff : MODE == 1 ? TL.T : TL.FZT);
+    const T* M = tab + (MODE == 0 ? moff : MODE == 1 ? TL.T : TL.FZP);
     // forward sweeps (M, T or Z^T) and backward sweeps (T^T or Z)
     auto fwd = [&](T* v) {
-        if constexpr (MODE == 2) dense_apply<N>(M, v, v);
+        if constexpr (MODE == 2) fdm_fwd<N>(M, v);
         else eo_apply<N, +1>(M, v, v);
     };
     auto bwd = [&](T* v) {
-        if constexpr (MODE == 2) dense_apply<N>(tab + TL.FZ, v, v);
+        if constexpr (MODE == 2) fdm_bwd<N>(M, v);
         else eo_apply<N, +1>(tab + TL.TT, v, v);
     };
     T v[N];
@@ -87,11 +107,20 @@ basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __re
             for (int k = 0; k < N; ++k) v[k] *= dg[k];
         }
         if constexpr (MODE == 2) {
-            const T* cs = inv_diag + size_t(cell0 + c) * 4;
             const T* lam = tab + TL.FLAM;
             const T yz = pick<N>(lam, ta) * cs[1] + pick<N>(lam, tb) * cs[2];
+            // 1/d by the hardware reciprocal refined with two Newton steps
+            // (d > 0): independent per k, unlike the full division sequence
 #pragma unroll
-            for (int k = 0; k < N; ++k) v[k] = v[k] * cs[3] / (lam[k] * cs[0] + yz);
+            for (int k = 0; k < N; ++k) {
+                const T d = fma(lam[k], cs[0], yz);
+                T r;
+                if constexpr (sizeof(T) == 8) r = __builtin_amdgcn_rcp(d);
+                else r = __builtin_amdgcn_rcpf(d);
+                r = fma(r, fma(-d, r, T(1)), r);
+                r = fma(r, fma(-d, r, T(1)), r);
+                v[k] = v[k] * cs[3] * r;
+            }
         }
         if constexpr (MODE != 0) bwd(v);
 #pragma unroll

@@ -54,20 +54,60 @@ __device__ __forceinline__ void eo_apply(const T* __restrict__ P, const T* in, T
     }
 }
 
-// out = M in for a general n x n matrix M (row major, uniform pointer).
-// `in` and `out` may be the same array.
+// Eigenvector transforms of the block preconditioner (Section 6.4) in the
+// parity-split form (basis1d.hpp, fdm_1d): the ceil(n/2) reflection-even
+// eigenvectors z_m store entries 0..h (h = n/2), the odd ones entries
+// 0..h-1, so each transform costs about n^2/2 multiply-adds.
+// fdm_fwd: v <- Z^T v (even coefficients first, then odd ones).
 template <int N, typename T>
-__device__ __forceinline__ void dense_apply(const T* __restrict__ M, const T* in, T* out) {
-    T r[N];
+__device__ __forceinline__ void fdm_fwd(const T* __restrict__ P, T* v) {
+    constexpr int H = N / 2, NE = N - H, NO = H;
+    T e[H > 0 ? H : 1], o[H > 0 ? H : 1], r[N];
 #pragma unroll
-    for (int q = 0; q < N; ++q) {
-        T acc = M[q * N] * in[0];
-#pragma unroll
-        for (int j = 1; j < N; ++j) acc = fma(M[q * N + j], in[j], acc);
-        r[q] = acc;
+    for (int j = 0; j < H; ++j) {
+        e[j] = v[j] + v[N - 1 - j];
+        o[j] = v[j] - v[N - 1 - j];
     }
 #pragma unroll
-    for (int q = 0; q < N; ++q) out[q] = r[q];
+    for (int m = 0; m < NE; ++m) {
+        T acc = (N % 2 == 1) ? P[m * (H + 1) + H] * v[H] : T(0);
+#pragma unroll
+        for (int j = 0; j < H; ++j) acc = fma(P[m * (H + 1) + j], e[j], acc);
+        r[m] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < NO; ++m) {
+        T acc = T(0);
+#pragma unroll
+        for (int j = 0; j < H; ++j) acc = fma(P[NE * (H + 1) + m * H + j], o[j], acc);
+        r[NE + m] = acc;
+    }
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = r[m];
+}
+// fdm_bwd: v <- Z v for v ordered as fdm_fwd leaves it.
+template <int N, typename T>
+__device__ __forceinline__ void fdm_bwd(const T* __restrict__ P, T* v) {
+    constexpr int H = N / 2, NE = N - H, NO = H;
+    T r[N];
+#pragma unroll
+    for (int j = 0; j < H; ++j) {
+        T ev = T(0), od = T(0);
+#pragma unroll
+        for (int m = 0; m < NE; ++m) ev = fma(P[m * (H + 1) + j], v[m], ev);
+#pragma unroll
+        for (int m = 0; m < NO; ++m) od = fma(P[NE * (H + 1) + m * H + j], v[NE + m], od);
+        r[j] = ev + od;
+        r[N - 1 - j] = ev - od;
+    }
+    if constexpr (N % 2 == 1) {
+        T mid = T(0);
+#pragma unroll
+        for (int m = 0; m < NE; ++m) mid = fma(P[m * (H + 1) + H], v[m], mid);
+        r[H] = mid;
+    }
+#pragma unroll
+    for (int m = 0; m < N; ++m) v[m] = r[m];
 }
 
 // P[i] for a lane-varying index 0 <= i < N, from uniform (scalar) loads.

@@ -126,3 +126,7 @@ def test_host_fdm_tables_diagonalize_the_oracle_1d_matrices(basis, k):
         assert np.allclose(Z.T @ M @ Z, np.eye(k + 1), atol=1e-12)
         assert np.allclose(Z.T @ L @ Z, np.diag(lam), atol=1e-10 * np.max(np.abs(lam)))
         assert np.all(lam > 0)
+        # reflection-even eigenvectors first, then the odd ones
+        ne = k + 1 - (k + 1) // 2
+        assert np.array_equal(zt[:ne], zt[:ne, ::-1])
+        assert np.array_equal(zt[ne:], -zt[ne:, ::-1])
