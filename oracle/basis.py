@@ -178,11 +178,20 @@ def nodal_gl(p: int) -> Basis1D:
     return lagrange(gauss_lobatto_points(p + 1), "nodal_gl")
 
 
+def nodal_gauss(p: int) -> Basis1D:
+    """Lagrange basis in the p+1 Gauss points: with the (p+1)-point Gauss rule
+    the interpolation matrix S is the identity (collocation, Section 4.1)."""
+    x, _ = gauss(p + 1)
+    return lagrange(x, "nodal_gauss")
+
+
 def make_basis(kind: str, p: int) -> Basis1D:
     if kind == "hermite_like":
         return hermite_like(p)
     if kind == "nodal_gl":
         return nodal_gl(p)
+    if kind == "nodal_gauss":
+        return nodal_gauss(p)
     raise ValueError(kind)
 
 

@@ -146,3 +146,19 @@ def test_classical_hermite_condition_p3():
     """Table 1 first entry also equals the classical cubic Hermite basis."""
     c = b1d.mass_condition_number(b1d.classical_hermite_cubic(), 3)
     assert abs(c - 1.06e3) <= 10.0
+
+
+@pytest.mark.parametrize("p", [1, 2, 3, 5, 8])
+def test_nodal_gauss_collocation_and_diagonal_mass(p):
+    """Section 4.1: with nodes at the p+1 Gauss points, S = I and (Gauss being
+    exact to degree 2p+1) the exact mass matrix is diag(weights); the face rows
+    S_f are dense."""
+    bas = b1d.make_basis("nodal_gauss", p)
+    x, w = b1d.gauss(p + 1)
+    assert np.allclose(bas.values(x), np.eye(p + 1), atol=1e-13)
+    xe, we = b1d.gauss(p + 3)
+    V = bas.values(xe)
+    M = V.T @ (we[:, None] * V)
+    assert np.allclose(M, np.diag(w), atol=1e-14)
+    v0 = bas.values([0.0])[0]
+    assert np.all(np.abs(v0) > 1e-3) and abs(v0.sum() - 1.0) < 1e-13

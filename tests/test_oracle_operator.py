@@ -177,3 +177,22 @@ def test_mms_convergence_deformed():
         errs.append(mms.l2_error(op, u, mms.sine))
     rate = np.log2(errs[0] / errs[1])
     assert rate > 2.7, rate
+
+
+@pytest.mark.parametrize("k", [1, 2, 4])
+def test_nodal_gauss_basis_same_space(k):
+    """The nodal Gauss basis (Section 4.1, S = I) spans the same space: with
+    E_ij = phi^HL_i(x^Gauss_j), A_Gauss = V^T A_HL V for V = E^-T, on a deformed
+    mesh; the Gauss operator is SPD and its matrix-free product equals CSR."""
+    mesh = unit_cube((2, 1, 2), 0.1)
+    Ah = SIPG(mesh, k, 2.0, "hermite_like").assemble().toarray()
+    opg = SIPG(mesh, k, 2.0, "nodal_gauss")
+    Ag = opg.assemble().toarray()
+    xg, _ = b1d.gauss(k + 1)
+    E = b1d.hermite_like(k).values(xg).T            # E[i, j] = phi_i(x_j)
+    V = np.linalg.inv(E).T
+    Vg = np.kron(np.eye(mesh.ncells), precond.kron3(V))
+    assert np.max(np.abs(Vg.T @ Ah @ Vg - Ag)) <= 1e-13 * np.max(np.abs(Ag))
+    np.linalg.cholesky(Ag)
+    x = np.random.default_rng(k).uniform(-1, 1, opg.ndofs)
+    assert np.allclose(opg.apply_naive(x), Ag @ x, rtol=0, atol=1e-13 * np.abs(Ag @ x).max())
