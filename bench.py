@@ -33,7 +33,8 @@ HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
 # FLOP per unknown of the matrix-free product, Table 4 (Hermite-like / nodal GL)
 TABLE4_FLOP = {"hermite_like": {1: 244, 2: 191, 3: 218, 4: 206, 5: 225, 7: 241},
-               "nodal_gl": {1: 258, 2: 210, 3: 240, 4: 229, 5: 250, 7: 267}}
+               "nodal_gl": {1: 258, 2: 210, 3: 240, 4: 229, 5: 250, 7: 267},
+               "nodal_gauss": {1: 204, 2: 168, 3: 180, 4: 171, 5: 180, 7: 186}}
 
 
 def alg_bytes_per_dof(mesh, k: int, esz: int, per_point: bool) -> float:
@@ -418,9 +419,12 @@ def main():
     if not args.no_variants:
         variants = []
         plan = [("scale_k4_64c_affine", "hermite_like", "f64"), ("scale_k4_64c_affine", "nodal_gl", "f64"),
-                ("scale_k4_64c_deformed", "nodal_gl", "f64"),
+                ("scale_k4_64c_affine", "nodal_gauss", "f64"),
+                ("scale_k4_64c_deformed", "nodal_gl", "f64"), ("scale_k4_64c_deformed", "nodal_gauss", "f64"),
                 ("scale_k7_32c_affine", "hermite_like", "f64"), ("scale_k7_32c_affine", "nodal_gl", "f64"),
+                ("scale_k7_32c_affine", "nodal_gauss", "f64"),
                 ("scale_k7_32c_deformed", "hermite_like", "f64"), ("scale_k7_32c_deformed", "nodal_gl", "f64"),
+                ("scale_k7_32c_deformed", "nodal_gauss", "f64"),
                 ("scale_k4_64c_deformed", "hermite_like", "f32"), ("mixed_k5_48c_deformed", "hermite_like", "f32")]
         for name, basis, dt in plan:
             c = with_basis(CONFIGS[name], basis)

@@ -40,7 +40,10 @@ typedef enum {
     SIPG_E_BUDGET = -7       /* request exceeds the configured memory budget */
 } sipg_status;
 
-typedef enum { SIPG_BASIS_HERMITE_LIKE = 0, SIPG_BASIS_NODAL_GL = 1 } sipg_basis;
+/* Bases (Section 4.1): the Hermite-like basis, and for comparison the nodal
+ * Lagrange bases in the Gauss-Lobatto points and in the Gauss points (the
+ * latter collocated with the quadrature: S = I, dense face rows). */
+typedef enum { SIPG_BASIS_HERMITE_LIKE = 0, SIPG_BASIS_NODAL_GL = 1, SIPG_BASIS_NODAL_GAUSS = 2 } sipg_basis;
 typedef enum { SIPG_F64 = 0, SIPG_F32 = 1 } sipg_dtype;
 
 /* How metric terms are stored (Section 3 and Section 4.2):

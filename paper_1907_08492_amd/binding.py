@@ -31,7 +31,7 @@ lib = C.CDLL(LIB_PATH)
 # ----------------------------------------------------------------- constants
 SIPG_OK, SIPG_E_ARG, SIPG_E_OOM, SIPG_E_HIP, SIPG_E_UNSUPPORTED = 0, -1, -2, -3, -4
 SIPG_E_NOTREADY, SIPG_E_NOCONV, SIPG_E_BUDGET = -5, -6, -7
-BASIS = {"hermite_like": 0, "nodal_gl": 1}
+BASIS = {"hermite_like": 0, "nodal_gl": 1, "nodal_gauss": 2}
 DTYPE = {"f64": 0, "f32": 1}
 GEOMETRY = {"auto": 0, "cell": 1, "qpoint": 2}
 BC_MODES = {"T": 0, "TT": 1, "VALUES": 2, "PJACOBI": 3, "FDM": 4}

@@ -75,7 +75,11 @@ static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl, const st
         tab[L.Sgl + i] = T(gl.S[i]);
         tab[L.SGgl + i] = T(gl.Sg[i]);
     }
-    for (int i = 0; i < n; ++i) tab[L.FLAM + i] = T(lam[i]);
+    for (int i = 0; i < n; ++i) {
+        tab[L.FLAM + i] = T(lam[i]);
+        tab[L.FV0 + i] = T(t.v0[i]);
+        tab[L.FV1 + i] = T(t.v1[i]);
+    }
     for (size_t i = 0; i < fzp.size(); ++i) tab[L.FZP + i] = T(fzp[i]);
     return tab;
 }
@@ -120,8 +124,8 @@ extern "C" {
 const char* sipg_last_error(void) { return g_last_error.c_str(); }
 
 int sipg_host_tables(int degree, int basis, sipg_tables1d* out) {
-    if (degree < 1 || degree > 15 || (basis != 0 && basis != 1) || !out) {
-        set_error("sipg_host_tables: degree must be in [1,15], basis 0 or 1, out non-null");
+    if (degree < 1 || degree > 15 || basis < 0 || basis > 2 || !out) {
+        set_error("sipg_host_tables: degree must be in [1,15], basis 0, 1 or 2, out non-null");
         return SIPG_E_ARG;
     }
     Tables1D t;
@@ -148,8 +152,8 @@ int sipg_host_tables(int degree, int basis, sipg_tables1d* out) {
 }
 
 int sipg_host_fdm_tables(int degree, int basis, double penalty_factor, double* zt, double* lam) {
-    if (degree < 1 || degree > 15 || (basis != 0 && basis != 1) || !zt || !lam || !(penalty_factor > 0.0)) {
-        set_error("sipg_host_fdm_tables: degree in [1,15], basis 0 or 1, penalty > 0, non-null outputs");
+    if (degree < 1 || degree > 15 || basis < 0 || basis > 2 || !zt || !lam || !(penalty_factor > 0.0)) {
+        set_error("sipg_host_fdm_tables: degree in [1,15], basis 0, 1 or 2, penalty > 0, non-null outputs");
         return SIPG_E_ARG;
     }
     std::vector<double> z, l;
@@ -168,7 +172,10 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
     *out = nullptr;
     if (degree < 1 || degree > 8) { set_error("sipg_setup: degree must be in [1,8]"); return SIPG_E_ARG; }
     if (!(penalty_factor > 0.0) || !std::isfinite(penalty_factor)) { set_error("sipg_setup: penalty_factor must be > 0"); return SIPG_E_ARG; }
-    if (basis != SIPG_BASIS_HERMITE_LIKE && basis != SIPG_BASIS_NODAL_GL) { set_error("sipg_setup: bad basis"); return SIPG_E_ARG; }
+    if (basis != SIPG_BASIS_HERMITE_LIKE && basis != SIPG_BASIS_NODAL_GL && basis != SIPG_BASIS_NODAL_GAUSS) {
+        set_error("sipg_setup: bad basis");
+        return SIPG_E_ARG;
+    }
     if (dtype != SIPG_F64 && dtype != SIPG_F32) { set_error("sipg_setup: bad dtype"); return SIPG_E_ARG; }
     if (geometry < SIPG_GEOM_AUTO || geometry > SIPG_GEOM_QPOINT) { set_error("sipg_setup: bad geometry mode"); return SIPG_E_ARG; }
     for (int d = 0; d < 3; ++d) {

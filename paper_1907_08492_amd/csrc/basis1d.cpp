@@ -186,8 +186,24 @@ static std::vector<ProductPoly> nodal_gl(int p) {
     return f;
 }
 
+// Lagrange basis in the p+1 Gauss points (collocated with the quadrature).
+static std::vector<ProductPoly> nodal_gauss(int p) {
+    std::vector<double> x, w;
+    gauss_rule(p + 1, x, w);
+    std::vector<ProductPoly> f;
+    for (int j = 0; j <= p; ++j) {
+        ProductPoly l{1.0, {}, false};
+        double den = 1.0;
+        for (int m = 0; m <= p; ++m)
+            if (m != j) { l.roots.push_back(x[m]); den *= (x[j] - x[m]); }
+        l.c = 1.0 / den;
+        f.push_back(l);
+    }
+    return f;
+}
+
 std::vector<ProductPoly> make_basis(int kind, int p) {
-    return kind == 0 ? hermite_like(p) : nodal_gl(p);
+    return kind == 0 ? hermite_like(p) : kind == 1 ? nodal_gl(p) : nodal_gauss(p);
 }
 
 // Gauss-Jordan inverse with partial pivoting (n <= 16).

@@ -25,7 +25,8 @@ void gauss_rule(int n, std::vector<double>& x, std::vector<double>& w);
 // The n Gauss-Lobatto points on [0,1].
 std::vector<double> gauss_lobatto_points(int n);
 
-// Degree-p 1D basis: 0 = Hermite-like, 1 = nodal Gauss-Lobatto Lagrange.
+// Degree-p 1D basis: 0 = Hermite-like, 1 = nodal Gauss-Lobatto Lagrange,
+// 2 = nodal Gauss Lagrange.
 std::vector<ProductPoly> make_basis(int kind, int p);
 
 // All 1D tables (see sipg_host_tables in sipg.h), n = p + 1, row major.

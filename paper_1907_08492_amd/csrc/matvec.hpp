@@ -117,7 +117,8 @@ __device__ __forceinline__ void face_topology(int ix, int iy, int iz, int f, int
 }
 
 // basis: 0 Hermite-like (derivative rows touch layers {0,1} / {n-2,n-1}),
-//        1 nodal Gauss-Lobatto (derivative rows touch every layer).
+//        1 nodal Gauss-Lobatto (derivative rows touch every layer),
+//        2 nodal Gauss (value and derivative rows touch every layer).
 template <int N, int BASIS>
 struct Layers {
     static constexpr int NL = (BASIS == 0) ? 2 : N;
@@ -173,6 +174,8 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     constexpr int N2 = Sh::N2, N3 = Sh::N3, RS = Sh::RS, CS = Sh::CS, FR = Sh::FR;
     constexpr int CPB = Sh::CPB, NT = Sh::NT;
     constexpr TableLayout TL(N);
+    // nodal Gauss basis: S = I, dense face value rows
+    constexpr bool COLLOC = BASIS == 2;
 
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
@@ -280,20 +283,24 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         const T* dfs = tab + (s ? TL.df1 : TL.df0);
         const T* dfn = tab + (s ? TL.df0 : TL.df1);
         T vm[N], nm[N];
+        const T* fvs = tab + (s ? TL.FV1 : TL.FV0);
 #pragma unroll
         for (int a = 0; a < N; ++a) {
-            vm[a] = Xc[face_lidx<N, D>(s ? N - 1 : 0, a, b)];
-            T acc = T(0);
+            T acc = T(0), val = T(0);
 #pragma unroll
             for (int j = 0; j < Ly::NL; ++j) {
                 const int l = Ly::layer(s, j);
-                acc = fma(dfs[l], Xc[face_lidx<N, D>(l, a, b)], acc);
+                const T xl = Xc[face_lidx<N, D>(l, a, b)];
+                acc = fma(dfs[l], xl, acc);
+                if constexpr (COLLOC) val = fma(fvs[l], xl, val);
             }
+            if constexpr (!COLLOC) val = Xc[face_lidx<N, D>(s ? N - 1 : 0, a, b)];
+            vm[a] = val;
             nm[a] = acc;
         }
         T r[N];
         const int row = b * FR;
-        eo_apply<N, +1>(tab + TL.S, vm, r);
+        s_apply<N, COLLOC>(tab + TL.S, vm, r);
         T* o = fel(0, D, c, s) + row;
 #pragma unroll
         for (int a = 0; a < N; ++a) o[a] = r[a];
@@ -301,7 +308,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         o = fel(4, D, c, s) + row;
 #pragma unroll
         for (int a = 0; a < N; ++a) o[a] = r[a];
-        eo_apply<N, +1>(tab + TL.S, nm, r);
+        s_apply<N, COLLOC>(tab + TL.S, nm, r);
         o = fel(1, D, c, s) + row;
 #pragma unroll
         for (int a = 0; a < N; ++a) o[a] = r[a];
@@ -319,6 +326,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                     for (int a = 0; a < N; ++a) nbv[j][a] = Xn[face_lidx<N, 0>(l, a, b)];
                 }
             }
+            const T* fvn = tab + (s ? TL.FV0 : TL.FV1);
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 T acc = T(0), val = T(0);
@@ -326,12 +334,13 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 for (int j = 0; j < Ly::NL; ++j) {
                     const int l = Ly::layer(1 - s, j);
                     acc = fma(dfn[l], nbv[j][a], acc);
-                    if (l == (s ? 0 : N - 1)) val = nbv[j][a];
+                    if constexpr (COLLOC) val = fma(fvn[l], nbv[j][a], val);
+                    else if (l == (s ? 0 : N - 1)) val = nbv[j][a];
                 }
                 vp[a] = val;
                 np[a] = acc;
             }
-            eo_apply<N, +1>(tab + TL.S, vp, r);
+            s_apply<N, COLLOC>(tab + TL.S, vp, r);
             o = fel(2, D, c, s) + row;
 #pragma unroll
             for (int a = 0; a < N; ++a) o[a] = r[a];
@@ -339,7 +348,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
             o = fel(5, D, c, s) + row;
 #pragma unroll
             for (int a = 0; a < N; ++a) o[a] = r[a];
-            eo_apply<N, +1>(tab + TL.S, np, r);
+            s_apply<N, COLLOC>(tab + TL.S, np, r);
             o = fel(3, D, c, s) + row;
 #pragma unroll
             for (int a = 0; a < N; ++a) o[a] = r[a];
@@ -361,16 +370,16 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
             for (int b = 0; b < N; ++b) v[b] = src[b * FR];
         };
         T um[N], gdm[N], g1m[N], g2m[N];
-        col(0, um);  eo_apply<N, +1>(tab + TL.S, um, um);
-        col(1, gdm); eo_apply<N, +1>(tab + TL.S, gdm, gdm);
-        col(4, g1m); eo_apply<N, +1>(tab + TL.S, g1m, g1m);
+        col(0, um);  s_apply<N, COLLOC>(tab + TL.S, um, um);
+        col(1, gdm); s_apply<N, COLLOC>(tab + TL.S, gdm, gdm);
+        col(4, g1m); s_apply<N, COLLOC>(tab + TL.S, g1m, g1m);
         eo_apply<N, -1>(tab + TL.D, um, g2m);
         T up[N], gdp[N], g1p[N], g2p[N];
         const bool interior = fnb >= 0;
         if (interior) {
-            col(2, up);  eo_apply<N, +1>(tab + TL.S, up, up);
-            col(3, gdp); eo_apply<N, +1>(tab + TL.S, gdp, gdp);
-            col(5, g1p); eo_apply<N, +1>(tab + TL.S, g1p, g1p);
+            col(2, up);  s_apply<N, COLLOC>(tab + TL.S, up, up);
+            col(3, gdp); s_apply<N, COLLOC>(tab + TL.S, gdp, gdp);
+            col(5, g1p); s_apply<N, COLLOC>(tab + TL.S, g1p, g1p);
             eo_apply<N, -1>(tab + TL.D, up, g2p);
         } else {
             // mirror principle: u+ = -u-, grad u+ = grad u-
@@ -415,9 +424,9 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         eo_apply<N, -1>(tab + TL.DT, w2, tmp);
 #pragma unroll
         for (int b = 0; b < N; ++b) vv[b] += tmp[b];
-        eo_apply<N, +1>(tab + TL.ST, vv, vv);
-        eo_apply<N, +1>(tab + TL.ST, w1, w1);
-        eo_apply<N, +1>(tab + TL.ST, wd, wd);
+        s_apply<N, COLLOC>(tab + TL.ST, vv, vv);
+        s_apply<N, COLLOC>(tab + TL.ST, w1, w1);
+        s_apply<N, COLLOC>(tab + TL.ST, wd, wd);
         T* s0 = fel(0, D, c, s) + a;
         T* s1 = fel(1, D, c, s) + a;
         T* s2 = fel(2, D, c, s) + a;
@@ -462,8 +471,8 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         eo_apply<N, -1>(tab + TL.DT, cv, cv);
 #pragma unroll
         for (int a = 0; a < N; ++a) av[a] += cv[a];
-        eo_apply<N, +1>(tab + TL.ST, av, av);
-        eo_apply<N, +1>(tab + TL.ST, bv, bv);
+        s_apply<N, COLLOC>(tab + TL.ST, av, av);
+        s_apply<N, COLLOC>(tab + TL.ST, bv, bv);
 #pragma unroll
         for (int a = 0; a < N; ++a) { s0[a] = av[a]; s1[a] = bv[a]; }
     }
@@ -475,19 +484,19 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     T* C = B + CPB * CS;
     T v[N];
     // C1: z pencils (thread (i1, i2)) : S along z
-    if (act) {
+    if (act && !COLLOC) {
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, tb, k)];
-        eo_apply<N, +1>(tab + TL.S, v, v);
+        s_apply<N, COLLOC>(tab + TL.S, v, v);
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, tb, k)] = v[k];
     }
     __syncthreads();
     // C2: y pencils (thread (i1, q3)) : S along y
-    if (act) {
+    if (act && !COLLOC) {
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, k, tb)];
-        eo_apply<N, +1>(tab + TL.S, v, v);
+        s_apply<N, COLLOC>(tab + TL.S, v, v);
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, k, tb)] = v[k];
     }
@@ -497,7 +506,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         T g[N];
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(k, ta, tb)];
-        eo_apply<N, +1>(tab + TL.S, v, v);
+        s_apply<N, COLLOC>(tab + TL.S, v, v);
         eo_apply<N, -1>(tab + TL.D, v, g);
 #pragma unroll
         for (int k = 0; k < N; ++k) { A[Sh::lds_idx(k, ta, tb)] = v[k]; B[Sh::lds_idx(k, ta, tb)] = g[k]; }
@@ -568,16 +577,16 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         eo_apply<N, -1>(tab + TL.DT, g, g);
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] += g[k];
-        eo_apply<N, +1>(tab + TL.ST, v, v);
+        s_apply<N, COLLOC>(tab + TL.ST, v, v);
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::lds_idx(k, ta, tb)] = v[k];
     }
     __syncthreads();
     // C8: y pencils : S^T along y
-    if (act) {
+    if (act && !COLLOC) {
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, k, tb)];
-        eo_apply<N, +1>(tab + TL.ST, v, v);
+        s_apply<N, COLLOC>(tab + TL.ST, v, v);
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, k, tb)] = v[k];
     }
@@ -586,7 +595,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     if (act) {
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, tb, k)];
-        eo_apply<N, +1>(tab + TL.ST, v, v);
+        s_apply<N, COLLOC>(tab + TL.ST, v, v);
         const int i1 = ta, i2 = tb;
         const T* df0 = tab + TL.df0;
         const T* df1 = tab + TL.df1;
@@ -594,6 +603,11 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         const T cy0 = pick<N>(df0, i2), cy1 = pick<N>(df1, i2);
         const bool hx0 = BASIS != 0 || i1 <= 1, hx1 = BASIS != 0 || i1 >= N - 2;
         const bool hy0 = BASIS != 0 || i2 <= 1, hy1 = BASIS != 0 || i2 >= N - 2;
+        // value test rows: unit rows at the end layers, or dense (Gauss)
+        const T* fv0 = tab + TL.FV0;
+        const T* fv1 = tab + TL.FV1;
+        const T vx0 = COLLOC ? pick<N>(fv0, i1) : T(i1 == 0), vx1 = COLLOC ? pick<N>(fv1, i1) : T(i1 == N - 1);
+        const T vy0 = COLLOC ? pick<N>(fv0, i2) : T(i2 == 0), vy1 = COLLOC ? pick<N>(fv1, i2) : T(i2 == N - 1);
         const T* P0 = fel(0, 0, c, 0); const T* Q0 = fel(1, 0, c, 0);
         const T* P1 = fel(0, 0, c, 1); const T* Q1 = fel(1, 0, c, 1);
         const T* P2 = fel(0, 1, c, 0); const T* Q2 = fel(1, 1, c, 0);
@@ -605,18 +619,30 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         for (int k = 0; k < N; ++k) {
             T r = v[k];
             // x faces: tangential (t1, t2) = (i2, k), layer i1
-            if (hx0) r += (i1 == 0 ? P0[k * FR + i2] : T(0)) + cx0 * Q0[k * FR + i2];
-            if (hx1) r += (i1 == N - 1 ? P1[k * FR + i2] : T(0)) + cx1 * Q1[k * FR + i2];
+            if constexpr (COLLOC) {
+                r += vx0 * P0[k * FR + i2] + cx0 * Q0[k * FR + i2];
+                r += vx1 * P1[k * FR + i2] + cx1 * Q1[k * FR + i2];
+            } else {
+                if (hx0) r += (i1 == 0 ? P0[k * FR + i2] : T(0)) + cx0 * Q0[k * FR + i2];
+                if (hx1) r += (i1 == N - 1 ? P1[k * FR + i2] : T(0)) + cx1 * Q1[k * FR + i2];
+            }
             // y faces: tangential (i1, k), layer i2
-            if (hy0) r += (i2 == 0 ? P2[k * FR + i1] : T(0)) + cy0 * Q2[k * FR + i1];
-            if (hy1) r += (i2 == N - 1 ? P3[k * FR + i1] : T(0)) + cy1 * Q3[k * FR + i1];
+            if constexpr (COLLOC) {
+                r += vy0 * P2[k * FR + i1] + cy0 * Q2[k * FR + i1];
+                r += vy1 * P3[k * FR + i1] + cy1 * Q3[k * FR + i1];
+            } else {
+                if (hy0) r += (i2 == 0 ? P2[k * FR + i1] : T(0)) + cy0 * Q2[k * FR + i1];
+                if (hy1) r += (i2 == N - 1 ? P3[k * FR + i1] : T(0)) + cy1 * Q3[k * FR + i1];
+            }
             // z faces: tangential (i1, i2), layer k (compile time)
             if (BASIS != 0 || k <= 1) {
-                if (k == 0) r += P4[i2 * FR + i1];
+                if constexpr (COLLOC) r += fv0[k] * P4[i2 * FR + i1];
+                else if (k == 0) r += P4[i2 * FR + i1];
                 r += df0[k] * Q4[i2 * FR + i1];
             }
             if (BASIS != 0 || k >= N - 2) {
-                if (k == N - 1) r += P5[i2 * FR + i1];
+                if constexpr (COLLOC) r += fv1[k] * P5[i2 * FR + i1];
+                else if (k == N - 1) r += P5[i2 * FR + i1];
                 r += df1[k] * Q5[i2 * FR + i1];
             }
             yc[k * N2] = r;

@@ -45,15 +45,17 @@ template <int N, typename F>
 static int dispatch(int basis, int dtype, int geom, F&& launch) {
     using I0 = std::integral_constant<int, 0>;
     using I1 = std::integral_constant<int, 1>;
+    using I2 = std::integral_constant<int, 2>;
     using GC = std::integral_constant<int, GEOM_CELL>;
     using GQ = std::integral_constant<int, GEOM_QPOINT>;
-    const bool hl = basis == SIPG_BASIS_HERMITE_LIKE, cell = geom == GEOM_CELL;
-    if (dtype == SIPG_F64) {
-        if (hl) return cell ? launch(I0{}, double{}, GC{}) : launch(I0{}, double{}, GQ{});
-        return cell ? launch(I1{}, double{}, GC{}) : launch(I1{}, double{}, GQ{});
-    }
-    if (hl) return cell ? launch(I0{}, float{}, GC{}) : launch(I0{}, float{}, GQ{});
-    return cell ? launch(I1{}, float{}, GC{}) : launch(I1{}, float{}, GQ{});
+    const bool cell = geom == GEOM_CELL;
+    auto by_geom = [&](auto b, auto t) { return cell ? launch(b, t, GC{}) : launch(b, t, GQ{}); };
+    auto by_basis = [&](auto t) {
+        if (basis == SIPG_BASIS_HERMITE_LIKE) return by_geom(I0{}, t);
+        if (basis == SIPG_BASIS_NODAL_GL) return by_geom(I1{}, t);
+        return by_geom(I2{}, t);
+    };
+    return dtype == SIPG_F64 ? by_basis(double{}) : by_basis(float{});
 }
 
 }  // namespace sipg

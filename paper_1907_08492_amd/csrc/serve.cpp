@@ -283,7 +283,7 @@ int sipg_server_create(const sipg_server_opts* opts, sipg_server** out) {
 int sipg_submit(sipg_server* s, const sipg_request* r, uint64_t* ticket) {
     if (!s || !r || !ticket) { set_error("sipg_submit: null argument"); return SIPG_E_ARG; }
     if (r->degree < 1 || r->degree > 8 || r->nmodes < 1 || r->nmodes > 16 || !(r->rel_tol > 0.0) ||
-        r->max_iter < 0 || !(r->penalty_factor > 0.0) || (r->basis != 0 && r->basis != 1)) {
+        r->max_iter < 0 || !(r->penalty_factor > 0.0) || r->basis < 0 || r->basis > 2) {
         set_error("sipg_submit: invalid request");
         return SIPG_E_ARG;
     }

@@ -54,6 +54,18 @@ __device__ __forceinline__ void eo_apply(const T* __restrict__ P, const T* in, T
     }
 }
 
+// An interpolation-type sweep (S or S^T) that is the identity for a basis
+// collocated with the quadrature (nodal Gauss basis, S = I, Section 4.1).
+template <int N, bool IDENTITY, typename T>
+__device__ __forceinline__ void s_apply(const T* __restrict__ P, const T* in, T* out) {
+    if constexpr (IDENTITY) {
+#pragma unroll
+        for (int i = 0; i < N; ++i) out[i] = in[i];
+    } else {
+        eo_apply<N, +1>(P, in, out);
+    }
+}
+
 // Eigenvector transforms of the block preconditioner (Section 6.4) in the
 // parity-split form (basis1d.hpp, fdm_1d): the ceil(n/2) reflection-even
 // eigenvectors z_m store entries 0..h (h = n/2), the odd ones entries

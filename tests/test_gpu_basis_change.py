@@ -82,7 +82,7 @@ def test_pjacobi_requires_diagonal():
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
 @pytest.mark.parametrize("mesh_name", ["brick", "deformed", "affine"])
-@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl", "nodal_gauss"])
 def test_fdm_block_preconditioner(k, mesh_name, basis):
     """SIPG_BC_FDM (fast diagonalization on the device) equals the oracle's
     explicit solve with the Kronecker-sum block of eq. (KDlaplace_dg)."""

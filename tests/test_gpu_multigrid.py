@@ -31,7 +31,7 @@ def test_rhs_sines(k, deform):
 
 
 @pytest.mark.parametrize("k", [1, 2, 4, 7])
-@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl", "nodal_gauss"])
 def test_transfer_matches_oracle(k, basis):
     torch, P = require_gpu()
     banner(f"transfer k={k} {basis}")

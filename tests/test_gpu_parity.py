@@ -40,7 +40,7 @@ def run_apply(torch, P, mesh, k, basis, dtype, x, geometry="auto", eta=2.0):
 
 
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 6, 7, 8])
-@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl", "nodal_gauss"])
 @pytest.mark.parametrize("mesh_name", list(MESHES))
 def test_apply_f64(mesh_name, basis, k):
     torch, P = require_gpu()
@@ -67,7 +67,7 @@ def test_apply_f64_per_point_geometry_on_affine_mesh(mesh_name, k):
 
 
 @pytest.mark.parametrize("k", [1, 3, 4, 5, 7, 8])
-@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl", "nodal_gauss"])
 @pytest.mark.parametrize("mesh_name", ["deformed", "paper_affine"])
 def test_apply_f32(mesh_name, basis, k):
     torch, P = require_gpu()

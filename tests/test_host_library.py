@@ -29,7 +29,7 @@ def test_exports_every_declared_symbol():
     assert set(P.EXPORTED) == set(names)
 
 
-@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl", "nodal_gauss"])
 @pytest.mark.parametrize("k", list(range(1, 9)))
 def test_host_tables_match_oracle(basis, k):
     t = P.host_tables(k, basis)
@@ -112,7 +112,7 @@ def test_single_hip_runtime_in_process():
     assert len(hip) == 1, hip
 
 
-@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl", "nodal_gauss"])
 @pytest.mark.parametrize("k", [1, 2, 3, 4, 5, 7, 8])
 def test_host_fdm_tables_diagonalize_the_oracle_1d_matrices(basis, k):
     """The library's own 1D eigen-decomposition (Cholesky + Jacobi rotations)
