@@ -1,4 +1,5 @@
-"""Nested-mesh embedding used to check the multigrid transfer.
+"""Nested-space embeddings used to check the multigrid transfers: between a
+brick and its coarsening by two (h), and between degrees on one mesh (p).
 
 Test infrastructure (see oracle/__init__.py).  A coarse cell of a brick is
 split into 2 x 2 x 2 children; on child side s of a direction the coarse 1D
@@ -57,3 +58,27 @@ def restrict(fine: np.ndarray, nc_fine, kind: str, k: int) -> np.ndarray:
                 P = np.kron(M[s3], np.kron(M[s2], M[s1]))
                 C += F[s3::2, s2::2, s1::2] @ P
     return C.reshape(-1)
+
+
+def degree_embedding(kind: str, kf: int, kc: int):
+    """E[i, j] with phi^{kc}_j(xi) = sum_i E[i, j] phi^{kf}_i(xi) (kc <= kf):
+    the degree-kc space is a subspace of the degree-kf one.  Least squares on
+    kf + 4 Gauss points (exact: polynomials of degree kf)."""
+    bf = b1d.make_basis(kind, kf)
+    bc = b1d.make_basis(kind, kc)
+    x, _ = b1d.gauss(kf + 4)
+    E, *_ = np.linalg.lstsq(bf.values(x), bc.values(x), rcond=None)
+    return E
+
+
+def p_prolongate(coarse: np.ndarray, ncells: int, kind: str, kf: int, kc: int) -> np.ndarray:
+    """Degree-kf coefficients of a degree-kc function, cell by cell."""
+    E = degree_embedding(kind, kf, kc)
+    P = np.kron(E, np.kron(E, E))
+    return (np.asarray(coarse, dtype=np.float64).reshape(ncells, (kc + 1) ** 3) @ P.T).reshape(-1)
+
+
+def p_restrict(fine: np.ndarray, ncells: int, kind: str, kf: int, kc: int) -> np.ndarray:
+    E = degree_embedding(kind, kf, kc)
+    P = np.kron(E, np.kron(E, E))
+    return (np.asarray(fine, dtype=np.float64).reshape(ncells, (kf + 1) ** 3) @ P).reshape(-1)

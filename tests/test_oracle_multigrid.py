@@ -34,3 +34,23 @@ def test_restriction_is_transpose():
     lhs = omg.prolongate(c, nc, "hermite_like", k) @ f
     rhs = c @ omg.restrict(f, nc, "hermite_like", k)
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("kind", ["hermite_like", "nodal_gl", "nodal_gauss"])
+@pytest.mark.parametrize("kf,kc", [(2, 1), (3, 1), (4, 2), (5, 2), (7, 3), (8, 4), (5, 4)])
+def test_degree_embedding_reproduces_coarse_function(kind, kf, kc):
+    """The degree-kf coefficients from p_prolongate define the same function as
+    the degree-kc ones at random points; restriction is the transpose."""
+    rng = np.random.default_rng(kf * 10 + kc)
+    c = rng.uniform(-1, 1, 2 * (kc + 1) ** 3)
+    f = omg.p_prolongate(c, 2, kind, kf, kc).reshape(2, (kf + 1) ** 3)
+    pts = rng.uniform(0, 1, (40, 3))
+    vf, _ = tensor_eval(b1d.make_basis(kind, kf), pts)
+    vc, _ = tensor_eval(b1d.make_basis(kind, kc), pts)
+    for cell in range(2):
+        ref = vc @ c.reshape(2, -1)[cell]
+        assert np.max(np.abs(vf @ f[cell] - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+    g = rng.uniform(-1, 1, 2 * (kf + 1) ** 3)
+    lhs = omg.p_prolongate(c, 2, kind, kf, kc) @ g
+    rhs = c @ omg.p_restrict(g, 2, kind, kf, kc)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
