@@ -226,6 +226,9 @@ int sipg_launch_shape(int degree, int dtype, int32_t* cells_per_block, int32_t* 
  * Chebyshev iteration (eq. chebyshev) around P^-1 of the form of eq. (jacobi)
  * (point Jacobi in the nodal Gauss-Lobatto basis through the basis change,
  * or the block Jacobi of Section 6.4 by fast diagonalization).  The
+ * Optionally the first levels lower the polynomial degree on the fine mesh
+ * (p_coarsening); the transfer between degrees is the exact embedding of
+ * the lower-degree space and its transpose.  The
  * smoothing range is [range_lo, range_hi] times the largest eigenvalue of
  * P^-1 A estimated by lanczos_steps conjugate-gradient (Lanczos) steps from
  * [-5.5, -4.5, ..., 5.5, -5.5, ...] (Section 6.2); the coarsest level is
@@ -245,6 +248,10 @@ typedef struct {
     int32_t smoother;            /* P^-1 inside the Chebyshev smoother: 0 point Jacobi in the
                                     nodal Gauss-Lobatto basis (SIPG_BC_PJACOBI), 1 the block
                                     Jacobi of Section 6.4 (SIPG_BC_FDM) */
+    int32_t p_coarsening;        /* levels that lower the degree on the fine mesh before the
+                                    mesh is coarsened: 0 none, 1 k -> max(1, k/2), 2 k -> k-1.
+                                    Needed for meshes with odd cell counts, which cannot be
+                                    coarsened by two */
 } sipg_mg_opts;
 typedef struct {
     int32_t levels;
@@ -282,6 +289,8 @@ int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int m
 int sipg_mg_transfer(sipg_mg* mg, int level, int mode, const void* in, void* out, void* stream);
 /* Unknowns and cell counts of a level. */
 int sipg_mg_level_ndofs(const sipg_mg* mg, int level, int64_t* ndofs, int32_t cells[3]);
+/* Polynomial degree of a level (host). */
+int sipg_mg_level_degree(const sipg_mg* mg, int level, int32_t* degree);
 
 /* b_i = sum_K sum_q f(F_K(xi_q)) phi_i(xi_q) det J w_q for
  * f(x) = sum_m amps[m] sin(w[3m] pi x1) sin(w[3m+1] pi x2) sin(w[3m+2] pi x3),
@@ -307,7 +316,9 @@ typedef struct {
     int64_t hbm_budget_bytes;    /* device memory the server may hold (64 GiB) */
     int32_t workers;             /* concurrent solves, 1..16 (4) */
     int32_t precision;           /* 0 mixed FP32 V-cycle, 1 FP64 (0) */
-    int32_t smoother;            /* sipg_mg_opts.smoother of every solve (0) */
+    int32_t smoother;            /* sipg_mg_opts.smoother of every solve (1: block Jacobi) */
+    int32_t p_coarsening;        /* sipg_mg_opts.p_coarsening of every solve (1: halve the
+                                    degree; requests have odd cell counts too) */
 } sipg_server_opts;
 typedef struct {
     sipg_mesh mesh;

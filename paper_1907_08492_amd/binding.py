@@ -47,7 +47,7 @@ EXPORTED = [
     "sipg_server_default_opts", "sipg_server_create", "sipg_submit", "sipg_poll", "sipg_wait",
     "sipg_release", "sipg_server_stats", "sipg_server_destroy", "sipg_copy_device",
     "sipg_batch_create", "sipg_batch_apply", "sipg_batch_get_info", "sipg_batch_destroy",
-    "sipg_host_fdm_tables",
+    "sipg_host_fdm_tables", "sipg_mg_level_degree",
 ]
 
 
@@ -71,7 +71,7 @@ class SipgSolveInfo(C.Structure):
 class SipgMgOpts(C.Structure):
     _fields_ = [("smoother_degree", C.c_int32), ("lanczos_steps", C.c_int32), ("range_lo", C.c_double),
                 ("range_hi", C.c_double), ("coarse_reduction", C.c_double), ("min_coarse_cells", C.c_int32),
-                ("precision", C.c_int32), ("smoother", C.c_int32)]
+                ("precision", C.c_int32), ("smoother", C.c_int32), ("p_coarsening", C.c_int32)]
 
 
 class SipgMgInfo(C.Structure):
@@ -82,7 +82,7 @@ class SipgMgInfo(C.Structure):
 
 class SipgServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("workers", C.c_int32), ("precision", C.c_int32),
-                ("smoother", C.c_int32)]
+                ("smoother", C.c_int32), ("p_coarsening", C.c_int32)]
 
 
 class SipgRequest(C.Structure):
@@ -138,6 +138,7 @@ lib.sipg_mg_apply_vcycle.argtypes = [_vp, _vp, _vp, _vp]
 lib.sipg_mg_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
 lib.sipg_mg_transfer.argtypes = [_vp, C.c_int, C.c_int, _vp, _vp, _vp]
 lib.sipg_mg_level_ndofs.argtypes = [_vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
+lib.sipg_mg_level_degree.argtypes = [_vp, C.c_int, C.POINTER(C.c_int32)]
 lib.sipg_assemble_rhs_sines.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), _vp, _vp]
 lib.sipg_server_default_opts.argtypes = [C.POINTER(SipgServerOpts)]
 lib.sipg_server_create.argtypes = [C.POINTER(SipgServerOpts), C.POINTER(_vp)]
@@ -405,6 +406,11 @@ class Multigrid:
         _check(lib.sipg_mg_level_ndofs(self._h, level, C.byref(n), cells), "sipg_mg_level_ndofs")
         return int(n.value), tuple(cells)
 
+    def level_degree(self, level: int) -> int:
+        d = C.c_int32()
+        _check(lib.sipg_mg_level_degree(self._h, level, C.byref(d)), "sipg_mg_level_degree")
+        return int(d.value)
+
     def transfer(self, level: int, mode: str, x, out, stream=None):
         dt = _torch().float32 if self.precision == "mixed" else _torch().float64
         _check(lib.sipg_mg_transfer(self._h, level, {"prolongate": 0, "restrict": 1}[mode],
@@ -450,13 +456,13 @@ class Server:
     """Continuous-batching request loop of multigrid Poisson solves."""
 
     def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 4, precision: str = "mixed",
-                 smoother: str = "pjacobi"):
+                 smoother: str = "fdm", p_coarsening: int = 1):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Server needs a GPU (HIP device)")
         torch.cuda.init()
         o = SipgServerOpts(int(hbm_budget_bytes), int(workers), {"mixed": 0, "f64": 1}[precision],
-                           SMOOTHERS[smoother])
+                           SMOOTHERS[smoother], int(p_coarsening))
         h = _vp()
         _check(lib.sipg_server_create(C.byref(o), C.byref(h)), "sipg_server_create")
         self._h = h

@@ -301,6 +301,26 @@ bool child_embedding(int kind, int p, std::vector<double>& M0, std::vector<doubl
     return true;
 }
 
+bool degree_embedding(int kind, int pf, int pc, std::vector<double>& E) {
+    const int nf = pf + 1, nc = pc + 1;
+    if (pc > pf || pc < 1) return false;
+    const std::vector<ProductPoly> ff = make_basis(kind, pf), fc = make_basis(kind, pc);
+    const std::vector<double> x = gauss_lobatto_points(nf);   // nf distinct points
+    // V[m][i] = phi^f_i(x_m); C[m][j] = phi^c_j(x_m); E = V^-1 C (nf x nc)
+    std::vector<double> V(nf * nf), Vi;
+    for (int m = 0; m < nf; ++m)
+        for (int i = 0; i < nf; ++i) V[m * nf + i] = ff[i].value(x[m]);
+    if (!invert(nf, V, Vi)) return false;
+    E.assign(nf * nc, 0.0);
+    for (int i = 0; i < nf; ++i)
+        for (int j = 0; j < nc; ++j) {
+            double acc = 0.0;
+            for (int m = 0; m < nf; ++m) acc += Vi[i * nf + m] * fc[j].value(x[m]);
+            E[i * nc + j] = acc;
+        }
+    return true;
+}
+
 // Generalized symmetric-definite eigenproblem L y = lambda M y of size m
 // (row major): Cholesky M = C C^T, the symmetric C^-1 L C^-T diagonalized by
 // cyclic Jacobi rotations, y = C^-T (rotations).  Columns of Y are the

@@ -45,6 +45,11 @@ bool build_tables(int kind, int p, Tables1D& t);
 // (row major, n x n).  Exact: both sides are polynomials of degree p.
 bool child_embedding(int kind, int p, std::vector<double>& M0, std::vector<double>& M1);
 
+// Embedding of the degree-pc space into the degree-pf space (pc <= pf) of
+// the same basis kind on one interval: phi^pc_j = sum_i E[i][j] phi^pf_i
+// (row major, (pf+1) x (pc+1)).  Exact: interpolation in pf+1 points.
+bool degree_embedding(int kind, int pf, int pc, std::vector<double>& E);
+
 // 1D matrices of the separable block preconditioner of Section 6.4 (eq.
 // KDlaplace_dg) on the unit interval, penalty eta (p+1)^2, interior element:
 // generalized eigenvectors (rows of Zt) and eigenvalues of L z = lambda M z,

@@ -77,12 +77,45 @@ template <typename T>
 struct Level {
     sipg_op* op = nullptr;
     int nc[3] = {0, 0, 0};
-    int64_t n = 0;
+    int np = 0;                         // degree + 1
+    int next = 0;                       // transfer to level l+1: 0 mesh coarsening, 1 lower degree
+    int64_t n = 0;                      // unknowns
     DevBuf<T> b, u, uo, r, z;
+    DevBuf<T> emb;                      // h: child embedding M_0, M_1; p: E then E^T
     double lmin = 0.0, lmax = 0.0;
     std::vector<double> sigma, theta;   // Chebyshev coefficients per step
+    int64_t ncells() const { return int64_t(nc[0]) * nc[1] * nc[2]; }
     ~Level() { if (op) sipg_destroy(op); }
 };
+
+// Level sequence of the hierarchy: first the degree is lowered on the fine
+// mesh (p_coarsening 1: k -> max(1, k/2); 2: k -> k-1), then the brick is
+// coarsened by two while every cell count is even and at least
+// min_coarse_cells coarse cells remain (at most 16 levels).
+struct LevelSpec {
+    int nc[3];
+    int degree;
+    int next;
+};
+std::vector<LevelSpec> mg_level_sequence(const int n[3], int degree, const sipg_mg_opts& o) {
+    std::vector<LevelSpec> seq;
+    LevelSpec cur{{n[0], n[1], n[2]}, degree, 0};
+    for (;;) {
+        seq.push_back(cur);
+        if (seq.size() >= 16) break;
+        if (o.p_coarsening != 0 && cur.degree > 1) {
+            seq.back().next = 1;
+            cur.degree = o.p_coarsening == 1 ? std::max(1, cur.degree / 2) : cur.degree - 1;
+            continue;
+        }
+        const bool can = cur.nc[0] % 2 == 0 && cur.nc[1] % 2 == 0 && cur.nc[2] % 2 == 0 &&
+                         int64_t(cur.nc[0] / 2) * (cur.nc[1] / 2) * (cur.nc[2] / 2) >= o.min_coarse_cells;
+        if (!can) break;
+        seq.back().next = 0;
+        for (int d = 0; d < 3; ++d) cur.nc[d] /= 2;
+    }
+    return seq;
+}
 
 struct Scratch {
     DevBuf<double> partial, scal;
@@ -126,8 +159,6 @@ static void chebyshev_coefficients(double a, double b, int m, std::vector<double
 template <typename T>
 struct Hierarchy {
     std::vector<std::unique_ptr<Level<T>>> lv;
-    DevBuf<T> emb;   // M_0, M_1 of the child embedding (n x n each)
-    int n = 0;
     int smooth_steps = 5;
     int coarse_steps = 1;
     int pmode = SIPG_BC_PJACOBI;   // P^-1 of the smoother: SIPG_BC_PJACOBI or SIPG_BC_FDM
@@ -163,11 +194,25 @@ struct Hierarchy {
         if ((rc = smooth(l, true, smooth_steps, L.sigma, L.theta, st)) != SIPG_OK) return rc;
         if ((rc = launch_matvec(L.op, L.u.p, L.r.p, st)) != SIPG_OK) return rc;
         if ((rc = vec_sub<T>(L.b.p, L.r.p, L.r.p, L.n, st)) != SIPG_OK) return rc;
-        Level<T>& C = *lv[l + 1];
-        if ((rc = transfer_restrict<T>(n, L.nc, L.r.p, C.b.p, emb.p, st)) != SIPG_OK) return rc;
+        if ((rc = restrict_to(l, L.r.p, lv[l + 1]->b.p, st)) != SIPG_OK) return rc;
         if ((rc = vcycle(l + 1, st)) != SIPG_OK) return rc;
-        if ((rc = transfer_prolongate_add<T>(n, L.nc, C.u.p, L.u.p, emb.p, st)) != SIPG_OK) return rc;
+        if ((rc = prolongate_add(l, lv[l + 1]->u.p, L.u.p, st)) != SIPG_OK) return rc;
         return smooth(l, false, smooth_steps, L.sigma, L.theta, st);
+    }
+
+    // coarse = R fine  from level l to level l+1
+    int restrict_to(int l, const T* fine, T* coarse, hipStream_t st) {
+        Level<T>& L = *lv[l];
+        const Level<T>& C = *lv[l + 1];
+        if (L.next == 0) return transfer_restrict<T>(L.np, L.nc, fine, coarse, L.emb.p, st);
+        return transfer_degree<T>(L.np, C.np, L.ncells(), true, fine, coarse, L.emb.p, L.emb.p + L.np * C.np, st);
+    }
+    // fine += P coarse  from level l+1 to level l
+    int prolongate_add(int l, const T* coarse, T* fine, hipStream_t st) {
+        Level<T>& L = *lv[l];
+        const Level<T>& C = *lv[l + 1];
+        if (L.next == 0) return transfer_prolongate_add<T>(L.np, L.nc, coarse, fine, L.emb.p, st);
+        return transfer_degree<T>(L.np, C.np, L.ncells(), false, coarse, fine, L.emb.p, L.emb.p + L.np * C.np, st);
     }
 
     // Extreme eigenvalues of P^-1 A on level l from `steps` conjugate gradient
@@ -240,6 +285,24 @@ struct sipg_mg {
 };
 
 namespace sipg {
+// Device bytes of a solver for (mesh, degree) with options o: the FP64 fine
+// operator and CG vectors plus, per level, metric terms, block-preconditioner
+// scalars, the GL diagonal and five level vectors.
+int64_t mg_estimate_bytes(const sipg_mesh& mesh, int degree, const sipg_mg_opts& o) {
+    const bool deformed = mesh.deform_amp != 0.0;
+    auto geo = [&](int n) -> int64_t { return (deformed ? int64_t(6 * n * n * n + 3 * 7 * n * n) : 32) + 4; };
+    const int esz = o.precision == 0 ? 4 : 8;
+    const int n0 = degree + 1;
+    const int64_t cells0 = int64_t(mesh.n[0]) * mesh.n[1] * mesh.n[2];
+    int64_t bytes = 8 * (geo(n0) * cells0 + 6 * cells0 * n0 * n0 * n0) + (int64_t(1) << 20);
+    for (const LevelSpec& sp : mg_level_sequence(mesh.n, degree, o)) {
+        const int n = sp.degree + 1;
+        const int64_t cells = int64_t(sp.nc[0]) * sp.nc[1] * sp.nc[2];
+        bytes += esz * (geo(n) * cells + 6 * cells * n * n * n) + 4096 * 8;
+    }
+    return bytes;
+}
+
 sipg_op* mg_fine_operator(sipg_mg* mg) { return mg->fine64; }
 double* mg_rhs_buffer(sipg_mg* mg) { return mg->wb.p; }
 double mg_last_rhs_norm(const sipg_mg* mg) { return mg->last_bnorm; }
@@ -249,35 +312,52 @@ template <typename T>
 static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, int degree, double penalty,
                            int basis, const sipg_mg_opts& o, hipStream_t st) {
     const int dt = std::is_same<T, double>::value ? SIPG_F64 : SIPG_F32;
-    int nc[3] = {mesh->n[0], mesh->n[1], mesh->n[2]};
-    H.n = degree + 1;
     H.smooth_steps = o.smoother_degree;
     H.pmode = o.smoother == 1 ? SIPG_BC_FDM : SIPG_BC_PJACOBI;
-    for (;;) {
+    const std::vector<LevelSpec> seq = mg_level_sequence(mesh->n, degree, o);
+    int rc;
+    for (size_t l = 0; l < seq.size(); ++l) {
+        const LevelSpec& sp = seq[l];
         auto L = std::make_unique<Level<T>>();
         sipg_mesh m = *mesh;
-        for (int d = 0; d < 3; ++d) { m.n[d] = nc[d]; L->nc[d] = nc[d]; }
-        int rc = sipg_setup(&m, degree, penalty, basis, dt, SIPG_GEOM_AUTO, st, &L->op);
-        if (rc != SIPG_OK) return rc;
+        for (int d = 0; d < 3; ++d) { m.n[d] = sp.nc[d]; L->nc[d] = sp.nc[d]; }
+        L->np = sp.degree + 1;
+        L->next = sp.next;
+        if ((rc = sipg_setup(&m, sp.degree, penalty, basis, dt, SIPG_GEOM_AUTO, st, &L->op)) != SIPG_OK) return rc;
         if (H.pmode == SIPG_BC_PJACOBI && (rc = sipg_compute_gl_diagonal(L->op, nullptr, st)) != SIPG_OK) return rc;
         L->n = L->op->ndofs;
         if ((rc = L->b.alloc(L->n)) || (rc = L->u.alloc(L->n)) || (rc = L->uo.alloc(L->n)) ||
             (rc = L->r.alloc(L->n)) || (rc = L->z.alloc(L->n)))
             return rc;
+        // transfer matrices to the next level
+        if (l + 1 < seq.size()) {
+            std::vector<T> e;
+            if (sp.next == 0) {
+                std::vector<double> M0, M1;
+                if (!child_embedding(basis, sp.degree, M0, M1)) { set_error("multigrid: singular embedding"); return SIPG_E_ARG; }
+                const int nn = L->np * L->np;
+                e.resize(2 * nn);
+                for (int i = 0; i < nn; ++i) { e[i] = T(M0[i]); e[nn + i] = T(M1[i]); }
+            } else {
+                std::vector<double> E;
+                const int nf = L->np, ncd = seq[l + 1].degree + 1;
+                if (!degree_embedding(basis, sp.degree, seq[l + 1].degree, E)) {
+                    set_error("multigrid: singular degree embedding");
+                    return SIPG_E_ARG;
+                }
+                e.resize(2 * nf * ncd);
+                for (int i = 0; i < nf; ++i)
+                    for (int j = 0; j < ncd; ++j) {
+                        e[i * ncd + j] = T(E[i * ncd + j]);               // E  (nf x nc)
+                        e[nf * ncd + j * nf + i] = T(E[i * ncd + j]);     // E^T (nc x nf)
+                    }
+            }
+            if ((rc = L->emb.alloc(int64_t(e.size()))) != SIPG_OK) return rc;
+            SIPG_HIP(hipMemcpyAsync(L->emb.p, e.data(), sizeof(T) * e.size(), hipMemcpyHostToDevice, st));
+            SIPG_HIP(hipStreamSynchronize(st));
+        }
         H.lv.push_back(std::move(L));
-        const bool can = nc[0] % 2 == 0 && nc[1] % 2 == 0 && nc[2] % 2 == 0 &&
-                         int64_t(nc[0] / 2) * (nc[1] / 2) * (nc[2] / 2) >= o.min_coarse_cells;
-        if (!can || int(H.lv.size()) >= 16) break;
-        for (int d = 0; d < 3; ++d) nc[d] /= 2;
     }
-    // embedding matrices
-    std::vector<double> M0, M1;
-    if (!child_embedding(basis, degree, M0, M1)) { set_error("multigrid: singular embedding"); return SIPG_E_ARG; }
-    std::vector<T> e(2 * H.n * H.n);
-    for (int i = 0; i < H.n * H.n; ++i) { e[i] = T(M0[i]); e[H.n * H.n + i] = T(M1[i]); }
-    int rc;
-    if ((rc = H.emb.alloc(int64_t(e.size()))) != SIPG_OK) return rc;
-    SIPG_HIP(hipMemcpyAsync(H.emb.p, e.data(), sizeof(T) * e.size(), hipMemcpyHostToDevice, st));
     // eigenvalue estimates and Chebyshev coefficients
     for (size_t l = 0; l < H.lv.size(); ++l) {
         const bool coarsest = l + 1 == H.lv.size();
@@ -326,6 +406,7 @@ int sipg_mg_default_opts(sipg_mg_opts* o) {
     o->min_coarse_cells = 1;
     o->precision = 0;
     o->smoother = 0;
+    o->p_coarsening = 0;
     return SIPG_OK;
 }
 
@@ -338,7 +419,7 @@ int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, 
     if (opts) o = *opts;
     if (o.smoother_degree < 1 || o.smoother_degree > 64 || o.lanczos_steps < 2 || !(o.range_lo > 0.0) ||
         !(o.range_hi > o.range_lo) || !(o.coarse_reduction > 1.0) || (o.precision != 0 && o.precision != 1) ||
-        o.min_coarse_cells < 1 || (o.smoother != 0 && o.smoother != 1)) {
+        o.min_coarse_cells < 1 || (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2) {
         set_error("sipg_mg_setup: invalid options");
         return SIPG_E_ARG;
     }
@@ -461,13 +542,11 @@ int sipg_mg_transfer(sipg_mg* mg, int level, int mode, const void* in, void* out
     }
     hipStream_t st = static_cast<hipStream_t>(stream);
     auto run = [&](auto& H) -> int {
-        using T = typename std::remove_reference<decltype(*H.emb.p)>::type;
+        using T = typename std::remove_reference<decltype(*H.lv[0]->emb.p)>::type;
         auto& L = *H.lv[level];
-        auto& C = *H.lv[level + 1];
-        if (mode == 1) return transfer_restrict<T>(H.n, L.nc, static_cast<const T*>(in), static_cast<T*>(out), H.emb.p, st);
+        if (mode == 1) return H.restrict_to(level, static_cast<const T*>(in), static_cast<T*>(out), st);
         SIPG_HIP(hipMemsetAsync(out, 0, sizeof(T) * size_t(L.n), st));
-        (void)C;
-        return transfer_prolongate_add<T>(H.n, L.nc, static_cast<const T*>(in), static_cast<T*>(out), H.emb.p, st);
+        return H.prolongate_add(level, static_cast<const T*>(in), static_cast<T*>(out), st);
     };
     return mg->precision == 0 ? run(mg->h32) : run(mg->h64);
 }
@@ -480,6 +559,12 @@ int sipg_mg_level_ndofs(const sipg_mg* mg, int level, int64_t* ndofs, int32_t ce
         if (cells) for (int d = 0; d < 3; ++d) cells[d] = L.nc[d];
     };
     if (mg->precision == 0) get(mg->h32); else get(mg->h64);
+    return SIPG_OK;
+}
+
+int sipg_mg_level_degree(const sipg_mg* mg, int level, int32_t* degree) {
+    if (!mg || !degree || level < 0 || level >= mg->levels) { set_error("sipg_mg_level_degree: bad argument"); return SIPG_E_ARG; }
+    *degree = mg->precision == 0 ? mg->h32.lv[level]->np - 1 : mg->h64.lv[level]->np - 1;
     return SIPG_OK;
 }
 

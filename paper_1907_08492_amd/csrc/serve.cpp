@@ -96,17 +96,17 @@ static Key make_key(const sipg_request& r, int precision) {
 // Upper estimate of a hierarchy's device memory before it exists: the FP64
 // fine operator, the V-cycle levels (8/7 of the fine size) with five vectors
 // each, and the metric terms (per point on deformed meshes).
-static int64_t estimate_hierarchy_bytes(const sipg_request& r, int precision) {
-    const int n = r.degree + 1;
-    const int64_t cells = int64_t(r.mesh.n[0]) * r.mesh.n[1] * r.mesh.n[2];
-    const int64_t dofs = cells * n * n * n;
-    const bool deformed = r.mesh.deform_amp != 0.0;
-    const int esz = precision == 0 ? 4 : 8;
-    // metric terms plus the four cell scalars of the block preconditioner
-    const int64_t geo_per_cell = (deformed ? int64_t(6 * n * n * n + 3 * 7 * n * n) : 32) + 4;
-    const int64_t fine64 = 8 * (geo_per_cell * cells + 6 * dofs);        // geometry, rhs and CG vectors
-    const int64_t levels = (esz * (geo_per_cell * cells + 6 * dofs)) * 8 / 7 + 4096 * 8;
-    return fine64 + levels + (int64_t(1) << 20);
+static sipg_mg_opts solver_opts(const sipg_server_opts& so) {
+    sipg_mg_opts o;
+    sipg_mg_default_opts(&o);
+    o.precision = so.precision;
+    o.smoother = so.smoother;
+    o.p_coarsening = so.p_coarsening;
+    return o;
+}
+
+static int64_t estimate_hierarchy_bytes(const sipg_request& r, const sipg_server_opts& so) {
+    return mg_estimate_bytes(r.mesh, r.degree, solver_opts(so));
 }
 
 static void finish_job(sipg_server* s, Job* j, int status) {
@@ -131,7 +131,7 @@ static Job* admit(sipg_server* s) {
         for (auto c = range.first; c != range.second; ++c)
             if (!c->second.busy) { cached = true; break; }
         const int64_t vec_bytes = j->req.x_out ? 0 : 8 * j->ndofs;   // server-owned solution
-        const int64_t need = vec_bytes + (cached ? 0 : estimate_hierarchy_bytes(j->req, s->opts.precision));
+        const int64_t need = vec_bytes + (cached ? 0 : estimate_hierarchy_bytes(j->req, s->opts));
         // evict idle hierarchies (least recently used first) until it fits
         while (s->used_bytes + need > s->opts.hbm_budget_bytes) {
             auto victim = s->cache.end();
@@ -176,10 +176,7 @@ static void worker_main(sipg_server* s) {
         int status = SIPG_OK;
         int64_t built_bytes = 0;
         if (!mg) {
-            sipg_mg_opts o;
-            sipg_mg_default_opts(&o);
-            o.precision = s->opts.precision;
-            o.smoother = s->opts.smoother;
+            const sipg_mg_opts o = solver_opts(s->opts);
             status = sipg_mg_setup(&j->req.mesh, j->req.degree, j->req.penalty_factor, j->req.basis, &o, st, &mg);
             if (status == SIPG_OK) {
                 sipg_mg_info info;
@@ -246,7 +243,8 @@ int sipg_server_default_opts(sipg_server_opts* o) {
     o->hbm_budget_bytes = int64_t(64) << 30;
     o->workers = 4;
     o->precision = 0;
-    o->smoother = 0;
+    o->smoother = 1;
+    o->p_coarsening = 1;
     return SIPG_OK;
 }
 
@@ -257,7 +255,7 @@ int sipg_server_create(const sipg_server_opts* opts, sipg_server** out) {
     sipg_server_default_opts(&o);
     if (opts) o = *opts;
     if (o.workers < 1 || o.workers > 16 || o.hbm_budget_bytes <= 0 || (o.precision != 0 && o.precision != 1) ||
-        (o.smoother != 0 && o.smoother != 1)) {
+        (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2) {
         set_error("sipg_server_create: workers in [1,16], budget > 0, precision and smoother 0 or 1");
         return SIPG_E_ARG;
     }
@@ -294,7 +292,7 @@ int sipg_submit(sipg_server* s, const sipg_request* r, uint64_t* ticket) {
     j->key = make_key(*r, s->opts.precision);
     const int n = r->degree + 1;
     j->ndofs = int64_t(r->mesh.n[0]) * r->mesh.n[1] * r->mesh.n[2] * n * n * n;
-    const int64_t need = estimate_hierarchy_bytes(*r, s->opts.precision) + 3 * 8 * j->ndofs;
+    const int64_t need = estimate_hierarchy_bytes(*r, s->opts) + 3 * 8 * j->ndofs;
     if (need > s->opts.hbm_budget_bytes) {
         set_error("sipg_submit: the request alone exceeds the memory budget");
         return SIPG_E_BUDGET;

@@ -47,6 +47,9 @@ int launch_gl_diagonal(const sipg_op* op, void* diag, hipStream_t st);
 int cg_solve_device(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
                     sipg_solve_info* info, hipStream_t st);
 
+// Device bytes a multigrid solver for this problem will hold.
+int64_t mg_estimate_bytes(const sipg_mesh& mesh, int degree, const sipg_mg_opts& o);
+
 // Accessors of the multigrid solver used by the request loop.
 sipg_op* mg_fine_operator(sipg_mg* mg);
 double* mg_rhs_buffer(sipg_mg* mg);

@@ -194,6 +194,73 @@ int transfer_restrict(int n, const int nf[3], const T* fine, T* coarse, const T*
     return SIPG_OK;
 }
 
+// Transfer between two degrees on the same mesh (p-multigrid): per cell
+// out (+)= (M x M x M) in with a rectangular 1D matrix M (NO x NI, row major):
+// M = E (prolongation, degree embedding) or E^T (restriction).  One
+// workgroup of 64 threads per cell; three sweeps through LDS.
+template <int NI, int NO, typename T, bool ADD>
+__global__ void __launch_bounds__(64)
+ptransfer_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ M) {
+    constexpr int I3 = NI * NI * NI, B = NI * NI * NO, C = NI * NO * NO, O3 = NO * NO * NO;
+    __shared__ T a[I3];
+    __shared__ T b[B];
+    __shared__ T c[C];
+    const size_t cell = blockIdx.x;
+    const int tid = threadIdx.x;
+    for (int e = tid; e < I3; e += 64) a[e] = in[cell * I3 + e];
+    __syncthreads();
+    for (int e = tid; e < B; e += 64) {   // b[i3][i2][o1]
+        const int o1 = e % NO, r = e / NO;
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc = fma(M[o1 * NI + i], a[r * NI + i], acc);
+        b[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < C; e += 64) {   // c[i3][o2][o1]
+        const int o1 = e % NO, o2 = (e / NO) % NO, i3 = e / (NO * NO);
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc = fma(M[o2 * NI + i], b[(i3 * NI + i) * NO + o1], acc);
+        c[e] = acc;
+    }
+    __syncthreads();
+    for (int e = tid; e < O3; e += 64) {  // out[o3][o2][o1]
+        const int r = e % (NO * NO), o3 = e / (NO * NO);
+        T acc = T(0);
+#pragma unroll
+        for (int i = 0; i < NI; ++i) acc = fma(M[o3 * NI + i], c[i * NO * NO + r], acc);
+        if constexpr (ADD) out[cell * O3 + e] += acc;
+        else out[cell * O3 + e] = acc;
+    }
+}
+
+// Degree pairs (fine n, coarse n) of the two coarsening rules: halving the
+// degree (k -> max(1, k/2)) and lowering it by one.
+#define SIPG_PAIRS(X)                                                                     \
+    X(3, 2) X(4, 2) X(4, 3) X(5, 3) X(5, 4) X(6, 3) X(6, 4) X(6, 5) X(7, 4) X(7, 6) X(8, 4) \
+    X(8, 5) X(8, 7) X(9, 5) X(9, 8)
+
+template <typename T>
+int transfer_degree(int nf, int nc, int64_t ncells, bool restrict_, const T* in, T* out, const T* E,
+                    const T* Et, hipStream_t st) {
+    const unsigned g = unsigned(ncells);
+#define SIPG_PCASE(F, C)                                                                     \
+    if (nf == F && nc == C) {                                                                \
+        if (restrict_) ptransfer_kernel<F, C, T, false><<<g, 64, 0, st>>>(in, out, Et);      \
+        else ptransfer_kernel<C, F, T, true><<<g, 64, 0, st>>>(in, out, E);                  \
+        SIPG_HIP(hipGetLastError());                                                         \
+        return SIPG_OK;                                                                      \
+    }
+    SIPG_PAIRS(SIPG_PCASE)
+#undef SIPG_PCASE
+    set_error("transfer: unsupported pair of degrees");
+    return SIPG_E_UNSUPPORTED;
+}
+
+template int transfer_degree<float>(int, int, int64_t, bool, const float*, float*, const float*, const float*, hipStream_t);
+template int transfer_degree<double>(int, int, int64_t, bool, const double*, double*, const double*, const double*, hipStream_t);
+
 template int transfer_prolongate_add<float>(int, const int[3], const float*, float*, const float*, hipStream_t);
 template int transfer_prolongate_add<double>(int, const int[3], const double*, double*, const double*, hipStream_t);
 template int transfer_restrict<float>(int, const int[3], const float*, float*, const float*, hipStream_t);

@@ -23,5 +23,10 @@ template <typename T>
 int transfer_prolongate_add(int n, const int nc_fine[3], const T* coarse, T* fine, const T* emb, hipStream_t st);
 template <typename T>
 int transfer_restrict(int n, const int nc_fine[3], const T* fine, T* coarse, const T* emb, hipStream_t st);
+// Between degrees on one mesh: restriction out = (E^T)^{x3} in (Et: nc x nf),
+// or prolongation out += E^{x3} in (E: nf x nc); nf, nc = degree + 1.
+template <typename T>
+int transfer_degree(int nf, int nc, int64_t ncells, bool restrict_, const T* in, T* out, const T* E, const T* Et,
+                    hipStream_t st);
 
 }  // namespace sipg

@@ -168,3 +168,87 @@ def test_vcycle_with_block_jacobi_is_symmetric_in_fp64():
     rhs = float(torch.dot(a, mg.vcycle(b)))
     assert abs(lhs - rhs) <= 1e-10 * abs(lhs), (lhs, rhs)
     mg.close()
+
+
+@pytest.mark.parametrize("rule,degrees", [(1, [5, 2, 1]), (2, [4, 3, 2, 1])])
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl"])
+def test_degree_transfer_matches_oracle(rule, degrees, basis):
+    """Levels that lower the degree on an odd mesh (no mesh coarsening is
+    possible): prolongation and restriction between degrees equal the oracle's
+    embedding and its transpose."""
+    torch, P = require_gpu()
+    banner(f"degree transfer rule={rule} {basis}")
+    mesh = unit_cube((3, 2, 3), 0.1)
+    mg = P.Multigrid(mesh, degrees[0], 2.0, basis, precision="f64", lanczos_steps=4, p_coarsening=rule)
+    assert mg.info.levels == len(degrees)
+    assert [mg.level_degree(l) for l in range(len(degrees))] == degrees
+    rng = np.random.default_rng(rule)
+    for l in range(len(degrees) - 1):
+        kf, kc = degrees[l], degrees[l + 1]
+        nf, _ = mg.level(l)
+        nc, cells = mg.level(l + 1)
+        assert cells == (3, 2, 3)
+        c = rng.uniform(-1, 1, nc)
+        f = rng.uniform(-1, 1, nf)
+        out_f = torch.empty(nf, dtype=torch.float64, device="cuda")
+        out_c = torch.empty(nc, dtype=torch.float64, device="cuda")
+        pf = mg.transfer(l, "prolongate", torch.from_numpy(c).cuda(), out_f).cpu().numpy()
+        rc = mg.transfer(l, "restrict", torch.from_numpy(f).cuda(), out_c).cpu().numpy()
+        e = rel_errors(pf, omg.p_prolongate(c, mesh.ncells, basis, kf, kc))
+        assert e[0] < 1e-12 and e[1] < 1e-12, (l, e)
+        e = rel_errors(rc, omg.p_restrict(f, mesh.ncells, basis, kf, kc))
+        assert e[0] < 1e-12 and e[1] < 1e-12, (l, e)
+    mg.close()
+
+
+def test_degree_then_mesh_levels():
+    """p levels first, then mesh coarsening at the lowest degree; the mesh
+    transfer of that level matches the oracle at degree 1."""
+    torch, P = require_gpu()
+    banner("p then h levels")
+    mesh = unit_cube((4, 2, 6), 0.1)
+    mg = P.Multigrid(mesh, 3, 2.0, precision="f64", lanczos_steps=4, p_coarsening=1)
+    assert [mg.level_degree(l) for l in range(mg.info.levels)] == [3, 1, 1]
+    assert mg.level(2)[1] == (2, 1, 3)
+    nc, _ = mg.level(2)
+    c = np.random.default_rng(9).uniform(-1, 1, nc)
+    nf, _ = mg.level(1)
+    out_f = torch.empty(nf, dtype=torch.float64, device="cuda")
+    pf = mg.transfer(1, "prolongate", torch.from_numpy(c).cuda(), out_f).cpu().numpy()
+    e = rel_errors(pf, omg.prolongate(c, (4, 2, 6), "hermite_like", 1))
+    assert e[0] < 1e-12 and e[1] < 1e-12, e
+    mg.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "f64"])
+@pytest.mark.parametrize("rule", [1, 2])
+def test_mg_solve_odd_mesh_with_degree_levels(precision, rule):
+    """7^3 cells (odd: no mesh coarsening) with degree levels converges to
+    1e-10 in few iterations and gives the oracle's discrete solution."""
+    torch, P = require_gpu()
+    banner(f"mg solve odd mesh rule={rule} {precision}")
+    mesh = unit_cube(7, 0.1)
+    ref = SIPG(mesh, 4, 2.0)
+    b = mms.rhs(ref, mms.sine_rhs)
+    mg = P.Multigrid(mesh, 4, 2.0, precision=precision, p_coarsening=rule)
+    x, info = mg.solve(torch.from_numpy(b).cuda(), rel_tol=1e-10)
+    xs = x.cpu().numpy()
+    r = b - ref.apply_naive(xs)
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-10
+    assert info.iterations <= 25, info.iterations
+    assert mg.info.coarse_steps < 400, mg.info.coarse_steps
+    mg.close()
+
+
+def test_vcycle_with_degree_levels_is_symmetric_in_fp64():
+    torch, P = require_gpu()
+    banner("vcycle symmetry p levels")
+    mesh = unit_cube((4, 4, 2), 0.1)
+    mg = P.Multigrid(mesh, 5, 2.0, precision="f64", p_coarsening=1)
+    rng = np.random.default_rng(6)
+    a = torch.from_numpy(rng.uniform(-1, 1, mg.ndofs)).cuda()
+    b = torch.from_numpy(rng.uniform(-1, 1, mg.ndofs)).cuda()
+    lhs = float(torch.dot(b, mg.vcycle(a)))
+    rhs = float(torch.dot(a, mg.vcycle(b)))
+    assert abs(lhs - rhs) <= 1e-10 * abs(lhs), (lhs, rhs)
+    mg.close()
