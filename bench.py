@@ -228,7 +228,7 @@ def solver_benchmark(torch, P, reps: int = 3):
     return out
 
 
-def serve_benchmark(P, precision: str, seconds: float, rate: float, workers: int = 4,
+def serve_benchmark(P, precision: str, seconds: float, rate: float, workers: int = 8,
                     budget_bytes: int = 96 << 30, tol: float = 1e-8):
     """Poisson arrivals of multigrid Poisson solves (unit cube n^3, n log-uniform
     in [8, 48], k in {3, 4, 5}, 8 random sine modes, tolerance 1e-8) served by
@@ -300,7 +300,7 @@ def main():
     ap.add_argument("--serve-seconds", type=float, default=1.0,
                     help="arrival window of the serving leg (0 skips it; 60 is the full stream)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
-    ap.add_argument("--serve-workers", type=int, default=4)
+    ap.add_argument("--serve-workers", type=int, default=8)
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "

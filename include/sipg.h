@@ -314,7 +314,7 @@ int sipg_assemble_rhs_sines(const sipg_op* op, int nmodes, const double* amps, c
  */
 typedef struct {
     int64_t hbm_budget_bytes;    /* device memory the server may hold (64 GiB) */
-    int32_t workers;             /* concurrent solves, 1..16 (4) */
+    int32_t workers;             /* concurrent solves, 1..16 (8) */
     int32_t precision;           /* 0 mixed FP32 V-cycle, 1 FP64 (0) */
     int32_t smoother;            /* sipg_mg_opts.smoother of every solve (1: block Jacobi) */
     int32_t p_coarsening;        /* sipg_mg_opts.p_coarsening of every solve (1: halve the

@@ -455,7 +455,7 @@ def _result_dict(r: SipgResult) -> dict:
 class Server:
     """Continuous-batching request loop of multigrid Poisson solves."""
 
-    def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 4, precision: str = "mixed",
+    def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 8, precision: str = "mixed",
                  smoother: str = "fdm", p_coarsening: int = 1):
         torch = _torch()
         if not torch.cuda.is_available():

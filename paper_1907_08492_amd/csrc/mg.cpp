@@ -117,15 +117,30 @@ std::vector<LevelSpec> mg_level_sequence(const int n[3], int degree, const sipg_
     return seq;
 }
 
+// Lanczos steps are bounded so that their coefficients fit the scratch.
+constexpr int kMaxLanczos = 512;
+
 struct Scratch {
-    DevBuf<double> partial, scal;
+    DevBuf<double> partial, scal, coef;
     double* host = nullptr;
     ~Scratch() { if (host) (void)hipHostFree(host); }
     int init() {
         int rc;
         if ((rc = partial.alloc(kVecPartials)) != SIPG_OK) return rc;
         if ((rc = scal.alloc(8)) != SIPG_OK) return rc;
+        if ((rc = coef.alloc(2 * kMaxLanczos)) != SIPG_OK) return rc;
         SIPG_HIP(hipHostMalloc(&host, sizeof(double) * 8, hipHostMallocDefault));
+        return SIPG_OK;
+    }
+    // scal[slot] = a . b on the device (no host synchronisation)
+    template <typename T>
+    int dot_dev(const T* a, const T* b, int64_t n, int slot, hipStream_t st) {
+        return vec_dot_async<T>(a, b, partial.p, scal.p + slot, n, st);
+    }
+    int read(int slot, double& out, hipStream_t st) {
+        SIPG_HIP(hipMemcpyAsync(host, scal.p + slot, sizeof(double), hipMemcpyDeviceToHost, st));
+        SIPG_HIP(hipStreamSynchronize(st));
+        out = host[0];
         return SIPG_OK;
     }
     template <typename T>
@@ -217,33 +232,47 @@ struct Hierarchy {
 
     // Extreme eigenvalues of P^-1 A on level l from `steps` conjugate gradient
     // (Lanczos) steps started from the vector [-5.5, -4.5, ..., 5.5, ...].
+    // The CG coefficients stay on the device (scalar slots 0: r.z, 1: p.Ap,
+    // 2: new r.z) and are read once at the end.
     int lanczos(int l, int steps, Scratch& sc, hipStream_t st) {
         Level<T>& L = *lv[l];
         std::vector<T> h(L.n);
         for (int64_t i = 0; i < L.n; ++i) h[i] = T(-5.5 + double(i % 12));
         SIPG_HIP(hipMemcpyAsync(L.r.p, h.data(), sizeof(T) * L.n, hipMemcpyHostToDevice, st));
-        // x = 0, r = b; z = P^-1 r; p = z  (p in uo, Ap in b)
+        steps = std::min(steps, kMaxLanczos);
+        double* da = sc.coef.p;               // alpha_k
+        double* db = sc.coef.p + steps;       // beta_k
         int rc;
+        double* s_rz = sc.scal.p;
+        double* s_pap = sc.scal.p + 1;
+        double* s_rzn = sc.scal.p + 2;
+        // x = 0, r = b; z = P^-1 r; p = z  (p in uo, Ap in b)
         if ((rc = launch_basis_change(L.op, pmode, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
         SIPG_HIP(hipMemcpyAsync(L.uo.p, L.z.p, sizeof(T) * L.n, hipMemcpyDeviceToDevice, st));
-        double rz;
-        if ((rc = sc.dot<T>(L.r.p, L.z.p, L.n, rz, st)) != SIPG_OK) return rc;
-        std::vector<double> alpha, beta;
-        for (int k = 0; k < steps && rz > 0.0; ++k) {
+        if ((rc = sc.dot_dev<T>(L.r.p, L.z.p, L.n, 0, st)) != SIPG_OK) return rc;
+        for (int k = 0; k < steps; ++k) {
             if ((rc = launch_matvec(L.op, L.uo.p, L.b.p, st)) != SIPG_OK) return rc;
-            double pap;
-            if ((rc = sc.dot<T>(L.uo.p, L.b.p, L.n, pap, st)) != SIPG_OK) return rc;
-            if (!(pap > 0.0)) break;
-            const double a = rz / pap;
-            if ((rc = vec_axpby<T>(-a, L.b.p, 1.0, L.r.p, L.n, st)) != SIPG_OK) return rc;
+            if ((rc = sc.dot_dev<T>(L.uo.p, L.b.p, L.n, 1, st)) != SIPG_OK) return rc;
+            if ((rc = scalar_ratio(s_rz, s_pap, da + k, st)) != SIPG_OK) return rc;          // alpha
+            if ((rc = vec_axpy_dev<T>(s_rz, s_pap, -1.0, L.b.p, L.r.p, L.n, st)) != SIPG_OK) return rc;
             if ((rc = launch_basis_change(L.op, pmode, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
-            double rz_new;
-            if ((rc = sc.dot<T>(L.r.p, L.z.p, L.n, rz_new, st)) != SIPG_OK) return rc;
-            const double bta = rz_new / rz;
+            if ((rc = sc.dot_dev<T>(L.r.p, L.z.p, L.n, 2, st)) != SIPG_OK) return rc;
+            if ((rc = scalar_ratio(s_rzn, s_rz, db + k, st)) != SIPG_OK) return rc;          // beta
+            if ((rc = vec_xpby_dev<T>(L.z.p, s_rzn, s_rz, L.uo.p, L.n, st)) != SIPG_OK) return rc;
+            if ((rc = scalar_ratio(s_rzn, nullptr, s_rz, st)) != SIPG_OK) return rc;
+        }
+        std::vector<double> ab(2 * steps);
+        SIPG_HIP(hipMemcpyAsync(ab.data(), sc.coef.p, sizeof(double) * ab.size(), hipMemcpyDeviceToHost, st));
+        SIPG_HIP(hipStreamSynchronize(st));
+        // keep the steps before the first breakdown (zero residual or a
+        // non-positive curvature)
+        std::vector<double> alpha, beta;
+        for (int k = 0; k < steps; ++k) {
+            const double a = ab[k], bt = ab[steps + k];
+            if (!(a > 0.0) || !std::isfinite(a)) break;
             alpha.push_back(a);
-            beta.push_back(bta);
-            if ((rc = vec_axpby<T>(1.0, L.z.p, bta, L.uo.p, L.n, st)) != SIPG_OK) return rc;
-            rz = rz_new;
+            beta.push_back(std::isfinite(bt) && bt >= 0.0 ? bt : 0.0);
+            if (!(bt > 0.0) || !std::isfinite(bt)) break;
         }
         const int m = int(alpha.size());
         if (m == 0) { set_error("multigrid: Lanczos breakdown"); return SIPG_E_NOCONV; }
@@ -390,7 +419,7 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
     mg->levels = int(H.lv.size());
     int64_t bytes = mg->fine64 ? mg->fine64->device_bytes : 0;
     for (auto& L : H.lv) bytes += L->op->device_bytes + int64_t(5 * sizeof(T)) * L->n;
-    mg->device_bytes = bytes + int64_t(sizeof(double)) * (kVecPartials + 8 + 5 * mg->ndofs);
+    mg->device_bytes = bytes + int64_t(sizeof(double)) * (kVecPartials + 8 + 2 * kMaxLanczos + 5 * mg->ndofs);
     return SIPG_OK;
 }
 
@@ -500,25 +529,27 @@ int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int m
     double rr;
     if ((rc = sc.dot<double>(r.p, r.p, n, rr, st)) != SIPG_OK) return rc;
     info->initial_residual = std::sqrt(rr);
+    // CG coefficients stay on the device (scalar slots 0: r.z, 1: p.Ap,
+    // 2: new r.z, 3: r.r); the host reads r.r once per iteration.
+    double* s_rz = sc.scal.p;
+    double* s_pap = sc.scal.p + 1;
+    double* s_rzn = sc.scal.p + 2;
     int it = 0;
-    double rz = 0.0;
     while (std::sqrt(rr) > target && it < max_iter) {
         if ((rc = sipg_mg_apply_vcycle(mg, r.p, z.p, stream)) != SIPG_OK) return rc;
-        double rz_new;
-        if ((rc = sc.dot<double>(r.p, z.p, n, rz_new, st)) != SIPG_OK) return rc;
+        if ((rc = sc.dot_dev<double>(r.p, z.p, n, 2, st)) != SIPG_OK) return rc;
         if (it == 0) {
             SIPG_HIP(hipMemcpyAsync(p.p, z.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
         } else {
-            if ((rc = vec_axpby<double>(1.0, z.p, rz_new / rz, p.p, n, st)) != SIPG_OK) return rc;
+            if ((rc = vec_xpby_dev<double>(z.p, s_rzn, s_rz, p.p, n, st)) != SIPG_OK) return rc;
         }
-        rz = rz_new;
+        if ((rc = scalar_ratio(s_rzn, nullptr, s_rz, st)) != SIPG_OK) return rc;
         if ((rc = launch_matvec(mg->fine64, p.p, ap.p, st)) != SIPG_OK) return rc;
-        double pap;
-        if ((rc = sc.dot<double>(p.p, ap.p, n, pap, st)) != SIPG_OK) return rc;
-        const double alpha = rz / pap;
-        if ((rc = vec_axpby<double>(alpha, p.p, 1.0, x, n, st)) != SIPG_OK) return rc;
-        if ((rc = vec_axpby<double>(-alpha, ap.p, 1.0, r.p, n, st)) != SIPG_OK) return rc;
-        if ((rc = sc.dot<double>(r.p, r.p, n, rr, st)) != SIPG_OK) return rc;
+        if ((rc = sc.dot_dev<double>(p.p, ap.p, n, 1, st)) != SIPG_OK) return rc;
+        if ((rc = vec_axpy_dev<double>(s_rz, s_pap, 1.0, p.p, x, n, st)) != SIPG_OK) return rc;
+        if ((rc = vec_axpy_dev<double>(s_rz, s_pap, -1.0, ap.p, r.p, n, st)) != SIPG_OK) return rc;
+        if ((rc = sc.dot_dev<double>(r.p, r.p, n, 3, st)) != SIPG_OK) return rc;
+        if ((rc = sc.read(3, rr, st)) != SIPG_OK) return rc;
         ++it;
     }
     info->iterations = it;

@@ -241,7 +241,7 @@ extern "C" {
 int sipg_server_default_opts(sipg_server_opts* o) {
     if (!o) { set_error("sipg_server_default_opts: null"); return SIPG_E_ARG; }
     o->hbm_budget_bytes = int64_t(64) << 30;
-    o->workers = 4;
+    o->workers = 8;
     o->precision = 0;
     o->smoother = 1;
     o->p_coarsening = 1;

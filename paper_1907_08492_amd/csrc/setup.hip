@@ -289,10 +289,11 @@ int build_geometry(sipg_op* op, const std::vector<double>& xq, const std::vector
     Rule r{};
     r.n = op->n;
     for (int i = 0; i < op->n; ++i) { r.x[i] = xq[i]; r.w[i] = wq[i]; }
+    // stream-ordered temporaries: a plain free would wait for the whole device
     double* vol = nullptr;
     int* bad = nullptr;
-    SIPG_HIP(hipMalloc(&vol, sizeof(double) * op->ncells));
-    SIPG_HIP(hipMalloc(&bad, sizeof(int)));
+    SIPG_HIP(hipMallocAsync(reinterpret_cast<void**>(&vol), sizeof(double) * op->ncells, st));
+    SIPG_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(int), st));
     SIPG_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
     const int bs = 128;
     const unsigned gc = unsigned((op->ncells + bs - 1) / bs);
@@ -316,9 +317,9 @@ int build_geometry(sipg_op* op, const std::vector<double>& xq, const std::vector
     }
     int hbad = 0;
     SIPG_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    SIPG_HIP(hipFreeAsync(vol, st));
+    SIPG_HIP(hipFreeAsync(bad, st));
     SIPG_HIP(hipStreamSynchronize(st));
-    SIPG_HIP(hipFree(vol));
-    SIPG_HIP(hipFree(bad));
     if (hbad) {
         set_error("sipg_setup: the mesh map has a non-positive Jacobian determinant");
         return SIPG_E_ARG;

@@ -46,6 +46,27 @@ __global__ void __launch_bounds__(kVT) convert_kernel(const TI* __restrict__ x, 
     for (int64_t i = int64_t(blockIdx.x) * kVT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kVT) y[i] = TO(x[i]);
 }
 
+// Coefficients held in device memory (no host round trip between a dot
+// product and the update that uses it): c = sign * num[0] / den[0].
+// y = c x + y
+template <typename T>
+__global__ void __launch_bounds__(kVT) axpy_dev_kernel(const double* __restrict__ num, const double* __restrict__ den,
+                                                       double sign, const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+    const T c = T(sign * (num[0] / den[0]));
+    for (int64_t i = int64_t(blockIdx.x) * kVT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kVT) y[i] = c * x[i] + y[i];
+}
+// y = x + c y
+template <typename T>
+__global__ void __launch_bounds__(kVT) xpby_dev_kernel(const T* __restrict__ x, const double* __restrict__ num,
+                                                       const double* __restrict__ den, T* __restrict__ y, int64_t n) {
+    const T c = T(num[0] / den[0]);
+    for (int64_t i = int64_t(blockIdx.x) * kVT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kVT) y[i] = x[i] + c * y[i];
+}
+// out[0] = num[0] / den[0] (den = nullptr: out[0] = num[0])
+__global__ void scalar_kernel(const double* __restrict__ num, const double* __restrict__ den, double* __restrict__ out) {
+    if (threadIdx.x == 0) out[0] = den ? num[0] / den[0] : num[0];
+}
+
 __device__ __forceinline__ double vblock_sum(double v) {
     __shared__ double sh[kVT / 64];
     for (int o = 32; o > 0; o >>= 1) v += __shfl_down(v, o, 64);
@@ -112,7 +133,27 @@ int vec_dot_async(const T* a, const T* b, double* partial, double* out, int64_t 
     return SIPG_OK;
 }
 
+template <typename T>
+int vec_axpy_dev(const double* num, const double* den, double sign, const T* x, T* y, int64_t n, hipStream_t st) {
+    axpy_dev_kernel<T><<<vblocks(n), kVT, 0, st>>>(num, den, sign, x, y, n);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+template <typename T>
+int vec_xpby_dev(const T* x, const double* num, const double* den, T* y, int64_t n, hipStream_t st) {
+    xpby_dev_kernel<T><<<vblocks(n), kVT, 0, st>>>(x, num, den, y, n);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+int scalar_ratio(const double* num, const double* den, double* out, hipStream_t st) {
+    scalar_kernel<<<1, 64, 0, st>>>(num, den, out);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
 #define SIPG_VEC_INST(T)                                                                        \
+    template int vec_axpy_dev<T>(const double*, const double*, double, const T*, T*, int64_t, hipStream_t); \
+    template int vec_xpby_dev<T>(const T*, const double*, const double*, T*, int64_t, hipStream_t); \
     template int vec_cheb<T>(const T*, T*, const T*, double, double, int64_t, hipStream_t);  \
     template int vec_sub<T>(const T*, const T*, T*, int64_t, hipStream_t);                   \
     template int vec_axpby<T>(double, const T*, double, T*, int64_t, hipStream_t);           \
