@@ -26,13 +26,28 @@ struct BcShape {
 // (TL.FZP, parity-split), 1 / (vol (lambda_i/h_1^2 + lambda_j/h_2^2 +
 // lambda_k/h_3^2)) from the eigenvalues TL.FLAM and the four cell scalars in
 // inv_diag, then Z.
-template <int N, typename T, int MODE>
+//
+// MERGE (modes 1 and 2 only): one step of the Chebyshev iteration of eq.
+// (chebyshev) in the same pass (the "merged" arrangement of Section 6): the
+// input is the residual b - A u formed while loading (au = A u; au null:
+// r = b), and the output u_old is overwritten by
+//     u + sigma (u - u_old) + theta P^-1 r
+// (u null: u = 0; sigma = 0: u_old is not read).
+template <typename T>
+struct BcMerge {
+    const T* au;
+    const T* u;
+    T sigma, theta;
+};
+
+template <int N, typename T, int MODE, bool MERGE>
 __global__ void __launch_bounds__(BcShape<N>::NT)
 basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __restrict__ tab,
-                    int moff, const T* __restrict__ inv_diag, int ncells) {
+                    int moff, const T* __restrict__ inv_diag, int ncells, BcMerge<T> mg) {
     using Sh = BcShape<N>;
     constexpr int N2 = N * N, N3 = N2 * N, CPB = Sh::CPB, NT = Sh::NT, CS = Sh::CS;
     constexpr TableLayout TL(N);
+    static_assert(!MERGE || MODE != 0, "the merged step needs a preconditioner mode");
     __shared__ T lds[CPB * CS];
     const int tid = threadIdx.x;
     const int cell0 = blockIdx.x * CPB;
@@ -45,6 +60,16 @@ basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __re
     for (int j = 0; j < XPER; ++j) {
         const int e = tid + j * NT;
         xv[j] = e < ncb * N3 ? src[e] : T(0);
+    }
+    if constexpr (MERGE) {
+        if (mg.au) {
+            const T* __restrict__ asrc = mg.au + size_t(cell0) * N3;
+#pragma unroll
+            for (int j = 0; j < XPER; ++j) {
+                const int e = tid + j * NT;
+                if (e < ncb * N3) xv[j] -= asrc[e];
+            }
+        }
     }
     const int c = tid / N2, t = tid % N2, ta = t % N, tb = t / N;
     const bool act = c < ncb;
@@ -140,9 +165,19 @@ basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __re
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(ta, tb, k)];
             bwd(v);
-            T* __restrict__ dst = out + size_t(cell0 + c) * N3 + ta + N * tb;
+            const size_t off = size_t(cell0 + c) * N3 + ta + N * tb;
+            T* __restrict__ dst = out + off;
+            if constexpr (MERGE) {
 #pragma unroll
-            for (int k = 0; k < N; ++k) dst[k * N2] = v[k];
+                for (int k = 0; k < N; ++k) {
+                    const T ui = mg.u ? mg.u[off + k * N2] : T(0);
+                    const T uo = mg.sigma != T(0) ? dst[k * N2] : ui;
+                    dst[k * N2] = ui + mg.sigma * (ui - uo) + mg.theta * v[k];
+                }
+            } else {
+#pragma unroll
+                for (int k = 0; k < N; ++k) dst[k * N2] = v[k];
+            }
         }
         return;
     }
@@ -162,16 +197,62 @@ static int launch_bc_t(const sipg_op* op, int mode, const void* in, void* out, h
     const T* i_ = static_cast<const T*>(in);
     T* o_ = static_cast<T*>(out);
     constexpr int NT = threads_per_block(N);
+    const BcMerge<T> none{nullptr, nullptr, T(0), T(0)};
     if (mode == SIPG_BC_PJACOBI) {
-        basis_change_kernel<N, T, 1><<<nblk, NT, 0, st>>>(i_, o_, tab, 0, static_cast<const T*>(op->gl_inv_diag), ncells);
+        basis_change_kernel<N, T, 1, false><<<nblk, NT, 0, st>>>(i_, o_, tab, 0, static_cast<const T*>(op->gl_inv_diag), ncells, none);
     } else if (mode == SIPG_BC_FDM) {
-        basis_change_kernel<N, T, 2><<<nblk, NT, 0, st>>>(i_, o_, tab, 0, static_cast<const T*>(op->fdm_cell), ncells);
+        basis_change_kernel<N, T, 2, false><<<nblk, NT, 0, st>>>(i_, o_, tab, 0, static_cast<const T*>(op->fdm_cell), ncells, none);
     } else {
         const int off = mode == SIPG_BC_T ? TL.T : mode == SIPG_BC_TT ? TL.TT : TL.ET;
-        basis_change_kernel<N, T, 0><<<nblk, NT, 0, st>>>(i_, o_, tab, off, nullptr, ncells);
+        basis_change_kernel<N, T, 0, false><<<nblk, NT, 0, st>>>(i_, o_, tab, off, nullptr, ncells, none);
     }
     SIPG_HIP(hipGetLastError());
     return SIPG_OK;
+}
+
+template <int N, typename T>
+static int launch_cheb_t(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
+                         double sigma, double theta, hipStream_t st) {
+    const int ncells = int(op->ncells);
+    const unsigned nblk = unsigned((ncells + cells_per_block(N) - 1) / cells_per_block(N));
+    constexpr int NT = threads_per_block(N);
+    const T* tab = static_cast<const T*>(op->tables);
+    const BcMerge<T> m{static_cast<const T*>(au), static_cast<const T*>(u), T(sigma), T(theta)};
+    if (mode == SIPG_BC_PJACOBI)
+        basis_change_kernel<N, T, 1, true><<<nblk, NT, 0, st>>>(static_cast<const T*>(b), static_cast<T*>(uo), tab, 0,
+                                                                static_cast<const T*>(op->gl_inv_diag), ncells, m);
+    else
+        basis_change_kernel<N, T, 2, true><<<nblk, NT, 0, st>>>(static_cast<const T*>(b), static_cast<T*>(uo), tab, 0,
+                                                                static_cast<const T*>(op->fdm_cell), ncells, m);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
+template <int N>
+static int launch_cheb_n(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
+                         double sigma, double theta, hipStream_t st) {
+    return op->dtype == SIPG_F64 ? launch_cheb_t<N, double>(op, mode, b, au, u, uo, sigma, theta, st)
+                                 : launch_cheb_t<N, float>(op, mode, b, au, u, uo, sigma, theta, st);
+}
+
+int launch_precond_cheb(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
+                        double sigma, double theta, hipStream_t st) {
+    if (mode != SIPG_BC_PJACOBI && mode != SIPG_BC_FDM) {
+        set_error("merged Chebyshev step: preconditioner mode expected");
+        return SIPG_E_ARG;
+    }
+    switch (op->n) {
+        case 2: return launch_cheb_n<2>(op, mode, b, au, u, uo, sigma, theta, st);
+        case 3: return launch_cheb_n<3>(op, mode, b, au, u, uo, sigma, theta, st);
+        case 4: return launch_cheb_n<4>(op, mode, b, au, u, uo, sigma, theta, st);
+        case 5: return launch_cheb_n<5>(op, mode, b, au, u, uo, sigma, theta, st);
+        case 6: return launch_cheb_n<6>(op, mode, b, au, u, uo, sigma, theta, st);
+        case 7: return launch_cheb_n<7>(op, mode, b, au, u, uo, sigma, theta, st);
+        case 8: return launch_cheb_n<8>(op, mode, b, au, u, uo, sigma, theta, st);
+        case 9: return launch_cheb_n<9>(op, mode, b, au, u, uo, sigma, theta, st);
+    }
+    set_error("merged Chebyshev step: unsupported degree");
+    return SIPG_E_UNSUPPORTED;
 }
 
 template <int N>

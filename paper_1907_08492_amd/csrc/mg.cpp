@@ -187,15 +187,15 @@ struct Hierarchy {
             if (j == 0 && zero_init) {
                 // u_0 = 0 (kept in uo for the next step), u_1 = theta_0 P^-1 b
                 SIPG_HIP(hipMemsetAsync(L.uo.p, 0, sizeof(T) * size_t(L.n), st));
-                if ((rc = launch_basis_change(L.op, pmode, L.b.p, L.z.p, st)) != SIPG_OK) return rc;
-                if ((rc = vec_scale<T>(th[0], L.z.p, L.u.p, L.n, st)) != SIPG_OK) return rc;
+                if ((rc = launch_precond_cheb(L.op, pmode, L.b.p, nullptr, nullptr, L.u.p, 0.0, th[0], st)) != SIPG_OK)
+                    return rc;
                 continue;
             }
+            // u_{j+1} = u_j + sigma_j (u_j - u_{j-1}) + theta_j P^-1 (b - A u_j)
+            // into uo (residual, preconditioner and update in one pass), then swap
             if ((rc = launch_matvec(L.op, L.u.p, L.r.p, st)) != SIPG_OK) return rc;
-            if ((rc = vec_sub<T>(L.b.p, L.r.p, L.r.p, L.n, st)) != SIPG_OK) return rc;
-            if ((rc = launch_basis_change(L.op, pmode, L.r.p, L.z.p, st)) != SIPG_OK) return rc;
-            // u_{j+1} = u_j + sigma_j (u_j - u_{j-1}) + theta_j z into uo, then swap
-            if ((rc = vec_cheb<T>(L.u.p, L.uo.p, L.z.p, j == 0 ? 0.0 : sig[j], th[j], L.n, st)) != SIPG_OK) return rc;
+            if ((rc = launch_precond_cheb(L.op, pmode, L.b.p, L.r.p, L.u.p, L.uo.p, j == 0 ? 0.0 : sig[j], th[j], st)) != SIPG_OK)
+                return rc;
             std::swap(L.u.p, L.uo.p);
         }
         return SIPG_OK;

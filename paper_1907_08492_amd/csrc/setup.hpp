@@ -37,6 +37,12 @@ int launch_matvec_batched_n(const BatchGroup& g, hipStream_t st);
 // Cell-wise basis change / preconditioner (see sipg_basis_change).
 int launch_basis_change(const sipg_op* op, int mode, const void* in, void* out, hipStream_t st);
 
+// One Chebyshev step merged with the residual and the preconditioner
+// (mode SIPG_BC_PJACOBI or SIPG_BC_FDM): uo = u + sigma (u - uo) + theta P^-1
+// (b - au); au null means au = 0, u null means u = 0, sigma = 0 does not read uo.
+int launch_precond_cheb(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
+                        double sigma, double theta, hipStream_t st);
+
 // Right-hand side of a sum of sine modes (see sipg_assemble_rhs_sines).
 int launch_rhs_sines(const sipg_op* op, int nmodes, const double* amps, const int* waves, void* b, hipStream_t st);
 
