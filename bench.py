@@ -204,8 +204,9 @@ def solver_benchmark(torch, P, reps: int = 3):
     op = P.Operator(cfg.mesh, cfg.degree, cfg.eta)
     b = op.assemble_rhs([3 * np.pi ** 2], [(1, 1, 1)])
     bn = float(torch.linalg.norm(b))
+    x_ref = None
     for smoother in ("pjacobi", "fdm"):
-        for prec in ("mixed", "f64"):
+        for prec in ("f64", "mixed"):
             t0 = time.perf_counter()
             mg = P.Multigrid(cfg.mesh, cfg.degree, cfg.eta, precision=prec, smoother=smoother)
             torch.cuda.synchronize()
@@ -219,8 +220,14 @@ def solver_benchmark(torch, P, reps: int = 3):
                 torch.cuda.synchronize()
                 ts.append(time.perf_counter() - t0)
             t = float(np.median(ts))
+            # the true FP64 residual of every solve, and its distance to the
+            # all-FP64 solution of the first configuration
+            if x_ref is None:
+                x_ref = x.clone()
+            diff = float(torch.linalg.norm(x - x_ref) / torch.linalg.norm(x_ref))
             out.append({"smoother": smoother, "precision": prec, "ndofs": mg.ndofs, "levels": mg.info.levels,
                         "iterations": info.iterations, "rel_residual": info.true_residual / bn,
+                        "rel_diff_to_f64_pjacobi_solution": diff,
                         "solve_s": t, "dof_per_s": mg.ndofs / t, "setup_s": setup})
             mg.close()
             del x
