@@ -150,13 +150,20 @@ int sipg_apply(const sipg_op* op, const void* x, void* y, void* stream);
  */
 typedef struct sipg_batch sipg_batch;
 typedef struct {
-    int32_t nops, launches;
+    int32_t nops, launches;      /* launches = groups of equal degree/basis/precision/geometry */
     int64_t ndofs, ncells, workgroups;
     int64_t device_bytes;
+    int32_t per_operator_groups; /* groups that sipg_batch_tune set to one launch per operator */
 } sipg_batch_info;
 int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x, void* const* y,
                       sipg_batch** out);
 int sipg_batch_apply(const sipg_batch* batch, void* stream);
+/* Schedule autotuning: for every group, time `reps` applications as one grid
+ * and as one launch per operator on `stream` (HIP events) and keep the faster
+ * schedule for later sipg_batch_apply calls.  Runs the products, so the
+ * outputs are overwritten; synchronises the stream.  Results are the same in
+ * both schedules (same kernel body). */
+int sipg_batch_tune(sipg_batch* batch, int reps, void* stream);
 int sipg_batch_get_info(const sipg_batch* batch, sipg_batch_info* info);
 int sipg_batch_destroy(sipg_batch* batch);
 

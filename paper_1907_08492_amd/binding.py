@@ -47,7 +47,7 @@ EXPORTED = [
     "sipg_server_default_opts", "sipg_server_create", "sipg_submit", "sipg_poll", "sipg_wait",
     "sipg_release", "sipg_server_stats", "sipg_server_destroy", "sipg_copy_device",
     "sipg_batch_create", "sipg_batch_apply", "sipg_batch_get_info", "sipg_batch_destroy",
-    "sipg_host_fdm_tables", "sipg_mg_level_degree",
+    "sipg_host_fdm_tables", "sipg_mg_level_degree", "sipg_batch_tune",
 ]
 
 
@@ -105,7 +105,8 @@ class SipgServerStats(C.Structure):
 
 class SipgBatchInfo(C.Structure):
     _fields_ = [("nops", C.c_int32), ("launches", C.c_int32), ("ndofs", C.c_int64),
-                ("ncells", C.c_int64), ("workgroups", C.c_int64), ("device_bytes", C.c_int64)]
+                ("ncells", C.c_int64), ("workgroups", C.c_int64), ("device_bytes", C.c_int64),
+                ("per_operator_groups", C.c_int32)]
 
 
 class SipgTables1D(C.Structure):
@@ -153,6 +154,7 @@ lib.sipg_batch_create.argtypes = [C.c_int, C.POINTER(_vp), C.POINTER(_vp), C.POI
 lib.sipg_batch_apply.argtypes = [_vp, _vp]
 lib.sipg_batch_get_info.argtypes = [_vp, C.POINTER(SipgBatchInfo)]
 lib.sipg_batch_destroy.argtypes = [_vp]
+lib.sipg_batch_tune.argtypes = [_vp, C.c_int, _vp]
 lib.sipg_host_fdm_tables.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
 for _f in EXPORTED:
     if _f not in ("sipg_ndofs", "sipg_last_error"):
@@ -355,6 +357,13 @@ class Batch:
 
     def apply(self, stream=None):
         _check(lib.sipg_batch_apply(self._h, _vp(_stream_ptr(stream))), "sipg_batch_apply")
+
+    def tune(self, reps: int = 3, stream=None):
+        """Pick one grid or one launch per operator for every group by timing."""
+        _check(lib.sipg_batch_tune(self._h, int(reps), _vp(_stream_ptr(stream))), "sipg_batch_tune")
+        info = SipgBatchInfo()
+        _check(lib.sipg_batch_get_info(self._h, C.byref(info)), "sipg_batch_get_info")
+        self.info = info
 
     def close(self):
         if getattr(self, "_h", None):

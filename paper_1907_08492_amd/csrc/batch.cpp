@@ -25,6 +25,13 @@ struct sipg_batch {
     int nops = 0;
     int64_t ndofs = 0, ncells = 0, nblocks = 0;
     std::vector<sipg::BatchGroup> groups;
+    // per group: its operators and vectors (host copies), and the schedule
+    // chosen by sipg_batch_tune (0: one grid, 1: one launch per operator)
+    std::vector<std::vector<int>> members;
+    std::vector<int> schedule;
+    std::vector<const sipg_op*> ops;
+    std::vector<const void*> x;
+    std::vector<void*> y;
     void* mem = nullptr;
     size_t bytes = 0;
 };
@@ -125,6 +132,9 @@ int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x,
     if (!b) { set_error("sipg_batch_create: out of host memory"); return SIPG_E_OOM; }
     b->device = device;
     b->nops = nops;
+    b->ops.assign(ops, ops + nops);
+    b->x.assign(x, x + nops);
+    b->y.assign(y, y + nops);
     // host images of the device arrays, laid out group after group
     std::vector<char> host;
     struct Off { size_t params, blk_op, blk_first; };
@@ -178,6 +188,8 @@ int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x,
         b->ndofs += g.ndofs;
         b->nblocks += nblk;
         b->groups.push_back(g);
+        b->members.push_back(idx);
+        b->schedule.push_back(0);
     }
     int prev = 0;
     (void)hipGetDevice(&prev);
@@ -201,12 +213,47 @@ int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x,
     return SIPG_OK;
 }
 
+static int run_group(const sipg_batch* b, size_t gi, int schedule, hipStream_t st) {
+    if (schedule == 0) return launch_matvec_batched(b->groups[gi], st);
+    for (int i : b->members[gi])
+        if (int rc = launch_matvec(b->ops[i], b->x[i], b->y[i], st)) return rc;
+    return SIPG_OK;
+}
+
 int sipg_batch_apply(const sipg_batch* b, void* stream) {
     if (!b) { set_error("sipg_batch_apply: null batch"); return SIPG_E_ARG; }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    for (const BatchGroup& g : b->groups)
-        if (int rc = launch_matvec_batched(g, st)) return rc;
+    for (size_t gi = 0; gi < b->groups.size(); ++gi)
+        if (int rc = run_group(b, gi, b->schedule[gi], st)) return rc;
     return SIPG_OK;
+}
+
+int sipg_batch_tune(sipg_batch* b, int reps, void* stream) {
+    if (!b || reps < 1) { set_error("sipg_batch_tune: null batch or reps < 1"); return SIPG_E_ARG; }
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    hipEvent_t e0, e1;
+    SIPG_HIP(hipEventCreate(&e0));
+    SIPG_HIP(hipEventCreate(&e1));
+    int rc = SIPG_OK;
+    for (size_t gi = 0; gi < b->groups.size() && rc == SIPG_OK; ++gi) {
+        float best = 0.0f;
+        int pick = 0;
+        for (int sched = 0; sched < 2 && rc == SIPG_OK; ++sched) {
+            if ((rc = run_group(b, gi, sched, st)) != SIPG_OK) break;   // warm-up
+            hipError_t e = hipEventRecord(e0, st);
+            for (int r = 0; r < reps && rc == SIPG_OK && e == hipSuccess; ++r) rc = run_group(b, gi, sched, st);
+            if (e == hipSuccess) e = hipEventRecord(e1, st);
+            if (e == hipSuccess) e = hipEventSynchronize(e1);
+            float ms = 0.0f;
+            if (e == hipSuccess) e = hipEventElapsedTime(&ms, e0, e1);
+            if (e != hipSuccess) { rc = hip_fail(e, "sipg_batch_tune: timing"); break; }
+            if (sched == 0 || ms < best) { best = ms; pick = sched; }
+        }
+        b->schedule[gi] = pick;
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    return rc;
 }
 
 int sipg_batch_get_info(const sipg_batch* b, sipg_batch_info* info) {
@@ -217,6 +264,8 @@ int sipg_batch_get_info(const sipg_batch* b, sipg_batch_info* info) {
     info->ncells = b->ncells;
     info->workgroups = b->nblocks;
     info->device_bytes = int64_t(b->bytes);
+    info->per_operator_groups = 0;
+    for (int sch : b->schedule) info->per_operator_groups += sch;
     return SIPG_OK;
 }
 

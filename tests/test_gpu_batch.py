@@ -137,3 +137,28 @@ def test_batch_many_small_operators_one_launch():
     b.close()
     for op in ops:
         op.close()
+
+
+def test_batch_tune_keeps_results():
+    """The schedule autotuner may switch groups to one launch per operator;
+    the outputs stay bit-identical."""
+    torch, P = require_gpu()
+    banner("batch tune")
+    rng = np.random.default_rng(5)
+    specs = _mixed_specs(rng, 16)
+    ops, xs, ys = _setup(torch, P, specs, seed0=50)
+    b = P.Batch(ops, xs, ys)
+    b.apply()
+    torch.cuda.synchronize()
+    before = [y.clone() for y in ys]
+    b.tune(2)
+    assert 0 <= b.info.per_operator_groups <= b.info.launches
+    for y in ys:
+        y.fill_(float("nan"))
+    b.apply()
+    torch.cuda.synchronize()
+    for y0, y1 in zip(before, ys):
+        assert torch.equal(y0, y1)
+    b.close()
+    for op in ops:
+        op.close()
