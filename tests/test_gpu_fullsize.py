@@ -100,3 +100,29 @@ def test_full_size_preconditioners_on_sampled_cells(mode):
                               for i in range(len(cells))])
     err = np.max(np.abs(z_s - ref)) / np.max(np.abs(ref))
     assert err <= 1e-12, err
+
+
+def test_largest_supported_size_on_sampled_cells():
+    """2,097,152,000 unknowns (256^3 cells, k = 4, the paper's affine brick),
+    just below the 2^31 limit of the in-kernel indices: the product on sampled
+    cells (including the last ones) equals the oracle's rows."""
+    torch, P = require_gpu()
+    from workloads import paper_affine_brick
+    banner("largest size 256^3 k=4 affine")
+    mesh = paper_affine_brick(256)
+    k = 4
+    n3 = (k + 1) ** 3
+    op = P.Operator(mesh, k, 2.0)
+    assert op.ndofs == 256 ** 3 * n3 < 2 ** 31
+    x = uniform_vector(op.ndofs, 0)
+    xd = torch.from_numpy(x).cuda()
+    y = op.apply(xd)
+    torch.cuda.synchronize()
+    cells = np.unique(np.concatenate([_sample_cells(mesh, 12, 4), [mesh.ncells - 2, mesh.ncells - 1]]))
+    ys = y.view(-1, n3)[torch.from_numpy(cells).cuda()].cpu().numpy().reshape(-1)
+    del xd, y
+    op.close()
+    torch.cuda.empty_cache()
+    ref = SIPG(mesh, k, 2.0, cells=cells).apply_naive(x)
+    err = np.max(np.abs(ys - ref)) / np.max(np.abs(ref))
+    assert err <= 1e-12, err

@@ -94,6 +94,10 @@ def test_argument_errors_without_gpu():
     assert P.lib.sipg_ndofs(None) == -1
     assert P.lib.sipg_destroy(None) == 0
     assert P.lib.sipg_launch_shape(0, 0, None, None, None) == -1
+    # more than 2^31 - 1 unknowns is rejected before any device work
+    big = P.make_mesh(type("M", (), dict(n=(1300, 1300, 1300), lo=(0, 0, 0), hi=(1, 1, 1)))())
+    assert P.lib.sipg_setup(C.byref(big), 1, 1.0, 0, 0, 0, None, C.byref(h)) == -1
+    assert "too large" in P.lib.sipg_last_error().decode()
     assert P.lib.sipg_batch_create(0, None, None, None, C.byref(h)) == -1
     assert P.lib.sipg_batch_create(1, None, None, None, None) == -1
     null3 = (C.c_void_p * 1)(None)
