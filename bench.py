@@ -313,6 +313,8 @@ def main():
                     help="arrival window of the serving leg (0 skips it; 60 is the full stream)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
     ap.add_argument("--serve-workers", type=int, default=8)
+    ap.add_argument("--serve-sustained-rate", type=float, default=25.0,
+                    help="arrival rate of the below-saturation latency run (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
@@ -478,6 +480,14 @@ def main():
             serve[prec] = serve_benchmark(P, prec, args.serve_seconds, args.serve_rate, args.serve_workers)
             torch.cuda.empty_cache()
         serve["mixed_over_f64_solves_per_s"] = serve["mixed"]["solves_per_s"] / serve["f64"]["solves_per_s"]
+        # latency below saturation: the same stream thinned to a rate both
+        # precisions sustain, over a longer window
+        if args.serve_sustained_rate > 0:
+            serve["sustained"] = {}
+            for prec in ("mixed", "f64"):
+                print(f"[bench] serving {prec}: {args.serve_sustained_rate}/s for 4 s", file=sys.stderr, flush=True)
+                serve["sustained"][prec] = serve_benchmark(P, prec, 4.0, args.serve_sustained_rate, args.serve_workers)
+                torch.cuda.empty_cache()
         out["serving"] = serve
 
     if not args.no_cpu:

@@ -74,6 +74,7 @@ struct sipg_server {
     bool stop = false;
     std::vector<std::thread> workers;
     hipStream_t house = nullptr;     // stream for releasing result buffers
+    std::vector<sipg_mg*> evicted;   // hierarchies to free outside the lock
     int64_t peak_bytes = 0;
     int64_t completed = 0;
 };
@@ -93,9 +94,7 @@ static Key make_key(const sipg_request& r, int precision) {
     return k;
 }
 
-// Upper estimate of a hierarchy's device memory before it exists: the FP64
-// fine operator, the V-cycle levels (8/7 of the fine size) with five vectors
-// each, and the metric terms (per point on deformed meshes).
+// Multigrid options of every solve of the server.
 static sipg_mg_opts solver_opts(const sipg_server_opts& so) {
     sipg_mg_opts o;
     sipg_mg_default_opts(&o);
@@ -105,6 +104,9 @@ static sipg_mg_opts solver_opts(const sipg_server_opts& so) {
     return o;
 }
 
+// Upper estimate of a hierarchy's device memory before it exists (its level
+// sequence, metric terms, diagonals and level vectors, plus the FP64 fine
+// operator and CG vectors).
 static int64_t estimate_hierarchy_bytes(const sipg_request& r, const sipg_server_opts& so) {
     return mg_estimate_bytes(r.mesh, r.degree, solver_opts(so));
 }
@@ -141,7 +143,9 @@ static Job* admit(sipg_server* s) {
                 if (victim == s->cache.end() || c->second.last_used < victim->second.last_used) victim = c;
             }
             if (victim == s->cache.end()) break;
-            sipg_mg_destroy(victim->second.mg);
+            // freed by the admitting worker after it releases the lock (a
+            // device free waits for the whole device)
+            s->evicted.push_back(victim->second.mg);
             s->used_bytes -= victim->second.bytes;
             s->cache.erase(victim);
         }
@@ -171,7 +175,10 @@ static void worker_main(sipg_server* s) {
         for (auto c = range.first; c != range.second; ++c)
             if (!c->second.busy) { ce = &c->second; break; }
         if (ce) { ce->busy = true; mg = ce->mg; }
+        std::vector<sipg_mg*> to_free;
+        to_free.swap(s->evicted);
         lk.unlock();
+        for (sipg_mg* e : to_free) sipg_mg_destroy(e);
 
         int status = SIPG_OK;
         int64_t built_bytes = 0;
@@ -374,6 +381,7 @@ int sipg_server_destroy(sipg_server* s) {
     (void)hipStreamSynchronize(s->house);
     (void)hipStreamDestroy(s->house);
     for (auto& kv : s->cache) sipg_mg_destroy(kv.second.mg);
+    for (sipg_mg* e : s->evicted) sipg_mg_destroy(e);
     delete s;
     return SIPG_OK;
 }
