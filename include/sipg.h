@@ -247,7 +247,7 @@ int sipg_launch_shape(int degree, int dtype, int32_t* cells_per_block, int32_t* 
  */
 typedef struct {
     int32_t smoother_degree;     /* Chebyshev degree per smoothing (5) */
-    int32_t lanczos_steps;       /* eigenvalue estimate steps (15) */
+    int32_t lanczos_steps;       /* eigenvalue estimate steps (15; at most 512) */
     double range_lo, range_hi;   /* smoothing range factors (0.06, 1.2) */
     double coarse_reduction;     /* coarse solve residual reduction (1e5) */
     int32_t min_coarse_cells;    /* stop coarsening below this many cells (1) */

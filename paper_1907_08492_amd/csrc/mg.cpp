@@ -446,7 +446,7 @@ int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, 
     sipg_mg_opts o;
     sipg_mg_default_opts(&o);
     if (opts) o = *opts;
-    if (o.smoother_degree < 1 || o.smoother_degree > 64 || o.lanczos_steps < 2 || !(o.range_lo > 0.0) ||
+    if (o.smoother_degree < 1 || o.smoother_degree > 64 || o.lanczos_steps < 2 || o.lanczos_steps > kMaxLanczos || !(o.range_lo > 0.0) ||
         !(o.range_hi > o.range_lo) || !(o.coarse_reduction > 1.0) || (o.precision != 0 && o.precision != 1) ||
         o.min_coarse_cells < 1 || (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2) {
         set_error("sipg_mg_setup: invalid options");

@@ -263,7 +263,7 @@ int sipg_server_create(const sipg_server_opts* opts, sipg_server** out) {
     if (opts) o = *opts;
     if (o.workers < 1 || o.workers > 16 || o.hbm_budget_bytes <= 0 || (o.precision != 0 && o.precision != 1) ||
         (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2) {
-        set_error("sipg_server_create: workers in [1,16], budget > 0, precision and smoother 0 or 1");
+        set_error("sipg_server_create: workers in [1,16], budget > 0, precision and smoother 0 or 1, p_coarsening 0..2");
         return SIPG_E_ARG;
     }
     sipg_server* s = new (std::nothrow) sipg_server();
