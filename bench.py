@@ -318,7 +318,7 @@ def main():
     args = ap.parse_args()
     if args.gpus != 1:
         print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
-              "the multi-GPU sharding is a design in DESIGN.md, not a measured path.", file=sys.stderr)
+              "sharding over several GPUs is designed but not built or measured.", file=sys.stderr)
         sys.exit(2)
 
     import torch

@@ -21,7 +21,8 @@ ARCH = "gfx950"
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [
     f"--offload-arch={ARCH}", "-O3", "-fPIC", "-std=c++17",
-    # packed FP32 instructions stay off (build notes)
+    # packed FP32 instructions stay off: the compiler forms v_pk_* FP32 ops
+    # from plain float code otherwise
     "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
     "-Wall", "-Wno-unused-function", "-Wno-unused-variable",
 ]
