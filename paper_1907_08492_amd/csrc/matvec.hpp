@@ -10,12 +10,15 @@
 // works on the two faces of normal direction d of every cell, so the
 // direction is a compile-time constant inside its code, and each lane owns
 // one row (t1 direction) and one column (t2 direction) of one face:
-//   G   gather the own value/derivative layers (LDS) and the neighbour's value
-//       and derivative layers (registers, loaded at kernel start; two layers
-//       for the Hermite-like basis, all n for the nodal basis), combine them
-//       with S_f and D_f, and interpolate along t1 (S, and S' for values)
-//   F   interpolate along t2 (S, and D for the tangential derivative), flux
-//       at the face Gauss points, transposed sweeps along t2
+//   G1  gather the own value/derivative layers (LDS), combine them with S_f
+//       and D_f and interpolate along t1 (S, and S' for values); combine the
+//       neighbour's layers (registers loaded at kernel start: two layers for
+//       the Hermite-like basis, all n for the nodal bases) likewise
+//   F1  own side along t2 (S, and D for the tangential derivative), kept in
+//       registers
+//   G2  neighbour side along t1, written over the own side's arrays
+//   F2  neighbour side along t2, flux at the face Gauss points, transposed
+//       sweeps along t2
 //   I   transposed sweeps along t1 -> P (value test) and Q (normal-derivative
 //       test) coefficient arrays of the face
 // Cell integral: S along z, y, x, collocation D along x, y, z (eq.
@@ -72,7 +75,10 @@ struct Shape {
     static constexpr int FROWS = CPB * 2 * N;              // face rows (= columns) per direction
     static constexpr int FR = face_row_stride(N);          // row stride of a face array
     static constexpr int FARR = N * FR;                    // one face array (all faces of a direction)
-    static constexpr int WORDS = CPB * CS + 18 * FARR;     // words of T per workgroup
+    // words of T per workgroup: the x/work arrays, then 9 face arrays; in the
+    // cell steps arrays FV, FT of every direction persist and the cell arrays
+    // B, C start at the FN arrays
+    static constexpr int WORDS = CPB * CS + (9 * FARR > 6 * FARR + 2 * CPB * CS ? 9 * FARR : 6 * FARR + 2 * CPB * CS);
     __host__ __device__ static constexpr int lds_idx(int i1, int i2, int i3) { return i1 + RS * (i2 + N * i3); }
 };
 
@@ -82,7 +88,6 @@ constexpr size_t matvec_lds_bytes() {
     constexpr size_t b = size_t(S::WORDS) * sizeof(T);
     static_assert(b == matvec_lds_bytes_rt(N, sizeof(T)), "LDS size formula mismatch");
     static_assert(S::FR >= S::FROWS, "face row holds every face of a direction");
-    static_assert(2 * S::CPB * S::CS <= 12 * S::FARR, "cell arrays B, C fit the face work arrays");
     static_assert(b <= 160 * 1024, "LDS budget of a gfx950 CU exceeded");
     static_assert(S::NT == 192 && S::CPB * N * N <= S::NT, "three wavefronts, one pencil per thread");
     static_assert(S::FROWS <= 64, "one face row per lane of a direction wavefront");
@@ -148,6 +153,14 @@ __device__ __forceinline__ void by_direction(int wave, F&& fn) {
     else fn(DirC<2>{});
 }
 
+// Orders the LDS accesses of one wavefront before and after it (the lanes of
+// a wavefront exchange data through LDS without a workgroup barrier).
+__device__ __forceinline__ void wave_sync() {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+}
+
 // Minimum wavefronts per SIMD requested from the register allocator: two for
 // n >= 7 with per-cell metric terms, so that two workgroups share a compute
 // unit (the few spilled registers cost less than the idle SIMD); with
@@ -180,13 +193,13 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     extern __shared__ __align__(16) unsigned char smem_raw[];
     T* lds = reinterpret_cast<T*>(smem_raw);
     T* ldsX = lds;                                   // [CPB][CS]   x, later the cell work array A
-    // Face arrays [6 arrays][3 directions][n rows][FR]: a row holds that row
+    // Face arrays [3 arrays][3 directions][n rows][FR]: a row holds that row
     // of every (cell, side) face of the direction, (2 cell + side) n + column.
-    // Arrays 0, 1 (P, Q at the end of the face steps) persist; arrays 2..5
-    // are reused by the cell arrays B, C.
+    // Arrays FV, FT (P, Q at the end of the face steps) persist; the cell
+    // arrays B, C start at the FN arrays.
     T* ldsF = lds + CPB * CS;
 
-    const T* __restrict__ tab = p.tab;
+    const auto tab = ctab(p.tab);
     const int tid = threadIdx.x;
     const int wave = __builtin_amdgcn_readfirstlane(tid >> 6);   // = face direction in the face steps
     const int lane = tid & 63;
@@ -222,33 +235,57 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 
     // ------------------------------------------------------------ prefetch
     // Registers, before any LDS work: the metric terms of this lane's flux
-    // column (used in F) and the neighbour layers of this lane's row (used
-    // in G).
+    // column (used in F1, F2) and the neighbour layers of this lane's row
+    // (used in G1).
     // For n >= 7 (FP64) the registers are needed by the sweeps: the face
-    // records are then loaded at the start of step F and the cell metric
-    // terms at the start of C4.
+    // records are then loaded in two parts, at the start of steps F1 and G2,
+    // and the cell metric terms at the start of C4.
     constexpr bool EARLY = N <= 6 || sizeof(T) == 4;
     constexpr int NREC = GEOM == GEOM_CELL ? 7 : 7 * N;
+    // frec: the penalty term, this lane's own side scaled normal (3
+    // components), the neighbour side's (3); the side slots of the stored
+    // record (lower cell first) are chosen here, by the load addresses.
     T frec[NREC];
     T nbv[Ly::NL][N];
-    auto load_frec = [&](auto dc) {
+    // part 1: own side normal (used from F1 on); part 2: penalty term and
+    // neighbour side normal (used in F2)
+    auto load_frec = [&](auto dc, int part) {
         constexpr int D = decltype(dc)::value;
         const T* __restrict__ fg = D == 0 ? p.fgeom0 : D == 1 ? p.fgeom1 : p.fgeom2;
+        const int own = fs ? 1 : 4, nb = fs ? 4 : 1;
         if constexpr (GEOM == GEOM_CELL) {
+            const T* __restrict__ r = fg + size_t(fidx) * 8;
+            if (part & 1) {
 #pragma unroll
-            for (int k = 0; k < 7; ++k) frec[k] = fg[size_t(fidx) * 8 + k];
+                for (int k = 0; k < 3; ++k) frec[1 + k] = r[own + k];
+            }
+            if (part & 2) {
+                frec[0] = r[0];
+#pragma unroll
+                for (int k = 0; k < 3; ++k) frec[4 + k] = r[nb + k];
+            }
         } else {
             const T* __restrict__ r = fg + size_t(fidx) * (7 * N2) + fab;
+            if (part & 1) {
 #pragma unroll
-            for (int k = 0; k < 7; ++k)
+                for (int k = 0; k < 3; ++k)
 #pragma unroll
-                for (int b = 0; b < N; ++b) frec[k * N + b] = r[k * N2 + N * b];
+                    for (int b = 0; b < N; ++b) frec[(1 + k) * N + b] = r[(own + k) * N2 + N * b];
+            }
+            if (part & 2) {
+#pragma unroll
+                for (int b = 0; b < N; ++b) frec[b] = r[N * b];
+#pragma unroll
+                for (int k = 0; k < 3; ++k)
+#pragma unroll
+                    for (int b = 0; b < N; ++b) frec[(4 + k) * N + b] = r[(nb + k) * N2 + N * b];
+            }
         }
     };
     by_direction(wave, [&](auto dc) {
         constexpr int D = decltype(dc)::value;
         if (!fact) return;
-        if constexpr (EARLY) load_frec(dc);
+        if constexpr (EARLY) load_frec(dc, 3);
         // x-neighbours inside the workgroup are read from the x tile in G
         if (fnb >= 0 && !(D == 0 && (fs ? fc + 1 < ncb : fc > 0))) {
             const T* __restrict__ xn = p.x + size_t(fnb) * N3;
@@ -273,165 +310,180 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     }
     __syncthreads();
 
-    // ------------------------ G: gather face layers, interpolate along t1
+    // Face steps G1, F1, G2, F2, I.  Wavefront d touches only the face arrays
+    // of direction d, so the steps are separated by wavefront-level syncs; the
+    // block barrier comes before the cell steps, which read every direction.
+    // Array roles: FV value, FT t1 derivative, FN normal derivative; the own
+    // side's arrays are consumed (F1) before the neighbour side's are written
+    // (G2) into the same place.
+    constexpr int FV = 0, FT = 1, FN = 2;
     by_direction(wave, [&](auto dc) {
         constexpr int D = decltype(dc)::value;
-        if (!fact) return;
-        const int b = fab;                 // this lane's row
-        const int s = fs, c = fc;
-        const T* Xc = ldsX + c * CS;
-        const T* dfs = tab + (s ? TL.df1 : TL.df0);
-        const T* dfn = tab + (s ? TL.df0 : TL.df1);
-        T vm[N], nm[N];
-        const T* fvs = tab + (s ? TL.FV1 : TL.FV0);
-#pragma unroll
-        for (int a = 0; a < N; ++a) {
-            T acc = T(0), val = T(0);
-#pragma unroll
-            for (int j = 0; j < Ly::NL; ++j) {
-                const int l = Ly::layer(s, j);
-                const T xl = Xc[face_lidx<N, D>(l, a, b)];
-                acc = fma(dfs[l], xl, acc);
-                if constexpr (COLLOC) val = fma(fvs[l], xl, val);
-            }
-            if constexpr (!COLLOC) val = Xc[face_lidx<N, D>(s ? N - 1 : 0, a, b)];
-            vm[a] = val;
-            nm[a] = acc;
-        }
+        constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
+        const int s = fs, c = fc, rc = fab;   // rc: this lane's row (G) / column (F)
+        const bool interior = fnb >= 0;
         T r[N];
-        const int row = b * FR;
-        s_apply<N, COLLOC>(tab + TL.S, vm, r);
-        T* o = fel(0, D, c, s) + row;
+        auto put_row = [&](int m, const T* v) {
+            T* o = fel(m, D, c, s) + rc * FR;
 #pragma unroll
-        for (int a = 0; a < N; ++a) o[a] = r[a];
-        eo_apply<N, -1>(tab + TL.SG, vm, r);
-        o = fel(4, D, c, s) + row;
+            for (int q = 0; q < N; ++q) o[q] = v[q];
+        };
+        auto col = [&](int m, T* v) {
+            const T* src = fel(m, D, c, s) + rc;
 #pragma unroll
-        for (int a = 0; a < N; ++a) o[a] = r[a];
-        s_apply<N, COLLOC>(tab + TL.S, nm, r);
-        o = fel(1, D, c, s) + row;
-#pragma unroll
-        for (int a = 0; a < N; ++a) o[a] = r[a];
-        if (fnb >= 0) {
-            // neighbour side: its value layer touches the face; its
-            // derivative row combines the layers loaded at kernel start
-            T vp[N], np[N];
-            if (D == 0 && (s ? c + 1 < ncb : c > 0)) {
-                // the x-neighbour is the adjacent cell of this workgroup
-                const T* Xn = ldsX + (s ? c + 1 : c - 1) * CS;
-#pragma unroll
-                for (int j = 0; j < Ly::NL; ++j) {
-                    const int l = Ly::layer(1 - s, j);
-#pragma unroll
-                    for (int a = 0; a < N; ++a) nbv[j][a] = Xn[face_lidx<N, 0>(l, a, b)];
-                }
-            }
-            const T* fvn = tab + (s ? TL.FV0 : TL.FV1);
+            for (int q = 0; q < N; ++q) v[q] = src[q * FR];
+        };
+        // ---- G1: own value and normal-derivative layers of row rc, S and S'
+        // along t1; the neighbour's layers combined into its value and
+        // derivative rows (vp, np) for G2
+        T vp[N], np[N];
+        if (fact) {
+            const int b = rc;
+            const T* Xc = ldsX + c * CS;
+            const auto dfs = tab + (s ? TL.df1 : TL.df0);
+            const auto fvs = tab + (s ? TL.FV1 : TL.FV0);
+            T vm[N], nm[N];
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 T acc = T(0), val = T(0);
 #pragma unroll
                 for (int j = 0; j < Ly::NL; ++j) {
-                    const int l = Ly::layer(1 - s, j);
-                    acc = fma(dfn[l], nbv[j][a], acc);
-                    if constexpr (COLLOC) val = fma(fvn[l], nbv[j][a], val);
-                    else if (l == (s ? 0 : N - 1)) val = nbv[j][a];
+                    const int l = Ly::layer(s, j);
+                    const T xl = Xc[face_lidx<N, D>(l, a, b)];
+                    acc = fma(dfs[l], xl, acc);
+                    if constexpr (COLLOC) val = fma(fvs[l], xl, val);
                 }
-                vp[a] = val;
-                np[a] = acc;
+                if constexpr (!COLLOC) val = Xc[face_lidx<N, D>(s ? N - 1 : 0, a, b)];
+                vm[a] = val;
+                nm[a] = acc;
             }
-            s_apply<N, COLLOC>(tab + TL.S, vp, r);
-            o = fel(2, D, c, s) + row;
+            s_apply<N, COLLOC>(tab + TL.S, vm, r);
+            put_row(FV, r);
+            eo_apply<N, -1>(tab + TL.SG, vm, r);
+            put_row(FT, r);
+            s_apply<N, COLLOC>(tab + TL.S, nm, r);
+            put_row(FN, r);
+            if (interior) {
+                // neighbour side: its value layer touches the face; its
+                // derivative row combines the layers loaded at kernel start
+                if (D == 0 && (s ? c + 1 < ncb : c > 0)) {
+                    // the x-neighbour is the adjacent cell of this workgroup
+                    const T* Xn = ldsX + (s ? c + 1 : c - 1) * CS;
 #pragma unroll
-            for (int a = 0; a < N; ++a) o[a] = r[a];
-            eo_apply<N, -1>(tab + TL.SG, vp, r);
-            o = fel(5, D, c, s) + row;
+                    for (int j = 0; j < Ly::NL; ++j) {
+                        const int l = Ly::layer(1 - s, j);
 #pragma unroll
-            for (int a = 0; a < N; ++a) o[a] = r[a];
-            s_apply<N, COLLOC>(tab + TL.S, np, r);
-            o = fel(3, D, c, s) + row;
+                        for (int a = 0; a < N; ++a) nbv[j][a] = Xn[face_lidx<N, 0>(l, a, b)];
+                    }
+                }
+                const auto dfn = tab + (s ? TL.df0 : TL.df1);
+                const auto fvn = tab + (s ? TL.FV0 : TL.FV1);
 #pragma unroll
-            for (int a = 0; a < N; ++a) o[a] = r[a];
+                for (int a = 0; a < N; ++a) {
+                    T acc = T(0), val = T(0);
+#pragma unroll
+                    for (int j = 0; j < Ly::NL; ++j) {
+                        const int l = Ly::layer(1 - s, j);
+                        acc = fma(dfn[l], nbv[j][a], acc);
+                        if constexpr (COLLOC) val = fma(fvn[l], nbv[j][a], val);
+                        else if (l == (s ? 0 : N - 1)) val = nbv[j][a];
+                    }
+                    vp[a] = val;
+                    np[a] = acc;
+                }
+            }
         }
-    });
-    __syncthreads();
-
-    // ----------------- F: along t2: S, D, flux at the points, S^T / D^T
-    by_direction(wave, [&](auto dc) {
-        constexpr int D = decltype(dc)::value;
-        constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
-        if (!fact) return;
-        const int a = fab;                 // this lane's column
-        const int s = fs, c = fc, f = 2 * D + s;
-        if constexpr (!EARLY) load_frec(dc);
-        auto col = [&](int sl, T* v) {
-            const T* src = fel(sl, D, c, s) + a;
-#pragma unroll
-            for (int b = 0; b < N; ++b) v[b] = src[b * FR];
-        };
-        T um[N], gdm[N], g1m[N], g2m[N];
-        col(0, um);  s_apply<N, COLLOC>(tab + TL.S, um, um);
-        col(1, gdm); s_apply<N, COLLOC>(tab + TL.S, gdm, gdm);
-        col(4, g1m); s_apply<N, COLLOC>(tab + TL.S, g1m, g1m);
-        eo_apply<N, -1>(tab + TL.D, um, g2m);
-        T up[N], gdp[N], g1p[N], g2p[N];
-        const bool interior = fnb >= 0;
-        if (interior) {
-            col(2, up);  s_apply<N, COLLOC>(tab + TL.S, up, up);
-            col(3, gdp); s_apply<N, COLLOC>(tab + TL.S, gdp, gdp);
-            col(5, g1p); s_apply<N, COLLOC>(tab + TL.S, g1p, g1p);
-            eo_apply<N, -1>(tab + TL.D, up, g2p);
-        } else {
-            // mirror principle: u+ = -u-, grad u+ = grad u-
-#pragma unroll
-            for (int b = 0; b < N; ++b) { up[b] = -um[b]; gdp[b] = gdm[b]; g1p[b] = g1m[b]; g2p[b] = g2m[b]; }
-        }
-        T wa = T(1);
-        if constexpr (GEOM == GEOM_CELL) wa = pick<N>(tab + TL.w, a);
-        // own side (g-) and neighbour side (g+) scaled normals in the cell's
-        // reference coordinates; the stored record uses the normal pointing
-        // from the lower to the upper cell of the face.
+        wave_sync();
+        // Face record at point b of this lane's column (without the point
+        // weight for per-cell records, which multiplies the flux outputs):
+        // penalty term, own side (g-) and neighbour side (g+) scaled normals
+        // in the cell's reference coordinates.  The stored normal points from
+        // the lower to the upper cell of the face; sg turns it outward for
+        // this side and is applied once per point.
         const T sg = s ? T(1) : T(-1);
-        T vv[N], wd[N], w1[N], w2[N];
+        auto pen = [&](int b) -> T { return GEOM == GEOM_CELL ? frec[0] : frec[b]; };
+        auto gmn = [&](int k, int b) -> T { return GEOM == GEOM_CELL ? frec[1 + k] : frec[(1 + k) * N + b]; };
+        auto gpn = [&](int k, int b) -> T { return GEOM == GEOM_CELL ? frec[4 + k] : frec[(4 + k) * N + b]; };
+        // ---- F1: own side along t2 at the face points (u, and du/dn, du/dt1
+        // by S, du/dt2 by D after S), reduced to u- and the normal flux
+        // g-.grad u-.  On a boundary face the mirror principle gives the
+        // neighbour the same gradient and the same scaled normal, so its
+        // normal flux equals the own one.
+        T um[N], dsum[N];
+        if (fact) {
+            if constexpr (!EARLY) load_frec(dc, 1);
+            T gdm[N], g1m[N], g2m[N];
+            col(FV, um);  s_apply<N, COLLOC>(tab + TL.S, um, um);
+            col(FN, gdm); s_apply<N, COLLOC>(tab + TL.S, gdm, gdm);
+            col(FT, g1m); s_apply<N, COLLOC>(tab + TL.S, g1m, g1m);
+            eo_apply<N, -1>(tab + TL.D, um, g2m);
 #pragma unroll
-        for (int b = 0; b < N; ++b) {
-            T rec[7];
-            if constexpr (GEOM == GEOM_CELL) {
-                const T jw = wa * tab[TL.w + b];
-#pragma unroll
-                for (int k = 0; k < 7; ++k) rec[k] = frec[k] * jw;
-            } else {
-#pragma unroll
-                for (int k = 0; k < 7; ++k) rec[k] = frec[k * N + b];
+            for (int b = 0; b < N; ++b) {
+                const T dm = gmn(D, b) * gdm[b] + gmn(t1, b) * g1m[b] + gmn(t2, b) * g2m[b];
+                dsum[b] = interior ? dm : dm + dm;
             }
-            T gm[3], gp[3];
-#pragma unroll
-            for (int k = 0; k < 3; ++k) {
-                gm[k] = sg * (s ? rec[1 + k] : rec[4 + k]);
-                gp[k] = sg * (s ? rec[4 + k] : rec[1 + k]);
-            }
-            const T jump = um[b] - up[b];
-            const T dm = gm[D] * gdm[b] + gm[t1] * g1m[b] + gm[t2] * g2m[b];
-            const T dp = gp[D] * gdp[b] + gp[t1] * g1p[b] + gp[t2] * g2p[b];
-            vv[b] = rec[0] * jump - T(0.5) * (dm + dp);
-            const T hj = T(-0.5) * jump;
-            wd[b] = hj * gm[D];
-            w1[b] = hj * gm[t1];
-            w2[b] = hj * gm[t2];
         }
-        // integration, t2 part: a'' = S^T (v + D^T w_t2), c'' = S^T w_t1, b'' = S^T w_d
-        T tmp[N];
-        eo_apply<N, -1>(tab + TL.DT, w2, tmp);
+        wave_sync();
+        // ---- G2: neighbour rows along t1
+        if (fact) {
+            if constexpr (!EARLY) load_frec(dc, 2);
+            if (interior) {
+                s_apply<N, COLLOC>(tab + TL.S, vp, r);
+                put_row(FV, r);
+                eo_apply<N, -1>(tab + TL.SG, vp, r);
+                put_row(FT, r);
+                s_apply<N, COLLOC>(tab + TL.S, np, r);
+                put_row(FN, r);
+            }
+        }
+        wave_sync();
+        // ---- F2: neighbour side along t2, flux at the points, S^T / D^T
+        // along t2
+        if (fact) {
+            const int a = rc;                  // this lane's column
+            T up[N];
+            if (interior) {
+                T gdp[N], g1p[N], g2p[N];
+                col(FV, up);  s_apply<N, COLLOC>(tab + TL.S, up, up);
+                col(FN, gdp); s_apply<N, COLLOC>(tab + TL.S, gdp, gdp);
+                col(FT, g1p); s_apply<N, COLLOC>(tab + TL.S, g1p, g1p);
+                eo_apply<N, -1>(tab + TL.D, up, g2p);
 #pragma unroll
-        for (int b = 0; b < N; ++b) vv[b] += tmp[b];
-        s_apply<N, COLLOC>(tab + TL.ST, vv, vv);
-        s_apply<N, COLLOC>(tab + TL.ST, w1, w1);
-        s_apply<N, COLLOC>(tab + TL.ST, wd, wd);
-        T* s0 = fel(0, D, c, s) + a;
-        T* s1 = fel(1, D, c, s) + a;
-        T* s2 = fel(2, D, c, s) + a;
+                for (int b = 0; b < N; ++b) dsum[b] += gpn(D, b) * gdp[b] + gpn(t1, b) * g1p[b] + gpn(t2, b) * g2p[b];
+            } else {
+                // mirror principle: u+ = -u-
 #pragma unroll
-        for (int b = 0; b < N; ++b) { s0[b * FR] = vv[b]; s1[b * FR] = w1[b]; s2[b * FR] = wd[b]; }
+                for (int b = 0; b < N; ++b) up[b] = -um[b];
+            }
+            T vv[N], wd[N], w1[N], w2[N];
+            const T hs = T(-0.5) * sg;
+#pragma unroll
+            for (int b = 0; b < N; ++b) {
+                const T jump = um[b] - up[b];
+                vv[b] = pen(b) * jump + hs * dsum[b];
+                const T hj = hs * jump;
+                wd[b] = hj * gmn(D, b);
+                w1[b] = hj * gmn(t1, b);
+                w2[b] = hj * gmn(t2, b);
+                if constexpr (GEOM == GEOM_CELL) {
+                    const T jw = pick<N>(tab + TL.w, a) * tab[TL.w + b];
+                    vv[b] *= jw; wd[b] *= jw; w1[b] *= jw; w2[b] *= jw;
+                }
+            }
+            // integration, t2 part: a'' = S^T (v + D^T w_t2), c'' = S^T w_t1, b'' = S^T w_d
+            T tmp[N];
+            eo_apply<N, -1>(tab + TL.DT, w2, tmp);
+#pragma unroll
+            for (int b = 0; b < N; ++b) vv[b] += tmp[b];
+            s_apply<N, COLLOC>(tab + TL.ST, vv, vv);
+            s_apply<N, COLLOC>(tab + TL.ST, w1, w1);
+            s_apply<N, COLLOC>(tab + TL.ST, wd, wd);
+            T* s0 = fel(FV, D, c, s) + a;
+            T* s1 = fel(FT, D, c, s) + a;
+            T* s2 = fel(FN, D, c, s) + a;
+#pragma unroll
+            for (int b = 0; b < N; ++b) { s0[b * FR] = vv[b]; s1[b * FR] = w1[b]; s2[b * FR] = wd[b]; }
+        }
     });
 
     // Cell metric terms of this thread's z pencil (used in C5).
@@ -457,14 +509,14 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     if constexpr (EARLY) {
         if (act) load_gpre();
     }
-    __syncthreads();
+    wave_sync();
 
-    // ----------------------- I: along t1: S^T / D^T -> P (array 0), Q (array 1)
+    // ----------------------- I: along t1: S^T / D^T -> P (array FV), Q (array FT)
     if (fact) {
         const int b = fab;
-        T* s0 = fel(0, wave, fc, fs) + b * FR;
-        T* s1 = fel(1, wave, fc, fs) + b * FR;
-        const T* s2 = fel(2, wave, fc, fs) + b * FR;
+        T* s0 = fel(FV, wave, fc, fs) + b * FR;
+        T* s1 = fel(FT, wave, fc, fs) + b * FR;
+        const T* s2 = fel(FN, wave, fc, fs) + b * FR;
         T av[N], cv[N], bv[N];
 #pragma unroll
         for (int a = 0; a < N; ++a) { av[a] = s0[a]; cv[a] = s1[a]; bv[a] = s2[a]; }
@@ -480,7 +532,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 
     // ================================================================ cell
     T* A = ldsX + (act ? c : 0) * CS;
-    T* B = ldsF + 6 * Sh::FARR + (act ? c : 0) * CS;
+    T* B = ldsF + 6 * Sh::FARR + (act ? c : 0) * CS;    // from the FN arrays on
     T* C = B + CPB * CS;
     T v[N];
     // C1: z pencils (thread (i1, i2)) : S along z
@@ -597,15 +649,15 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, tb, k)];
         s_apply<N, COLLOC>(tab + TL.ST, v, v);
         const int i1 = ta, i2 = tb;
-        const T* df0 = tab + TL.df0;
-        const T* df1 = tab + TL.df1;
+        const auto df0 = tab + TL.df0;
+        const auto df1 = tab + TL.df1;
         const T cx0 = pick<N>(df0, i1), cx1 = pick<N>(df1, i1);
         const T cy0 = pick<N>(df0, i2), cy1 = pick<N>(df1, i2);
         const bool hx0 = BASIS != 0 || i1 <= 1, hx1 = BASIS != 0 || i1 >= N - 2;
         const bool hy0 = BASIS != 0 || i2 <= 1, hy1 = BASIS != 0 || i2 >= N - 2;
         // value test rows: unit rows at the end layers, or dense (Gauss)
-        const T* fv0 = tab + TL.FV0;
-        const T* fv1 = tab + TL.FV1;
+        const auto fv0 = tab + TL.FV0;
+        const auto fv1 = tab + TL.FV1;
         const T vx0 = COLLOC ? pick<N>(fv0, i1) : T(i1 == 0), vx1 = COLLOC ? pick<N>(fv1, i1) : T(i1 == N - 1);
         const T vy0 = COLLOC ? pick<N>(fv0, i2) : T(i2 == 0), vy1 = COLLOC ? pick<N>(fv1, i2) : T(i2 == N - 1);
         const T* P0 = fel(0, 0, c, 0); const T* Q0 = fel(1, 0, c, 0);

@@ -30,12 +30,14 @@ __host__ __device__ constexpr int face_row_stride(int n) {
 }
 
 // Dynamic LDS bytes of the matrix-free kernel (must match Shape<N> in
-// matvec.hpp): the x/work array of every cell plus 18 face arrays (6 per
-// direction) of n rows; the cell arrays B, C alias 12 of the face arrays.
+// matvec.hpp): the x/work array of every cell plus 9 face arrays (3 per
+// direction) of n rows; the cell arrays B, C start at the seventh face array.
 __host__ __device__ constexpr size_t matvec_lds_bytes_rt(int n, int esz) {
     const int rs = (n % 2 == 0) ? n + 1 : n;
     const int cs = rs * n * n;
-    return size_t(cells_per_block(n) * cs + 18 * n * face_row_stride(n)) * esz;
+    const int cells = cells_per_block(n) * cs, farr = n * face_row_stride(n);
+    const int faces = 9 * farr > 6 * farr + 2 * cells ? 9 * farr : 6 * farr + 2 * cells;
+    return size_t(cells + faces) * esz;
 }
 
 // ---------------------------------------------------------------------------

@@ -6,13 +6,25 @@
 
 namespace sipg {
 
+// Read-only coefficient tables seen through the constant address space: the
+// compiler then always reads wavefront-uniform entries with scalar loads into
+// scalar registers (for global pointers it has to prove that no store of the
+// kernel may reach them first, and with many LDS stores it may not).
+template <typename T>
+using const_ptr = const __attribute__((address_space(4))) T*;
+template <typename T>
+__device__ __forceinline__ const_ptr<T> ctab(const T* p) {
+    return (const_ptr<T>)p;
+}
+
 // out = M in for an n x n matrix in even-odd packed form (sipg_common.hpp),
 // with M[n-1-q][n-1-j] = EPS M[q][j].  Costs about n^2/2 multiply-adds
 // instead of n^2 (even-odd decomposition, Section 4.1 / Section 5).
 // `in` and `out` may be the same array.  P must be a wavefront-uniform
-// pointer so that the coefficients come through scalar loads.
-template <int N, int EPS, typename T>
-__device__ __forceinline__ void eo_apply(const T* __restrict__ P, const T* in, T* out) {
+// pointer so that the coefficients come through scalar loads (a pointer to
+// the constant address space, ctab(), guarantees them).
+template <int N, int EPS, typename T, typename PT>
+__device__ __forceinline__ void eo_apply(PT P, const T* in, T* out) {
     constexpr int H = N / 2;
     constexpr int oA = 0, oB = H * H, oC = 2 * H * H, oR = 2 * H * H + H, oM = 2 * H * H + 2 * H;
     T e[H], o[H];
@@ -56,8 +68,8 @@ __device__ __forceinline__ void eo_apply(const T* __restrict__ P, const T* in, T
 
 // An interpolation-type sweep (S or S^T) that is the identity for a basis
 // collocated with the quadrature (nodal Gauss basis, S = I, Section 4.1).
-template <int N, bool IDENTITY, typename T>
-__device__ __forceinline__ void s_apply(const T* __restrict__ P, const T* in, T* out) {
+template <int N, bool IDENTITY, typename T, typename PT>
+__device__ __forceinline__ void s_apply(PT P, const T* in, T* out) {
     if constexpr (IDENTITY) {
 #pragma unroll
         for (int i = 0; i < N; ++i) out[i] = in[i];
@@ -123,9 +135,9 @@ __device__ __forceinline__ void fdm_bwd(const T* __restrict__ P, T* v) {
 }
 
 // P[i] for a lane-varying index 0 <= i < N, from uniform (scalar) loads.
-template <int N, typename T>
-__device__ __forceinline__ T pick(const T* __restrict__ P, int i) {
-    T r = P[0];
+template <int N, typename PT>
+__device__ __forceinline__ auto pick(PT P, int i) {
+    auto r = P[0];
 #pragma unroll
     for (int j = 1; j < N; ++j) r = (i == j) ? P[j] : r;
     return r;
