@@ -285,8 +285,9 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     by_direction(wave, [&](auto dc) {
         constexpr int D = decltype(dc)::value;
         if (!fact) return;
-        if constexpr (EARLY) load_frec(dc, 3);
-        // x-neighbours inside the workgroup are read from the x tile in G
+        // x-neighbours inside the workgroup are read from the x tile in G1;
+        // the neighbour layers go first, as G1 needs them before F1 needs
+        // the face records
         if (fnb >= 0 && !(D == 0 && (fs ? fc + 1 < ncb : fc > 0))) {
             const T* __restrict__ xn = p.x + size_t(fnb) * N3;
 #pragma unroll
@@ -296,6 +297,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 for (int a = 0; a < N; ++a) nbv[j][a] = xn[face_gidx<N, D>(l, a, fab)];
             }
         }
+        if constexpr (EARLY) load_frec(dc, 3);
     });
     // --------------------------------------------------------------- x tile
     // (loaded into registers at kernel start, with every other load of the
@@ -412,14 +414,19 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         T um[N], dsum[N];
         if (fact) {
             if constexpr (!EARLY) load_frec(dc, 1);
-            T gdm[N], g1m[N], g2m[N];
-            col(FV, um);  s_apply<N, COLLOC>(tab + TL.S, um, um);
-            col(FN, gdm); s_apply<N, COLLOC>(tab + TL.S, gdm, gdm);
-            col(FT, g1m); s_apply<N, COLLOC>(tab + TL.S, g1m, g1m);
-            eo_apply<N, -1>(tab + TL.D, um, g2m);
+            // one derivative component at a time: u, du/dt2 = D u, du/dn, du/dt1
+            T g[N];
+            col(FV, um); s_apply<N, COLLOC>(tab + TL.S, um, um);
+            eo_apply<N, -1>(tab + TL.D, um, g);
+#pragma unroll
+            for (int b = 0; b < N; ++b) dsum[b] = gmn(t2, b) * g[b];
+            col(FN, g); s_apply<N, COLLOC>(tab + TL.S, g, g);
+#pragma unroll
+            for (int b = 0; b < N; ++b) dsum[b] = fma(gmn(D, b), g[b], dsum[b]);
+            col(FT, g); s_apply<N, COLLOC>(tab + TL.S, g, g);
 #pragma unroll
             for (int b = 0; b < N; ++b) {
-                const T dm = gmn(D, b) * gdm[b] + gmn(t1, b) * g1m[b] + gmn(t2, b) * g2m[b];
+                const T dm = fma(gmn(t1, b), g[b], dsum[b]);
                 dsum[b] = interior ? dm : dm + dm;
             }
         }
@@ -443,13 +450,17 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
             const int a = rc;                  // this lane's column
             T up[N];
             if (interior) {
-                T gdp[N], g1p[N], g2p[N];
-                col(FV, up);  s_apply<N, COLLOC>(tab + TL.S, up, up);
-                col(FN, gdp); s_apply<N, COLLOC>(tab + TL.S, gdp, gdp);
-                col(FT, g1p); s_apply<N, COLLOC>(tab + TL.S, g1p, g1p);
-                eo_apply<N, -1>(tab + TL.D, up, g2p);
+                T g[N];
+                col(FV, up); s_apply<N, COLLOC>(tab + TL.S, up, up);
+                eo_apply<N, -1>(tab + TL.D, up, g);
 #pragma unroll
-                for (int b = 0; b < N; ++b) dsum[b] += gpn(D, b) * gdp[b] + gpn(t1, b) * g1p[b] + gpn(t2, b) * g2p[b];
+                for (int b = 0; b < N; ++b) dsum[b] = fma(gpn(t2, b), g[b], dsum[b]);
+                col(FN, g); s_apply<N, COLLOC>(tab + TL.S, g, g);
+#pragma unroll
+                for (int b = 0; b < N; ++b) dsum[b] = fma(gpn(D, b), g[b], dsum[b]);
+                col(FT, g); s_apply<N, COLLOC>(tab + TL.S, g, g);
+#pragma unroll
+                for (int b = 0; b < N; ++b) dsum[b] = fma(gpn(t1, b), g[b], dsum[b]);
             } else {
                 // mirror principle: u+ = -u-
 #pragma unroll
@@ -487,10 +498,19 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     });
 
     // Cell metric terms of this thread's z pencil (used in C5).
-    const int c = tid / N2;                 // cell of this thread in the cell phases
-    const int t = tid % N2;                 // pencil of this thread
+    // Cell steps: thread -> (cell c, pencil t).  Where a wavefront holds whole
+    // cells (WAVE_CELLS), wavefront w owns cells w CPW ..., so the cell steps
+    // only need wavefront-level syncs.
+    constexpr int CPW = 64 / N2;
+    constexpr bool WAVE_CELLS = 3 * CPW >= CPB;
+    const int c = WAVE_CELLS ? wave * CPW + lane / N2 : tid / N2;   // cell of this thread in the cell steps
+    const int t = WAVE_CELLS ? lane % N2 : tid % N2;                // pencil of this thread
     const int ta = t % N, tb = t / N;
-    const bool act = c < ncb;
+    const bool act = (!WAVE_CELLS || lane < CPW * N2) && c < ncb;
+    auto cell_sync = [&]() {
+        if constexpr (WAVE_CELLS) wave_sync();
+        else __syncthreads();
+    };
     constexpr int NG = GEOM == GEOM_CELL ? 6 : 6 * N;
     T gpre[NG];
     auto load_gpre = [&]() {
@@ -543,7 +563,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, tb, k)] = v[k];
     }
-    __syncthreads();
+    cell_sync();
     // C2: y pencils (thread (i1, q3)) : S along y
     if (act && !COLLOC) {
 #pragma unroll
@@ -552,7 +572,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, k, tb)] = v[k];
     }
-    __syncthreads();
+    cell_sync();
     // C3: x pencils (thread (q2, q3)) : S along x -> u; D along x -> du/dxi1
     if (act) {
         T g[N];
@@ -563,7 +583,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
         for (int k = 0; k < N; ++k) { A[Sh::lds_idx(k, ta, tb)] = v[k]; B[Sh::lds_idx(k, ta, tb)] = g[k]; }
     }
-    __syncthreads();
+    cell_sync();
     // C4: y pencils : D along y -> du/dxi2
     if (act) {
         if constexpr (!EARLY) load_gpre();
@@ -573,7 +593,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
         for (int k = 0; k < N; ++k) C[Sh::lds_idx(ta, k, tb)] = v[k];
     }
-    __syncthreads();
+    cell_sync();
     // C5: z pencils (thread (q1, q2)) : D along z -> du/dxi3, metric, D^T along z
     if (act) {
         T g1[N], g2[N], g3[N];
@@ -610,7 +630,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
             C[Sh::lds_idx(ta, tb, k)] = g2[k];
         }
     }
-    __syncthreads();
+    cell_sync();
     // C6: y pencils : r += D^T t2
     if (act) {
         T g[N];
@@ -620,7 +640,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, k, tb)] = v[k] + g[k];
     }
-    __syncthreads();
+    cell_sync();
     // C7: x pencils : r += D^T t1, then S^T along x
     if (act) {
         T g[N];
@@ -633,7 +653,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::lds_idx(k, ta, tb)] = v[k];
     }
-    __syncthreads();
+    cell_sync();
     // C8: y pencils : S^T along y
     if (act && !COLLOC) {
 #pragma unroll
@@ -642,7 +662,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
         for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, k, tb)] = v[k];
     }
-    __syncthreads();
+    cell_sync();
     // C9: z pencils (thread (i1, i2)) : S^T along z, add face terms, write y
     if (act) {
 #pragma unroll
