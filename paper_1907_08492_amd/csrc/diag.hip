@@ -74,7 +74,7 @@ __global__ void gl_diagonal_kernel(const T* __restrict__ tab, int n, const T* __
                     const double wq = double(w[qa]) * double(w[qb]);
                     for (int k = 0; k < 7; ++k) rec[k] = double(fg[fidx * 8 + k]) * wq;
                 } else {
-                    for (int k = 0; k < 7; ++k) rec[k] = double(fg[fidx * 7 * n2 + k * n2 + qa + n * qb]);
+                    for (int k = 0; k < 7; ++k) rec[k] = double(fg[fidx * 7 * n2 + k * n2 + qb + n * qa]);
                 }
                 double gm[3];
                 for (int k = 0; k < 3; ++k) gm[k] = s ? rec[1 + k] : -rec[4 + k];

@@ -265,20 +265,16 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 for (int k = 0; k < 3; ++k) frec[4 + k] = r[nb + k];
             }
         } else {
-            const T* __restrict__ r = fg + size_t(fidx) * (7 * N2) + fab;
+            // record [value k][column a][point b]: this lane's column is a run
+            const T* __restrict__ r = fg + size_t(fidx) * (7 * N2) + N * fab;
             if (part & 1) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int b = 0; b < N; ++b) frec[(1 + k) * N + b] = r[(own + k) * N2 + N * b];
+                for (int k = 0; k < 3; ++k) load_run<N>(r + (own + k) * N2, frec + (1 + k) * N);
             }
             if (part & 2) {
+                load_run<N>(r, frec);
 #pragma unroll
-                for (int b = 0; b < N; ++b) frec[b] = r[N * b];
-#pragma unroll
-                for (int k = 0; k < 3; ++k)
-#pragma unroll
-                    for (int b = 0; b < N; ++b) frec[(4 + k) * N + b] = r[(nb + k) * N2 + N * b];
+                for (int k = 0; k < 3; ++k) load_run<N>(r + (nb + k) * N2, frec + (4 + k) * N);
             }
         }
     };
@@ -289,12 +285,21 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         // the neighbour layers go first, as G1 needs them before F1 needs
         // the face records
         if (fnb >= 0 && !(D == 0 && (fs ? fc + 1 < ncb : fc > 0))) {
+            // runs of consecutive values: the layers (x faces, whose layers
+            // are contiguous), else each layer's row
             const T* __restrict__ xn = p.x + size_t(fnb) * N3;
+            if constexpr (D == 0) {
+                const int l0 = Ly::layer(1 - fs, 0);
 #pragma unroll
-            for (int j = 0; j < Ly::NL; ++j) {
-                const int l = Ly::layer(1 - fs, j);
+                for (int a = 0; a < N; ++a) {
+                    T run[Ly::NL];
+                    load_run<Ly::NL>(xn + face_gidx<N, 0>(l0, a, fab), run);
 #pragma unroll
-                for (int a = 0; a < N; ++a) nbv[j][a] = xn[face_gidx<N, D>(l, a, fab)];
+                    for (int j = 0; j < Ly::NL; ++j) nbv[j][a] = run[j];
+                }
+            } else {
+#pragma unroll
+                for (int j = 0; j < Ly::NL; ++j) load_run<N>(xn + face_gidx<N, D>(Ly::layer(1 - fs, j), 0, fab), nbv[j]);
             }
         }
         if constexpr (EARLY) load_frec(dc, 3);

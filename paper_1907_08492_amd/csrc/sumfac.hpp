@@ -134,6 +134,24 @@ __device__ __forceinline__ void fdm_bwd(const T* __restrict__ P, T* v) {
     for (int m = 0; m < N; ++m) v[m] = r[m];
 }
 
+// dst[0..M) = src[0..M) with 16-byte loads where possible (global memory on
+// gfx950 takes them at element alignment), fewer load instructions and cache
+// accesses for a lane's run of consecutive values.
+template <int M, typename T>
+__device__ __forceinline__ void load_run(const T* __restrict__ src, T* dst) {
+    constexpr int V = 16 / int(sizeof(T));
+    typedef T vec __attribute__((ext_vector_type(V), aligned(sizeof(T))));
+    int i = 0;
+#pragma unroll
+    for (; i + V <= M; i += V) {
+        const vec v = *reinterpret_cast<const vec*>(src + i);
+#pragma unroll
+        for (int j = 0; j < V; ++j) dst[i + j] = v[j];
+    }
+#pragma unroll
+    for (; i < M; ++i) dst[i] = src[i];
+}
+
 // P[i] for a lane-varying index 0 <= i < N, from uniform (scalar) loads.
 template <int N, typename PT>
 __device__ __forceinline__ auto pick(PT P, int i) {
