@@ -51,9 +51,10 @@ def alg_bytes_per_dof(mesh, k: int, esz: int, per_point: bool) -> float:
     return esz * (2.0 + (cell + face) / ndofs)
 
 
+# the kernel, and setup.hip, which lays out the metric terms it reads
 KERNEL_SOURCES = ["paper_1907_08492_amd/csrc/matvec.hpp", "paper_1907_08492_amd/csrc/sumfac.hpp",
                   "paper_1907_08492_amd/csrc/sipg_common.hpp", "paper_1907_08492_amd/csrc/matvec_launch.hpp",
-                  "paper_1907_08492_amd/csrc/matvec_n5.hip"]
+                  "paper_1907_08492_amd/csrc/matvec_n5.hip", "paper_1907_08492_amd/csrc/setup.hip"]
 TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sipg_matvec_k4_64c_deformed_f64.traffic.json")
 
 
