@@ -13,14 +13,17 @@
 //   G1  gather the own value/derivative layers (LDS), combine them with S_f
 //       and D_f and interpolate along t1 (S, and S' for values); combine the
 //       neighbour's layers (registers loaded at kernel start: two layers for
-//       the Hermite-like basis, all n for the nodal bases) likewise
-//   F1  own side along t2 (S, and D for the tangential derivative), kept in
-//       registers
+//       the Hermite-like basis, all n for the nodal bases) into its value
+//       and derivative rows
+//   F1  own side along t2 (S, and D for the tangential derivative), reduced
+//       to u- and the normal flux at the face Gauss points, kept in registers
 //   G2  neighbour side along t1, written over the own side's arrays
 //   F2  neighbour side along t2, flux at the face Gauss points, transposed
 //       sweeps along t2
 //   I   transposed sweeps along t1 -> P (value test) and Q (normal-derivative
 //       test) coefficient arrays of the face
+// The face steps of a direction stay inside its wavefront (wavefront-level
+// syncs); where a wavefront holds whole cells, so do the cell steps.
 // Cell integral: S along z, y, x, collocation D along x, y, z (eq.
 // tensor_cell), merged metric at the points (eq. integral_laplace),
 // transposed sweeps back; the last sweep adds e_layer (x) P + D_f (x) Q of
