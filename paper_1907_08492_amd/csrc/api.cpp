@@ -81,6 +81,21 @@ static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl, const st
         tab[L.FV1 + i] = T(t.v1[i]);
     }
     for (size_t i = 0; i < fzp.size(); ++i) tab[L.FZP + i] = T(fzp[i]);
+    // 1D face matrices of the affine (reference-coordinate) face terms, by
+    // the n-point Gauss rule, which integrates these degree <= 2p products
+    // exactly: M_ij = (phi_i, phi_j), Ct_ij = (phi_i, phi_j'), Cs_ij = (phi_i', phi_j)
+    std::vector<double> M(size_t(n) * n, 0.0), Ct(size_t(n) * n, 0.0), Cs(size_t(n) * n, 0.0);
+    for (int i = 0; i < n; ++i)
+        for (int j = 0; j < n; ++j)
+            for (int q = 0; q < n; ++q) {
+                const double w = t.weights[q];
+                M[i * n + j] += w * t.S[q * n + i] * t.S[q * n + j];
+                Ct[i * n + j] += w * t.S[q * n + i] * t.Sg[q * n + j];
+                Cs[i * n + j] += w * t.Sg[q * n + i] * t.S[q * n + j];
+            }
+    pack_eo<T>(M, n, +1, &tab[L.MM]);
+    pack_eo<T>(Ct, n, -1, &tab[L.CT]);
+    pack_eo<T>(Cs, n, -1, &tab[L.CS]);
     return tab;
 }
 

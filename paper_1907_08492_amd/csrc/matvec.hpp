@@ -327,6 +327,10 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     // side's arrays are consumed (F1) before the neighbour side's are written
     // (G2) into the same place.
     constexpr int FV = 0, FT = 1, FN = 2;
+    // Per-cell (affine) records use the reference-coordinate face step below,
+    // except for the nodal bases at n >= 8, whose n^2 neighbour values per
+    // lane leave too few registers for it.
+    constexpr bool KRON = GEOM == GEOM_CELL && (BASIS == 0 || N <= 7);
     by_direction(wave, [&](auto dc) {
         constexpr int D = decltype(dc)::value;
         constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
@@ -343,16 +347,23 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
             for (int q = 0; q < N; ++q) v[q] = src[q * FR];
         };
-        // ---- G1: own value and normal-derivative layers of row rc, S and S'
-        // along t1; the neighbour's layers combined into its value and
-        // derivative rows (vp, np) for G2
-        T vp[N], np[N];
-        if (fact) {
+        // Face record of this lane's face: penalty term, own side (g-) and
+        // neighbour side (g+) scaled normals in the cell's reference
+        // coordinates, at point b of the lane's column (per-point records) or
+        // constant (per-cell records, without the point weights).  The stored
+        // normal points from the lower to the upper cell of the face; sg turns
+        // it outward for this side and is applied once per point.
+        const T sg = s ? T(1) : T(-1);
+        auto pen = [&](int b) -> T { return GEOM == GEOM_CELL ? frec[0] : frec[b]; };
+        auto gmn = [&](int k, int b) -> T { return GEOM == GEOM_CELL ? frec[1 + k] : frec[(1 + k) * N + b]; };
+        auto gpn = [&](int k, int b) -> T { return GEOM == GEOM_CELL ? frec[4 + k] : frec[(4 + k) * N + b]; };
+        // Row rc (points a along t1) of the own value and normal-derivative
+        // layers, combined with S_f and D_f from the LDS x tile.
+        auto own_rows = [&](T* vm, T* nm) {
             const int b = rc;
             const T* Xc = ldsX + c * CS;
             const auto dfs = tab + (s ? TL.df1 : TL.df0);
             const auto fvs = tab + (s ? TL.FV1 : TL.FV0);
-            T vm[N], nm[N];
 #pragma unroll
             for (int a = 0; a < N; ++a) {
                 T acc = T(0), val = T(0);
@@ -367,53 +378,140 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 vm[a] = val;
                 nm[a] = acc;
             }
+        };
+        // The same rows of the neighbour (interior faces): its value layer
+        // touches the face; its derivative row combines the layers loaded at
+        // kernel start, or read from the x tile for an x-neighbour inside the
+        // workgroup.
+        auto neighbour_rows = [&](T* vp, T* np) {
+            const int b = rc;
+            if (D == 0 && (s ? c + 1 < ncb : c > 0)) {
+                const T* Xn = ldsX + (s ? c + 1 : c - 1) * CS;
+#pragma unroll
+                for (int j = 0; j < Ly::NL; ++j) {
+                    const int l = Ly::layer(1 - s, j);
+#pragma unroll
+                    for (int a = 0; a < N; ++a) nbv[j][a] = Xn[face_lidx<N, 0>(l, a, b)];
+                }
+            }
+            const auto dfn = tab + (s ? TL.df0 : TL.df1);
+            const auto fvn = tab + (s ? TL.FV0 : TL.FV1);
+#pragma unroll
+            for (int a = 0; a < N; ++a) {
+                T acc = T(0), val = T(0);
+#pragma unroll
+                for (int j = 0; j < Ly::NL; ++j) {
+                    const int l = Ly::layer(1 - s, j);
+                    acc = fma(dfn[l], nbv[j][a], acc);
+                    if constexpr (COLLOC) val = fma(fvn[l], nbv[j][a], val);
+                    else if (l == (s ? 0 : N - 1)) val = nbv[j][a];
+                }
+                vp[a] = val;
+                np[a] = acc;
+            }
+        };
+        if constexpr (KRON) {
+            // ---- Affine face (constant J on the face and in both cells; the
+            // per-cell records are weight-free constants).  The face terms in
+            // reference coordinates are Kronecker products of the 1D matrices
+            // M = S^T W S, Ct = S^T W S', Cs = S'^T W S (t1 factor first),
+            // exact with the n-point Gauss rule (Section 3, affine cells):
+            //   P = (M x M) A + (Ct x M) T1 + (M x Ct) T2 + h g1 (Cs x M) J + h g2 (M x Cs) J
+            //   Q = h gn (M x M) J
+            // with J = U- - U+, A = pen J + h (gn- N- + gn+ N+),
+            // Tk = h (gk- U- + gk+ U+) and h = -sg/2; U, N the value and
+            // normal-derivative layers, g the scaled normals (mirror principle
+            // on the boundary: U+ = -U- in J, the gradient of u+ that of u-).
+            // The t1 products run along this lane's row, the t2 products along
+            // its column; no quadrature-point stage.
+            const T hs = T(-0.5) * sg;
+            if (fact) {
+                if constexpr (!EARLY) load_frec(dc, 3);
+                // gathered and combined point by point (fewer live registers)
+                const int b = rc;
+                const T* Xc = ldsX + c * CS;
+                const bool inwg = D == 0 && (s ? c + 1 < ncb : c > 0);   // x-neighbour in the workgroup
+                const T* Xn = ldsX + (s ? c + 1 : c - 1) * CS;
+                const auto dfs = tab + (s ? TL.df1 : TL.df0), fvs = tab + (s ? TL.FV1 : TL.FV0);
+                const auto dfn = tab + (s ? TL.df0 : TL.df1), fvn = tab + (s ? TL.FV0 : TL.FV1);
+                T jc[N], av[N], t1v[N], t2v[N], q[N];
+#pragma unroll
+                for (int a = 0; a < N; ++a) {
+                    T vm = T(0), nm = T(0), vp = T(0), np = T(0);
+#pragma unroll
+                    for (int j = 0; j < Ly::NL; ++j) {
+                        const int l = Ly::layer(s, j), ln = Ly::layer(1 - s, j);
+                        const T xl = Xc[face_lidx<N, D>(l, a, b)];
+                        nm = fma(dfs[l], xl, nm);
+                        if constexpr (COLLOC) vm = fma(fvs[l], xl, vm);
+                        if (interior) {
+                            const T xn = inwg ? Xn[face_lidx<N, 0>(ln, a, b)] : nbv[j][a];
+                            np = fma(dfn[ln], xn, np);
+                            if constexpr (COLLOC) vp = fma(fvn[ln], xn, vp);
+                            else if (ln == (s ? 0 : N - 1)) vp = xn;
+                        }
+                    }
+                    if constexpr (!COLLOC) vm = Xc[face_lidx<N, D>(s ? N - 1 : 0, a, b)];
+                    const T ug = interior ? vp : vm;    // u+ in its gradient
+                    const T ng = interior ? np : nm;
+                    jc[a] = interior ? vm - vp : vm + vm;
+                    av[a] = pen(0) * jc[a] + hs * (gmn(D, 0) * nm + gpn(D, 0) * ng);
+                    t1v[a] = hs * (gmn(t1, 0) * vm + gpn(t1, 0) * ug);
+                    t2v[a] = hs * (gmn(t2, 0) * vm + gpn(t2, 0) * ug);
+                }
+                eo_apply<N, +1>(tab + TL.MM, av, r);
+                eo_apply<N, -1>(tab + TL.CT, t1v, q);
+#pragma unroll
+                for (int a = 0; a < N; ++a) r[a] += q[a];
+                eo_apply<N, -1>(tab + TL.CS, jc, q);
+                const T h1 = hs * gmn(t1, 0);
+#pragma unroll
+                for (int a = 0; a < N; ++a) r[a] = fma(h1, q[a], r[a]);
+                put_row(FV, r);
+                eo_apply<N, +1>(tab + TL.MM, t2v, r);
+                put_row(FT, r);
+                eo_apply<N, +1>(tab + TL.MM, jc, r);
+                put_row(FN, r);
+            }
+            wave_sync();
+            if (fact) {
+                const int a = rc;                  // this lane's column
+                T r1[N], r2[N], mj[N], pv[N], q[N];
+                col(FV, r1);
+                col(FT, r2);
+                col(FN, mj);
+                eo_apply<N, +1>(tab + TL.MM, r1, pv);
+                eo_apply<N, -1>(tab + TL.CT, r2, q);
+#pragma unroll
+                for (int b = 0; b < N; ++b) pv[b] += q[b];
+                eo_apply<N, -1>(tab + TL.CS, mj, q);
+                const T h2 = hs * gmn(t2, 0);
+#pragma unroll
+                for (int b = 0; b < N; ++b) pv[b] = fma(h2, q[b], pv[b]);
+                eo_apply<N, +1>(tab + TL.MM, mj, q);
+                const T hn = hs * gmn(D, 0);
+                T* s0 = fel(FV, D, c, s) + a;
+                T* s1 = fel(FT, D, c, s) + a;
+#pragma unroll
+                for (int b = 0; b < N; ++b) { s0[b * FR] = pv[b]; s1[b * FR] = hn * q[b]; }
+            }
+        } else {
+        // ---- G1: own value and normal-derivative layers of row rc, S and S'
+        // along t1; the neighbour's layers combined into its value and
+        // derivative rows (vp, np) for G2
+        T vp[N], np[N];
+        if (fact) {
+            T vm[N], nm[N];
+            own_rows(vm, nm);
             s_apply<N, COLLOC>(tab + TL.S, vm, r);
             put_row(FV, r);
             eo_apply<N, -1>(tab + TL.SG, vm, r);
             put_row(FT, r);
             s_apply<N, COLLOC>(tab + TL.S, nm, r);
             put_row(FN, r);
-            if (interior) {
-                // neighbour side: its value layer touches the face; its
-                // derivative row combines the layers loaded at kernel start
-                if (D == 0 && (s ? c + 1 < ncb : c > 0)) {
-                    // the x-neighbour is the adjacent cell of this workgroup
-                    const T* Xn = ldsX + (s ? c + 1 : c - 1) * CS;
-#pragma unroll
-                    for (int j = 0; j < Ly::NL; ++j) {
-                        const int l = Ly::layer(1 - s, j);
-#pragma unroll
-                        for (int a = 0; a < N; ++a) nbv[j][a] = Xn[face_lidx<N, 0>(l, a, b)];
-                    }
-                }
-                const auto dfn = tab + (s ? TL.df0 : TL.df1);
-                const auto fvn = tab + (s ? TL.FV0 : TL.FV1);
-#pragma unroll
-                for (int a = 0; a < N; ++a) {
-                    T acc = T(0), val = T(0);
-#pragma unroll
-                    for (int j = 0; j < Ly::NL; ++j) {
-                        const int l = Ly::layer(1 - s, j);
-                        acc = fma(dfn[l], nbv[j][a], acc);
-                        if constexpr (COLLOC) val = fma(fvn[l], nbv[j][a], val);
-                        else if (l == (s ? 0 : N - 1)) val = nbv[j][a];
-                    }
-                    vp[a] = val;
-                    np[a] = acc;
-                }
-            }
+            if (interior) neighbour_rows(vp, np);
         }
         wave_sync();
-        // Face record at point b of this lane's column (without the point
-        // weight for per-cell records, which multiplies the flux outputs):
-        // penalty term, own side (g-) and neighbour side (g+) scaled normals
-        // in the cell's reference coordinates.  The stored normal points from
-        // the lower to the upper cell of the face; sg turns it outward for
-        // this side and is applied once per point.
-        const T sg = s ? T(1) : T(-1);
-        auto pen = [&](int b) -> T { return GEOM == GEOM_CELL ? frec[0] : frec[b]; };
-        auto gmn = [&](int k, int b) -> T { return GEOM == GEOM_CELL ? frec[1 + k] : frec[(1 + k) * N + b]; };
-        auto gpn = [&](int k, int b) -> T { return GEOM == GEOM_CELL ? frec[4 + k] : frec[(4 + k) * N + b]; };
         // ---- F1: own side along t2 at the face points (u, and du/dn, du/dt1
         // by S, du/dt2 by D after S), reduced to u- and the normal flux
         // g-.grad u-.  On a boundary face the mirror principle gives the
@@ -485,6 +583,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 w1[b] = hj * gmn(t1, b);
                 w2[b] = hj * gmn(t2, b);
                 if constexpr (GEOM == GEOM_CELL) {
+                    // per-cell records carry no point weights
                     const T jw = pick<N>(tab + TL.w, a) * tab[TL.w + b];
                     vv[b] *= jw; wd[b] *= jw; w1[b] *= jw; w2[b] *= jw;
                 }
@@ -503,6 +602,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
             for (int b = 0; b < N; ++b) { s0[b * FR] = vv[b]; s1[b * FR] = w1[b]; s2[b * FR] = wd[b]; }
         }
+        }   // per-point records
     });
 
     // Cell metric terms of this thread's z pencil (used in C5).
@@ -540,7 +640,8 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     wave_sync();
 
     // ----------------------- I: along t1: S^T / D^T -> P (array FV), Q (array FT)
-    if (fact) {
+    // (affine face step: P and Q are complete already)
+    if (!KRON && fact) {
         const int b = fab;
         T* s0 = fel(FV, wave, fc, fs) + b * FR;
         T* s1 = fel(FT, wave, fc, fs) + b * FR;

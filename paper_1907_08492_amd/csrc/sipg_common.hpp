@@ -58,6 +58,7 @@ struct TableLayout {
     int Sgl, SGgl, df0gl, df1gl;       // plain row-major tables of the nodal GL basis
     int FZP, FLAM;                     // block preconditioner: parity-split eigenvectors, eigenvalues
     int FV0, FV1;                      // face value rows S_f at 0 and 1
+    int MM, CT, CS;                    // even-odd packed 1D M = S^T W S, Ct = S^T W S', Cs = S'^T W S
     int total;
     __host__ __device__ constexpr TableLayout(int n_)
         : n(n_), es(eo_size(n_)), S(0), ST(es), D(2 * es), DT(3 * es), SG(4 * es),
@@ -65,7 +66,8 @@ struct TableLayout {
           Sgl(8 * es + 3 * n_), SGgl(8 * es + 3 * n_ + n_ * n_), df0gl(8 * es + 3 * n_ + 2 * n_ * n_),
           df1gl(8 * es + 4 * n_ + 2 * n_ * n_), FZP(8 * es + 5 * n_ + 2 * n_ * n_),
           FLAM(8 * es + 5 * n_ + 3 * n_ * n_), FV0(8 * es + 6 * n_ + 3 * n_ * n_),
-          FV1(8 * es + 7 * n_ + 3 * n_ * n_), total(8 * es + 8 * n_ + 3 * n_ * n_ + 1) {}
+          FV1(8 * es + 7 * n_ + 3 * n_ * n_), MM(8 * es + 8 * n_ + 3 * n_ * n_), CT(9 * es + 8 * n_ + 3 * n_ * n_),
+          CS(10 * es + 8 * n_ + 3 * n_ * n_), total(11 * es + 8 * n_ + 3 * n_ * n_ + 1) {}
 };
 
 enum GeomMode { GEOM_CELL = 1, GEOM_QPOINT = 2 };
