@@ -107,13 +107,19 @@ int sipg_destroy(sipg_op* op);
 int64_t sipg_ndofs(const sipg_op* op);
 
 /* Description of the operator (host memory).  `geometry` is the resolved
- * storage mode; `device_bytes` the operator's own device memory. */
+ * storage mode; `device_bytes` the operator's own device memory;
+ * `diagonal_metric` is 1 when the storage is per cell and every cell's
+ * merged tensor J^-1 J^-T det J is diagonal (an affine map with a diagonal
+ * linear part), in which case the cell term of the product is evaluated in
+ * reference coordinates with the 1D mass and stiffness matrices (Section 3,
+ * affine cells); such operators form their own group in a batch. */
 typedef struct {
     int32_t degree, basis, dtype, geometry;
     int32_t n[3];
     int64_t ndofs;
     int64_t device_bytes;
     int32_t cells_per_block, threads_per_block;
+    int32_t diagonal_metric;
 } sipg_op_info;
 int sipg_get_info(const sipg_op* op, sipg_op_info* info);
 
@@ -131,8 +137,9 @@ int sipg_apply(const sipg_op* op, const void* x, void* y, void* stream);
 /*
  * Batched product y_i = A_i x_i of nops independent operators (the same
  * element-wise evaluation as sipg_apply, Section 3), for many small problems
- * at once.  Operators of equal degree, basis, precision and geometry mode
- * share one grid, so a batch runs as one launch per such group.
+ * at once.  Operators of equal degree, basis, precision, geometry mode and
+ * diagonal_metric (sipg_op_info) share one grid, so a batch runs as one
+ * launch per such group.
  *   sipg_batch_create  ops[i], x[i], y[i] (host arrays of nops entries; x, y
  *                      device pointers of ops[i]'s size and precision) are
  *                      bound at creation.  The batch stores device pointers

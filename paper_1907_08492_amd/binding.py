@@ -60,7 +60,7 @@ class SipgOpInfo(C.Structure):
     _fields_ = [("degree", C.c_int32), ("basis", C.c_int32), ("dtype", C.c_int32),
                 ("geometry", C.c_int32), ("n", C.c_int32 * 3), ("ndofs", C.c_int64),
                 ("device_bytes", C.c_int64), ("cells_per_block", C.c_int32),
-                ("threads_per_block", C.c_int32)]
+                ("threads_per_block", C.c_int32), ("diagonal_metric", C.c_int32)]
 
 
 class SipgSolveInfo(C.Structure):

@@ -84,7 +84,10 @@ static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl, const st
     // 1D face matrices of the affine (reference-coordinate) face terms, by
     // the n-point Gauss rule, which integrates these degree <= 2p products
     // exactly: M_ij = (phi_i, phi_j), Ct_ij = (phi_i, phi_j'), Cs_ij = (phi_i', phi_j)
-    std::vector<double> M(size_t(n) * n, 0.0), Ct(size_t(n) * n, 0.0), Cs(size_t(n) * n, 0.0);
+    // and the 1D stiffness L_ij = (phi_i', phi_j') of the cell term with a
+    // diagonal metric
+    std::vector<double> M(size_t(n) * n, 0.0), Ct(size_t(n) * n, 0.0), Cs(size_t(n) * n, 0.0),
+        Lk(size_t(n) * n, 0.0);
     for (int i = 0; i < n; ++i)
         for (int j = 0; j < n; ++j)
             for (int q = 0; q < n; ++q) {
@@ -92,10 +95,12 @@ static std::vector<T> make_table(const Tables1D& t, const Tables1D& gl, const st
                 M[i * n + j] += w * t.S[q * n + i] * t.S[q * n + j];
                 Ct[i * n + j] += w * t.S[q * n + i] * t.Sg[q * n + j];
                 Cs[i * n + j] += w * t.Sg[q * n + i] * t.S[q * n + j];
+                Lk[i * n + j] += w * t.Sg[q * n + i] * t.Sg[q * n + j];
             }
     pack_eo<T>(M, n, +1, &tab[L.MM]);
     pack_eo<T>(Ct, n, -1, &tab[L.CT]);
     pack_eo<T>(Cs, n, -1, &tab[L.CS]);
+    pack_eo<T>(Lk, n, +1, &tab[L.LL]);
     return tab;
 }
 
@@ -215,6 +220,14 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
     op->basis = basis;
     op->dtype = dtype;
     op->geom = geometry == SIPG_GEOM_AUTO ? (mesh->deform_amp != 0.0 ? GEOM_QPOINT : GEOM_CELL) : geometry;
+    // Per-cell storage of an affine map whose linear part is diagonal (or the
+    // identity, all zero): J = L diag(h) is diagonal, so is every J^-1 J^-T det J.
+    {
+        const double* Lm = mesh->lin;
+        const bool offdiag_zero = Lm[1] == 0.0 && Lm[2] == 0.0 && Lm[3] == 0.0 && Lm[5] == 0.0 && Lm[6] == 0.0 &&
+                                  Lm[7] == 0.0;
+        op->diag_metric = op->geom == GEOM_CELL && offdiag_zero ? 1 : 0;
+    }
     op->eta = penalty_factor;
     for (int d = 0; d < 3; ++d) op->nc[d] = mesh->n[d];
     op->ncells = ncells;
@@ -316,6 +329,7 @@ int sipg_get_info(const sipg_op* op, sipg_op_info* info) {
     info->device_bytes = op->device_bytes;
     info->cells_per_block = cells_per_block(op->n);
     info->threads_per_block = threads_per_block(op->n);
+    info->diagonal_metric = op->diag_metric;
     return SIPG_OK;
 }
 

@@ -1,6 +1,7 @@
 // Batched application of many independent SIPG operators (sipg_batch_*).
 //
-// Operators are grouped by (degree, basis, precision, geometry mode); each
+// Operators are grouped by (degree, basis, precision, kernel geometry
+// variant: per point, per cell, per cell with a diagonal metric); each
 // group becomes one grid over the concatenated workgroup lists of its
 // operators, so a batch of small operators fills the 256 compute units that
 // each of them alone would leave mostly idle.  The per-operator kernel
@@ -123,10 +124,10 @@ int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x,
     std::string why;
     if (ranges_conflict(ranges, why)) { set_error("sipg_batch_create: " + why); return SIPG_E_ARG; }
 
-    // group by (n, basis, dtype, geometry); std::map gives a fixed order
+    // group by (n, basis, dtype, kernel geometry variant); std::map gives a fixed order
     std::map<std::tuple<int, int, int, int>, std::vector<int>> by_key;
     for (int i = 0; i < nops; ++i)
-        by_key[{ops[i]->n, ops[i]->basis, ops[i]->dtype, ops[i]->geom}].push_back(i);
+        by_key[{ops[i]->n, ops[i]->basis, ops[i]->dtype, matvec_geom(ops[i])}].push_back(i);
 
     auto* b = new (std::nothrow) sipg_batch;
     if (!b) { set_error("sipg_batch_create: out of host memory"); return SIPG_E_OOM; }

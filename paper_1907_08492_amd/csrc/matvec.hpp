@@ -28,6 +28,9 @@
 // tensor_cell), merged metric at the points (eq. integral_laplace),
 // transposed sweeps back; the last sweep adds e_layer (x) P + D_f (x) Q of
 // the six faces and writes y_K once.
+// Affine cells (Section 3 notes the reduction): with per-cell records the
+// face terms are Kronecker products in reference coordinates, and with a
+// diagonal metric so is the cell term.
 #pragma once
 
 #include <type_traits>
@@ -170,7 +173,7 @@ __device__ __forceinline__ void wave_sync() {
 // per-point metric terms the spill traffic would compete with the HBM
 // stream, so those keep one.
 template <int N, int GEOM>
-constexpr int matvec_min_waves() { return (N >= 7 && GEOM == GEOM_CELL) ? 2 : 1; }
+constexpr int matvec_min_waves() { return (N >= 7 && GEOM != GEOM_QPOINT) ? 2 : 1; }
 
 // XCD-aware order: consecutive workgroups are dispatched round-robin over
 // the 8 XCDs, so give each XCD a contiguous range of block indices (a range
@@ -244,7 +247,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     // records are then loaded in two parts, at the start of steps F1 and G2,
     // and the cell metric terms at the start of C4.
     constexpr bool EARLY = N <= 6 || sizeof(T) == 4;
-    constexpr int NREC = GEOM == GEOM_CELL ? 7 : 7 * N;
+    constexpr int NREC = GEOM != GEOM_QPOINT ? 7 : 7 * N;
     // frec: the penalty term, this lane's own side scaled normal (3
     // components), the neighbour side's (3); the side slots of the stored
     // record (lower cell first) are chosen here, by the load addresses.
@@ -256,7 +259,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         constexpr int D = decltype(dc)::value;
         const T* __restrict__ fg = D == 0 ? p.fgeom0 : D == 1 ? p.fgeom1 : p.fgeom2;
         const int own = fs ? 1 : 4, nb = fs ? 4 : 1;
-        if constexpr (GEOM == GEOM_CELL) {
+        if constexpr (GEOM != GEOM_QPOINT) {
             const T* __restrict__ r = fg + size_t(fidx) * 8;
             if (part & 1) {
 #pragma unroll
@@ -330,7 +333,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     // Per-cell (affine) records use the reference-coordinate face step below,
     // except for the nodal bases at n >= 8, whose n^2 neighbour values per
     // lane leave too few registers for it.
-    constexpr bool KRON = GEOM == GEOM_CELL && (BASIS == 0 || N <= 7);
+    constexpr bool KRON = GEOM != GEOM_QPOINT && (BASIS == 0 || N <= 7);
     by_direction(wave, [&](auto dc) {
         constexpr int D = decltype(dc)::value;
         constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
@@ -354,9 +357,9 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         // normal points from the lower to the upper cell of the face; sg turns
         // it outward for this side and is applied once per point.
         const T sg = s ? T(1) : T(-1);
-        auto pen = [&](int b) -> T { return GEOM == GEOM_CELL ? frec[0] : frec[b]; };
-        auto gmn = [&](int k, int b) -> T { return GEOM == GEOM_CELL ? frec[1 + k] : frec[(1 + k) * N + b]; };
-        auto gpn = [&](int k, int b) -> T { return GEOM == GEOM_CELL ? frec[4 + k] : frec[(4 + k) * N + b]; };
+        auto pen = [&](int b) -> T { return GEOM != GEOM_QPOINT ? frec[0] : frec[b]; };
+        auto gmn = [&](int k, int b) -> T { return GEOM != GEOM_QPOINT ? frec[1 + k] : frec[(1 + k) * N + b]; };
+        auto gpn = [&](int k, int b) -> T { return GEOM != GEOM_QPOINT ? frec[4 + k] : frec[(4 + k) * N + b]; };
         // Row rc (points a along t1) of the own value and normal-derivative
         // layers, combined with S_f and D_f from the LDS x tile.
         auto own_rows = [&](T* vm, T* nm) {
@@ -582,7 +585,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 wd[b] = hj * gmn(D, b);
                 w1[b] = hj * gmn(t1, b);
                 w2[b] = hj * gmn(t2, b);
-                if constexpr (GEOM == GEOM_CELL) {
+                if constexpr (GEOM != GEOM_QPOINT) {
                     // per-cell records carry no point weights
                     const T jw = pick<N>(tab + TL.w, a) * tab[TL.w + b];
                     vv[b] *= jw; wd[b] *= jw; w1[b] *= jw; w2[b] *= jw;
@@ -619,11 +622,16 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         if constexpr (WAVE_CELLS) wave_sync();
         else __syncthreads();
     };
-    constexpr int NG = GEOM == GEOM_CELL ? 6 : 6 * N;
+    constexpr bool DIAGM = GEOM == GEOM_CELL_DIAG;   // diagonal per-cell metric: reference-coordinate cell term
+    constexpr int NG = GEOM != GEOM_QPOINT ? 6 : 6 * N;
     T gpre[NG];
     auto load_gpre = [&]() {
         const int cell = cell0 + c;
-        if constexpr (GEOM == GEOM_CELL) {
+        if constexpr (DIAGM) {
+            // the diagonal G_00, G_11, G_22 of the stored 00,01,02,11,12,22
+#pragma unroll
+            for (int m = 0; m < 3; ++m) gpre[m] = p.cgeom[size_t(cell) * 8 + (m == 0 ? 0 : m == 1 ? 3 : 5)];
+        } else if constexpr (GEOM == GEOM_CELL) {
 #pragma unroll
             for (int m = 0; m < 6; ++m) gpre[m] = p.cgeom[size_t(cell) * 8 + m];
         } else {
@@ -664,6 +672,106 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     T* B = ldsF + 6 * Sh::FARR + (act ? c : 0) * CS;    // from the FN arrays on
     T* C = B + CPB * CS;
     T v[N];
+    // Last step of either cell path: this thread's z pencil v (cell term in
+    // nodal coefficients), plus e_layer (x) P + D_f (x) Q of the six faces,
+    // written to y.
+    auto add_faces_and_store = [&](const T* v) {
+        const int i1 = ta, i2 = tb;
+        const auto df0 = tab + TL.df0;
+        const auto df1 = tab + TL.df1;
+        const T cx0 = pick<N>(df0, i1), cx1 = pick<N>(df1, i1);
+        const T cy0 = pick<N>(df0, i2), cy1 = pick<N>(df1, i2);
+        const bool hx0 = BASIS != 0 || i1 <= 1, hx1 = BASIS != 0 || i1 >= N - 2;
+        const bool hy0 = BASIS != 0 || i2 <= 1, hy1 = BASIS != 0 || i2 >= N - 2;
+        // value test rows: unit rows at the end layers, or dense (Gauss)
+        const auto fv0 = tab + TL.FV0;
+        const auto fv1 = tab + TL.FV1;
+        const T vx0 = COLLOC ? pick<N>(fv0, i1) : T(i1 == 0), vx1 = COLLOC ? pick<N>(fv1, i1) : T(i1 == N - 1);
+        const T vy0 = COLLOC ? pick<N>(fv0, i2) : T(i2 == 0), vy1 = COLLOC ? pick<N>(fv1, i2) : T(i2 == N - 1);
+        const T* P0 = fel(0, 0, c, 0); const T* Q0 = fel(1, 0, c, 0);
+        const T* P1 = fel(0, 0, c, 1); const T* Q1 = fel(1, 0, c, 1);
+        const T* P2 = fel(0, 1, c, 0); const T* Q2 = fel(1, 1, c, 0);
+        const T* P3 = fel(0, 1, c, 1); const T* Q3 = fel(1, 1, c, 1);
+        const T* P4 = fel(0, 2, c, 0); const T* Q4 = fel(1, 2, c, 0);
+        const T* P5 = fel(0, 2, c, 1); const T* Q5 = fel(1, 2, c, 1);
+        T* __restrict__ yc = p.y + size_t(cell0 + c) * N3 + i1 + N * i2;
+#pragma unroll
+        for (int k = 0; k < N; ++k) {
+            T r = v[k];
+            // x faces: tangential (t1, t2) = (i2, k), layer i1
+            if constexpr (COLLOC) {
+                r += vx0 * P0[k * FR + i2] + cx0 * Q0[k * FR + i2];
+                r += vx1 * P1[k * FR + i2] + cx1 * Q1[k * FR + i2];
+            } else {
+                if (hx0) r += (i1 == 0 ? P0[k * FR + i2] : T(0)) + cx0 * Q0[k * FR + i2];
+                if (hx1) r += (i1 == N - 1 ? P1[k * FR + i2] : T(0)) + cx1 * Q1[k * FR + i2];
+            }
+            // y faces: tangential (i1, k), layer i2
+            if constexpr (COLLOC) {
+                r += vy0 * P2[k * FR + i1] + cy0 * Q2[k * FR + i1];
+                r += vy1 * P3[k * FR + i1] + cy1 * Q3[k * FR + i1];
+            } else {
+                if (hy0) r += (i2 == 0 ? P2[k * FR + i1] : T(0)) + cy0 * Q2[k * FR + i1];
+                if (hy1) r += (i2 == N - 1 ? P3[k * FR + i1] : T(0)) + cy1 * Q3[k * FR + i1];
+            }
+            // z faces: tangential (i1, i2), layer k (compile time)
+            if (BASIS != 0 || k <= 1) {
+                if constexpr (COLLOC) r += fv0[k] * P4[i2 * FR + i1];
+                else if (k == 0) r += P4[i2 * FR + i1];
+                r += df0[k] * Q4[i2 * FR + i1];
+            }
+            if (BASIS != 0 || k >= N - 2) {
+                if constexpr (COLLOC) r += fv1[k] * P5[i2 * FR + i1];
+                else if (k == N - 1) r += P5[i2 * FR + i1];
+                r += df1[k] * Q5[i2 * FR + i1];
+            }
+            yc[k * N2] = r;
+        }
+    };
+    if constexpr (DIAGM) {
+        // ---- Cell term with a diagonal metric (G_00, G_11, G_22 per cell)
+        // in reference coordinates, with the 1D mass M = S^T W S and
+        // stiffness L = S'^T W S' (exact with the n-point Gauss rule):
+        //   y = G_00 (L x M x M) x + G_11 (M x L x M) x + G_22 (M x M x L) x
+        // (x-direction factor first): three pencil steps instead of nine.
+        // K1: x pencils (thread (i2, i3)): M and L along x
+        if (act) {
+            if constexpr (!EARLY) load_gpre();
+            T l[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(k, ta, tb)];
+            eo_apply<N, +1>(tab + TL.LL, v, l);
+            eo_apply<N, +1>(tab + TL.MM, v, v);
+#pragma unroll
+            for (int k = 0; k < N; ++k) { A[Sh::lds_idx(k, ta, tb)] = v[k]; B[Sh::lds_idx(k, ta, tb)] = l[k]; }
+        }
+        cell_sync();
+        // K2: y pencils (thread (i1, i3)): M_y M_x x, and G_00 M_y L_x x + G_11 L_y M_x x
+        if (act) {
+            T l[N], t[N], q[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) { v[k] = A[Sh::lds_idx(ta, k, tb)]; l[k] = B[Sh::lds_idx(ta, k, tb)]; }
+            eo_apply<N, +1>(tab + TL.MM, l, t);
+            eo_apply<N, +1>(tab + TL.LL, v, q);
+#pragma unroll
+            for (int k = 0; k < N; ++k) t[k] = gpre[0] * t[k] + gpre[1] * q[k];
+            eo_apply<N, +1>(tab + TL.MM, v, v);
+#pragma unroll
+            for (int k = 0; k < N; ++k) { A[Sh::lds_idx(ta, k, tb)] = v[k]; B[Sh::lds_idx(ta, k, tb)] = t[k]; }
+        }
+        cell_sync();
+        // K3: z pencils (thread (i1, i2)): M_z t + G_22 L_z (M_y M_x x), faces, write
+        if (act) {
+            T t[N], q[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) { v[k] = A[Sh::lds_idx(ta, tb, k)]; t[k] = B[Sh::lds_idx(ta, tb, k)]; }
+            eo_apply<N, +1>(tab + TL.LL, v, q);
+            eo_apply<N, +1>(tab + TL.MM, t, v);
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = fma(gpre[2], q[k], v[k]);
+            add_faces_and_store(v);
+        }
+    } else {
     // C1: z pencils (thread (i1, i2)) : S along z
     if (act && !COLLOC) {
 #pragma unroll
@@ -777,58 +885,9 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, tb, k)];
         s_apply<N, COLLOC>(tab + TL.ST, v, v);
-        const int i1 = ta, i2 = tb;
-        const auto df0 = tab + TL.df0;
-        const auto df1 = tab + TL.df1;
-        const T cx0 = pick<N>(df0, i1), cx1 = pick<N>(df1, i1);
-        const T cy0 = pick<N>(df0, i2), cy1 = pick<N>(df1, i2);
-        const bool hx0 = BASIS != 0 || i1 <= 1, hx1 = BASIS != 0 || i1 >= N - 2;
-        const bool hy0 = BASIS != 0 || i2 <= 1, hy1 = BASIS != 0 || i2 >= N - 2;
-        // value test rows: unit rows at the end layers, or dense (Gauss)
-        const auto fv0 = tab + TL.FV0;
-        const auto fv1 = tab + TL.FV1;
-        const T vx0 = COLLOC ? pick<N>(fv0, i1) : T(i1 == 0), vx1 = COLLOC ? pick<N>(fv1, i1) : T(i1 == N - 1);
-        const T vy0 = COLLOC ? pick<N>(fv0, i2) : T(i2 == 0), vy1 = COLLOC ? pick<N>(fv1, i2) : T(i2 == N - 1);
-        const T* P0 = fel(0, 0, c, 0); const T* Q0 = fel(1, 0, c, 0);
-        const T* P1 = fel(0, 0, c, 1); const T* Q1 = fel(1, 0, c, 1);
-        const T* P2 = fel(0, 1, c, 0); const T* Q2 = fel(1, 1, c, 0);
-        const T* P3 = fel(0, 1, c, 1); const T* Q3 = fel(1, 1, c, 1);
-        const T* P4 = fel(0, 2, c, 0); const T* Q4 = fel(1, 2, c, 0);
-        const T* P5 = fel(0, 2, c, 1); const T* Q5 = fel(1, 2, c, 1);
-        T* __restrict__ yc = p.y + size_t(cell0 + c) * N3 + i1 + N * i2;
-#pragma unroll
-        for (int k = 0; k < N; ++k) {
-            T r = v[k];
-            // x faces: tangential (t1, t2) = (i2, k), layer i1
-            if constexpr (COLLOC) {
-                r += vx0 * P0[k * FR + i2] + cx0 * Q0[k * FR + i2];
-                r += vx1 * P1[k * FR + i2] + cx1 * Q1[k * FR + i2];
-            } else {
-                if (hx0) r += (i1 == 0 ? P0[k * FR + i2] : T(0)) + cx0 * Q0[k * FR + i2];
-                if (hx1) r += (i1 == N - 1 ? P1[k * FR + i2] : T(0)) + cx1 * Q1[k * FR + i2];
-            }
-            // y faces: tangential (i1, k), layer i2
-            if constexpr (COLLOC) {
-                r += vy0 * P2[k * FR + i1] + cy0 * Q2[k * FR + i1];
-                r += vy1 * P3[k * FR + i1] + cy1 * Q3[k * FR + i1];
-            } else {
-                if (hy0) r += (i2 == 0 ? P2[k * FR + i1] : T(0)) + cy0 * Q2[k * FR + i1];
-                if (hy1) r += (i2 == N - 1 ? P3[k * FR + i1] : T(0)) + cy1 * Q3[k * FR + i1];
-            }
-            // z faces: tangential (i1, i2), layer k (compile time)
-            if (BASIS != 0 || k <= 1) {
-                if constexpr (COLLOC) r += fv0[k] * P4[i2 * FR + i1];
-                else if (k == 0) r += P4[i2 * FR + i1];
-                r += df0[k] * Q4[i2 * FR + i1];
-            }
-            if (BASIS != 0 || k >= N - 2) {
-                if constexpr (COLLOC) r += fv1[k] * P5[i2 * FR + i1];
-                else if (k == N - 1) r += P5[i2 * FR + i1];
-                r += df1[k] * Q5[i2 * FR + i1];
-            }
-            yc[k * N2] = r;
-        }
+        add_faces_and_store(v);
     }
+    }   // quadrature cell term
 }
 
 // One operator: workgroup b handles cells b*CPB ... of it.

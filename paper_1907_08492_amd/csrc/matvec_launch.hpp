@@ -40,7 +40,8 @@ static int launch_group(const BatchGroup& g, hipStream_t st) {
     return SIPG_OK;
 }
 
-// Calls launch<N, BASIS, T, GEOM>() for the run-time (basis, dtype, geometry).
+// Calls launch<N, BASIS, T, GEOM>() for the run-time (basis, dtype, kernel
+// geometry variant, matvec_geom).
 template <int N, typename F>
 static int dispatch(int basis, int dtype, int geom, F&& launch) {
     using I0 = std::integral_constant<int, 0>;
@@ -48,8 +49,12 @@ static int dispatch(int basis, int dtype, int geom, F&& launch) {
     using I2 = std::integral_constant<int, 2>;
     using GC = std::integral_constant<int, GEOM_CELL>;
     using GQ = std::integral_constant<int, GEOM_QPOINT>;
-    const bool cell = geom == GEOM_CELL;
-    auto by_geom = [&](auto b, auto t) { return cell ? launch(b, t, GC{}) : launch(b, t, GQ{}); };
+    using GD = std::integral_constant<int, GEOM_CELL_DIAG>;
+    auto by_geom = [&](auto b, auto t) {
+        if (geom == GEOM_CELL) return launch(b, t, GC{});
+        if (geom == GEOM_CELL_DIAG) return launch(b, t, GD{});
+        return launch(b, t, GQ{});
+    };
     auto by_basis = [&](auto t) {
         if (basis == SIPG_BASIS_HERMITE_LIKE) return by_geom(I0{}, t);
         if (basis == SIPG_BASIS_NODAL_GL) return by_geom(I1{}, t);
@@ -65,7 +70,7 @@ static int dispatch(int basis, int dtype, int geom, F&& launch) {
     namespace sipg {                                                                                    \
     template <>                                                                                         \
     int launch_matvec_n<NV>(const sipg_op* op, const void* x, void* y, hipStream_t st) {                \
-        return dispatch<NV>(op->basis, op->dtype, op->geom, [&](auto b, auto t, auto g) {               \
+        return dispatch<NV>(op->basis, op->dtype, matvec_geom(op), [&](auto b, auto t, auto g) {        \
             return launch_one<NV, decltype(b)::value, decltype(t), decltype(g)::value>(op, x, y, st);   \
         });                                                                                             \
     }                                                                                                   \

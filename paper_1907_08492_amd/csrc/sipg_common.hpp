@@ -58,7 +58,7 @@ struct TableLayout {
     int Sgl, SGgl, df0gl, df1gl;       // plain row-major tables of the nodal GL basis
     int FZP, FLAM;                     // block preconditioner: parity-split eigenvectors, eigenvalues
     int FV0, FV1;                      // face value rows S_f at 0 and 1
-    int MM, CT, CS;                    // even-odd packed 1D M = S^T W S, Ct = S^T W S', Cs = S'^T W S
+    int MM, CT, CS, LL;                // even-odd packed 1D M = S^T W S, Ct = S^T W S', Cs = S'^T W S, L = S'^T W S'
     int total;
     __host__ __device__ constexpr TableLayout(int n_)
         : n(n_), es(eo_size(n_)), S(0), ST(es), D(2 * es), DT(3 * es), SG(4 * es),
@@ -67,14 +67,17 @@ struct TableLayout {
           df1gl(8 * es + 4 * n_ + 2 * n_ * n_), FZP(8 * es + 5 * n_ + 2 * n_ * n_),
           FLAM(8 * es + 5 * n_ + 3 * n_ * n_), FV0(8 * es + 6 * n_ + 3 * n_ * n_),
           FV1(8 * es + 7 * n_ + 3 * n_ * n_), MM(8 * es + 8 * n_ + 3 * n_ * n_), CT(9 * es + 8 * n_ + 3 * n_ * n_),
-          CS(10 * es + 8 * n_ + 3 * n_ * n_), total(11 * es + 8 * n_ + 3 * n_ * n_ + 1) {}
+          CS(10 * es + 8 * n_ + 3 * n_ * n_), LL(11 * es + 8 * n_ + 3 * n_ * n_), total(12 * es + 8 * n_ + 3 * n_ * n_ + 1) {}
 };
 
-enum GeomMode { GEOM_CELL = 1, GEOM_QPOINT = 2 };
+// Geometry storage modes (GEOM_CELL, GEOM_QPOINT as in the C ABI).  The
+// product kernel has a third variant for per-cell storage whose metric
+// tensors are all diagonal (affine map with a diagonal linear part).
+enum GeomMode { GEOM_CELL = 1, GEOM_QPOINT = 2, GEOM_CELL_DIAG = 3 };
 
 // Number of stored values per cell / per face for each geometry mode.
-__host__ __device__ constexpr int cell_geom_stride(int mode, int n) { return mode == GEOM_CELL ? 8 : 6 * n * n * n; }
-__host__ __device__ constexpr int face_geom_stride(int mode, int n) { return mode == GEOM_CELL ? 8 : 7 * n * n; }
+__host__ __device__ constexpr int cell_geom_stride(int mode, int n) { return mode == GEOM_QPOINT ? 6 * n * n * n : 8; }
+__host__ __device__ constexpr int face_geom_stride(int mode, int n) { return mode == GEOM_QPOINT ? 7 * n * n : 8; }
 
 // Mesh description in the form the device kernels take it.
 struct MeshDev {
@@ -89,6 +92,7 @@ struct MeshDev {
 // The operator handle (opaque in the C ABI).
 struct sipg_op {
     int degree = 0, n = 0, basis = 0, dtype = 0, geom = 0;
+    int diag_metric = 0;             // per-cell storage and every metric tensor diagonal
     int nc[3] = {0, 0, 0};
     int64_t ncells = 0, ndofs = 0;
     double eta = 0.0;
@@ -105,6 +109,8 @@ struct sipg_op {
 };
 
 namespace sipg {
+// Geometry variant of the product kernel for this operator.
+inline int matvec_geom(const sipg_op* op) { return op->geom == GEOM_CELL && op->diag_metric ? GEOM_CELL_DIAG : op->geom; }
 void set_error(const std::string& msg);
 int hip_fail(hipError_t e, const char* what);
 }  // namespace sipg

@@ -47,7 +47,7 @@ def test_batch_equals_single_products_and_oracle():
     specs = _mixed_specs(rng, 40)
     ops, xs, ys = _setup(torch, P, specs)
     b = P.Batch(ops, xs, ys)
-    keys = {(op.degree, op.basis, op.dtype_name, op.info.geometry) for op in ops}
+    keys = {(op.degree, op.basis, op.dtype_name, op.info.geometry, op.info.diagonal_metric) for op in ops}
     assert b.info.nops == 40 and b.info.launches == len(keys)
     assert b.info.ndofs == sum(op.ndofs for op in ops)
     b.apply()
