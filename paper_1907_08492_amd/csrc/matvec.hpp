@@ -330,10 +330,12 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     // side's arrays are consumed (F1) before the neighbour side's are written
     // (G2) into the same place.
     constexpr int FV = 0, FT = 1, FN = 2;
-    // Per-cell (affine) records use the reference-coordinate face step below,
-    // except for the nodal bases at n >= 8, whose n^2 neighbour values per
-    // lane leave too few registers for it.
-    constexpr bool KRON = GEOM != GEOM_QPOINT && (BASIS == 0 || N <= 7);
+    // Per-cell (affine) records use the reference-coordinate face step below
+    // in the Hermite-like basis.  The nodal bases keep the quadrature face
+    // steps: the Gauss basis has no interpolation sweeps to save there, and
+    // for both the dense n-layer face rows dominate (measured: no gain for
+    // Gauss-Lobatto, a loss for Gauss).
+    constexpr bool KRON = GEOM != GEOM_QPOINT && BASIS == 0;
     by_direction(wave, [&](auto dc) {
         constexpr int D = decltype(dc)::value;
         constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
