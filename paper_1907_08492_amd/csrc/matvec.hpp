@@ -436,7 +436,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 const int b = rc;
                 const T* Xc = ldsX + c * CS;
                 const bool inwg = D == 0 && (s ? c + 1 < ncb : c > 0);   // x-neighbour in the workgroup
-                const T* Xn = ldsX + (s ? c + 1 : c - 1) * CS;
+                const T* Xn = ldsX + (inwg ? (s ? c + 1 : c - 1) : c) * CS;
                 const auto dfs = tab + (s ? TL.df1 : TL.df0), fvs = tab + (s ? TL.FV1 : TL.FV0);
                 const auto dfn = tab + (s ? TL.df0 : TL.df1), fvn = tab + (s ? TL.FV0 : TL.FV1);
                 T jc[N], av[N], t1v[N], t2v[N], q[N];
