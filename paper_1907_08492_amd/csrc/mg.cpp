@@ -17,7 +17,9 @@
 #include <chrono>
 #include <cmath>
 #include <cstring>
+#include <map>
 #include <memory>
+#include <mutex>
 #include <new>
 #include <type_traits>
 #include <vector>
@@ -83,6 +85,8 @@ struct Level {
     DevBuf<T> b, u, uo, r, z;
     DevBuf<T> emb;                      // h: child embedding M_0, M_1; p: E then E^T
     double lmin = 0.0, lmax = 0.0;
+    int steps = 0;                      // Lanczos steps of its eigenvalue estimate
+    std::vector<double> key;            // what defines the level operator (eigenvalue cache)
     std::vector<double> sigma, theta;   // Chebyshev coefficients per step
     int64_t ncells() const { return int64_t(nc[0]) * nc[1] * nc[2]; }
     ~Level() { if (op) sipg_destroy(op); }
@@ -236,13 +240,11 @@ struct Hierarchy {
     // 2: new r.z) and are read once at the end.
     int lanczos(int l, int steps, Scratch& sc, hipStream_t st) {
         Level<T>& L = *lv[l];
-        std::vector<T> h(L.n);
-        for (int64_t i = 0; i < L.n; ++i) h[i] = T(-5.5 + double(i % 12));
-        SIPG_HIP(hipMemcpyAsync(L.r.p, h.data(), sizeof(T) * L.n, hipMemcpyHostToDevice, st));
+        int rc;
+        if ((rc = vec_sawtooth<T>(L.r.p, L.n, st)) != SIPG_OK) return rc;
         steps = std::min(steps, kMaxLanczos);
         double* da = sc.coef.p;               // alpha_k
         double* db = sc.coef.p + steps;       // beta_k
-        int rc;
         double* s_rz = sc.scal.p;
         double* s_pap = sc.scal.p + 1;
         double* s_rzn = sc.scal.p + 2;
@@ -337,6 +339,24 @@ double* mg_rhs_buffer(sipg_mg* mg) { return mg->wb.p; }
 double mg_last_rhs_norm(const sipg_mg* mg) { return mg->last_bnorm; }
 }  // namespace sipg
 
+// Eigenvalue estimates of P^-1 A per level operator, shared by every
+// hierarchy of the process.  The Lanczos run is deterministic for a given
+// level (mesh, degree, penalty, basis, precision, preconditioner, number of
+// steps), so a level estimated before is not estimated again: a stream of
+// solves sets up many hierarchies whose levels coincide.
+static std::mutex g_lambda_mu;
+static std::map<std::vector<double>, std::pair<double, double>> g_lambda;
+
+static std::vector<double> level_key(const sipg_mesh& m, int degree, double penalty, int basis, int dtype,
+                                     int pmode, int steps) {
+    std::vector<double> k = {double(m.n[0]), double(m.n[1]), double(m.n[2])};
+    for (int d = 0; d < 3; ++d) { k.push_back(m.lo[d]); k.push_back(m.hi[d]); }
+    for (int i = 0; i < 9; ++i) k.push_back(m.lin[i]);
+    k.insert(k.end(), {m.deform_amp, double(degree), penalty, double(basis), double(dtype), double(pmode),
+                       double(steps)});
+    return k;
+}
+
 template <typename T>
 static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, int degree, double penalty,
                            int basis, const sipg_mg_opts& o, hipStream_t st) {
@@ -352,6 +372,15 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
         for (int d = 0; d < 3; ++d) { m.n[d] = sp.nc[d]; L->nc[d] = sp.nc[d]; }
         L->np = sp.degree + 1;
         L->next = sp.next;
+        {
+            // the coarse solve needs both ends of the spectrum: more Lanczos
+            // steps, bounded well below the level size so that the FP32
+            // recurrence does not lose orthogonality into spurious extreme values
+            const bool coarsest = l + 1 == seq.size();
+            const int64_t nl = int64_t(sp.nc[0]) * sp.nc[1] * sp.nc[2] * L->np * L->np * L->np;
+            L->steps = coarsest ? int(std::min<int64_t>(nl / 4 + 2, 120)) : o.lanczos_steps;
+            L->key = level_key(m, sp.degree, penalty, basis, dt, H.pmode, L->steps);
+        }
         if ((rc = sipg_setup(&m, sp.degree, penalty, basis, dt, SIPG_GEOM_AUTO, st, &L->op)) != SIPG_OK) return rc;
         if (H.pmode == SIPG_BC_PJACOBI && (rc = sipg_compute_gl_diagonal(L->op, nullptr, st)) != SIPG_OK) return rc;
         L->n = L->op->ndofs;
@@ -391,11 +420,17 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
     for (size_t l = 0; l < H.lv.size(); ++l) {
         const bool coarsest = l + 1 == H.lv.size();
         Level<T>& L = *H.lv[l];
-        // the coarse solve needs both ends of the spectrum: more Lanczos steps,
-        // bounded well below the level size so that the FP32 recurrence does
-        // not lose orthogonality into spurious extreme values
-        const int steps = coarsest ? int(std::min<int64_t>(L.n / 4 + 2, 120)) : o.lanczos_steps;
-        if ((rc = H.lanczos(int(l), steps, mg->sc, st)) != SIPG_OK) return rc;
+        bool known = false;
+        {
+            std::lock_guard<std::mutex> g(g_lambda_mu);
+            auto it = g_lambda.find(L.key);
+            if (it != g_lambda.end()) { L.lmin = it->second.first; L.lmax = it->second.second; known = true; }
+        }
+        if (!known) {
+            if ((rc = H.lanczos(int(l), L.steps, mg->sc, st)) != SIPG_OK) return rc;
+            std::lock_guard<std::mutex> g(g_lambda_mu);
+            g_lambda.emplace(L.key, std::make_pair(L.lmin, L.lmax));
+        }
         if (!coarsest) {
             chebyshev_coefficients(o.range_lo * L.lmax, o.range_hi * L.lmax, H.smooth_steps, L.sigma, L.theta);
         } else {

@@ -41,6 +41,13 @@ __global__ void __launch_bounds__(kVT) scale_kernel(T alpha, const T* __restrict
     for (int64_t i = int64_t(blockIdx.x) * kVT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kVT) y[i] = alpha * x[i];
 }
 
+// x_i = -5.5 + (i mod 12): the start vector of the eigenvalue estimates
+template <typename T>
+__global__ void __launch_bounds__(kVT) sawtooth_kernel(T* __restrict__ x, int64_t n) {
+    for (int64_t i = int64_t(blockIdx.x) * kVT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kVT)
+        x[i] = T(-5.5 + double(i % 12));
+}
+
 template <typename TO, typename TI>
 __global__ void __launch_bounds__(kVT) convert_kernel(const TI* __restrict__ x, TO* __restrict__ y, int64_t n) {
     for (int64_t i = int64_t(blockIdx.x) * kVT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kVT) y[i] = TO(x[i]);
@@ -118,6 +125,12 @@ int vec_scale(double alpha, const T* x, T* y, int64_t n, hipStream_t st) {
     SIPG_HIP(hipGetLastError());
     return SIPG_OK;
 }
+template <typename T>
+int vec_sawtooth(T* x, int64_t n, hipStream_t st) {
+    sawtooth_kernel<T><<<vblocks(n), kVT, 0, st>>>(x, n);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
 template <typename TO, typename TI>
 int vec_convert(const TI* x, TO* y, int64_t n, hipStream_t st) {
     convert_kernel<TO, TI><<<vblocks(n), kVT, 0, st>>>(x, y, n);
@@ -158,6 +171,7 @@ int scalar_ratio(const double* num, const double* den, double* out, hipStream_t 
     template int vec_sub<T>(const T*, const T*, T*, int64_t, hipStream_t);                   \
     template int vec_axpby<T>(double, const T*, double, T*, int64_t, hipStream_t);           \
     template int vec_scale<T>(double, const T*, T*, int64_t, hipStream_t);                   \
+    template int vec_sawtooth<T>(T*, int64_t, hipStream_t);                                  \
     template int vec_dot_async<T>(const T*, const T*, double*, double*, int64_t, hipStream_t);
 SIPG_VEC_INST(float)
 SIPG_VEC_INST(double)

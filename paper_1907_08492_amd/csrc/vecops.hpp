@@ -13,6 +13,8 @@ template <typename T> int vec_sub(const T* b, const T* a, T* r, int64_t n, hipSt
 template <typename T> int vec_axpby(double alpha, const T* x, double beta, T* y, int64_t n, hipStream_t st);
 template <typename T> int vec_scale(double alpha, const T* x, T* y, int64_t n, hipStream_t st);
 template <typename TO, typename TI> int vec_convert(const TI* x, TO* y, int64_t n, hipStream_t st);
+// x_i = -5.5 + (i mod 12)
+template <typename T> int vec_sawtooth(T* x, int64_t n, hipStream_t st);
 // Updates whose coefficient c = sign * num[0] / den[0] is read from device
 // memory:  y = c x + y  and  y = x + c y  (sign = +1); out[0] = num[0] / den[0]
 // (or num[0] when den is null).
