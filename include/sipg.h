@@ -333,6 +333,13 @@ typedef struct {
     int32_t smoother;            /* sipg_mg_opts.smoother of every solve (1: block Jacobi) */
     int32_t p_coarsening;        /* sipg_mg_opts.p_coarsening of every solve (1: halve the
                                     degree; requests have odd cell counts too) */
+    double coarse_reduction;     /* sipg_mg_opts.coarse_reduction of every solve (10).  An
+                                    odd or prime cell count cannot be coarsened, so the
+                                    coarse level of such a request is its whole mesh at
+                                    the reduced degree; inside the V-cycle preconditioner
+                                    a reduction of 10 there (instead of the 1e5 of the
+                                    plain solver) halves the solve time of the served mix
+                                    for the same final residual, at 3% more CG steps */
 } sipg_server_opts;
 typedef struct {
     sipg_mesh mesh;

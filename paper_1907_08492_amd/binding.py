@@ -82,7 +82,7 @@ class SipgMgInfo(C.Structure):
 
 class SipgServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("workers", C.c_int32), ("precision", C.c_int32),
-                ("smoother", C.c_int32), ("p_coarsening", C.c_int32)]
+                ("smoother", C.c_int32), ("p_coarsening", C.c_int32), ("coarse_reduction", C.c_double)]
 
 
 class SipgRequest(C.Structure):
@@ -465,13 +465,13 @@ class Server:
     """Continuous-batching request loop of multigrid Poisson solves."""
 
     def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 8, precision: str = "mixed",
-                 smoother: str = "fdm", p_coarsening: int = 1):
+                 smoother: str = "fdm", p_coarsening: int = 1, coarse_reduction: float = 10.0):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Server needs a GPU (HIP device)")
         torch.cuda.init()
         o = SipgServerOpts(int(hbm_budget_bytes), int(workers), {"mixed": 0, "f64": 1}[precision],
-                           SMOOTHERS[smoother], int(p_coarsening))
+                           SMOOTHERS[smoother], int(p_coarsening), float(coarse_reduction))
         h = _vp()
         _check(lib.sipg_server_create(C.byref(o), C.byref(h)), "sipg_server_create")
         self._h = h

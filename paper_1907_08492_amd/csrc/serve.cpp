@@ -101,6 +101,7 @@ static sipg_mg_opts solver_opts(const sipg_server_opts& so) {
     o.precision = so.precision;
     o.smoother = so.smoother;
     o.p_coarsening = so.p_coarsening;
+    o.coarse_reduction = so.coarse_reduction;
     return o;
 }
 
@@ -252,6 +253,7 @@ int sipg_server_default_opts(sipg_server_opts* o) {
     o->precision = 0;
     o->smoother = 1;
     o->p_coarsening = 1;
+    o->coarse_reduction = 10.0;
     return SIPG_OK;
 }
 
@@ -262,8 +264,10 @@ int sipg_server_create(const sipg_server_opts* opts, sipg_server** out) {
     sipg_server_default_opts(&o);
     if (opts) o = *opts;
     if (o.workers < 1 || o.workers > 16 || o.hbm_budget_bytes <= 0 || (o.precision != 0 && o.precision != 1) ||
-        (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2) {
-        set_error("sipg_server_create: workers in [1,16], budget > 0, precision and smoother 0 or 1, p_coarsening 0..2");
+        (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2 ||
+        !(o.coarse_reduction > 1.0)) {
+        set_error("sipg_server_create: workers in [1,16], budget > 0, precision and smoother 0 or 1, p_coarsening 0..2, "
+                  "coarse_reduction > 1");
         return SIPG_E_ARG;
     }
     sipg_server* s = new (std::nothrow) sipg_server();
