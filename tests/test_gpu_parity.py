@@ -66,9 +66,24 @@ def test_apply_f64_per_point_geometry_on_affine_mesh(mesh_name, k):
     assert e2 <= 1e-12 and emax <= 1e-12, (e2, emax)
 
 
+@pytest.mark.parametrize("geometry,mesh_name,expected", [
+    ("auto", "cartesian", 1), ("auto", "brick_aniso", 1), ("auto", "paper_affine", 0),
+    ("auto", "deformed", 0), ("qpoint", "cartesian", 0), ("cell", "brick_aniso", 1)])
+def test_diagonal_metric_variant(geometry, mesh_name, expected):
+    """Per-cell storage of an affine map with a diagonal linear part selects the
+    reference-coordinate cell term (sipg_op_info.diagonal_metric); the other
+    operators keep the quadrature cell term.  Both are checked against the
+    oracle by the parity tests above."""
+    torch, P = require_gpu()
+    banner(f"diagonal metric {geometry} {mesh_name}")
+    op = P.Operator(MESHES[mesh_name], 3, 2.0, "hermite_like", "f64", geometry)
+    assert op.info.diagonal_metric == expected
+    op.close()
+
+
 @pytest.mark.parametrize("k", [1, 3, 4, 5, 7, 8])
 @pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl", "nodal_gauss"])
-@pytest.mark.parametrize("mesh_name", ["deformed", "paper_affine"])
+@pytest.mark.parametrize("mesh_name", ["deformed", "paper_affine", "cartesian"])
 def test_apply_f32(mesh_name, basis, k):
     torch, P = require_gpu()
     banner(f"apply f32 {mesh_name} {basis} k={k}")
