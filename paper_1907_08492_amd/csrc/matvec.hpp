@@ -637,11 +637,17 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
             for (int m = 0; m < 6; ++m) gpre[m] = p.cgeom[size_t(cell) * 8 + m];
         } else {
-            const T* gq = p.cgeom + size_t(cell) * (6 * N3) + ta + N * tb;
+            // pairs of points along z with 16-byte loads, then the last point
+            // for odd n (layout of cell_metric_offset)
+            const T* gq = p.cgeom + size_t(cell) * (6 * N3);
+            const int tp = ta + N * tb;
+            constexpr int H = N / 2;
 #pragma unroll
-            for (int m = 0; m < 6; ++m)
+            for (int m = 0; m < 6; ++m) {
 #pragma unroll
-                for (int k = 0; k < N; ++k) gpre[m * N + k] = __builtin_nontemporal_load(gq + m * N3 + N2 * k);
+                for (int kp = 0; kp < H; ++kp) load_run<2>(gq + (m * H + kp) * 2 * N2 + 2 * tp, gpre + m * N + 2 * kp);
+                if constexpr (N % 2 == 1) gpre[m * N + N - 1] = gq[12 * H * N2 + m * N2 + tp];
+            }
         }
     };
     if constexpr (EARLY) {

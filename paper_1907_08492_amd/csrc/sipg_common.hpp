@@ -79,6 +79,18 @@ enum GeomMode { GEOM_CELL = 1, GEOM_QPOINT = 2, GEOM_CELL_DIAG = 3 };
 __host__ __device__ constexpr int cell_geom_stride(int mode, int n) { return mode == GEOM_QPOINT ? 6 * n * n * n : 8; }
 __host__ __device__ constexpr int face_geom_stride(int mode, int n) { return mode == GEOM_QPOINT ? 7 * n * n : 8; }
 
+// Offset, inside a cell's per-point record of 6 n^3 values, of metric
+// component m at point q = q1 + n (q2 + n q3).  The points of one (q1, q2)
+// pencil along q3 are stored in pairs next to each other, so that the thread
+// of a pencil reads them with 16-byte loads and a wavefront's load is one
+// contiguous, 16-byte aligned range per cell: first the pairs of every
+// component ([m][q3 / 2][pencil][2]), then, for odd n, the last point of
+// every pencil ([m][pencil]).
+__host__ __device__ constexpr int cell_metric_offset(int n, int m, int q) {
+    const int n2 = n * n, t = q % n2, k = q / n2, h = n / 2;
+    return k < 2 * h ? (m * h + k / 2) * 2 * n2 + 2 * t + (k & 1) : 12 * h * n2 + m * n2 + t;
+}
+
 // Mesh description in the form the device kernels take it.
 struct MeshDev {
     int n[3];
