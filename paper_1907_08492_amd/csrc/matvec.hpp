@@ -178,11 +178,39 @@ constexpr int matvec_min_waves() { return (N >= 7 && GEOM != GEOM_QPOINT) ? 2 : 
 // XCD-aware order: consecutive workgroups are dispatched round-robin over
 // the 8 XCDs, so give each XCD a contiguous range of block indices (a range
 // of consecutive cells, whose x- and y-neighbours then meet in that XCD's L2).
-__device__ __forceinline__ int xcd_block(int blk, int nblk) {
+// Workgroup blk is the sl-th of its XCD, whose range starts at `start` and
+// holds `len` blocks.
+struct XcdSlot { int start, len, sl; };
+__device__ __forceinline__ XcdSlot xcd_slot(int blk, int nblk) {
     const int per = (nblk + 7) / 8;
     const int xcd = blk % 8, sl = blk / 8;
     const int full = nblk % 8 == 0 ? 8 : nblk % 8;   // XCDs that get `per` blocks
-    return (xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1)) + sl;
+    return {xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1), xcd < full ? per : per - 1, sl};
+}
+__device__ __forceinline__ int xcd_block(int blk, int nblk) {
+    const XcdSlot x = xcd_slot(blk, nblk);
+    return x.start + x.sl;
+}
+
+// The same, with the blocks of three consecutive z-layers interleaved inside
+// each XCD's range: with P blocks per layer, the range is cut into groups of
+// 3P blocks, and a group is visited as block j of its first, second and third
+// layer, then block j + 1 of each, and so on (a transpose of the 3 x P group;
+// a last, shorter group keeps the plain order).  In the lexicographic cell
+// order a z-neighbour is P blocks away, beyond what one XCD's L2 holds while
+// it streams the blocks in between; interleaved, two of every three z-faces
+// meet their second reader while its records and neighbour layers are still
+// there, and y-neighbours, 3 rows away, still do.
+__device__ __forceinline__ int xcd_block_zinterleaved(int blk, int nblk, int layer_blocks) {
+    constexpr int TZ = 3;
+    const XcdSlot x = xcd_slot(blk, nblk);
+    const int G = TZ * layer_blocks;
+    int b = x.sl;
+    if (layer_blocks > 0 && G <= x.len) {
+        const int g = x.sl / G, s = x.sl - g * G;
+        if ((g + 1) * G <= x.len) b = g * G + (s % TZ) * layer_blocks + s / TZ;
+    }
+    return x.start + b;
 }
 
 // The product on workgroup `blk` of the operator `p`: cells blk*CPB ...
@@ -898,11 +926,14 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     }   // quadrature cell term
 }
 
-// One operator: workgroup b handles cells b*CPB ... of it.
+// One operator: workgroup b handles cells b*CPB ... of it, in the
+// z-interleaved XCD order (P = blocks per z-layer of cells, rounded).
 template <int N, int BASIS, typename T, int GEOM>
 __global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
 sipg_matvec_kernel(MatvecParams<T> p) {
-    matvec_block<N, BASIS, T, GEOM>(p, xcd_block(blockIdx.x, gridDim.x));
+    constexpr int CPB = cells_per_block(N);
+    const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
+    matvec_block<N, BASIS, T, GEOM>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks));
 }
 
 // Many independent operators of the same degree, basis, precision and

@@ -163,6 +163,24 @@ def test_hermite_like_reads_only_two_neighbour_layers():
     assert not np.array_equal(Y0[12], Y1[12])
 
 
+@pytest.mark.parametrize("k,basis,dtype", [(4, "hermite_like", "f64"), (2, "nodal_gl", "f64"), (3, "hermite_like", "f32")])
+def test_z_interleaved_block_order(k, basis, dtype):
+    # 50 z-layers: the kernel's XCD ranges hold full groups of three
+    # interleaved z-layers of blocks and a shorter last group in plain order
+    torch, P = require_gpu()
+    banner(f"z-interleaved block order {basis} k={k} {dtype}")
+    mesh = unit_cube((4, 3, 50), 0.1)
+    ref_op = SIPG(mesh, k, 2.0, basis)
+    x = uniform_vector(ref_op.ndofs, seed=11)
+    if dtype == "f32":
+        x = x.astype(np.float32).astype(np.float64)
+    ref = ref_op.apply_naive(x)
+    y = run_apply(torch, P, mesh, k, basis, dtype, x)
+    e2, emax = rel_errors(y, ref)
+    tol = 1e-12 if dtype == "f64" else 1e-5
+    assert e2 <= tol and emax <= tol, (e2, emax)
+
+
 def test_deterministic():
     torch, P = require_gpu()
     banner("determinism")

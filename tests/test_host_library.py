@@ -77,6 +77,42 @@ def test_xcd_remap_is_a_permutation(nblk):
     assert sorted(m) == list(range(nblk))
 
 
+def _xcd_remap_zinterleaved(blk, nblk, layer_blocks, tz=3):
+    """Model of the single-operator kernel's order: inside each XCD's range,
+    groups of tz * layer_blocks blocks are visited as a transposed
+    tz x layer_blocks array; a last, shorter group keeps the plain order."""
+    per = (nblk + 7) // 8
+    xcd, slot = blk % 8, blk // 8
+    full = 8 if nblk % 8 == 0 else nblk % 8
+    start = xcd * per if xcd < full else full * per + (xcd - full) * (per - 1)
+    length = per if xcd < full else per - 1
+    g_size = tz * layer_blocks
+    b = slot
+    if layer_blocks > 0 and g_size <= length:
+        g, s = divmod(slot, g_size)
+        if (g + 1) * g_size <= length:
+            b = g * g_size + (s % tz) * layer_blocks + s // tz
+    return start + b
+
+
+@pytest.mark.parametrize("nblk,layer_blocks", [(1, 0), (9, 1), (100, 2), (100, 5), (128, 3), (1000, 7),
+                                               (43691, 683), (7296, 96), (43691, 5000)])
+def test_xcd_zinterleaved_remap_is_a_permutation(nblk, layer_blocks):
+    m = [_xcd_remap_zinterleaved(b, nblk, layer_blocks) for b in range(nblk)]
+    assert sorted(m) == list(range(nblk))
+
+
+def test_xcd_zinterleaved_remap_visits_z_neighbours_together():
+    # 64^3 cells, 6 per block: in each full group, slots 3j, 3j+1, 3j+2 are
+    # block j of three consecutive z-layers (P = 683 blocks apart)
+    nblk, P = 43691, 683
+    m = [_xcd_remap_zinterleaved(b, nblk, P) for b in range(nblk)]
+    for xcd in range(8):
+        seq = m[xcd::8]
+        for j in range(0, 3 * P, 3):
+            assert seq[j + 1] - seq[j] == P and seq[j + 2] - seq[j + 1] == P
+
+
 def test_argument_errors_without_gpu():
     m = P.make_mesh(type("M", (), dict(n=(2, 2, 2), lo=(0, 0, 0), hi=(1, 1, 1)))())
     h = C.c_void_p()
