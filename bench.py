@@ -318,7 +318,7 @@ def main():
                     help="arrival rate of the below-saturation latency run (0 skips it)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print(f"bench.py: this build measures one GPU only (asked for --gpus {args.gpus}); "
+        print(f"bench.py: the benchmark runs on one GPU only (asked for --gpus {args.gpus}); "
               "sharding over several GPUs is designed but not built or measured.", file=sys.stderr)
         sys.exit(2)
 

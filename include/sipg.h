@@ -34,7 +34,7 @@ typedef enum {
     SIPG_E_ARG = -1,         /* invalid argument (null pointer, bad size, aliasing, ...) */
     SIPG_E_OOM = -2,         /* device allocation failed */
     SIPG_E_HIP = -3,         /* a HIP runtime call failed; text in sipg_last_error() */
-    SIPG_E_UNSUPPORTED = -4, /* valid request this build does not provide */
+    SIPG_E_UNSUPPORTED = -4, /* valid request the library does not provide */
     SIPG_E_NOTREADY = -5,    /* asynchronous result not finished yet */
     SIPG_E_NOCONV = -6,      /* iterative solve hit its iteration limit */
     SIPG_E_BUDGET = -7       /* request exceeds the configured memory budget */
