@@ -4,14 +4,17 @@
 A step is one pass of the whole hot path over one synthetic input vector:
 y = A x (matrix-free SIPG product: gather, cell and face sum factorization,
 flux, integration, one write per cell) followed by z = P^-1 y (the basis-change
-preconditioner of eq. (jacobi)).  The headline workload is the Hermite-like
+preconditioner of eq. (jacobi)), both in one launch (sipg_apply_pjacobi: each
+workgroup applies P^-1 to its cells' y before writing them).  The product and
+the preconditioner alone are timed as separate legs.  The headline workload is the Hermite-like
 operator of degree 4 on 64^3 cells of the sine-deformed unit cube in FP64
 (32.8 M unknowns, metric terms stored per quadrature point).  Throughput
 follows eq. (throughput): unknowns times steps over the wall time of the
 timed steps, with the inputs resident in HBM.
 
-The JSON line also carries the roofline of the dominant kernel (the matvec:
-algorithmic bytes per launch over its average duration from HIP events), the
+The JSON line also carries the roofline of the dominant kernel (the fused
+step: algorithmic bytes per launch over its average duration from HIP
+events), the
 other matvec variants of the same study (affine/deformed, k = 4 and 7,
 Hermite-like and nodal Gauss-Lobatto, FP64 and FP32), and the FP64 CPU oracle
 timed on a bounded sample on the host.
@@ -55,7 +58,7 @@ def alg_bytes_per_dof(mesh, k: int, esz: int, per_point: bool) -> float:
 KERNEL_SOURCES = ["paper_1907_08492_amd/csrc/matvec.hpp", "paper_1907_08492_amd/csrc/sumfac.hpp",
                   "paper_1907_08492_amd/csrc/sipg_common.hpp", "paper_1907_08492_amd/csrc/matvec_launch.hpp",
                   "paper_1907_08492_amd/csrc/matvec_n5.hip", "paper_1907_08492_amd/csrc/setup.hip"]
-TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sipg_matvec_k4_64c_deformed_f64.traffic.json")
+TRAFFIC_FILE = os.path.join(ROOT, "profiles", "sipg_matvec_pjacobi_k4_64c_deformed_f64.traffic.json")
 
 
 def kernel_source_hash() -> str:
@@ -84,6 +87,22 @@ def measured_traffic(avg_launch_s: float):
 def make_inputs(torch, ndofs, dtype, nrot, seed0=0):
     from workloads import uniform_vector
     return [torch.from_numpy(uniform_vector(ndofs, seed0 + i)).to("cuda", dtype=dtype) for i in range(nrot)]
+
+
+def time_launches(torch, launch, launches: int, warmup: int):
+    """Per-launch durations (ms) of launch(i) from HIP events on the current
+    stream (the one the library launches on)."""
+    st = torch.cuda.current_stream()
+    for i in range(warmup):
+        launch(i)
+    torch.cuda.synchronize()
+    ev = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)) for _ in range(launches)]
+    for i in range(launches):
+        ev[i][0].record(st)
+        launch(i)
+        ev[i][1].record(st)
+    torch.cuda.synchronize()
+    return [a.elapsed_time(b) for a, b in ev]
 
 
 def time_matvec(torch, op, xs, ys, launches: int, warmup: int):
@@ -357,22 +376,16 @@ def main():
         del a, b
 
     st = torch.cuda.current_stream()
-    ev_mv = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
-             for _ in range(args.steps)]
-    ev_pj = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+    ev_st = [(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
              for _ in range(args.steps)]
 
     def step(i, timed):
         x, y, z = xs[i % nrot], ys[i % nrot], zs[i % nrot]
         if timed:
-            ev_mv[i][0].record(st)
-        op.apply(x, y)
+            ev_st[i][0].record(st)
+        op.apply_pjacobi(x, y, z)
         if timed:
-            ev_mv[i][1].record(st)
-            ev_pj[i][0].record(st)
-        op.basis_change("PJACOBI", y, z)
-        if timed:
-            ev_pj[i][1].record(st)
+            ev_st[i][1].record(st)
 
     print(f"[bench] warmup {args.warmup}", file=sys.stderr, flush=True)
     for i in range(args.warmup):
@@ -385,15 +398,22 @@ def main():
     torch.cuda.synchronize()
     t1 = time.perf_counter()
     T = t1 - t0
-    mv_ms = np.array([a.elapsed_time(b) for a, b in ev_mv])
-    pj_ms = np.array([a.elapsed_time(b) for a, b in ev_pj])
+    st_ms = np.array([a.elapsed_time(b) for a, b in ev_st])
     ndofs = op.ndofs
     value = ndofs * args.steps / T
+    # the product and the preconditioner alone, as separate launches
+    nleg = max(10, args.steps // 2)
+    mv_ms = np.array(time_launches(torch, lambda i: op.apply(xs[i % nrot], ys[i % nrot]), nleg, 3))
+    pj_ms = np.array(time_launches(torch, lambda i: op.basis_change("PJACOBI", ys[i % nrot], zs[i % nrot]),
+                                   nleg, 3))
     bpd = alg_bytes_per_dof(mesh, k, 8, per_point=True)
-    mv_s = float(mv_ms.mean()) * 1e-3
-    achieved = bpd * ndofs / mv_s / 1e9
     pj_bpd = 8.0 * 3          # read y, read 1/diag, write z
-    traffic, traffic_bytes = measured_traffic(mv_s)
+    step_bpd = bpd + 16.0     # the product, plus read 1/diag and write z (y is not read again)
+    st_s = float(st_ms.mean()) * 1e-3
+    achieved = step_bpd * ndofs / st_s / 1e9
+    traffic, traffic_bytes = measured_traffic(st_s)
+    mv_s = float(mv_ms.mean()) * 1e-3
+    mv_gbs = bpd * ndofs / mv_s / 1e9
     pj_s = float(pj_ms.mean()) * 1e-3
 
     out = {
@@ -412,19 +432,24 @@ def main():
         "config": {"workload": "SIPG Hermite-like matvec + P^-1, k=4, 64^3 cells of the sine-deformed unit cube "
                                "(amplitude 0.1), per-point metric terms, penalty 2(k+1)^2/h",
                    "ndofs": ndofs, "degree": k, "cells": list(mesh.n), "basis": "hermite_like",
-                   "geometry": "per quadrature point", "parallelism": "1 GPU"},
+                   "geometry": "per quadrature point", "parallelism": "1 GPU",
+                   "step": "y = A x and z = P^-1 y in one launch (sipg_apply_pjacobi)"},
         "roofline": {"bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
                      "frac": achieved / HBM_PEAK_GBS, "traffic": traffic,
                      "traffic_bytes_per_launch": traffic_bytes,
-                     "kernel": "sipg_matvec_kernel<5,0,double,2>",
-                     "alg_bytes_per_dof": bpd, "avg_launch_ms": mv_s * 1e3},
-        # mean over launches; the paper reports the best timing, so the
-        # median and the best launch are given too
-        "matvec": {"dof_per_s": ndofs / mv_s, "avg_ms": mv_s * 1e3, "min_ms": float(mv_ms.min()),
+                     "kernel": "sipg_matvec_pjacobi_kernel<5,0,double,2>",
+                     "alg_bytes_per_dof": step_bpd, "avg_launch_ms": st_s * 1e3},
+        # the product alone (sipg_apply).  Mean over launches; the paper
+        # reports the best timing, so the median and the best launch are
+        # given too
+        "matvec": {"kernel": "sipg_matvec_kernel<5,0,double,2>",
+                   "dof_per_s": ndofs / mv_s, "avg_ms": mv_s * 1e3, "min_ms": float(mv_ms.min()),
                    "median_ms": float(np.median(mv_ms)), "dof_per_s_median": ndofs / (float(np.median(mv_ms)) * 1e-3),
                    "dof_per_s_max": ndofs / (float(mv_ms.min()) * 1e-3),
-                   "alg_GBs": achieved, "hbm_frac": achieved / HBM_PEAK_GBS,
+                   "alg_bytes_per_dof": bpd, "alg_GBs": mv_gbs, "hbm_frac": mv_gbs / HBM_PEAK_GBS,
                    "valu_frac_table4": TABLE4_FLOP["hermite_like"][k] * ndofs / mv_s / (FP64_PEAK_TFLOPS * 1e12)},
+        # the step as two launches (sipg_apply, then sipg_basis_change), for comparison
+        "two_launch_step_ms": (mv_s + pj_s) * 1e3,
         "pjacobi": {"dof_per_s": ndofs / pj_s, "avg_ms": pj_s * 1e3, "alg_GBs": pj_bpd * ndofs / pj_s / 1e9,
                     "hbm_frac": pj_bpd * ndofs / pj_s / 1e9 / HBM_PEAK_GBS},
         # block-Jacobi of Section 6.4: read r, write z (+ 4 scalars per cell)

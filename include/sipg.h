@@ -201,6 +201,20 @@ enum { SIPG_BC_T = 0, SIPG_BC_TT = 1, SIPG_BC_VALUES = 2, SIPG_BC_PJACOBI = 3, S
 int sipg_basis_change(const sipg_op* op, int mode, const void* in, void* out, void* stream);
 
 /*
+ * y = A x and z = P^-1 y in one pass, with P^-1 the point-Jacobi
+ * preconditioner of eq. (jacobi) as in SIPG_BC_PJACOBI: the product of
+ * sipg_apply, then, cell by cell in the same workgroup, (T^T)^{x3}
+ * diag(A_GL)^-1 T^{x3} of that cell's y.  y equals sipg_apply's output bit
+ * for bit; z equals sipg_basis_change(SIPG_BC_PJACOBI, y) up to rounding.
+ * Saves the second read of y and a launch.
+ *   x, y, z  device pointers, ndofs elements each, operator precision; they
+ *            must not overlap (SIPG_E_ARG).
+ * Needs sipg_compute_gl_diagonal first (else SIPG_E_ARG).  Allocates nothing;
+ * stream ordered.
+ */
+int sipg_apply_pjacobi(const sipg_op* op, const void* x, void* y, void* z, void* stream);
+
+/*
  * Compute diag(A) of the operator in the nodal Gauss-Lobatto basis, i.e. the
  * element-wise diagonal P_d of eq. (jacobi), and keep its inverse inside the
  * operator for SIPG_BC_PJACOBI.  Computed on the device by the same weak form.

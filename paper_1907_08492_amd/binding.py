@@ -38,7 +38,7 @@ BC_MODES = {"T": 0, "TT": 1, "VALUES": 2, "PJACOBI": 3, "FDM": 4}
 SMOOTHERS = {"pjacobi": 0, "fdm": 1}
 
 EXPORTED = [
-    "sipg_setup", "sipg_destroy", "sipg_ndofs", "sipg_get_info", "sipg_apply",
+    "sipg_setup", "sipg_destroy", "sipg_ndofs", "sipg_get_info", "sipg_apply", "sipg_apply_pjacobi",
     "sipg_basis_change", "sipg_compute_gl_diagonal", "sipg_cg_solve",
     "sipg_last_error", "sipg_host_tables", "sipg_launch_shape",
     "sipg_mg_default_opts", "sipg_mg_setup", "sipg_mg_destroy", "sipg_mg_get_info",
@@ -123,6 +123,7 @@ lib.sipg_ndofs.argtypes = [_vp]
 lib.sipg_ndofs.restype = C.c_int64
 lib.sipg_get_info.argtypes = [_vp, C.POINTER(SipgOpInfo)]
 lib.sipg_apply.argtypes = [_vp, _vp, _vp, _vp]
+lib.sipg_apply_pjacobi.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.sipg_basis_change.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
 lib.sipg_compute_gl_diagonal.argtypes = [_vp, _vp, _vp]
 lib.sipg_cg_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
@@ -285,6 +286,15 @@ class Operator:
         _check(lib.sipg_apply(self._h, self._vec(x, "x"), self._vec(y, "out"), _vp(_stream_ptr(stream))),
                "sipg_apply")
         return y
+
+    def apply_pjacobi(self, x, y=None, z=None, stream=None):
+        """y = A x and z = P^-1 y (eq. (jacobi)) in one pass; needs
+        compute_gl_diagonal first.  Returns (y, z)."""
+        y = self.empty() if y is None else y
+        z = self.empty() if z is None else z
+        _check(lib.sipg_apply_pjacobi(self._h, self._vec(x, "x"), self._vec(y, "y"), self._vec(z, "z"),
+                                      _vp(_stream_ptr(stream))), "sipg_apply_pjacobi")
+        return y, z
 
     def basis_change(self, mode: str, x, out=None, stream=None):
         y = self.empty() if out is None else out

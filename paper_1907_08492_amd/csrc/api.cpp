@@ -129,6 +129,21 @@ int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st) {
     return SIPG_E_UNSUPPORTED;
 }
 
+int launch_matvec_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st) {
+    switch (op->n) {
+        case 2: return launch_matvec_pjacobi_n<2>(op, x, y, z, st);
+        case 3: return launch_matvec_pjacobi_n<3>(op, x, y, z, st);
+        case 4: return launch_matvec_pjacobi_n<4>(op, x, y, z, st);
+        case 5: return launch_matvec_pjacobi_n<5>(op, x, y, z, st);
+        case 6: return launch_matvec_pjacobi_n<6>(op, x, y, z, st);
+        case 7: return launch_matvec_pjacobi_n<7>(op, x, y, z, st);
+        case 8: return launch_matvec_pjacobi_n<8>(op, x, y, z, st);
+        case 9: return launch_matvec_pjacobi_n<9>(op, x, y, z, st);
+    }
+    set_error("unsupported degree");
+    return SIPG_E_UNSUPPORTED;
+}
+
 static bool ranges_overlap(const void* a, const void* b, size_t bytes) {
     const char* pa = static_cast<const char*>(a);
     const char* pb = static_cast<const char*>(b);
@@ -338,6 +353,20 @@ int sipg_apply(const sipg_op* op, const void* x, void* y, void* stream) {
     const size_t bytes = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
     if (ranges_overlap(x, y, bytes)) { set_error("sipg_apply: x and y overlap"); return SIPG_E_ARG; }
     return launch_matvec(op, x, y, static_cast<hipStream_t>(stream));
+}
+
+int sipg_apply_pjacobi(const sipg_op* op, const void* x, void* y, void* z, void* stream) {
+    if (!op || !x || !y || !z) { set_error("sipg_apply_pjacobi: null argument"); return SIPG_E_ARG; }
+    if (!op->gl_inv_diag) {
+        set_error("sipg_apply_pjacobi: needs sipg_compute_gl_diagonal first");
+        return SIPG_E_ARG;
+    }
+    const size_t bytes = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
+    if (ranges_overlap(x, y, bytes) || ranges_overlap(x, z, bytes) || ranges_overlap(y, z, bytes)) {
+        set_error("sipg_apply_pjacobi: x, y and z must not overlap");
+        return SIPG_E_ARG;
+    }
+    return launch_matvec_pjacobi(op, x, y, z, static_cast<hipStream_t>(stream));
 }
 
 int sipg_basis_change(const sipg_op* op, int mode, const void* in, void* out, void* stream) {

@@ -51,6 +51,9 @@ struct MatvecParams {
     const T* __restrict__ fgeom2;
     int nx, ny, nz;
     int ncells;
+    // fused preconditioner (sipg_apply_pjacobi): 1 / diag(A_GL), output z
+    const T* __restrict__ dinv;
+    T* __restrict__ z;
 };
 
 // Kernel parameters of operator `op` for the product y = A x.
@@ -68,6 +71,8 @@ inline MatvecParams<T> matvec_params(const sipg_op* op, const void* x, void* y) 
     p.ny = op->nc[1];
     p.nz = op->nc[2];
     p.ncells = int(op->ncells);
+    p.dinv = nullptr;
+    p.z = nullptr;
     return p;
 }
 
@@ -214,7 +219,9 @@ __device__ __forceinline__ int xcd_block_zinterleaved(int blk, int nblk, int lay
 }
 
 // The product on workgroup `blk` of the operator `p`: cells blk*CPB ...
-template <int N, int BASIS, typename T, int GEOM>
+// With PJAC, each cell's y is also multiplied by P^-1 of eq. (jacobi) in the
+// same workgroup and written to p.z (z = (T^T)^{x3} diag(A_GL)^-1 T^{x3} y).
+template <int N, int BASIS, typename T, int GEOM, bool PJAC = false>
 __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int blk) {
     using Sh = Shape<N>;
     using Ly = Layers<N, BASIS>;
@@ -711,7 +718,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     // Last step of either cell path: this thread's z pencil v (cell term in
     // nodal coefficients), plus e_layer (x) P + D_f (x) Q of the six faces,
     // written to y.
-    auto add_faces_and_store = [&](const T* v) {
+    auto add_faces_and_store = [&](T* v) {
         const int i1 = ta, i2 = tb;
         const auto df0 = tab + TL.df0;
         const auto df1 = tab + TL.df1;
@@ -762,6 +769,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 r += df1[k] * Q5[i2 * FR + i1];
             }
             yc[k * N2] = r;
+            if constexpr (PJAC) v[k] = r;
         }
     };
     if constexpr (DIAGM) {
@@ -924,6 +932,56 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         add_faces_and_store(v);
     }
     }   // quadrature cell term
+
+    if constexpr (PJAC) {
+        // z = P^-1 y on this cell, sweeps as in the stand-alone basis change:
+        // T along z, y, x, the inverse GL diagonal, T^T along x, y, z.  The
+        // thread holds its z pencil of y in v; A, which it last read at the
+        // same places, is the work array (no other pencil touches them).
+        if (act) {
+            eo_apply<N, +1>(tab + TL.T, v, v);
+#pragma unroll
+            for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, tb, k)] = v[k];
+        }
+        cell_sync();
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, k, tb)];
+            eo_apply<N, +1>(tab + TL.T, v, v);
+#pragma unroll
+            for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, k, tb)] = v[k];
+        }
+        cell_sync();
+        if (act) {
+            const T* __restrict__ dg = p.dinv + size_t(cell0 + c) * N3 + N * (ta + N * tb);
+            T d[N];
+#pragma unroll
+            for (int k = 0; k < N; ++k) { v[k] = A[Sh::lds_idx(k, ta, tb)]; d[k] = dg[k]; }
+            eo_apply<N, +1>(tab + TL.T, v, v);
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] *= d[k];
+            eo_apply<N, +1>(tab + TL.TT, v, v);
+#pragma unroll
+            for (int k = 0; k < N; ++k) A[Sh::lds_idx(k, ta, tb)] = v[k];
+        }
+        cell_sync();
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, k, tb)];
+            eo_apply<N, +1>(tab + TL.TT, v, v);
+#pragma unroll
+            for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, k, tb)] = v[k];
+        }
+        cell_sync();
+        if (act) {
+#pragma unroll
+            for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, tb, k)];
+            eo_apply<N, +1>(tab + TL.TT, v, v);
+            T* __restrict__ zc = p.z + size_t(cell0 + c) * N3 + ta + N * tb;
+#pragma unroll
+            for (int k = 0; k < N; ++k) zc[k * N2] = v[k];
+        }
+    }
 }
 
 // One operator: workgroup b handles cells b*CPB ... of it, in the
@@ -934,6 +992,16 @@ sipg_matvec_kernel(MatvecParams<T> p) {
     constexpr int CPB = cells_per_block(N);
     const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
     matvec_block<N, BASIS, T, GEOM>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks));
+}
+
+// The same product followed, cell by cell, by P^-1 of eq. (jacobi): y = A x
+// and z = P^-1 y in one pass (p.dinv, p.z set).
+template <int N, int BASIS, typename T, int GEOM>
+__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
+sipg_matvec_pjacobi_kernel(MatvecParams<T> p) {
+    constexpr int CPB = cells_per_block(N);
+    const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
+    matvec_block<N, BASIS, T, GEOM, true>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks));
 }
 
 // Many independent operators of the same degree, basis, precision and

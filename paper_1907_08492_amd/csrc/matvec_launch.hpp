@@ -7,7 +7,7 @@
 
 namespace sipg {
 
-template <int N, int BASIS, typename T, int GEOM, typename K>
+template <int N, int BASIS, typename T, int GEOM, int KIND, typename K>
 static int set_lds_limit(K kernel) {
     // Raising the dynamic LDS limit is idempotent; racing first calls from
     // several threads are harmless.
@@ -23,9 +23,23 @@ static int set_lds_limit(K kernel) {
 template <int N, int BASIS, typename T, int GEOM>
 static int launch_one(const sipg_op* op, const void* x, void* y, hipStream_t st) {
     auto kern = &sipg_matvec_kernel<N, BASIS, T, GEOM>;
-    if (int rc = set_lds_limit<N, BASIS, T, GEOM>(kern)) return rc;
+    if (int rc = set_lds_limit<N, BASIS, T, GEOM, 0>(kern)) return rc;
     const unsigned nblk = unsigned((op->ncells + cells_per_block(N) - 1) / cells_per_block(N));
     kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(matvec_params<T>(op, x, y));
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
+// y = A x and z = P^-1 y (eq. (jacobi)) in one pass; op->gl_inv_diag is set.
+template <int N, int BASIS, typename T, int GEOM>
+static int launch_one_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st) {
+    auto kern = &sipg_matvec_pjacobi_kernel<N, BASIS, T, GEOM>;
+    if (int rc = set_lds_limit<N, BASIS, T, GEOM, 2>(kern)) return rc;
+    const unsigned nblk = unsigned((op->ncells + cells_per_block(N) - 1) / cells_per_block(N));
+    MatvecParams<T> p = matvec_params<T>(op, x, y);
+    p.dinv = static_cast<const T*>(op->gl_inv_diag);
+    p.z = static_cast<T*>(z);
+    kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
     SIPG_HIP(hipGetLastError());
     return SIPG_OK;
 }
@@ -33,7 +47,7 @@ static int launch_one(const sipg_op* op, const void* x, void* y, hipStream_t st)
 template <int N, int BASIS, typename T, int GEOM>
 static int launch_group(const BatchGroup& g, hipStream_t st) {
     auto kern = &sipg_matvec_batched_kernel<N, BASIS, T, GEOM>;
-    if (int rc = set_lds_limit<N, BASIS, T, GEOM>(kern)) return rc;
+    if (int rc = set_lds_limit<N, BASIS, T, GEOM, 1>(kern)) return rc;
     kern<<<unsigned(g.nblocks), threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(
         static_cast<const MatvecParams<T>*>(g.params), g.blk_op, g.blk_first);
     SIPG_HIP(hipGetLastError());
@@ -65,13 +79,20 @@ static int dispatch(int basis, int dtype, int geom, F&& launch) {
 
 }  // namespace sipg
 
-// Defines the two per-degree entry points of setup.hpp for degree NV - 1.
+// Defines the three per-degree entry points of setup.hpp for degree NV - 1.
 #define SIPG_MATVEC_DEGREE(NV)                                                                          \
     namespace sipg {                                                                                    \
     template <>                                                                                         \
     int launch_matvec_n<NV>(const sipg_op* op, const void* x, void* y, hipStream_t st) {                \
         return dispatch<NV>(op->basis, op->dtype, matvec_geom(op), [&](auto b, auto t, auto g) {        \
             return launch_one<NV, decltype(b)::value, decltype(t), decltype(g)::value>(op, x, y, st);   \
+        });                                                                                             \
+    }                                                                                                   \
+    template <>                                                                                         \
+    int launch_matvec_pjacobi_n<NV>(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st) { \
+        return dispatch<NV>(op->basis, op->dtype, matvec_geom(op), [&](auto b, auto t, auto g) {        \
+            return launch_one_pjacobi<NV, decltype(b)::value, decltype(t), decltype(g)::value>(op, x, y, z, \
+                                                                                                 st);   \
         });                                                                                             \
     }                                                                                                   \
     template <>                                                                                         \

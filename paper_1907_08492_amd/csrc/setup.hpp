@@ -16,6 +16,10 @@ int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st);
 // Per-degree launchers (one translation unit each).
 template <int N>
 int launch_matvec_n(const sipg_op* op, const void* x, void* y, hipStream_t st);
+// y = A x and z = P^-1 y of eq. (jacobi) in one pass (needs op->gl_inv_diag).
+int launch_matvec_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st);
+template <int N>
+int launch_matvec_pjacobi_n(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st);
 
 // Operators of one degree, basis, precision and geometry mode applied by one
 // grid (sipg_batch_apply).  Device arrays: `params` holds one kernel

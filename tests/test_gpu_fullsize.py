@@ -102,6 +102,36 @@ def test_full_size_preconditioners_on_sampled_cells(mode):
     assert err <= 1e-12, err
 
 
+def test_full_size_apply_pjacobi_on_sampled_cells():
+    """The fused product and P^-1 (sipg_apply_pjacobi, the benchmark's step)
+    on the headline mesh: y on sampled cells against the oracle's rows, and z
+    on those cells against the oracle's P^-1 of the oracle's y (P^-1 acts
+    cell by cell)."""
+    torch, P = require_gpu()
+    banner("full size apply_pjacobi")
+    cfg = CONFIGS["scale_k4_64c_deformed"]
+    mesh, k = cfg.mesh, cfg.degree
+    n3 = (k + 1) ** 3
+    op = P.Operator(mesh, k, cfg.eta)
+    op.compute_gl_diagonal(return_diag=False)
+    x = uniform_vector(op.ndofs, 0)
+    xd = torch.from_numpy(x).cuda()
+    y, z = op.apply_pjacobi(xd)
+    torch.cuda.synchronize()
+    cells = _sample_cells(mesh, 24, 5)
+    y_s = _rows(y.cpu().numpy(), cells, n3)
+    z_s = _rows(z.cpu().numpy(), cells, n3)
+    del xd, y, z
+    op.close()
+    torch.cuda.empty_cache()
+    ref_y = SIPG(mesh, k, cfg.eta, cells=cells).apply_naive(x)
+    akk, _ = SIPG(mesh, k, cfg.eta, "nodal_gl", cells=cells).local_blocks()
+    ref_z = precond.pjacobi_hl(k, np.einsum("cii->ci", akk).reshape(-1), ref_y, len(cells))
+    err_y = np.max(np.abs(y_s - ref_y)) / np.max(np.abs(ref_y))
+    err_z = np.max(np.abs(z_s - ref_z)) / np.max(np.abs(ref_z))
+    assert err_y <= 1e-12 and err_z <= 1e-12, (err_y, err_z)
+
+
 def test_largest_supported_size_on_sampled_cells():
     """2,097,152,000 unknowns (256^3 cells, k = 4, the paper's affine brick),
     just below the 2^31 limit of the in-kernel indices: the product on sampled
