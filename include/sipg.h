@@ -280,6 +280,10 @@ typedef struct {
                                     mesh is coarsened: 0 none, 1 k -> max(1, k/2), 2 k -> k-1.
                                     Needed for meshes with odd cell counts, which cannot be
                                     coarsened by two */
+    int32_t fused_smoother;      /* 1 (default): on Hermite-like levels each Chebyshev step is
+                                    one launch, the product with the residual, P^-1 and the
+                                    update fused (the "merged" arrangement of Section 6); 0: the
+                                    product, then one merged pass.  Same results up to rounding */
 } sipg_mg_opts;
 typedef struct {
     int32_t levels;

@@ -144,6 +144,31 @@ int launch_matvec_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hi
     return SIPG_E_UNSUPPORTED;
 }
 
+int launch_matvec_cheb(const sipg_op* op, int mode, const void* b, const void* u, void* uo, double sigma,
+                       double theta, hipStream_t st) {
+    if (op->basis != SIPG_BASIS_HERMITE_LIKE) {
+        set_error("fused Chebyshev step: Hermite-like basis only");
+        return SIPG_E_UNSUPPORTED;
+    }
+    if ((mode == SIPG_BC_PJACOBI && !op->gl_inv_diag) || (mode == SIPG_BC_FDM && !op->fdm_cell) ||
+        (mode != SIPG_BC_PJACOBI && mode != SIPG_BC_FDM)) {
+        set_error("fused Chebyshev step: preconditioner mode or its data missing");
+        return SIPG_E_ARG;
+    }
+    switch (op->n) {
+        case 2: return launch_matvec_cheb_n<2>(op, mode, b, u, uo, sigma, theta, st);
+        case 3: return launch_matvec_cheb_n<3>(op, mode, b, u, uo, sigma, theta, st);
+        case 4: return launch_matvec_cheb_n<4>(op, mode, b, u, uo, sigma, theta, st);
+        case 5: return launch_matvec_cheb_n<5>(op, mode, b, u, uo, sigma, theta, st);
+        case 6: return launch_matvec_cheb_n<6>(op, mode, b, u, uo, sigma, theta, st);
+        case 7: return launch_matvec_cheb_n<7>(op, mode, b, u, uo, sigma, theta, st);
+        case 8: return launch_matvec_cheb_n<8>(op, mode, b, u, uo, sigma, theta, st);
+        case 9: return launch_matvec_cheb_n<9>(op, mode, b, u, uo, sigma, theta, st);
+    }
+    set_error("unsupported degree");
+    return SIPG_E_UNSUPPORTED;
+}
+
 static bool ranges_overlap(const void* a, const void* b, size_t bytes) {
     const char* pa = static_cast<const char*>(a);
     const char* pb = static_cast<const char*>(b);

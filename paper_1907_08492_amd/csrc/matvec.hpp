@@ -51,10 +51,24 @@ struct MatvecParams {
     const T* __restrict__ fgeom2;
     int nx, ny, nz;
     int ncells;
-    // fused preconditioner (sipg_apply_pjacobi): 1 / diag(A_GL), output z
+    // epilogues (see matvec_block): P^-1 data (1 / diag(A_GL) per unknown,
+    // or the 4 block-Jacobi scalars per cell), output z, and the Chebyshev
+    // step's right-hand side b, output uo and coefficients
     const T* __restrict__ dinv;
     T* __restrict__ z;
+    const T* __restrict__ b;
+    T* __restrict__ uo;
+    double sigma, theta;   // double in both precisions: one parameter layout
 };
+
+// Epilogues of the product kernel, applied per cell once y = A x is known:
+// EPI_PJACOBI writes y and z = P^-1 y (eq. (jacobi), point Jacobi in the GL
+// basis); EPI_CHEB_PJ / EPI_CHEB_FDM do not write y but one step of the
+// Chebyshev iteration of eq. (chebyshev) with u = x:
+//     uo <- u + sigma (u - uo) + theta P^-1 (b - A u)
+// with P^-1 the point Jacobi or the block Jacobi of Section 6.4 (the
+// "merged" arrangement of Section 6 fused into the product).
+enum { EPI_NONE = 0, EPI_PJACOBI = 1, EPI_CHEB_PJ = 2, EPI_CHEB_FDM = 3 };
 
 // Kernel parameters of operator `op` for the product y = A x.
 template <typename T>
@@ -73,6 +87,10 @@ inline MatvecParams<T> matvec_params(const sipg_op* op, const void* x, void* y) 
     p.ncells = int(op->ncells);
     p.dinv = nullptr;
     p.z = nullptr;
+    p.b = nullptr;
+    p.uo = nullptr;
+    p.sigma = 0.0;
+    p.theta = 0.0;
     return p;
 }
 
@@ -218,10 +236,9 @@ __device__ __forceinline__ int xcd_block_zinterleaved(int blk, int nblk, int lay
     return x.start + b;
 }
 
-// The product on workgroup `blk` of the operator `p`: cells blk*CPB ...
-// With PJAC, each cell's y is also multiplied by P^-1 of eq. (jacobi) in the
-// same workgroup and written to p.z (z = (T^T)^{x3} diag(A_GL)^-1 T^{x3} y).
-template <int N, int BASIS, typename T, int GEOM, bool PJAC = false>
+// The product on workgroup `blk` of the operator `p`: cells blk*CPB ...,
+// followed by the epilogue EPI on each cell (EPI_NONE: y only).
+template <int N, int BASIS, typename T, int GEOM, int EPI = EPI_NONE>
 __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int blk) {
     using Sh = Shape<N>;
     using Ly = Layers<N, BASIS>;
@@ -768,8 +785,8 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 else if (k == N - 1) r += P5[i2 * FR + i1];
                 r += df1[k] * Q5[i2 * FR + i1];
             }
-            yc[k * N2] = r;
-            if constexpr (PJAC) v[k] = r;
+            if constexpr (EPI <= EPI_PJACOBI) yc[k * N2] = r;
+            if constexpr (EPI != EPI_NONE) v[k] = r;
         }
     };
     if constexpr (DIAGM) {
@@ -933,13 +950,30 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     }
     }   // quadrature cell term
 
-    if constexpr (PJAC) {
-        // z = P^-1 y on this cell, sweeps as in the stand-alone basis change:
-        // T along z, y, x, the inverse GL diagonal, T^T along x, y, z.  The
-        // thread holds its z pencil of y in v; A, which it last read at the
-        // same places, is the work array (no other pencil touches them).
+    if constexpr (EPI != EPI_NONE) {
+        // P^-1 on this cell, sweeps as in the stand-alone basis change: T
+        // (or Z^T) along z, y, x, the diagonal, T^T (or Z) along x, y, z.
+        // The thread holds its z pencil of y in v; A, which it last read at
+        // the same places, is the work array (no other pencil touches them).
+        constexpr bool FDM = EPI == EPI_CHEB_FDM;
+        const size_t coff = size_t(cell0 + c) * N3 + ta + N * tb;   // this thread's z pencil
+        if constexpr (EPI != EPI_PJACOBI) {
+            // the residual b - A u
+            if (act) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) v[k] = p.b[coff + k * N2] - v[k];
+            }
+        }
+        auto fwd = [&](T* w) {
+            if constexpr (FDM) fdm_fwd<N>(p.tab + TL.FZP, w);
+            else eo_apply<N, +1>(tab + TL.T, w, w);
+        };
+        auto bwd = [&](T* w) {
+            if constexpr (FDM) fdm_bwd<N>(p.tab + TL.FZP, w);
+            else eo_apply<N, +1>(tab + TL.TT, w, w);
+        };
         if (act) {
-            eo_apply<N, +1>(tab + TL.T, v, v);
+            fwd(v);
 #pragma unroll
             for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, tb, k)] = v[k];
         }
@@ -947,20 +981,42 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         if (act) {
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, k, tb)];
-            eo_apply<N, +1>(tab + TL.T, v, v);
+            fwd(v);
 #pragma unroll
             for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, k, tb)] = v[k];
         }
         cell_sync();
         if (act) {
-            const T* __restrict__ dg = p.dinv + size_t(cell0 + c) * N3 + N * (ta + N * tb);
-            T d[N];
 #pragma unroll
-            for (int k = 0; k < N; ++k) { v[k] = A[Sh::lds_idx(k, ta, tb)]; d[k] = dg[k]; }
-            eo_apply<N, +1>(tab + TL.T, v, v);
+            for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(k, ta, tb)];
+            fwd(v);
+            if constexpr (FDM) {
+                // 1 / (vol (lambda_i/h_1^2 + lambda_j/h_2^2 + lambda_k/h_3^2)) from the
+                // cell's four scalars, by the hardware reciprocal refined with two
+                // Newton steps (d > 0)
+                const T* __restrict__ cs = p.dinv + size_t(cell0 + c) * 4;
+                const T c0 = cs[0], c3 = cs[3];
+                const T* lam = p.tab + TL.FLAM;
+                const T yz = pick<N>(lam, ta) * cs[1] + pick<N>(lam, tb) * cs[2];
 #pragma unroll
-            for (int k = 0; k < N; ++k) v[k] *= d[k];
-            eo_apply<N, +1>(tab + TL.TT, v, v);
+                for (int k = 0; k < N; ++k) {
+                    const T d = fma(lam[k], c0, yz);
+                    T q;
+                    if constexpr (sizeof(T) == 8) q = __builtin_amdgcn_rcp(d);
+                    else q = __builtin_amdgcn_rcpf(d);
+                    q = fma(q, fma(-d, q, T(1)), q);
+                    q = fma(q, fma(-d, q, T(1)), q);
+                    v[k] = v[k] * c3 * q;
+                }
+            } else {
+                const T* __restrict__ dg = p.dinv + size_t(cell0 + c) * N3 + N * (ta + N * tb);
+                T d[N];
+#pragma unroll
+                for (int k = 0; k < N; ++k) d[k] = dg[k];
+#pragma unroll
+                for (int k = 0; k < N; ++k) v[k] *= d[k];
+            }
+            bwd(v);
 #pragma unroll
             for (int k = 0; k < N; ++k) A[Sh::lds_idx(k, ta, tb)] = v[k];
         }
@@ -968,7 +1024,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         if (act) {
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, k, tb)];
-            eo_apply<N, +1>(tab + TL.TT, v, v);
+            bwd(v);
 #pragma unroll
             for (int k = 0; k < N; ++k) A[Sh::lds_idx(ta, k, tb)] = v[k];
         }
@@ -976,10 +1032,20 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         if (act) {
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, tb, k)];
-            eo_apply<N, +1>(tab + TL.TT, v, v);
-            T* __restrict__ zc = p.z + size_t(cell0 + c) * N3 + ta + N * tb;
+            bwd(v);
+            if constexpr (EPI == EPI_PJACOBI) {
 #pragma unroll
-            for (int k = 0; k < N; ++k) zc[k * N2] = v[k];
+                for (int k = 0; k < N; ++k) p.z[coff + k * N2] = v[k];
+            } else {
+                // uo <- u + sigma (u - uo) + theta P^-1 r  (sigma = 0: uo not read)
+                const T sg = T(p.sigma), th = T(p.theta);
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const T ui = p.x[coff + k * N2];
+                    const T uo = sg != T(0) ? p.uo[coff + k * N2] : ui;
+                    p.uo[coff + k * N2] = ui + sg * (ui - uo) + th * v[k];
+                }
+            }
         }
     }
 }
@@ -1001,7 +1067,18 @@ __global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
 sipg_matvec_pjacobi_kernel(MatvecParams<T> p) {
     constexpr int CPB = cells_per_block(N);
     const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
-    matvec_block<N, BASIS, T, GEOM, true>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks));
+    matvec_block<N, BASIS, T, GEOM, EPI_PJACOBI>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks));
+}
+
+// One step of the Chebyshev smoother fused into the product (u = p.x; p.b,
+// p.uo, p.dinv, p.sigma, p.theta set): uo <- u + sigma (u - uo) + theta P^-1
+// (b - A u), P^-1 point Jacobi (EPI_CHEB_PJ) or block Jacobi (EPI_CHEB_FDM).
+template <int N, int BASIS, typename T, int GEOM, int EPI>
+__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
+sipg_matvec_cheb_kernel(MatvecParams<T> p) {
+    constexpr int CPB = cells_per_block(N);
+    const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
+    matvec_block<N, BASIS, T, GEOM, EPI>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks));
 }
 
 // Many independent operators of the same degree, basis, precision and

@@ -44,6 +44,33 @@ static int launch_one_pjacobi(const sipg_op* op, const void* x, void* y, void* z
     return SIPG_OK;
 }
 
+// One Chebyshev smoothing step fused into the product (Hermite-like basis):
+// uo = u + sigma (u - uo) + theta P^-1 (b - A u), P^-1 by `mode`
+// (SIPG_BC_PJACOBI with op->gl_inv_diag, SIPG_BC_FDM with op->fdm_cell).
+template <int N, typename T, int GEOM>
+static int launch_one_cheb(const sipg_op* op, int mode, const void* b, const void* u, void* uo, double sigma,
+                           double theta, hipStream_t st) {
+    MatvecParams<T> p = matvec_params<T>(op, u, uo);   // y is not written by this epilogue
+    p.b = static_cast<const T*>(b);
+    p.uo = static_cast<T*>(uo);
+    p.sigma = sigma;
+    p.theta = theta;
+    const unsigned nblk = unsigned((op->ncells + cells_per_block(N) - 1) / cells_per_block(N));
+    if (mode == SIPG_BC_PJACOBI) {
+        auto kern = &sipg_matvec_cheb_kernel<N, 0, T, GEOM, EPI_CHEB_PJ>;
+        if (int rc = set_lds_limit<N, 0, T, GEOM, 3>(kern)) return rc;
+        p.dinv = static_cast<const T*>(op->gl_inv_diag);
+        kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
+    } else {
+        auto kern = &sipg_matvec_cheb_kernel<N, 0, T, GEOM, EPI_CHEB_FDM>;
+        if (int rc = set_lds_limit<N, 0, T, GEOM, 4>(kern)) return rc;
+        p.dinv = static_cast<const T*>(op->fdm_cell);
+        kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
+    }
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
 template <int N, int BASIS, typename T, int GEOM>
 static int launch_group(const BatchGroup& g, hipStream_t st) {
     auto kern = &sipg_matvec_batched_kernel<N, BASIS, T, GEOM>;
@@ -77,9 +104,23 @@ static int dispatch(int basis, int dtype, int geom, F&& launch) {
     return dtype == SIPG_F64 ? by_basis(double{}) : by_basis(float{});
 }
 
+// The same for the Hermite-like basis only: launch<T, GEOM>().
+template <int N, typename F>
+static int dispatch_hl(int dtype, int geom, F&& launch) {
+    using GC = std::integral_constant<int, GEOM_CELL>;
+    using GQ = std::integral_constant<int, GEOM_QPOINT>;
+    using GD = std::integral_constant<int, GEOM_CELL_DIAG>;
+    auto by_geom = [&](auto t) {
+        if (geom == GEOM_CELL) return launch(t, GC{});
+        if (geom == GEOM_CELL_DIAG) return launch(t, GD{});
+        return launch(t, GQ{});
+    };
+    return dtype == SIPG_F64 ? by_geom(double{}) : by_geom(float{});
+}
+
 }  // namespace sipg
 
-// Defines the three per-degree entry points of setup.hpp for degree NV - 1.
+// Defines the four per-degree entry points of setup.hpp for degree NV - 1.
 #define SIPG_MATVEC_DEGREE(NV)                                                                          \
     namespace sipg {                                                                                    \
     template <>                                                                                         \
@@ -93,6 +134,13 @@ static int dispatch(int basis, int dtype, int geom, F&& launch) {
         return dispatch<NV>(op->basis, op->dtype, matvec_geom(op), [&](auto b, auto t, auto g) {        \
             return launch_one_pjacobi<NV, decltype(b)::value, decltype(t), decltype(g)::value>(op, x, y, z, \
                                                                                                  st);   \
+        });                                                                                             \
+    }                                                                                                   \
+    template <>                                                                                         \
+    int launch_matvec_cheb_n<NV>(const sipg_op* op, int mode, const void* b, const void* u, void* uo,   \
+                                 double sigma, double theta, hipStream_t st) {                          \
+        return dispatch_hl<NV>(op->dtype, matvec_geom(op), [&](auto t, auto g) {                        \
+            return launch_one_cheb<NV, decltype(t), decltype(g)::value>(op, mode, b, u, uo, sigma, theta, st); \
         });                                                                                             \
     }                                                                                                   \
     template <>                                                                                         \

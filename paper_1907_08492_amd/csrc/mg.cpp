@@ -181,6 +181,7 @@ struct Hierarchy {
     int smooth_steps = 5;
     int coarse_steps = 1;
     int pmode = SIPG_BC_PJACOBI;   // P^-1 of the smoother: SIPG_BC_PJACOBI or SIPG_BC_FDM
+    bool fused = true;             // Chebyshev steps fused into the product (Hermite-like levels)
 
     // u = S^m(b; u) on level l (u = 0 on entry when zero_init).
     int smooth(int l, bool zero_init, int steps, const std::vector<double>& sig, const std::vector<double>& th,
@@ -196,10 +197,17 @@ struct Hierarchy {
                 continue;
             }
             // u_{j+1} = u_j + sigma_j (u_j - u_{j-1}) + theta_j P^-1 (b - A u_j)
-            // into uo (residual, preconditioner and update in one pass), then swap
-            if ((rc = launch_matvec(L.op, L.u.p, L.r.p, st)) != SIPG_OK) return rc;
-            if ((rc = launch_precond_cheb(L.op, pmode, L.b.p, L.r.p, L.u.p, L.uo.p, j == 0 ? 0.0 : sig[j], th[j], st)) != SIPG_OK)
-                return rc;
+            // into uo, then swap: one launch (product, residual, preconditioner
+            // and update fused) on Hermite-like levels, else the product and
+            // one merged pass
+            const double sj = j == 0 ? 0.0 : sig[j];
+            if (fused && L.op->basis == SIPG_BASIS_HERMITE_LIKE) {
+                if ((rc = launch_matvec_cheb(L.op, pmode, L.b.p, L.u.p, L.uo.p, sj, th[j], st)) != SIPG_OK) return rc;
+            } else {
+                if ((rc = launch_matvec(L.op, L.u.p, L.r.p, st)) != SIPG_OK) return rc;
+                if ((rc = launch_precond_cheb(L.op, pmode, L.b.p, L.r.p, L.u.p, L.uo.p, sj, th[j], st)) != SIPG_OK)
+                    return rc;
+            }
             std::swap(L.u.p, L.uo.p);
         }
         return SIPG_OK;
@@ -363,6 +371,7 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
     const int dt = std::is_same<T, double>::value ? SIPG_F64 : SIPG_F32;
     H.smooth_steps = o.smoother_degree;
     H.pmode = o.smoother == 1 ? SIPG_BC_FDM : SIPG_BC_PJACOBI;
+    H.fused = o.fused_smoother != 0;
     const std::vector<LevelSpec> seq = mg_level_sequence(mesh->n, degree, o);
     int rc;
     for (size_t l = 0; l < seq.size(); ++l) {
@@ -471,6 +480,7 @@ int sipg_mg_default_opts(sipg_mg_opts* o) {
     o->precision = 0;
     o->smoother = 0;
     o->p_coarsening = 0;
+    o->fused_smoother = 1;
     return SIPG_OK;
 }
 
@@ -483,7 +493,8 @@ int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, 
     if (opts) o = *opts;
     if (o.smoother_degree < 1 || o.smoother_degree > 64 || o.lanczos_steps < 2 || o.lanczos_steps > kMaxLanczos || !(o.range_lo > 0.0) ||
         !(o.range_hi > o.range_lo) || !(o.coarse_reduction > 1.0) || (o.precision != 0 && o.precision != 1) ||
-        o.min_coarse_cells < 1 || (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2) {
+        o.min_coarse_cells < 1 || (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2 ||
+        (o.fused_smoother != 0 && o.fused_smoother != 1)) {
         set_error("sipg_mg_setup: invalid options");
         return SIPG_E_ARG;
     }

@@ -20,6 +20,15 @@ int launch_matvec_n(const sipg_op* op, const void* x, void* y, hipStream_t st);
 int launch_matvec_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st);
 template <int N>
 int launch_matvec_pjacobi_n(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st);
+// One Chebyshev smoothing step fused into the product, Hermite-like basis
+// only: uo = u + sigma (u - uo) + theta P^-1 (b - A u), P^-1 by mode
+// (SIPG_BC_PJACOBI or SIPG_BC_FDM); sigma = 0 does not read uo.  u, uo, b
+// distinct.  SIPG_E_UNSUPPORTED for other bases.
+int launch_matvec_cheb(const sipg_op* op, int mode, const void* b, const void* u, void* uo, double sigma,
+                       double theta, hipStream_t st);
+template <int N>
+int launch_matvec_cheb_n(const sipg_op* op, int mode, const void* b, const void* u, void* uo, double sigma,
+                         double theta, hipStream_t st);
 
 // Operators of one degree, basis, precision and geometry mode applied by one
 // grid (sipg_batch_apply).  Device arrays: `params` holds one kernel

@@ -252,3 +252,26 @@ def test_vcycle_with_degree_levels_is_symmetric_in_fp64():
     rhs = float(torch.dot(a, mg.vcycle(b)))
     assert abs(lhs - rhs) <= 1e-10 * abs(lhs), (lhs, rhs)
     mg.close()
+
+
+@pytest.mark.parametrize("smoother", ["pjacobi", "fdm"])
+@pytest.mark.parametrize("precision", ["mixed", "f64"])
+def test_fused_smoother_matches_two_launch_smoother(smoother, precision):
+    """The Chebyshev step fused into the product (residual, P^-1 and update
+    in the product's workgroups) gives the V-cycle of the product followed by
+    the merged pass, up to rounding."""
+    torch, P = require_gpu()
+    banner(f"fused smoother {smoother} {precision}")
+    mesh = unit_cube((4, 4, 6), 0.1)
+    k = 4
+    r = np.random.default_rng(9).uniform(-1, 1, mesh.ncells * (k + 1) ** 3)
+    out = []
+    for fused in (1, 0):
+        mg = P.Multigrid(mesh, k, 2.0, precision=precision, smoother=smoother, fused_smoother=fused)
+        assert mg.info.levels >= 2 and mg.ndofs == r.size
+        out.append(mg.vcycle(torch.from_numpy(r).cuda()).cpu().numpy())
+        x, info = mg.solve(torch.from_numpy(r).cuda(), rel_tol=1e-10)
+        assert info.iterations <= 25
+        mg.close()
+    diff = np.max(np.abs(out[0] - out[1])) / np.max(np.abs(out[1]))
+    assert diff <= (1e-13 if precision == "f64" else 1e-6), diff
