@@ -789,6 +789,18 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
             if constexpr (EPI != EPI_NONE) v[k] = r;
         }
     };
+    // Chebyshev epilogues: this thread's z pencil of b, loaded before the
+    // last cell step so that its latency overlaps that step
+    const size_t coff = size_t(cell0 + c) * N3 + ta + N * tb;   // this thread's z pencil
+    T eb[EPI >= EPI_CHEB_PJ ? N : 1];
+    auto load_epi_b = [&]() {
+        if constexpr (EPI >= EPI_CHEB_PJ) {
+            if (act) {
+#pragma unroll
+                for (int k = 0; k < N; ++k) eb[k] = p.b[coff + k * N2];
+            }
+        }
+    };
     if constexpr (DIAGM) {
         // ---- Cell term with a diagonal metric (G_00, G_11, G_22 per cell)
         // in reference coordinates, with the 1D mass M = S^T W S and
@@ -822,6 +834,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         }
         cell_sync();
         // K3: z pencils (thread (i1, i2)): M_z t + G_22 L_z (M_y M_x x), faces, write
+        load_epi_b();
         if (act) {
             T t[N], q[N];
 #pragma unroll
@@ -942,6 +955,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     }
     cell_sync();
     // C9: z pencils (thread (i1, i2)) : S^T along z, add face terms, write y
+    load_epi_b();
     if (act) {
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = A[Sh::lds_idx(ta, tb, k)];
@@ -956,12 +970,29 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         // The thread holds its z pencil of y in v; A, which it last read at
         // the same places, is the work array (no other pencil touches them).
         constexpr bool FDM = EPI == EPI_CHEB_FDM;
-        const size_t coff = size_t(cell0 + c) * N3 + ta + N * tb;   // this thread's z pencil
-        if constexpr (EPI != EPI_PJACOBI) {
-            // the residual b - A u
-            if (act) {
+        constexpr bool CHEB = EPI != EPI_PJACOBI;
+        // operands of the later steps, loaded now: the diagonal (this
+        // thread's x pencil) or the cell's four scalars, and u, u_old
+        T d[N], cs[4], uu[CHEB ? N : 1], uold[CHEB ? N : 1];
+        if (act) {
+            if constexpr (FDM) {
 #pragma unroll
-                for (int k = 0; k < N; ++k) v[k] = p.b[coff + k * N2] - v[k];
+                for (int m = 0; m < 4; ++m) cs[m] = p.dinv[size_t(cell0 + c) * 4 + m];
+            } else {
+                const T* __restrict__ dg = p.dinv + size_t(cell0 + c) * N3 + N * (ta + N * tb);
+#pragma unroll
+                for (int k = 0; k < N; ++k) d[k] = dg[k];
+            }
+            if constexpr (CHEB) {
+                const bool rd = T(p.sigma) != T(0);
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    uu[k] = p.x[coff + k * N2];
+                    uold[k] = rd ? p.uo[coff + k * N2] : uu[k];
+                }
+                // the residual b - A u
+#pragma unroll
+                for (int k = 0; k < N; ++k) v[k] = eb[k] - v[k];
             }
         }
         auto fwd = [&](T* w) {
@@ -994,7 +1025,6 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 // 1 / (vol (lambda_i/h_1^2 + lambda_j/h_2^2 + lambda_k/h_3^2)) from the
                 // cell's four scalars, by the hardware reciprocal refined with two
                 // Newton steps (d > 0)
-                const T* __restrict__ cs = p.dinv + size_t(cell0 + c) * 4;
                 const T c0 = cs[0], c3 = cs[3];
                 const T* lam = p.tab + TL.FLAM;
                 const T yz = pick<N>(lam, ta) * cs[1] + pick<N>(lam, tb) * cs[2];
@@ -1009,10 +1039,6 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                     v[k] = v[k] * c3 * q;
                 }
             } else {
-                const T* __restrict__ dg = p.dinv + size_t(cell0 + c) * N3 + N * (ta + N * tb);
-                T d[N];
-#pragma unroll
-                for (int k = 0; k < N; ++k) d[k] = dg[k];
 #pragma unroll
                 for (int k = 0; k < N; ++k) v[k] *= d[k];
             }
@@ -1040,11 +1066,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 // uo <- u + sigma (u - uo) + theta P^-1 r  (sigma = 0: uo not read)
                 const T sg = T(p.sigma), th = T(p.theta);
 #pragma unroll
-                for (int k = 0; k < N; ++k) {
-                    const T ui = p.x[coff + k * N2];
-                    const T uo = sg != T(0) ? p.uo[coff + k * N2] : ui;
-                    p.uo[coff + k * N2] = ui + sg * (ui - uo) + th * v[k];
-                }
+                for (int k = 0; k < N; ++k) p.uo[coff + k * N2] = uu[k] + sg * (uu[k] - uold[k]) + th * v[k];
             }
         }
     }
