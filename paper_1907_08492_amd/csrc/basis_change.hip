@@ -127,7 +127,8 @@ basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __re
         for (int k = 0; k < N; ++k) v[k] = A[Sh::idx(k, ta, tb)];
         fwd(v);
         if constexpr (MODE == 1) {
-            const T* dg = inv_diag + size_t(cell0 + c) * N3 + N * (ta + N * tb);
+            T dg[N];
+            load_chunked_pencil<N>(inv_diag + size_t(cell0 + c) * N3, ta + N * tb, dg);
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] *= dg[k];
         }

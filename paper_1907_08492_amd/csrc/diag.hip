@@ -60,11 +60,11 @@ __global__ void gl_diagonal_kernel(const T* __restrict__ tab, int n, const T* __
         const bool interior = s ? idx[d] + 1 < nd[d] : idx[d] > 0;
         int fi[3] = {idx[0], idx[1], idx[2]};
         fi[d] += s;
-        int64_t fidx;
+        int64_t fidx, nf;
         const T* fg;
-        if (d == 0) { fidx = fi[0] + int64_t(nx + 1) * (fi[1] + int64_t(ny) * fi[2]); fg = fg0; }
-        else if (d == 1) { fidx = fi[0] + int64_t(nx) * (fi[1] + int64_t(ny + 1) * fi[2]); fg = fg1; }
-        else { fidx = fi[0] + int64_t(nx) * (fi[1] + int64_t(ny) * fi[2]); fg = fg2; }
+        if (d == 0) { fidx = fi[0] + int64_t(nx + 1) * (fi[1] + int64_t(ny) * fi[2]); fg = fg0; nf = int64_t(nx + 1) * ny * nz; }
+        else if (d == 1) { fidx = fi[0] + int64_t(nx) * (fi[1] + int64_t(ny + 1) * fi[2]); fg = fg1; nf = int64_t(nx) * (ny + 1) * nz; }
+        else { fidx = fi[0] + int64_t(nx) * (fi[1] + int64_t(ny) * fi[2]); fg = fg2; nf = int64_t(nx) * ny * (nz + 1); }
         const double dfl = double((s ? tab + TL.df1gl : tab + TL.df0gl)[layer]);
         double fs = 0.0;
         for (int qb = 0; qb < n; ++qb)
@@ -74,7 +74,7 @@ __global__ void gl_diagonal_kernel(const T* __restrict__ tab, int n, const T* __
                     const double wq = double(w[qa]) * double(w[qb]);
                     for (int k = 0; k < 7; ++k) rec[k] = double(fg[fidx * 8 + k]) * wq;
                 } else {
-                    for (int k = 0; k < 7; ++k) rec[k] = double(fg[fidx * 7 * n2 + k * n2 + qb + n * qa]);
+                    for (int k = 0; k < 7; ++k) rec[k] = double(fg[face_rec_offset(n, 16 / int(sizeof(T)), nf, fidx, k, qa, qb)]);
                 }
                 double gm[3];
                 for (int k = 0; k < 3; ++k) gm[k] = s ? rec[1 + k] : -rec[4 + k];
@@ -89,9 +89,9 @@ __global__ void gl_diagonal_kernel(const T* __restrict__ tab, int n, const T* __
             }
         acc += interior ? fs : 2.0 * fs;
     }
-    const size_t o = size_t(cell) * n3 + i;
-    if (diag) diag[o] = T(acc);
-    inv_diag[o] = T(1.0 / acc);
+    const size_t o = size_t(cell) * n3;
+    if (diag) diag[o + i] = T(acc);
+    inv_diag[o + inv_diag_offset(n, 16 / int(sizeof(T)), i)] = T(1.0 / acc);
 }
 
 int launch_gl_diagonal(const sipg_op* op, void* diag, hipStream_t st) {

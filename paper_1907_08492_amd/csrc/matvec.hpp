@@ -215,25 +215,37 @@ __device__ __forceinline__ int xcd_block(int blk, int nblk) {
     return x.start + x.sl;
 }
 
-// The same, with the blocks of three consecutive z-layers interleaved inside
-// each XCD's range: with P blocks per layer, the range is cut into groups of
-// 3P blocks, and a group is visited as block j of its first, second and third
-// layer, then block j + 1 of each, and so on (a transpose of the 3 x P group;
-// a last, shorter group keeps the plain order).  In the lexicographic cell
-// order a z-neighbour is P blocks away, beyond what one XCD's L2 holds while
-// it streams the blocks in between; interleaved, two of every three z-faces
-// meet their second reader while its records and neighbour layers are still
-// there, and y-neighbours, 3 rows away, still do.
-__device__ __forceinline__ int xcd_block_zinterleaved(int blk, int nblk, int layer_blocks) {
-    constexpr int TZ = 3;
+// The same, with the blocks of up to eight consecutive z-layers interleaved
+// inside each XCD's range: with P blocks per layer, the range is cut into
+// groups of TZ P blocks (TZ = min(8, layers in the range)), and a group is
+// visited column by column: block j of its first, second, ... layer, then
+// block j + 1 of each, and so on (a transpose of the TZ x P group; the last
+// group, with fewer layers and a shorter last row, is transposed the same
+// way).  In the lexicographic order a z-neighbour is P blocks away, beyond
+// what one XCD's L2 holds while it streams the blocks in between;
+// interleaved, the two cells of a z-face are read TZ - 1 or fewer blocks
+// apart, and the two XCDs that share the plane between their ranges reach it
+// at the same time.  y-neighbours, about TZ rows of blocks apart, are then
+// read again from the memory-side cache rather than from HBM.
+__device__ __forceinline__ int xcd_block_zinterleaved(int blk, int nblk, int P) {
     const XcdSlot x = xcd_slot(blk, nblk);
-    const int G = TZ * layer_blocks;
-    int b = x.sl;
-    if (layer_blocks > 0 && G <= x.len) {
-        const int g = x.sl / G, s = x.sl - g * G;
-        if ((g + 1) * G <= x.len) b = g * G + (s % TZ) * layer_blocks + s / TZ;
+    if (P <= 0) return x.start + x.sl;
+    const int TZ = min(8, (x.len + P - 1) / P);
+    const int G = TZ * P;
+    const int g = x.sl / G, s = x.sl - g * G;
+    const int m = min(G, x.len - g * G);          // blocks of this group
+    const int tz = (m + P - 1) / P;               // its layers
+    const int r = m - (tz - 1) * P;               // blocks of its last layer
+    int row, col;
+    if (s < r * tz) {
+        col = s / tz;
+        row = s - col * tz;
+    } else {                                      // tz > 1 here
+        const int t = s - r * tz;
+        col = r + t / (tz - 1);
+        row = t - (col - r) * (tz - 1);
     }
-    return x.start + b;
+    return x.start + g * G + row * P + col;
 }
 
 // The product on workgroup `blk` of the operator `p`: cells blk*CPB ...,
@@ -323,16 +335,27 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 for (int k = 0; k < 3; ++k) frec[4 + k] = r[nb + k];
             }
         } else {
-            // record [value k][column a][point b]: this lane's column is a run
-            const T* __restrict__ r = fg + size_t(fidx) * (7 * N2) + N * fab;
+            // plane-major records (face_rec_offset): this lane's column a =
+            // fab is read as CH-point chunks along t2, one plane per chunk;
+            // the lanes of consecutive faces read consecutive 16-byte pieces
+            constexpr int CH = 16 / int(sizeof(T)), J = N / CH, R = N % CH;
+            const size_t nf = D == 0 ? size_t(p.nx + 1) * p.ny * p.nz
+                              : D == 1 ? size_t(p.nx) * (p.ny + 1) * p.nz : size_t(p.nx) * p.ny * (p.nz + 1);
+            const T* __restrict__ rc = fg + (size_t(fidx) * N + fab) * CH;
+            const T* __restrict__ rt = fg + size_t(7 * J * CH * N) * nf + (size_t(fidx) * N + fab) * R;
+            auto comp = [&](int k, T* dst) {
+#pragma unroll
+                for (int j = 0; j < J; ++j) load_run<CH>(rc + size_t(k * J + j) * nf * (CH * N), dst + j * CH);
+                if constexpr (R > 0) load_run<R>(rt + size_t(k) * nf * (R * N), dst + J * CH);
+            };
             if (part & 1) {
 #pragma unroll
-                for (int k = 0; k < 3; ++k) load_run<N>(r + (own + k) * N2, frec + (1 + k) * N);
+                for (int k = 0; k < 3; ++k) comp(own + k, frec + (1 + k) * N);
             }
             if (part & 2) {
-                load_run<N>(r, frec);
+                comp(0, frec);
 #pragma unroll
-                for (int k = 0; k < 3; ++k) load_run<N>(r + (nb + k) * N2, frec + (4 + k) * N);
+                for (int k = 0; k < 3; ++k) comp(nb + k, frec + (4 + k) * N);
             }
         }
     };
@@ -979,9 +1002,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
                 for (int m = 0; m < 4; ++m) cs[m] = p.dinv[size_t(cell0 + c) * 4 + m];
             } else {
-                const T* __restrict__ dg = p.dinv + size_t(cell0 + c) * N3 + N * (ta + N * tb);
-#pragma unroll
-                for (int k = 0; k < N; ++k) d[k] = dg[k];
+                load_chunked_pencil<N>(p.dinv + size_t(cell0 + c) * N3, ta + N * tb, d);
             }
             if constexpr (CHEB) {
                 const bool rd = T(p.sigma) != T(0);

@@ -113,10 +113,9 @@ __global__ void cell_geometry_kernel(MeshDev m, Rule r, T* __restrict__ out,
 // Record = {JxW sigma, JxW J_L^-1 n, JxW J_R^-1 n} with n the unit normal
 // pointing from the lower cell L to the upper cell R; on boundary faces the
 // missing side takes the present cell's values (mirror principle).  Per-point
-// storage multiplies by the face quadrature weights and orders a record as
-// [value k][point a along t1][point b along t2], so that the n points of one
-// t1 column are contiguous; per-face storage keeps the weight-free constant
-// of an affine face.
+// storage multiplies by the face quadrature weights and stores the records
+// of a direction plane by plane (face_rec_offset); per-face storage keeps the
+// weight-free constant of an affine face.
 template <typename T, int MODE>
 __global__ void face_geometry_kernel(MeshDev m, Rule r, int d, double sigma0, T* __restrict__ out,
                                      const double* __restrict__ vol, int64_t nfaces) {
@@ -176,7 +175,7 @@ __global__ void face_geometry_kernel(MeshDev m, Rule r, int d, double sigma0, T*
                 rec[4 + a] = jxw * (JRi[3 * a] * nv[0] + JRi[3 * a + 1] * nv[1] + JRi[3 * a + 2] * nv[2]);
             }
             if (MODE == GEOM_QPOINT) {
-                for (int k = 0; k < 7; ++k) out[f * 7 * n2 + k * n2 + qb + n * qa] = T(rec[k]);
+                for (int k = 0; k < 7; ++k) out[face_rec_offset(n, 16 / int(sizeof(T)), nfaces, f, k, qa, qb)] = T(rec[k]);
             } else {
                 for (int k = 0; k < 7; ++k) out[f * 8 + k] = T(rec[k]);
                 out[f * 8 + 7] = T(0);

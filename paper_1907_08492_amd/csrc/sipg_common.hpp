@@ -91,6 +91,34 @@ __host__ __device__ constexpr int cell_metric_offset(int n, int m, int q) {
     return k < 2 * h ? (m * h + k / 2) * 2 * n2 + 2 * t + (k & 1) : 12 * h * n2 + m * n2 + t;
 }
 
+// Offset of stored value k (0..6) at face point (qa along t1, qb along t2) of
+// face f among the nf faces of one direction, per-point storage, with
+// `chunk` = 16 / sizeof(element) points per load.  The records of a
+// direction are stored plane by plane: plane (k, j) holds, for every face in
+// order, the points qb = chunk j, ..., chunk j + chunk - 1 of every qa
+// ([face][qa][chunk]); for n not a multiple of the chunk, the remaining
+// points of every qa follow in planes k ([face][qa][rest]).  The lanes of a
+// face step that own consecutive columns qa of the faces of consecutive
+// cells then read one contiguous, 16-byte aligned range per plane.
+__host__ __device__ constexpr int64_t face_rec_offset(int n, int chunk, int64_t nf, int64_t f, int k, int qa,
+                                                      int qb) {
+    const int J = n / chunk, R = n % chunk;
+    return qb < J * chunk ? ((int64_t(k) * J + qb / chunk) * nf + f) * (chunk * n) + chunk * qa + qb % chunk
+                          : int64_t(7) * J * chunk * n * nf + (int64_t(k) * nf + f) * (R * n) + R * qa + (qb - J * chunk);
+}
+
+// Offset, inside a cell's n^3 values of the inverse diagonal kept for
+// P^-1 of eq. (jacobi), of unknown i = i1 + n (i2 + n i3).  The kernels read
+// it by x pencils (thread t = i2 + n i3 takes i1 = 0..n-1), so each pencil's
+// values are stored in chunks of `chunk` = 16 / sizeof(element) consecutive
+// i1 next to each other ([i1 / chunk][t][chunk]), then the remaining i1 of
+// every pencil ([t][rest]): a pencil is read with 16-byte loads, and the
+// pencils of a cell read one contiguous range per load.
+__host__ __device__ constexpr int inv_diag_offset(int n, int chunk, int i) {
+    const int n2 = n * n, t = i / n, k = i % n, J = n / chunk, R = n % chunk;
+    return k < J * chunk ? (k / chunk) * chunk * n2 + chunk * t + k % chunk : J * chunk * n2 + R * t + (k - J * chunk);
+}
+
 // Mesh description in the form the device kernels take it.
 struct MeshDev {
     int n[3];
@@ -115,7 +143,7 @@ struct sipg_op {
     void* cell_geom = nullptr;       // [ncells][cell_geom_stride]
     void* face_geom[3] = {nullptr, nullptr, nullptr};   // [nfaces_d][face_geom_stride]
     int64_t nfaces[3] = {0, 0, 0};
-    void* gl_inv_diag = nullptr;     // 1 / diag(A_GL) for SIPG_BC_PJACOBI (optional)
+    void* gl_inv_diag = nullptr;     // 1 / diag(A_GL) for SIPG_BC_PJACOBI (optional; inv_diag_offset layout)
     void* fdm_cell = nullptr;        // [ncells][4]: 1/h_1^2, 1/h_2^2, 1/h_3^2, 1/(h_1 h_2 h_3)
     int64_t device_bytes = 0;
 };

@@ -152,6 +152,16 @@ __device__ __forceinline__ void load_run(const T* __restrict__ src, T* dst) {
     for (; i < M; ++i) dst[i] = src[i];
 }
 
+// The N values of pencil t of a cell stored in chunks of 16 bytes
+// (inv_diag_offset): `cell` points to the cell's N^3 values.
+template <int N, typename T>
+__device__ __forceinline__ void load_chunked_pencil(const T* __restrict__ cell, int t, T* dst) {
+    constexpr int CH = 16 / int(sizeof(T)), J = N / CH, R = N % CH;
+#pragma unroll
+    for (int j = 0; j < J; ++j) load_run<CH>(cell + j * CH * N * N + CH * t, dst + j * CH);
+    if constexpr (R > 0) load_run<R>(cell + J * CH * N * N + R * t, dst + J * CH);
+}
+
 // P[i] for a lane-varying index 0 <= i < N, from uniform (scalar) loads.
 template <int N, typename PT>
 __device__ __forceinline__ auto pick(PT P, int i) {
