@@ -71,6 +71,25 @@ typedef struct {
     double deform_amp;
 } sipg_mesh;
 
+/*
+ * Device memory provider.  The operator's own arrays (1D tables, metric
+ * terms, preconditioner data), solver hierarchies and workspaces live in
+ * memory obtained from `alloc(bytes, ctx)`: device memory of the current
+ * device, at least 256-byte aligned, or NULL when none is available (the
+ * call then fails with SIPG_E_OOM).  `free(ptr, ctx)` returns it.  The
+ * library calls `free` only for blocks no device work it queued still uses
+ * (it waits for that work first); both callbacks may be called from the
+ * request loop's worker threads.  Every entry point that takes a
+ * `const sipg_allocator*` accepts NULL, meaning hipMalloc / hipFree.  With a
+ * caching allocator (for example PyTorch's) the set-up and solver calls then
+ * allocate no device memory of their own.
+ */
+typedef struct {
+    void* (*alloc)(size_t bytes, void* ctx);
+    void (*free)(void* ptr, void* ctx);
+    void* ctx;
+} sipg_allocator;
+
 typedef struct sipg_op sipg_op;
 
 /*
@@ -87,20 +106,25 @@ typedef struct sipg_op sipg_op;
  *   degree          polynomial degree k, 1 <= k <= 8.
  *   penalty_factor  > 0.
  *   basis, dtype, geometry   see the enums above.
+ *   allocator       device memory provider of the operator (NULL: hipMalloc);
+ *                   the operator keeps a copy of the struct and uses it for
+ *                   every later allocation of its own (the diagonal of
+ *                   sipg_compute_gl_diagonal, the workspace of sipg_cg_solve)
+ *                   and to free everything in sipg_destroy.
  *   stream          stream for the set-up kernels; the call synchronises
  *                   that stream before it returns.
  *   out             receives the operator handle (owned by the caller, freed
  *                   with sipg_destroy).
- * The operator owns all its device memory (1D tables and metric terms),
- * allocated here with hipMalloc.  Errors: SIPG_E_ARG (null pointers, k out of
- * range, non-positive n or penalty, SIPG_GEOM_CELL on a deformed mesh, a
- * non-invertible map), SIPG_E_OOM, SIPG_E_HIP.
+ * Errors: SIPG_E_ARG (null pointers, k out of range, non-positive n or
+ * penalty, SIPG_GEOM_CELL on a deformed mesh, a non-invertible map, an
+ * allocator with only one of its callbacks), SIPG_E_OOM, SIPG_E_HIP.
  */
 int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int basis,
-               int dtype, int geometry, void* stream, sipg_op** out);
+               int dtype, int geometry, const sipg_allocator* allocator, void* stream, sipg_op** out);
 
-/* Release an operator and its device memory (NULL is accepted).  The caller
- * must make sure no work that uses it is still queued. */
+/* Release an operator and its device memory through its allocator (NULL is
+ * accepted).  The caller must make sure no work that uses it is still
+ * queued. */
 int sipg_destroy(sipg_op* op);
 
 /* Number of unknowns n_cells * (degree+1)^3, or -1 for NULL. */
@@ -229,8 +253,9 @@ int sipg_compute_gl_diagonal(sipg_op* op, void* diag_out, void* stream);
  * on entry and the solution on exit.  Stops when ||b - A x||_2 <= rel_tol *
  * ||b||_2 (recursive CG residual) or after max_iter iterations
  * (SIPG_E_NOCONV, info still filled).  Blocks the host: it reads one scalar
- * per iteration.  Workspace (3 vectors) is allocated and freed by the call.
- * Requires an SIPG_F64 operator.
+ * per iteration.  Its workspace (3 vectors and a few scalars) comes from the
+ * operator's allocator and is returned before the call ends.  Requires an
+ * SIPG_F64 operator.
  */
 typedef struct {
     int32_t iterations;
@@ -240,6 +265,7 @@ typedef struct {
 } sipg_solve_info;
 int sipg_cg_solve(const sipg_op* op, const double* b, double* x, double rel_tol,
                   int max_iter, sipg_solve_info* info, void* stream);
+
 
 /* Host-only: launch shape of the matrix-free kernel for a degree and precision:
  * cells per workgroup, threads per workgroup and dynamic LDS bytes. */
@@ -300,16 +326,19 @@ typedef struct sipg_mg sipg_mg;
 int sipg_mg_default_opts(sipg_mg_opts* opts);
 /* Build the hierarchy (operators, diagonals, eigenvalue estimates) for the
  * same problem as sipg_setup; opts may be NULL (defaults).  Synchronises
- * `stream`.  The solver owns all its device memory. */
+ * `stream`.  The solver owns all its device memory: the level operators,
+ * vectors and CG work vectors come from `allocator` (NULL: hipMalloc) and are
+ * returned in sipg_mg_destroy. */
 int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int basis,
-                  const sipg_mg_opts* opts, void* stream, sipg_mg** out);
+                  const sipg_mg_opts* opts, const sipg_allocator* allocator, void* stream, sipg_mg** out);
 int sipg_mg_destroy(sipg_mg* mg);
 int sipg_mg_get_info(const sipg_mg* mg, sipg_mg_info* info);
 /* z = V-cycle(r): one application of the preconditioner (device, double, ndofs). */
 int sipg_mg_apply_vcycle(sipg_mg* mg, const double* r, double* z, void* stream);
 /* Solve A x = b (device, double) to ||b - A x|| <= rel_tol ||b|| with the
  * preconditioned CG; x holds the initial guess.  Blocks the host (one scalar
- * read per dot product).  Allocates its 4 FP64 work vectors per call.
+ * read per convergence check).  Uses the FP64 work vectors allocated by
+ * sipg_mg_setup (so concurrent solves on one hierarchy are not allowed).
  * SIPG_E_NOCONV after max_iter iterations (info still filled). */
 int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int max_iter,
                   sipg_solve_info* info, void* stream);
@@ -387,7 +416,10 @@ typedef struct {
 typedef struct sipg_server sipg_server;
 
 int sipg_server_default_opts(sipg_server_opts* opts);
-int sipg_server_create(const sipg_server_opts* opts, sipg_server** out);
+/* opts may be NULL (defaults).  Hierarchies and server-owned result buffers
+ * come from `allocator` (NULL: hipMalloc), whose callbacks are then called
+ * from the worker threads too. */
+int sipg_server_create(const sipg_server_opts* opts, const sipg_allocator* allocator, sipg_server** out);
 /* Non-blocking.  *ticket identifies the request.  SIPG_E_BUDGET if the
  * request alone can never fit the budget, SIPG_E_ARG for an invalid one. */
 int sipg_submit(sipg_server* s, const sipg_request* req, uint64_t* ticket);
@@ -395,8 +427,10 @@ int sipg_submit(sipg_server* s, const sipg_request* req, uint64_t* ticket);
 int sipg_poll(sipg_server* s, uint64_t ticket, sipg_result* res);
 /* Blocks until the request finished, then fills *res. */
 int sipg_wait(sipg_server* s, uint64_t ticket, sipg_result* res);
-/* Forget a finished request (frees a server-owned solution buffer). */
-int sipg_release(sipg_server* s, uint64_t ticket);
+/* Forget a finished request.  A server-owned solution buffer is freed after
+ * the work queued on `stream` so far (for example a copy of the solution made
+ * with sipg_copy_device on that stream) has finished: the call waits for it. */
+int sipg_release(sipg_server* s, uint64_t ticket, void* stream);
 int sipg_server_stats(sipg_server* s, sipg_server_stats_t* stats);
 /* Finishes every submitted request, then frees the server. */
 int sipg_server_destroy(sipg_server* s);

@@ -48,6 +48,7 @@ EXPORTED = [
     "sipg_release", "sipg_server_stats", "sipg_server_destroy", "sipg_copy_device",
     "sipg_batch_create", "sipg_batch_apply", "sipg_batch_get_info", "sipg_batch_destroy",
     "sipg_host_fdm_tables", "sipg_mg_level_degree", "sipg_batch_tune",
+    "sipg_host_block_order",
 ]
 
 
@@ -110,6 +111,14 @@ class SipgBatchInfo(C.Structure):
                 ("per_operator_groups", C.c_int32)]
 
 
+_ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)
+_FREE_FN = C.CFUNCTYPE(None, C.c_void_p, C.c_void_p)
+
+
+class SipgAllocator(C.Structure):
+    _fields_ = [("alloc", _ALLOC_FN), ("free", _FREE_FN), ("ctx", C.c_void_p)]
+
+
 class SipgTables1D(C.Structure):
     _fields_ = [(name, C.POINTER(C.c_double)) for name in (
         "points", "weights", "shape", "shape_grad", "colloc_grad", "face_value0",
@@ -118,7 +127,7 @@ class SipgTables1D(C.Structure):
 
 _vp = C.c_void_p
 lib.sipg_setup.argtypes = [C.POINTER(SipgMesh), C.c_int, C.c_double, C.c_int, C.c_int, C.c_int,
-                           _vp, C.POINTER(_vp)]
+                           C.POINTER(SipgAllocator), _vp, C.POINTER(_vp)]
 lib.sipg_destroy.argtypes = [_vp]
 lib.sipg_ndofs.argtypes = [_vp]
 lib.sipg_ndofs.restype = C.c_int64
@@ -128,13 +137,15 @@ lib.sipg_apply_pjacobi.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.sipg_basis_change.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
 lib.sipg_compute_gl_diagonal.argtypes = [_vp, _vp, _vp]
 lib.sipg_cg_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
+lib.sipg_host_block_order.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int32)]
+
 lib.sipg_last_error.restype = C.c_char_p
 lib.sipg_host_tables.argtypes = [C.c_int, C.c_int, C.POINTER(SipgTables1D)]
 lib.sipg_launch_shape.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
                                   C.POINTER(C.c_int64)]
 lib.sipg_mg_default_opts.argtypes = [C.POINTER(SipgMgOpts)]
-lib.sipg_mg_setup.argtypes = [C.POINTER(SipgMesh), C.c_int, C.c_double, C.c_int, C.POINTER(SipgMgOpts), _vp,
-                              C.POINTER(_vp)]
+lib.sipg_mg_setup.argtypes = [C.POINTER(SipgMesh), C.c_int, C.c_double, C.c_int, C.POINTER(SipgMgOpts),
+                              C.POINTER(SipgAllocator), _vp, C.POINTER(_vp)]
 lib.sipg_mg_destroy.argtypes = [_vp]
 lib.sipg_mg_get_info.argtypes = [_vp, C.POINTER(SipgMgInfo)]
 lib.sipg_mg_apply_vcycle.argtypes = [_vp, _vp, _vp, _vp]
@@ -144,11 +155,11 @@ lib.sipg_mg_level_ndofs.argtypes = [_vp, C.c_int, C.POINTER(C.c_int64), C.POINTE
 lib.sipg_mg_level_degree.argtypes = [_vp, C.c_int, C.POINTER(C.c_int32)]
 lib.sipg_assemble_rhs_sines.argtypes = [_vp, C.c_int, C.POINTER(C.c_double), C.POINTER(C.c_int), _vp, _vp]
 lib.sipg_server_default_opts.argtypes = [C.POINTER(SipgServerOpts)]
-lib.sipg_server_create.argtypes = [C.POINTER(SipgServerOpts), C.POINTER(_vp)]
+lib.sipg_server_create.argtypes = [C.POINTER(SipgServerOpts), C.POINTER(SipgAllocator), C.POINTER(_vp)]
 lib.sipg_submit.argtypes = [_vp, C.POINTER(SipgRequest), C.POINTER(C.c_uint64)]
 lib.sipg_poll.argtypes = [_vp, C.c_uint64, C.POINTER(SipgResult)]
 lib.sipg_wait.argtypes = [_vp, C.c_uint64, C.POINTER(SipgResult)]
-lib.sipg_release.argtypes = [_vp, C.c_uint64]
+lib.sipg_release.argtypes = [_vp, C.c_uint64, _vp]
 lib.sipg_server_stats.argtypes = [_vp, C.POINTER(SipgServerStats)]
 lib.sipg_server_destroy.argtypes = [_vp]
 lib.sipg_copy_device.argtypes = [_vp, _vp, C.c_size_t, _vp]
@@ -206,6 +217,14 @@ def launch_shape(degree: int, dtype: str = "f64"):
     return cpb.value, nt.value, lds.value
 
 
+def host_block_order(nblocks: int, layer_blocks: int) -> np.ndarray:
+    """Block visited by each workgroup of the single-operator product kernel."""
+    out = np.zeros(nblocks, dtype=np.int32)
+    _check(lib.sipg_host_block_order(int(nblocks), int(layer_blocks), out.ctypes.data_as(C.POINTER(C.c_int32))),
+           "sipg_host_block_order")
+    return out
+
+
 def make_mesh(mesh) -> SipgMesh:
     """Convert any object with n, lo, hi, lin, deform_amp attributes."""
     m = SipgMesh()
@@ -234,6 +253,38 @@ def _stream_ptr(stream) -> int:
     return int(s.cuda_stream)
 
 
+# PyTorch's caching allocator as the library's device memory provider: the
+# operator, solver and request-loop memory then comes from (and goes back to)
+# torch's pool.  The callbacks run on the calling thread (the request loop's
+# workers too); blocks are taken on the current device.  The library returns a
+# block only once its own queued work on it is finished.
+@_ALLOC_FN
+def _torch_alloc(nbytes, ctx):
+    try:
+        torch = _torch()
+        return torch.cuda.caching_allocator_alloc(int(nbytes), device=torch.cuda.current_device())
+    except Exception:
+        return None
+
+
+@_FREE_FN
+def _torch_free(ptr, ctx):
+    _torch().cuda.caching_allocator_delete(int(ptr))
+
+
+TORCH_ALLOCATOR = SipgAllocator(_torch_alloc, _torch_free, None)
+
+
+def _allocator(kind):
+    """C pointer for allocator="torch" (PyTorch's caching allocator) or None
+    (hipMalloc inside the library)."""
+    if kind is None:
+        return None
+    if kind == "torch":
+        return C.byref(TORCH_ALLOCATOR)
+    raise ValueError("allocator must be 'torch' or None")
+
+
 @dataclass
 class SolveInfo:
     iterations: int
@@ -247,10 +298,11 @@ class Operator:
     """The SIPG operator of one mesh, degree and basis on the current device."""
 
     def __init__(self, mesh, degree: int, penalty: float = 2.0, basis: str = "hermite_like",
-                 dtype: str = "f64", geometry: str = "auto", stream=None):
+                 dtype: str = "f64", geometry: str = "auto", stream=None, allocator="torch"):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Operator needs a GPU (HIP device)")
+        self._allocator = allocator
         self.degree = int(degree)
         self.basis = basis
         self.dtype_name = dtype
@@ -258,8 +310,8 @@ class Operator:
         self._mesh = make_mesh(mesh)
         h = _vp()
         _check(lib.sipg_setup(C.byref(self._mesh), self.degree, float(penalty), BASIS[basis],
-                              DTYPE[dtype], GEOMETRY[geometry], _vp(_stream_ptr(stream)), C.byref(h)),
-               "sipg_setup")
+                              DTYPE[dtype], GEOMETRY[geometry], _allocator(allocator), _vp(_stream_ptr(stream)),
+                              C.byref(h)), "sipg_setup")
         self._h = h
         self.ndofs = int(lib.sipg_ndofs(h))
         info = SipgOpInfo()
@@ -336,6 +388,10 @@ class Operator:
 
     def close(self):
         if getattr(self, "_h", None):
+            if self._allocator == "torch":
+                # hipFree would wait for the device; the caching allocator does
+                # not, so queued work on the operator's memory ends first
+                _torch().cuda.synchronize()
             lib.sipg_destroy(self._h)
             self._h = None
 
@@ -393,10 +449,11 @@ class Multigrid:
     """FP64 CG preconditioned by a V-cycle (FP32 for precision="mixed")."""
 
     def __init__(self, mesh, degree: int, penalty: float = 2.0, basis: str = "hermite_like",
-                 precision: str = "mixed", stream=None, **opts):
+                 precision: str = "mixed", stream=None, allocator="torch", **opts):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Multigrid needs a GPU (HIP device)")
+        self._allocator = allocator
         o = SipgMgOpts()
         _check(lib.sipg_mg_default_opts(C.byref(o)), "sipg_mg_default_opts")
         o.precision = {"mixed": 0, "f64": 1}[precision]
@@ -405,7 +462,7 @@ class Multigrid:
         self._mesh = make_mesh(mesh)
         h = _vp()
         _check(lib.sipg_mg_setup(C.byref(self._mesh), int(degree), float(penalty), BASIS[basis], C.byref(o),
-                                 _vp(_stream_ptr(stream)), C.byref(h)), "sipg_mg_setup")
+                                 _allocator(allocator), _vp(_stream_ptr(stream)), C.byref(h)), "sipg_mg_setup")
         self._h = h
         self.precision = precision
         info = SipgMgInfo()
@@ -458,6 +515,8 @@ class Multigrid:
 
     def close(self):
         if getattr(self, "_h", None):
+            if self._allocator == "torch":
+                _torch().cuda.synchronize()
             lib.sipg_mg_destroy(self._h)
             self._h = None
 
@@ -476,7 +535,8 @@ class Server:
     """Continuous-batching request loop of multigrid Poisson solves."""
 
     def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 8, precision: str = "mixed",
-                 smoother: str = "fdm", p_coarsening: int = 1, coarse_reduction: float = 10.0):
+                 smoother: str = "fdm", p_coarsening: int = 1, coarse_reduction: float = 10.0,
+                 allocator="torch"):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Server needs a GPU (HIP device)")
@@ -484,7 +544,7 @@ class Server:
         o = SipgServerOpts(int(hbm_budget_bytes), int(workers), {"mixed": 0, "f64": 1}[precision],
                            SMOOTHERS[smoother], int(p_coarsening), float(coarse_reduction))
         h = _vp()
-        _check(lib.sipg_server_create(C.byref(o), C.byref(h)), "sipg_server_create")
+        _check(lib.sipg_server_create(C.byref(o), _allocator(allocator), C.byref(h)), "sipg_server_create")
         self._h = h
 
     @staticmethod
@@ -533,8 +593,10 @@ class Server:
                                     _vp(_stream_ptr(stream))), "sipg_copy_device")
         return out
 
-    def release(self, ticket: int):
-        _check(lib.sipg_release(self._h, ticket), "sipg_release")
+    def release(self, ticket: int, stream=None):
+        """Forget a finished request; a server-owned solution is freed once the
+        work queued on `stream` (default: the current stream) has finished."""
+        _check(lib.sipg_release(self._h, ticket, _vp(_stream_ptr(stream))), "sipg_release")
 
     def stats(self) -> dict:
         st = SipgServerStats()

@@ -9,6 +9,7 @@
 #include <vector>
 
 #include "basis1d.hpp"
+#include "matvec.hpp"
 #include "setup.hpp"
 #include "sipg_common.hpp"
 
@@ -21,6 +22,31 @@ void set_error(const std::string& msg) { g_last_error = msg; }
 int hip_fail(hipError_t e, const char* what) {
     g_last_error = std::string(what) + ": " + hipGetErrorString(e);
     return e == hipErrorOutOfMemory ? SIPG_E_OOM : SIPG_E_HIP;
+}
+
+int DevAlloc::alloc(void** out, size_t bytes, const char* what) const {
+    *out = nullptr;
+    if (bytes == 0) bytes = 256;
+    if (a.alloc) {
+        *out = a.alloc(bytes, a.ctx);
+        if (!*out) {
+            g_last_error = std::string(what) + ": the allocator returned no memory";
+            return SIPG_E_OOM;
+        }
+        return SIPG_OK;
+    }
+    hipError_t e = hipMalloc(out, bytes);
+    if (e != hipSuccess) {
+        *out = nullptr;
+        return hip_fail(e, what);
+    }
+    return SIPG_OK;
+}
+
+void DevAlloc::release(void* p) const {
+    if (!p) return;
+    if (a.free) a.free(p, a.ctx);
+    else (void)hipFree(p);
 }
 
 // Even-odd packing of an n x n row-major matrix (layout in sipg_common.hpp).
@@ -108,8 +134,7 @@ static int free_op(sipg_op* op) {
     if (!op) return SIPG_OK;
     void* ptrs[] = {op->tables, op->cell_geom, op->face_geom[0], op->face_geom[1], op->face_geom[2], op->gl_inv_diag,
                     op->fdm_cell};
-    for (void* p : ptrs)
-        if (p) (void)hipFree(p);
+    for (void* p : ptrs) op->mem.release(p);
     delete op;
     return SIPG_OK;
 }
@@ -227,9 +252,10 @@ int sipg_host_fdm_tables(int degree, int basis, double penalty_factor, double* z
 }
 
 int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int basis, int dtype,
-               int geometry, void* stream, sipg_op** out) {
+               int geometry, const sipg_allocator* allocator, void* stream, sipg_op** out) {
     if (!mesh || !out) { set_error("sipg_setup: null mesh or out"); return SIPG_E_ARG; }
     *out = nullptr;
+    if (!allocator_valid(allocator)) { set_error("sipg_setup: allocator needs both callbacks"); return SIPG_E_ARG; }
     if (degree < 1 || degree > 8) { set_error("sipg_setup: degree must be in [1,8]"); return SIPG_E_ARG; }
     if (!(penalty_factor > 0.0) || !std::isfinite(penalty_factor)) { set_error("sipg_setup: penalty_factor must be > 0"); return SIPG_E_ARG; }
     if (basis != SIPG_BASIS_HERMITE_LIKE && basis != SIPG_BASIS_NODAL_GL && basis != SIPG_BASIS_NODAL_GAUSS) {
@@ -255,6 +281,7 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
     hipStream_t st = static_cast<hipStream_t>(stream);
     sipg_op* op = new (std::nothrow) sipg_op();
     if (!op) { set_error("sipg_setup: out of host memory"); return SIPG_E_OOM; }
+    op->mem = DevAlloc(allocator);
     op->degree = degree;
     op->n = n;
     op->basis = basis;
@@ -309,14 +336,20 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
     }
     const size_t cg_bytes = esz * size_t(ncells) * cell_geom_stride(op->geom, n);
     auto fail = [&](hipError_t err, const char* what) { free_op(op); return hip_fail(err, what); };
-    if ((e = hipMalloc(&op->tables, tab_bytes)) != hipSuccess) return fail(e, "hipMalloc(tables)");
-    if ((e = hipMalloc(&op->cell_geom, cg_bytes)) != hipSuccess) return fail(e, "hipMalloc(cell geometry)");
+    auto take = [&](void** p, size_t bytes, const char* what) {
+        const int rc = op->mem.alloc(p, bytes, what);
+        if (rc != SIPG_OK) free_op(op);
+        return rc;
+    };
+    int arc;
+    if ((arc = take(&op->tables, tab_bytes, "sipg_setup: tables")) != SIPG_OK) return arc;
+    if ((arc = take(&op->cell_geom, cg_bytes, "sipg_setup: cell geometry")) != SIPG_OK) return arc;
     const size_t fdm_bytes = esz * size_t(ncells) * 4;
-    if ((e = hipMalloc(&op->fdm_cell, fdm_bytes)) != hipSuccess) return fail(e, "hipMalloc(block preconditioner)");
+    if ((arc = take(&op->fdm_cell, fdm_bytes, "sipg_setup: block preconditioner")) != SIPG_OK) return arc;
     op->device_bytes = int64_t(tab_bytes + cg_bytes + fdm_bytes);
     for (int d = 0; d < 3; ++d) {
         const size_t fb = esz * size_t(op->nfaces[d]) * face_geom_stride(op->geom, n);
-        if ((e = hipMalloc(&op->face_geom[d], fb)) != hipSuccess) return fail(e, "hipMalloc(face geometry)");
+        if ((arc = take(&op->face_geom[d], fb, "sipg_setup: face geometry")) != SIPG_OK) return arc;
         op->device_bytes += int64_t(fb);
     }
     if (dtype == SIPG_F64) {
@@ -353,6 +386,15 @@ int sipg_launch_shape(int degree, int dtype, int32_t* cpb, int32_t* nt, int64_t*
     if (cpb) *cpb = cells_per_block(n);
     if (nt) *nt = threads_per_block(n);
     if (lds) *lds = int64_t(matvec_lds_bytes_rt(n, dtype == SIPG_F64 ? 8 : 4));
+    return SIPG_OK;
+}
+
+int sipg_host_block_order(int nblocks, int layer_blocks, int32_t* order) {
+    if (nblocks < 1 || layer_blocks < 0 || !order) {
+        set_error("sipg_host_block_order: nblocks >= 1, layer_blocks >= 0, order non-null");
+        return SIPG_E_ARG;
+    }
+    for (int b = 0; b < nblocks; ++b) order[b] = xcd_block_zinterleaved(b, nblocks, layer_blocks);
     return SIPG_OK;
 }
 
@@ -411,8 +453,8 @@ int sipg_compute_gl_diagonal(sipg_op* op, void* diag_out, void* stream) {
     hipStream_t st = static_cast<hipStream_t>(stream);
     const size_t bytes = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
     if (!op->gl_inv_diag) {
-        hipError_t e = hipMalloc(&op->gl_inv_diag, bytes);
-        if (e != hipSuccess) { op->gl_inv_diag = nullptr; return hip_fail(e, "hipMalloc(gl diagonal)"); }
+        const int rc = op->mem.alloc(&op->gl_inv_diag, bytes, "sipg_compute_gl_diagonal");
+        if (rc != SIPG_OK) return rc;
         op->device_bytes += int64_t(bytes);
     }
     const int rc = launch_gl_diagonal(op, diag_out, st);

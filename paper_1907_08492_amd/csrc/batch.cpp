@@ -34,6 +34,7 @@ struct sipg_batch {
     std::vector<const void*> x;
     std::vector<void*> y;
     void* mem = nullptr;
+    sipg::DevAlloc alloc;           // provider of mem (the first operator's)
     size_t bytes = 0;
 };
 
@@ -194,14 +195,17 @@ int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x,
     }
     int prev = 0;
     (void)hipGetDevice(&prev);
+    // the table comes from the allocator of the first operator
+    b->alloc = ops[0]->mem;
     hipError_t e = hipSetDevice(device);
-    if (e == hipSuccess) e = hipMalloc(&b->mem, host.size());
-    if (e == hipSuccess) e = hipMemcpy(b->mem, host.data(), host.size(), hipMemcpyHostToDevice);
+    int arc = SIPG_OK;
+    if (e == hipSuccess) arc = b->alloc.alloc(&b->mem, host.size(), "sipg_batch_create: device tables");
+    if (e == hipSuccess && arc == SIPG_OK) e = hipMemcpy(b->mem, host.data(), host.size(), hipMemcpyHostToDevice);
     (void)hipSetDevice(prev);
-    if (e != hipSuccess) {
-        if (b->mem) (void)hipFree(b->mem);
+    if (e != hipSuccess || arc != SIPG_OK) {
+        b->alloc.release(b->mem);
         delete b;
-        return hip_fail(e, "sipg_batch_create: device tables");
+        return arc != SIPG_OK ? arc : hip_fail(e, "sipg_batch_create: device tables");
     }
     b->bytes = host.size();
     char* base = static_cast<char*>(b->mem);
@@ -272,7 +276,7 @@ int sipg_batch_get_info(const sipg_batch* b, sipg_batch_info* info) {
 
 int sipg_batch_destroy(sipg_batch* b) {
     if (!b) return SIPG_OK;
-    if (b->mem) (void)hipFree(b->mem);
+    b->alloc.release(b->mem);
     delete b;
     return SIPG_OK;
 }

@@ -87,51 +87,38 @@ __global__ void copy_scalar_kernel(double* scal, int from, int to) {
     if (threadIdx.x == 0 && blockIdx.x == 0) scal[to] = scal[from];
 }
 
-int cg_solve_device(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
-                    sipg_solve_info* info, hipStream_t st) {
+// Work arrays of one solve: r, p, ap (ndofs each), kRedBlocks partial sums,
+// 4 scalars.
+struct CgWork {
+    double *r, *p, *ap, *partial, *scal;
+};
+
+static int cg_iterate(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
+                      sipg_solve_info* info, const CgWork& w, hipStream_t st) {
     const int64_t n = op->ndofs;
-    double *r = nullptr, *p = nullptr, *ap = nullptr, *partial = nullptr, *scal = nullptr;
-    double* hscal = nullptr;
-    auto cleanup = [&]() {
-        if (r) (void)hipFree(r);
-        if (p) (void)hipFree(p);
-        if (ap) (void)hipFree(ap);
-        if (partial) (void)hipFree(partial);
-        if (scal) (void)hipFree(scal);
-        if (hscal) (void)hipHostFree(hscal);
-    };
-    if (hipMalloc(&r, sizeof(double) * n) != hipSuccess || hipMalloc(&p, sizeof(double) * n) != hipSuccess ||
-        hipMalloc(&ap, sizeof(double) * n) != hipSuccess ||
-        hipMalloc(&partial, sizeof(double) * kRedBlocks) != hipSuccess ||
-        hipMalloc(&scal, sizeof(double) * 4) != hipSuccess ||
-        hipHostMalloc(&hscal, sizeof(double) * 4, hipHostMallocDefault) != hipSuccess) {
-        cleanup();
-        set_error("sipg_cg_solve: workspace allocation failed");
-        return SIPG_E_OOM;
-    }
+    double *r = w.r, *p = w.p, *ap = w.ap, *partial = w.partial, *scal = w.scal;
     const int nb = int(std::min<int64_t>(kRedBlocks, (n + kRedThreads - 1) / kRedThreads));
     int status = SIPG_OK;
     auto read = [&](int slot, double& v) -> int {
-        if (hipMemcpyAsync(hscal, scal + slot, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
+        if (hipMemcpyAsync(&v, scal + slot, sizeof(double), hipMemcpyDeviceToHost, st) != hipSuccess ||
             hipStreamSynchronize(st) != hipSuccess) {
             set_error("sipg_cg_solve: device to host copy failed");
             return SIPG_E_HIP;
         }
-        v = hscal[0];
         return SIPG_OK;
     };
     // ||b||
     dot_kernel<<<nb, kRedThreads, 0, st>>>(b, b, partial, n);
     finish_kernel<<<1, kRedThreads, 0, st>>>(partial, nb, scal, 3);
     double bb = 0.0;
-    if ((status = read(3, bb)) != SIPG_OK) { cleanup(); return status; }
+    if ((status = read(3, bb)) != SIPG_OK) return status;
     const double bnorm = std::sqrt(bb);
     // r = b - A x, p = r
-    if ((status = launch_matvec(op, x, ap, st)) != SIPG_OK) { cleanup(); return status; }
+    if ((status = launch_matvec(op, x, ap, st)) != SIPG_OK) return status;
     residual_kernel<<<nb, kRedThreads, 0, st>>>(b, ap, r, p, partial, n);
     finish_kernel<<<1, kRedThreads, 0, st>>>(partial, nb, scal, 0);
     double rr = 0.0;
-    if ((status = read(0, rr)) != SIPG_OK) { cleanup(); return status; }
+    if ((status = read(0, rr)) != SIPG_OK) return status;
     info->initial_residual = std::sqrt(rr);
     const double target = rel_tol * (bnorm > 0.0 ? bnorm : 1.0);
     int it = 0;
@@ -164,7 +151,28 @@ int cg_solve_device(const sipg_op* op, const double* b, double* x, double rel_to
             status = SIPG_E_NOCONV;
         }
     }
-    cleanup();
+    return status;
+}
+
+int cg_solve_device(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
+                    sipg_solve_info* info, hipStream_t st) {
+    const size_t n = size_t(op->ndofs);
+    CgWork w{};
+    void* blk[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
+    const size_t bytes[5] = {8 * n, 8 * n, 8 * n, 8 * size_t(kRedBlocks), 8 * 4};
+    int status = SIPG_OK;
+    for (int i = 0; i < 5 && status == SIPG_OK; ++i) status = op->mem.alloc(&blk[i], bytes[i], "sipg_cg_solve: workspace");
+    if (status == SIPG_OK) {
+        w = CgWork{static_cast<double*>(blk[0]), static_cast<double*>(blk[1]), static_cast<double*>(blk[2]),
+                   static_cast<double*>(blk[3]), static_cast<double*>(blk[4])};
+        status = cg_iterate(op, b, x, rel_tol, max_iter, info, w, st);
+        // every launch of the solve is finished before the blocks go back
+        if (hipStreamSynchronize(st) != hipSuccess && status == SIPG_OK) {
+            set_error("sipg_cg_solve: stream synchronisation failed");
+            status = SIPG_E_HIP;
+        }
+    }
+    for (void* q : blk) op->mem.release(q);
     return status;
 }
 

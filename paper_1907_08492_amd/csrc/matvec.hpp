@@ -204,13 +204,13 @@ constexpr int matvec_min_waves() { return (N >= 7 && GEOM != GEOM_QPOINT) ? 2 : 
 // Workgroup blk is the sl-th of its XCD, whose range starts at `start` and
 // holds `len` blocks.
 struct XcdSlot { int start, len, sl; };
-__device__ __forceinline__ XcdSlot xcd_slot(int blk, int nblk) {
+__host__ __device__ __forceinline__ XcdSlot xcd_slot(int blk, int nblk) {
     const int per = (nblk + 7) / 8;
     const int xcd = blk % 8, sl = blk / 8;
     const int full = nblk % 8 == 0 ? 8 : nblk % 8;   // XCDs that get `per` blocks
     return {xcd < full ? xcd * per : full * per + (xcd - full) * (per - 1), xcd < full ? per : per - 1, sl};
 }
-__device__ __forceinline__ int xcd_block(int blk, int nblk) {
+__host__ __device__ __forceinline__ int xcd_block(int blk, int nblk) {
     const XcdSlot x = xcd_slot(blk, nblk);
     return x.start + x.sl;
 }
@@ -227,13 +227,13 @@ __device__ __forceinline__ int xcd_block(int blk, int nblk) {
 // apart, and the two XCDs that share the plane between their ranges reach it
 // at the same time.  y-neighbours, about TZ rows of blocks apart, are then
 // read again from the memory-side cache rather than from HBM.
-__device__ __forceinline__ int xcd_block_zinterleaved(int blk, int nblk, int P) {
+__host__ __device__ __forceinline__ int xcd_block_zinterleaved(int blk, int nblk, int P) {
     const XcdSlot x = xcd_slot(blk, nblk);
     if (P <= 0) return x.start + x.sl;
-    const int TZ = min(8, (x.len + P - 1) / P);
+    const int TZ = (x.len + P - 1) / P < 8 ? (x.len + P - 1) / P : 8;
     const int G = TZ * P;
     const int g = x.sl / G, s = x.sl - g * G;
-    const int m = min(G, x.len - g * G);          // blocks of this group
+    const int m = G < x.len - g * G ? G : x.len - g * G;   // blocks of this group
     const int tz = (m + P - 1) / P;               // its layers
     const int r = m - (tz - 1) * P;               // blocks of its last layer
     int row, col;

@@ -2,6 +2,8 @@
 // per-degree translation units matvec_n<N>.hip).
 #pragma once
 
+#include <mutex>
+
 #include "matvec.hpp"
 #include "setup.hpp"
 
@@ -9,14 +11,14 @@ namespace sipg {
 
 template <int N, int BASIS, typename T, int GEOM, int KIND, typename K>
 static int set_lds_limit(K kernel) {
-    // Raising the dynamic LDS limit is idempotent; racing first calls from
-    // several threads are harmless.
-    static bool done = false;
-    if (!done) {
-        SIPG_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kernel),
-                                     hipFuncAttributeMaxDynamicSharedMemorySize, int(matvec_lds_bytes<N, T>())));
-        done = true;
-    }
+    // once per kernel (the request loop's workers launch concurrently)
+    static std::once_flag once;
+    static hipError_t err = hipSuccess;
+    std::call_once(once, [&] {
+        err = hipFuncSetAttribute(reinterpret_cast<const void*>(kernel), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  int(matvec_lds_bytes<N, T>()));
+    });
+    if (err != hipSuccess) return hip_fail(err, "hipFuncSetAttribute(dynamic LDS)");
     return SIPG_OK;
 }
 

@@ -64,14 +64,19 @@ static void tridiag_extremes(const std::vector<double>& d, const std::vector<dou
     lmax = kth(n - 1);
 }
 
+// A device array of the solver, from the solver's allocator (which outlives
+// every buffer of the solver).
 template <typename T>
 struct DevBuf {
     T* p = nullptr;
-    ~DevBuf() { if (p) (void)hipFree(p); }
-    int alloc(int64_t n) {
-        hipError_t e = hipMalloc(&p, sizeof(T) * size_t(std::max<int64_t>(n, 1)));
-        if (e != hipSuccess) { p = nullptr; return hip_fail(e, "hipMalloc(multigrid)"); }
-        return SIPG_OK;
+    const DevAlloc* a = nullptr;
+    ~DevBuf() { if (p) a->release(p); }
+    int alloc(int64_t n, const DevAlloc& from) {
+        a = &from;
+        void* q = nullptr;
+        const int rc = from.alloc(&q, sizeof(T) * size_t(std::max<int64_t>(n, 1)), "multigrid");
+        p = static_cast<T*>(q);
+        return rc;
     }
 };
 
@@ -128,11 +133,11 @@ struct Scratch {
     DevBuf<double> partial, scal, coef;
     double* host = nullptr;
     ~Scratch() { if (host) (void)hipHostFree(host); }
-    int init() {
+    int init(const DevAlloc& mem) {
         int rc;
-        if ((rc = partial.alloc(kVecPartials)) != SIPG_OK) return rc;
-        if ((rc = scal.alloc(8)) != SIPG_OK) return rc;
-        if ((rc = coef.alloc(2 * kMaxLanczos)) != SIPG_OK) return rc;
+        if ((rc = partial.alloc(kVecPartials, mem)) != SIPG_OK) return rc;
+        if ((rc = scal.alloc(8, mem)) != SIPG_OK) return rc;
+        if ((rc = coef.alloc(2 * kMaxLanczos, mem)) != SIPG_OK) return rc;
         SIPG_HIP(hipHostMalloc(&host, sizeof(double) * 8, hipHostMallocDefault));
         return SIPG_OK;
     }
@@ -308,6 +313,9 @@ double mg_last_rhs_norm(const sipg_mg* mg);
 }  // namespace sipg
 
 struct sipg_mg {
+    DevAlloc mem;                        // provider of all device memory below (declared first:
+                                         // destroyed after the buffers it provided)
+    sipg_allocator user_alloc{nullptr, nullptr, nullptr};
     int precision = 0;                   // 0: FP32 V-cycle, 1: FP64 V-cycle
     sipg_op* fine64 = nullptr;           // FP64 operator of the outer iteration
     Hierarchy<float> h32;
@@ -390,11 +398,12 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
             L->steps = coarsest ? int(std::min<int64_t>(nl / 4 + 2, 120)) : o.lanczos_steps;
             L->key = level_key(m, sp.degree, penalty, basis, dt, H.pmode, L->steps);
         }
-        if ((rc = sipg_setup(&m, sp.degree, penalty, basis, dt, SIPG_GEOM_AUTO, st, &L->op)) != SIPG_OK) return rc;
+        if ((rc = sipg_setup(&m, sp.degree, penalty, basis, dt, SIPG_GEOM_AUTO, &mg->user_alloc, st, &L->op)) != SIPG_OK)
+            return rc;
         if (H.pmode == SIPG_BC_PJACOBI && (rc = sipg_compute_gl_diagonal(L->op, nullptr, st)) != SIPG_OK) return rc;
         L->n = L->op->ndofs;
-        if ((rc = L->b.alloc(L->n)) || (rc = L->u.alloc(L->n)) || (rc = L->uo.alloc(L->n)) ||
-            (rc = L->r.alloc(L->n)) || (rc = L->z.alloc(L->n)))
+        if ((rc = L->b.alloc(L->n, mg->mem)) || (rc = L->u.alloc(L->n, mg->mem)) || (rc = L->uo.alloc(L->n, mg->mem)) ||
+            (rc = L->r.alloc(L->n, mg->mem)) || (rc = L->z.alloc(L->n, mg->mem)))
             return rc;
         // transfer matrices to the next level
         if (l + 1 < seq.size()) {
@@ -419,7 +428,7 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
                         e[nf * ncd + j * nf + i] = T(E[i * ncd + j]);     // E^T (nc x nf)
                     }
             }
-            if ((rc = L->emb.alloc(int64_t(e.size()))) != SIPG_OK) return rc;
+            if ((rc = L->emb.alloc(int64_t(e.size()), mg->mem)) != SIPG_OK) return rc;
             SIPG_HIP(hipMemcpyAsync(L->emb.p, e.data(), sizeof(T) * e.size(), hipMemcpyHostToDevice, st));
             SIPG_HIP(hipStreamSynchronize(st));
         }
@@ -485,9 +494,10 @@ int sipg_mg_default_opts(sipg_mg_opts* o) {
 }
 
 int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, const sipg_mg_opts* opts,
-                  void* stream, sipg_mg** out) {
+                  const sipg_allocator* allocator, void* stream, sipg_mg** out) {
     if (!mesh || !out) { set_error("sipg_mg_setup: null argument"); return SIPG_E_ARG; }
     *out = nullptr;
+    if (!allocator_valid(allocator)) { set_error("sipg_mg_setup: allocator needs both callbacks"); return SIPG_E_ARG; }
     sipg_mg_opts o;
     sipg_mg_default_opts(&o);
     if (opts) o = *opts;
@@ -501,13 +511,16 @@ int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, 
     hipStream_t st = static_cast<hipStream_t>(stream);
     std::unique_ptr<sipg_mg> mg(new (std::nothrow) sipg_mg());
     if (!mg) { set_error("sipg_mg_setup: out of host memory"); return SIPG_E_OOM; }
+    mg->mem = DevAlloc(allocator);
+    if (allocator) mg->user_alloc = *allocator;
     mg->precision = o.precision;
-    int rc = sipg_setup(mesh, degree, penalty, basis, SIPG_F64, SIPG_GEOM_AUTO, stream, &mg->fine64);
+    int rc = sipg_setup(mesh, degree, penalty, basis, SIPG_F64, SIPG_GEOM_AUTO, &mg->user_alloc, stream, &mg->fine64);
     if (rc != SIPG_OK) return rc;
     mg->ndofs = mg->fine64->ndofs;
-    if ((rc = mg->sc.init()) != SIPG_OK) return rc;
-    if ((rc = mg->wb.alloc(mg->ndofs)) || (rc = mg->wr.alloc(mg->ndofs)) || (rc = mg->wz.alloc(mg->ndofs)) ||
-        (rc = mg->wp.alloc(mg->ndofs)) || (rc = mg->wap.alloc(mg->ndofs)))
+    if ((rc = mg->sc.init(mg->mem)) != SIPG_OK) return rc;
+    if ((rc = mg->wb.alloc(mg->ndofs, mg->mem)) || (rc = mg->wr.alloc(mg->ndofs, mg->mem)) ||
+        (rc = mg->wz.alloc(mg->ndofs, mg->mem)) || (rc = mg->wp.alloc(mg->ndofs, mg->mem)) ||
+        (rc = mg->wap.alloc(mg->ndofs, mg->mem)))
         return rc;
     rc = o.precision == 0 ? build_hierarchy<float>(mg.get(), mg->h32, mesh, degree, penalty, basis, o, st)
                           : build_hierarchy<double>(mg.get(), mg->h64, mesh, degree, penalty, basis, o, st);

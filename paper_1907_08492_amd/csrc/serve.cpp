@@ -64,6 +64,8 @@ struct Job {
 
 struct sipg_server {
     sipg_server_opts opts{};
+    sipg_allocator user_alloc{nullptr, nullptr, nullptr};
+    sipg::DevAlloc mem;              // provider of hierarchies and result buffers
     std::mutex mu;
     std::condition_variable cv_work, cv_done;
     std::deque<Job*> queue;
@@ -77,6 +79,7 @@ struct sipg_server {
     std::vector<sipg_mg*> evicted;   // hierarchies to free outside the lock
     int64_t peak_bytes = 0;
     int64_t completed = 0;
+    int running = 0;                 // admitted jobs not yet finished
 };
 
 namespace sipg {
@@ -123,9 +126,17 @@ static void finish_job(sipg_server* s, Job* j, int status) {
     s->completed++;
 }
 
+// A queued request that has waited this long is not overtaken by later,
+// smaller ones any more: nothing else is admitted until it fits.
+constexpr double kMaxOvertakeSeconds = 2.0;
+
 // Pick the oldest queued job that fits the budget (evicting idle cached
-// hierarchies if needed); called with the lock held.
+// hierarchies if needed); called with the lock held.  A request that does not
+// fit while no solve runs and nothing can be evicted (only results the client
+// has not released hold the budget) is finished with SIPG_E_BUDGET instead
+// of waiting for ever.
 static Job* admit(sipg_server* s) {
+    const Clock::time_point now = Clock::now();
     for (auto it = s->queue.begin(); it != s->queue.end(); ++it) {
         Job* j = *it;
         // an idle cached hierarchy of this problem?
@@ -150,8 +161,25 @@ static Job* admit(sipg_server* s) {
             s->used_bytes -= victim->second.bytes;
             s->cache.erase(victim);
         }
-        if (s->used_bytes + need > s->opts.hbm_budget_bytes) continue;   // try a smaller request
+        if (s->used_bytes + need > s->opts.hbm_budget_bytes) {
+            if (s->running == 0) {
+                bool evictable = false;
+                for (auto& c : s->cache) evictable = evictable || !c.second.busy;
+                if (!evictable) {
+                    set_error("request loop: unreleased results hold the memory budget");
+                    j->t_start = now;
+                    s->queue.erase(it);
+                    finish_job(s, j, SIPG_E_BUDGET);
+                    s->cv_done.notify_all();
+                    return admit(s);
+                }
+            }
+            // later, smaller requests may overtake it for a while
+            if (std::chrono::duration<double>(now - j->t_submit).count() > kMaxOvertakeSeconds) return nullptr;
+            continue;
+        }
         j->est_bytes = need;
+        s->running++;
         s->used_bytes += need;
         s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
         s->queue.erase(it);
@@ -185,7 +213,8 @@ static void worker_main(sipg_server* s) {
         int64_t built_bytes = 0;
         if (!mg) {
             const sipg_mg_opts o = solver_opts(s->opts);
-            status = sipg_mg_setup(&j->req.mesh, j->req.degree, j->req.penalty_factor, j->req.basis, &o, st, &mg);
+            status = sipg_mg_setup(&j->req.mesh, j->req.degree, j->req.penalty_factor, j->req.basis, &o,
+                                   &s->user_alloc, st, &mg);
             if (status == SIPG_OK) {
                 sipg_mg_info info;
                 sipg_mg_get_info(mg, &info);
@@ -195,9 +224,16 @@ static void worker_main(sipg_server* s) {
         double* b = status == SIPG_OK ? mg_rhs_buffer(mg) : nullptr;
         double* x = j->req.x_out;
         if (status == SIPG_OK && !x) {
-            // stream-ordered: no device-wide synchronisation between workers
-            if (hipMallocAsync(reinterpret_cast<void**>(&j->x_owned), sizeof(double) * size_t(j->ndofs), st) != hipSuccess)
+            const size_t xb = sizeof(double) * size_t(j->ndofs);
+            if (s->mem.a.alloc) {
+                void* q = nullptr;
+                status = s->mem.alloc(&q, xb, "request loop: solution buffer");
+                j->x_owned = static_cast<double*>(q);
+            } else if (hipMallocAsync(reinterpret_cast<void**>(&j->x_owned), xb, st) != hipSuccess) {
+                // stream-ordered: no device-wide synchronisation between workers
+                j->x_owned = nullptr;
                 status = SIPG_E_OOM;
+            }
             x = j->x_owned;
         }
         sipg_solve_info info{};
@@ -217,19 +253,24 @@ static void worker_main(sipg_server* s) {
         j->res.x = x;
 
         lk.lock();
-        // return or insert the hierarchy into the cache, settle the budget
+        // return or insert the hierarchy into the cache, settle the budget;
+        // a server-owned result buffer stays charged until it is released
         s->used_bytes -= j->est_bytes;
+        s->running--;
+        const int64_t kept = j->x_owned ? 8 * j->ndofs : 0;
         if (ce) {
             ce->busy = false;
             ce->last_used = Clock::now();
-            s->used_bytes += (j->req.x_out ? 0 : 8 * j->ndofs);   // result buffer stays until released
+            s->used_bytes += kept;
         } else if (mg) {
             CacheEntry e;
             e.mg = mg;
             e.bytes = built_bytes;
             e.last_used = Clock::now();
             s->cache.emplace(j->key, e);
-            s->used_bytes += built_bytes + (j->req.x_out ? 0 : 8 * j->ndofs);
+            s->used_bytes += built_bytes + kept;
+        } else {
+            s->used_bytes += kept;
         }
         s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
         finish_job(s, j, status);
@@ -257,9 +298,10 @@ int sipg_server_default_opts(sipg_server_opts* o) {
     return SIPG_OK;
 }
 
-int sipg_server_create(const sipg_server_opts* opts, sipg_server** out) {
+int sipg_server_create(const sipg_server_opts* opts, const sipg_allocator* allocator, sipg_server** out) {
     if (!out) { set_error("sipg_server_create: null out"); return SIPG_E_ARG; }
     *out = nullptr;
+    if (!allocator_valid(allocator)) { set_error("sipg_server_create: allocator needs both callbacks"); return SIPG_E_ARG; }
     sipg_server_opts o;
     sipg_server_default_opts(&o);
     if (opts) o = *opts;
@@ -273,6 +315,8 @@ int sipg_server_create(const sipg_server_opts* opts, sipg_server** out) {
     sipg_server* s = new (std::nothrow) sipg_server();
     if (!s) { set_error("sipg_server_create: out of host memory"); return SIPG_E_OOM; }
     s->opts = o;
+    if (allocator) s->user_alloc = *allocator;
+    s->mem = DevAlloc(allocator);
     int dev = 0;
     if (hipGetDevice(&dev) != hipSuccess) { delete s; set_error("sipg_server_create: no device"); return SIPG_E_HIP; }
     if (hipStreamCreateWithFlags(&s->house, hipStreamNonBlocking) != hipSuccess) {
@@ -340,17 +384,39 @@ int sipg_wait(sipg_server* s, uint64_t ticket, sipg_result* res) {
     return SIPG_OK;
 }
 
-int sipg_release(sipg_server* s, uint64_t ticket) {
+// Frees a result buffer whose writer (the worker stream) has finished.
+static void free_result(sipg_server* s, double* x) {
+    if (s->mem.a.free) s->mem.release(x);
+    else (void)hipFreeAsync(x, s->house);
+}
+
+int sipg_release(sipg_server* s, uint64_t ticket, void* stream) {
     if (!s) { set_error("sipg_release: null server"); return SIPG_E_ARG; }
-    std::lock_guard<std::mutex> lk(s->mu);
-    auto it = s->jobs.find(ticket);
-    if (it == s->jobs.end()) { set_error("sipg_release: unknown ticket"); return SIPG_E_ARG; }
-    if (!it->second->done) { set_error("sipg_release: request still running"); return SIPG_E_NOTREADY; }
-    if (it->second->x_owned) {
-        (void)hipFreeAsync(it->second->x_owned, s->house);
-        s->used_bytes -= 8 * it->second->ndofs;
+    double* x = nullptr;
+    int64_t bytes = 0;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        auto it = s->jobs.find(ticket);
+        if (it == s->jobs.end()) { set_error("sipg_release: unknown ticket"); return SIPG_E_ARG; }
+        if (!it->second->done) { set_error("sipg_release: request still running"); return SIPG_E_NOTREADY; }
+        x = it->second->x_owned;
+        bytes = x ? 8 * it->second->ndofs : 0;
+        s->jobs.erase(it);
     }
-    s->jobs.erase(it);
+    if (x) {
+        // the caller's queued reads of the solution (on `stream`) end first
+        hipEvent_t ev = nullptr;
+        if (hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess ||
+            hipEventRecord(ev, static_cast<hipStream_t>(stream)) != hipSuccess || hipEventSynchronize(ev) != hipSuccess) {
+            if (ev) (void)hipEventDestroy(ev);
+            set_error("sipg_release: could not wait for the caller's stream (buffer kept)");
+            return SIPG_E_HIP;
+        }
+        (void)hipEventDestroy(ev);
+        free_result(s, x);
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->used_bytes -= bytes;
+    }
     s->cv_work.notify_all();
     return SIPG_OK;
 }
@@ -381,7 +447,7 @@ int sipg_server_destroy(sipg_server* s) {
     s->cv_work.notify_all();
     for (auto& t : s->workers) t.join();
     for (auto& kv : s->jobs)
-        if (kv.second->x_owned) (void)hipFreeAsync(kv.second->x_owned, s->house);
+        if (kv.second->x_owned) free_result(s, kv.second->x_owned);
     (void)hipStreamSynchronize(s->house);
     (void)hipStreamDestroy(s->house);
     for (auto& kv : s->cache) sipg_mg_destroy(kv.second.mg);

@@ -62,7 +62,7 @@ int launch_rhs_sines(const sipg_op* op, int nmodes, const double* amps, const in
 // diag(A) in the nodal Gauss-Lobatto basis, written to `diag` (operator precision).
 int launch_gl_diagonal(const sipg_op* op, void* diag, hipStream_t st);
 
-// FP64 vector kernels of the conjugate gradient method.
+// FP64 conjugate gradient method, work arrays from the operator's allocator.
 int cg_solve_device(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
                     sipg_solve_info* info, hipStream_t st);
 

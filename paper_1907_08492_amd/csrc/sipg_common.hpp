@@ -119,6 +119,23 @@ __host__ __device__ constexpr int inv_diag_offset(int n, int chunk, int i) {
     return k < J * chunk ? (k / chunk) * chunk * n2 + chunk * t + k % chunk : J * chunk * n2 + R * t + (k - J * chunk);
 }
 
+// Device memory of the library's objects: through the caller's allocator
+// (sipg_allocator) when one was given, else hipMalloc / hipFree.
+struct DevAlloc {
+    sipg_allocator a{nullptr, nullptr, nullptr};
+    DevAlloc() = default;
+    explicit DevAlloc(const sipg_allocator* p) {
+        if (p) a = *p;
+    }
+    // *out = `bytes` bytes of device memory; SIPG_OK or SIPG_E_OOM / SIPG_E_HIP
+    // with the error text naming `what`
+    int alloc(void** out, size_t bytes, const char* what) const;
+    void release(void* p) const;
+};
+// An allocator argument is valid when it is NULL or sets both callbacks or
+// neither (neither: hipMalloc / hipFree).
+inline bool allocator_valid(const sipg_allocator* a) { return !a || (a->alloc != nullptr) == (a->free != nullptr); }
+
 // Mesh description in the form the device kernels take it.
 struct MeshDev {
     int n[3];
@@ -138,6 +155,7 @@ struct sipg_op {
     double eta = 0.0;
     sipg::MeshDev mesh{};
     int device = 0;
+    sipg::DevAlloc mem;              // provider of the memory below
     // device memory owned by the operator
     void* tables = nullptr;          // packed 1D tables, operator precision
     void* cell_geom = nullptr;       // [ncells][cell_geom_stride]

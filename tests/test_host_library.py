@@ -77,40 +77,28 @@ def test_xcd_remap_is_a_permutation(nblk):
     assert sorted(m) == list(range(nblk))
 
 
-def _xcd_remap_zinterleaved(blk, nblk, layer_blocks, tz=3):
-    """Model of the single-operator kernel's order: inside each XCD's range,
-    groups of tz * layer_blocks blocks are visited as a transposed
-    tz x layer_blocks array; a last, shorter group keeps the plain order."""
-    per = (nblk + 7) // 8
-    xcd, slot = blk % 8, blk // 8
-    full = 8 if nblk % 8 == 0 else nblk % 8
-    start = xcd * per if xcd < full else full * per + (xcd - full) * (per - 1)
-    length = per if xcd < full else per - 1
-    g_size = tz * layer_blocks
-    b = slot
-    if layer_blocks > 0 and g_size <= length:
-        g, s = divmod(slot, g_size)
-        if (g + 1) * g_size <= length:
-            b = g * g_size + (s % tz) * layer_blocks + s // tz
-    return start + b
-
-
 @pytest.mark.parametrize("nblk,layer_blocks", [(1, 0), (9, 1), (100, 2), (100, 5), (128, 3), (1000, 7),
-                                               (43691, 683), (7296, 96), (43691, 5000)])
-def test_xcd_zinterleaved_remap_is_a_permutation(nblk, layer_blocks):
-    m = [_xcd_remap_zinterleaved(b, nblk, layer_blocks) for b in range(nblk)]
-    assert sorted(m) == list(range(nblk))
+                                               (43691, 683), (7296, 96), (43691, 5000), (10923, 341),
+                                               (22118, 461), (5, 1), (65, 3)])
+def test_block_order_is_a_permutation(nblk, layer_blocks):
+    """The kernel's own block order (sipg_host_block_order, the device
+    function compiled for the host) visits every block exactly once."""
+    m = P.host_block_order(nblk, layer_blocks)
+    assert sorted(m.tolist()) == list(range(nblk))
 
 
-def test_xcd_zinterleaved_remap_visits_z_neighbours_together():
-    # 64^3 cells, 6 per block: in each full group, slots 3j, 3j+1, 3j+2 are
-    # block j of three consecutive z-layers (P = 683 blocks apart)
-    nblk, P = 43691, 683
-    m = [_xcd_remap_zinterleaved(b, nblk, P) for b in range(nblk)]
+def test_block_order_visits_z_neighbours_together():
+    # 64^3 cells, 6 per block: each XCD's range holds 8 z-layers (P = 683
+    # blocks each), visited column by column, so slots 8j .. 8j+7 of an XCD
+    # are block j of 8 consecutive layers (the last column is one short), and
+    # the blocks of one XCD form one contiguous range
+    nblk, P_ = 43691, 683
+    m = P.host_block_order(nblk, P_)
     for xcd in range(8):
         seq = m[xcd::8]
-        for j in range(0, 3 * P, 3):
-            assert seq[j + 1] - seq[j] == P and seq[j + 2] - seq[j + 1] == P
+        assert seq.max() - seq.min() + 1 == len(seq)
+        for j in range(0, 8 * 680, 8):
+            assert all(seq[j + i + 1] - seq[j + i] == P_ for i in range(7))
 
 
 def test_argument_errors_without_gpu():
@@ -118,13 +106,13 @@ def test_argument_errors_without_gpu():
     h = C.c_void_p()
     for deg, pen, basis, dt, geo in ((0, 1.0, 0, 0, 0), (9, 1.0, 0, 0, 0), (2, 0.0, 0, 0, 0),
                                      (2, 1.0, 5, 0, 0), (2, 1.0, 0, 7, 0), (2, 1.0, 0, 0, 9)):
-        rc = P.lib.sipg_setup(C.byref(m), deg, pen, basis, dt, geo, None, C.byref(h))
+        rc = P.lib.sipg_setup(C.byref(m), deg, pen, basis, dt, geo, None, None, C.byref(h))
         assert rc == -1, (deg, pen, basis, dt, geo)
         assert P.lib.sipg_last_error().decode()
     bad = P.make_mesh(type("M", (), dict(n=(2, 0, 2), lo=(0, 0, 0), hi=(1, 1, 1)))())
-    assert P.lib.sipg_setup(C.byref(bad), 2, 1.0, 0, 0, 0, None, C.byref(h)) == -1
+    assert P.lib.sipg_setup(C.byref(bad), 2, 1.0, 0, 0, 0, None, None, C.byref(h)) == -1
     deformed = P.make_mesh(type("M", (), dict(n=(2, 2, 2), lo=(0, 0, 0), hi=(1, 1, 1), deform_amp=0.1))())
-    assert P.lib.sipg_setup(C.byref(deformed), 2, 1.0, 0, 0, 1, None, C.byref(h)) == -1
+    assert P.lib.sipg_setup(C.byref(deformed), 2, 1.0, 0, 0, 1, None, None, C.byref(h)) == -1
     assert P.lib.sipg_apply(None, None, None, None) == -1
     assert P.lib.sipg_basis_change(None, 0, None, None, None) == -1
     assert P.lib.sipg_ndofs(None) == -1
@@ -132,7 +120,7 @@ def test_argument_errors_without_gpu():
     assert P.lib.sipg_launch_shape(0, 0, None, None, None) == -1
     # more than 2^31 - 1 unknowns is rejected before any device work
     big = P.make_mesh(type("M", (), dict(n=(1300, 1300, 1300), lo=(0, 0, 0), hi=(1, 1, 1)))())
-    assert P.lib.sipg_setup(C.byref(big), 1, 1.0, 0, 0, 0, None, C.byref(h)) == -1
+    assert P.lib.sipg_setup(C.byref(big), 1, 1.0, 0, 0, 0, None, None, C.byref(h)) == -1
     assert "too large" in P.lib.sipg_last_error().decode()
     assert P.lib.sipg_batch_create(0, None, None, None, C.byref(h)) == -1
     assert P.lib.sipg_batch_create(1, None, None, None, None) == -1
