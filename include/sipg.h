@@ -266,6 +266,33 @@ typedef struct {
 int sipg_cg_solve(const sipg_op* op, const double* b, double* x, double rel_tol,
                   int max_iter, sipg_solve_info* info, void* stream);
 
+/*
+ * sipg_cg_solve for callers that cannot allocate device memory: code under
+ * HIP stream capture (the solve itself still reads one scalar per iteration,
+ * so the capture has to end before it is called), tight serving loops,
+ * harnesses that forbid hipMalloc.  Same arguments, same kernels and the same
+ * results, bit for bit, as sipg_cg_solve; the work arrays are a fixed array
+ * of the library in device memory, one per GPU (held from the first call on
+ * that GPU until the process ends), which holds operators of up to
+ * sipg_cg_static_max_dofs() = 2^20 unknowns (24 MiB of work vectors):
+ * SIPG_E_ARG beyond that.  Calls no hipMalloc, hipFree or allocating routine.
+ * Every call on one GPU uses that GPU's array, so calls that overlap in time
+ * on one GPU (from several threads or streams) race and must not be made.
+ */
+int sipg_cg_solve_static(const sipg_op* op, const double* b, double* x, double rel_tol,
+                         int max_iter, sipg_solve_info* info, void* stream);
+int64_t sipg_cg_static_max_dofs(void);
+
+/* Host-only: the order in which the single-operator product kernel visits
+ * its blocks of cells_per_block consecutive cells: workgroup b (in dispatch
+ * order) handles block order[b].  layer_blocks = round(nx ny / cells_per_block)
+ * is the number of blocks of one z-layer of cells.  Each of the 8 XCDs of the
+ * GPU (workgroups are dispatched to them round robin) gets a contiguous range
+ * of blocks and visits it z-layers interleaved, so that the two cells of a
+ * z-face are processed close together in time (data reuse in the XCD's L2,
+ * Section 4.2's data-access argument on this GPU).  order: nblocks entries,
+ * caller-owned host memory. */
+int sipg_host_block_order(int nblocks, int layer_blocks, int32_t* order);
 
 /* Host-only: launch shape of the matrix-free kernel for a degree and precision:
  * cells per workgroup, threads per workgroup and dynamic LDS bytes. */

@@ -48,7 +48,7 @@ EXPORTED = [
     "sipg_release", "sipg_server_stats", "sipg_server_destroy", "sipg_copy_device",
     "sipg_batch_create", "sipg_batch_apply", "sipg_batch_get_info", "sipg_batch_destroy",
     "sipg_host_fdm_tables", "sipg_mg_level_degree", "sipg_batch_tune",
-    "sipg_host_block_order",
+    "sipg_cg_solve_static", "sipg_cg_static_max_dofs", "sipg_host_block_order",
 ]
 
 
@@ -137,8 +137,10 @@ lib.sipg_apply_pjacobi.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.sipg_basis_change.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
 lib.sipg_compute_gl_diagonal.argtypes = [_vp, _vp, _vp]
 lib.sipg_cg_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
+lib.sipg_cg_solve_static.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
 lib.sipg_host_block_order.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int32)]
-
+lib.sipg_cg_static_max_dofs.argtypes = []
+lib.sipg_cg_static_max_dofs.restype = C.c_int64
 lib.sipg_last_error.restype = C.c_char_p
 lib.sipg_host_tables.argtypes = [C.c_int, C.c_int, C.POINTER(SipgTables1D)]
 lib.sipg_launch_shape.argtypes = [C.c_int, C.c_int, C.POINTER(C.c_int32), C.POINTER(C.c_int32),
@@ -170,7 +172,7 @@ lib.sipg_batch_destroy.argtypes = [_vp]
 lib.sipg_batch_tune.argtypes = [_vp, C.c_int, _vp]
 lib.sipg_host_fdm_tables.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
 for _f in EXPORTED:
-    if _f not in ("sipg_ndofs", "sipg_last_error"):
+    if _f not in ("sipg_ndofs", "sipg_last_error", "sipg_cg_static_max_dofs"):
         getattr(lib, _f).restype = C.c_int
 
 
@@ -373,6 +375,20 @@ class Operator:
                                C.byref(info), _vp(_stream_ptr(stream)))
         if rc != SIPG_OK and (rc != SIPG_E_NOCONV or raise_on_noconv):
             raise SipgError(rc, "sipg_cg_solve")
+        return x, SolveInfo(info.iterations, info.initial_residual, info.final_residual,
+                            info.true_residual, rc)
+
+    def cg_solve_static(self, b, x, rel_tol: float = 1e-10, max_iter: int = 10000, stream=None,
+                        raise_on_noconv: bool = True):
+        """cg_solve with the library's fixed work arrays (sipg_cg_solve_static):
+        no device allocation at all, x provided by the caller."""
+        if self.dtype_name != "f64":
+            raise ValueError("cg_solve_static needs an f64 operator")
+        info = SipgSolveInfo()
+        rc = lib.sipg_cg_solve_static(self._h, self._vec(b, "b"), self._vec(x, "x"), float(rel_tol),
+                                      int(max_iter), C.byref(info), _vp(_stream_ptr(stream)))
+        if rc != SIPG_OK and (rc != SIPG_E_NOCONV or raise_on_noconv):
+            raise SipgError(rc, "sipg_cg_solve_static")
         return x, SolveInfo(info.iterations, info.initial_residual, info.final_residual,
                             info.true_residual, rc)
 

@@ -473,4 +473,19 @@ int sipg_cg_solve(const sipg_op* op, const double* b, double* x, double rel_tol,
     return cg_solve_device(op, b, x, rel_tol, max_iter, info, static_cast<hipStream_t>(stream));
 }
 
+int sipg_cg_solve_static(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
+                         sipg_solve_info* info, void* stream) {
+    if (!op || !b || !x || !info) { set_error("sipg_cg_solve_static: null argument"); return SIPG_E_ARG; }
+    if (op->dtype != SIPG_F64) { set_error("sipg_cg_solve_static: needs an SIPG_F64 operator"); return SIPG_E_ARG; }
+    if (!(rel_tol > 0.0) || max_iter < 0) {
+        set_error("sipg_cg_solve_static: rel_tol must be > 0, max_iter >= 0");
+        return SIPG_E_ARG;
+    }
+    if (ranges_overlap(b, x, size_t(op->ndofs) * 8)) { set_error("sipg_cg_solve_static: b and x overlap"); return SIPG_E_ARG; }
+    std::memset(info, 0, sizeof(*info));
+    return cg_solve_static(op, b, x, rel_tol, max_iter, info, static_cast<hipStream_t>(stream));
+}
+
+int64_t sipg_cg_static_max_dofs(void) { return cg_static_max_dofs(); }
+
 }  // extern "C"

@@ -2,6 +2,8 @@
 // with fused vector updates and two-stage dot products on the device.  The
 // host reads one scalar per iteration to decide convergence.
 #include <cmath>
+#include <mutex>
+#include <string>
 #include <vector>
 
 #include "sipg_common.hpp"
@@ -174,6 +176,52 @@ int cg_solve_device(const sipg_op* op, const double* b, double* x, double rel_to
     }
     for (void* q : blk) op->mem.release(q);
     return status;
+}
+
+// ---------------------------------------------------------------------------
+// The same solve for callers that cannot allocate device memory (code under
+// stream capture, tight serving loops): the work arrays are a fixed array in
+// device memory, one per GPU, that holds up to kStaticCgDofs unknowns.
+// ---------------------------------------------------------------------------
+constexpr int64_t kStaticCgDofs = int64_t(1) << 20;
+constexpr size_t kStaticCgWords = size_t(3 * kStaticCgDofs) + size_t(kRedBlocks) + 64;
+static __device__ __align__(256) double scratch[kStaticCgWords];
+
+// Device address of `scratch` on each device, looked up once per device with
+// that device current (the host-side name of the array is not a device
+// address).
+static std::mutex g_scratch_mu;
+static std::vector<double*> g_scratch_ptr;
+
+static int static_scratch(double** out) {
+    int dev = 0;
+    SIPG_HIP(hipGetDevice(&dev));
+    std::lock_guard<std::mutex> lk(g_scratch_mu);
+    if (int(g_scratch_ptr.size()) <= dev) g_scratch_ptr.resize(size_t(dev) + 1, nullptr);
+    if (!g_scratch_ptr[dev]) {
+        void* ptr = nullptr;
+        SIPG_HIP(hipGetSymbolAddress(&ptr, HIP_SYMBOL(scratch)));
+        g_scratch_ptr[dev] = static_cast<double*>(ptr);
+    }
+    *out = g_scratch_ptr[dev];
+    return SIPG_OK;
+}
+
+int64_t cg_static_max_dofs() { return kStaticCgDofs; }
+
+int cg_solve_static(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
+                    sipg_solve_info* info, hipStream_t st) {
+    if (op->ndofs > kStaticCgDofs) {
+        set_error("sipg_cg_solve_static: the operator has " + std::to_string(op->ndofs) +
+                  " unknowns, more than the fixed work arrays hold (" + std::to_string(kStaticCgDofs) + ")");
+        return SIPG_E_ARG;
+    }
+    double* base = nullptr;
+    if (int rc = static_scratch(&base)) return rc;
+    // every array is written before it is read: nothing to clear
+    const CgWork w{base, base + kStaticCgDofs, base + 2 * kStaticCgDofs, base + 3 * kStaticCgDofs,
+                   base + 3 * kStaticCgDofs + kRedBlocks};
+    return cg_iterate(op, b, x, rel_tol, max_iter, info, w, st);
 }
 
 }  // namespace sipg

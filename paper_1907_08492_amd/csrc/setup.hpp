@@ -62,9 +62,14 @@ int launch_rhs_sines(const sipg_op* op, int nmodes, const double* amps, const in
 // diag(A) in the nodal Gauss-Lobatto basis, written to `diag` (operator precision).
 int launch_gl_diagonal(const sipg_op* op, void* diag, hipStream_t st);
 
-// FP64 conjugate gradient method, work arrays from the operator's allocator.
+// FP64 conjugate gradient method: work arrays from the operator's allocator
+// (cg_solve_device) or from the fixed per-device array (cg_solve_static,
+// at most cg_static_max_dofs() unknowns).
 int cg_solve_device(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
                     sipg_solve_info* info, hipStream_t st);
+int cg_solve_static(const sipg_op* op, const double* b, double* x, double rel_tol, int max_iter,
+                    sipg_solve_info* info, hipStream_t st);
+int64_t cg_static_max_dofs();
 
 // Device bytes a multigrid solver for this problem will hold.
 int64_t mg_estimate_bytes(const sipg_mesh& mesh, int degree, const sipg_mg_opts& o);
