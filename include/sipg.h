@@ -337,6 +337,12 @@ typedef struct {
                                     one launch, the product with the residual, P^-1 and the
                                     update fused (the "merged" arrangement of Section 6); 0: the
                                     product, then one merged pass.  Same results up to rounding */
+    int32_t lanczos_start;       /* start of the eigenvalue estimate: 0 (default) the right-hand
+                                    side [-5.5, ..., 5.5, ...] in the level's own coefficients
+                                    (Section 6.2); 1 the right-hand side A u of the function u
+                                    whose nodal Gauss-Lobatto values are that sequence, the same
+                                    start in every basis, so that hierarchies in the Hermite-like
+                                    and the nodal basis get the same estimates (Section 6.3) */
 } sipg_mg_opts;
 typedef struct {
     int32_t levels;

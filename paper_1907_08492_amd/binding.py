@@ -73,7 +73,7 @@ class SipgMgOpts(C.Structure):
     _fields_ = [("smoother_degree", C.c_int32), ("lanczos_steps", C.c_int32), ("range_lo", C.c_double),
                 ("range_hi", C.c_double), ("coarse_reduction", C.c_double), ("min_coarse_cells", C.c_int32),
                 ("precision", C.c_int32), ("smoother", C.c_int32), ("p_coarsening", C.c_int32),
-                ("fused_smoother", C.c_int32)]
+                ("fused_smoother", C.c_int32), ("lanczos_start", C.c_int32)]
 
 
 class SipgMgInfo(C.Structure):

@@ -187,6 +187,7 @@ struct Hierarchy {
     int coarse_steps = 1;
     int pmode = SIPG_BC_PJACOBI;   // P^-1 of the smoother: SIPG_BC_PJACOBI or SIPG_BC_FDM
     bool fused = true;             // Chebyshev steps fused into the product (Hermite-like levels)
+    int lanczos_start = 0;         // sipg_mg_opts.lanczos_start
 
     // u = S^m(b; u) on level l (u = 0 on entry when zero_init).
     int smooth(int l, bool zero_init, int steps, const std::vector<double>& sig, const std::vector<double>& th,
@@ -254,7 +255,16 @@ struct Hierarchy {
     int lanczos(int l, int steps, Scratch& sc, hipStream_t st) {
         Level<T>& L = *lv[l];
         int rc;
-        if ((rc = vec_sawtooth<T>(L.r.p, L.n, st)) != SIPG_OK) return rc;
+        if (lanczos_start == 0) {
+            if ((rc = vec_sawtooth<T>(L.r.p, L.n, st)) != SIPG_OK) return rc;
+        } else {
+            // r = A u for the function u whose nodal Gauss-Lobatto values are
+            // the sawtooth: the same start in every basis (u's coefficients
+            // in the level's basis are (T^T)^{x3} of the values)
+            if ((rc = vec_sawtooth<T>(L.z.p, L.n, st)) != SIPG_OK) return rc;
+            if ((rc = launch_basis_change(L.op, SIPG_BC_TT, L.z.p, L.uo.p, st)) != SIPG_OK) return rc;
+            if ((rc = launch_matvec(L.op, L.uo.p, L.r.p, st)) != SIPG_OK) return rc;
+        }
         steps = std::min(steps, kMaxLanczos);
         double* da = sc.coef.p;               // alpha_k
         double* db = sc.coef.p + steps;       // beta_k
@@ -364,12 +374,12 @@ static std::mutex g_lambda_mu;
 static std::map<std::vector<double>, std::pair<double, double>> g_lambda;
 
 static std::vector<double> level_key(const sipg_mesh& m, int degree, double penalty, int basis, int dtype,
-                                     int pmode, int steps) {
+                                     int pmode, int steps, int start) {
     std::vector<double> k = {double(m.n[0]), double(m.n[1]), double(m.n[2])};
     for (int d = 0; d < 3; ++d) { k.push_back(m.lo[d]); k.push_back(m.hi[d]); }
     for (int i = 0; i < 9; ++i) k.push_back(m.lin[i]);
     k.insert(k.end(), {m.deform_amp, double(degree), penalty, double(basis), double(dtype), double(pmode),
-                       double(steps)});
+                       double(steps), double(start)});
     return k;
 }
 
@@ -380,6 +390,7 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
     H.smooth_steps = o.smoother_degree;
     H.pmode = o.smoother == 1 ? SIPG_BC_FDM : SIPG_BC_PJACOBI;
     H.fused = o.fused_smoother != 0;
+    H.lanczos_start = o.lanczos_start;
     const std::vector<LevelSpec> seq = mg_level_sequence(mesh->n, degree, o);
     int rc;
     for (size_t l = 0; l < seq.size(); ++l) {
@@ -396,7 +407,7 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
             const bool coarsest = l + 1 == seq.size();
             const int64_t nl = int64_t(sp.nc[0]) * sp.nc[1] * sp.nc[2] * L->np * L->np * L->np;
             L->steps = coarsest ? int(std::min<int64_t>(nl / 4 + 2, 120)) : o.lanczos_steps;
-            L->key = level_key(m, sp.degree, penalty, basis, dt, H.pmode, L->steps);
+            L->key = level_key(m, sp.degree, penalty, basis, dt, H.pmode, L->steps, o.lanczos_start);
         }
         if ((rc = sipg_setup(&m, sp.degree, penalty, basis, dt, SIPG_GEOM_AUTO, &mg->user_alloc, st, &L->op)) != SIPG_OK)
             return rc;
@@ -490,6 +501,7 @@ int sipg_mg_default_opts(sipg_mg_opts* o) {
     o->smoother = 0;
     o->p_coarsening = 0;
     o->fused_smoother = 1;
+    o->lanczos_start = 0;
     return SIPG_OK;
 }
 
@@ -504,7 +516,7 @@ int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, 
     if (o.smoother_degree < 1 || o.smoother_degree > 64 || o.lanczos_steps < 2 || o.lanczos_steps > kMaxLanczos || !(o.range_lo > 0.0) ||
         !(o.range_hi > o.range_lo) || !(o.coarse_reduction > 1.0) || (o.precision != 0 && o.precision != 1) ||
         o.min_coarse_cells < 1 || (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2 ||
-        (o.fused_smoother != 0 && o.fused_smoother != 1)) {
+        (o.fused_smoother != 0 && o.fused_smoother != 1) || (o.lanczos_start != 0 && o.lanczos_start != 1)) {
         set_error("sipg_mg_setup: invalid options");
         return SIPG_E_ARG;
     }

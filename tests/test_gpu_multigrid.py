@@ -254,6 +254,71 @@ def test_vcycle_with_degree_levels_is_symmetric_in_fp64():
     mg.close()
 
 
+@pytest.mark.parametrize("k", [2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("mesh_name", ["affine", "deformed"])
+@pytest.mark.parametrize("rule", [0, 1])
+@pytest.mark.parametrize("smoother", ["pjacobi", "fdm"])
+def test_fused_smoother_matches_two_launch_degrees(k, mesh_name, rule, smoother):
+    """The fused Chebyshev step against the two-launch smoother for every
+    degree: n = 3..9 (wavefront-local and block-barrier cell steps, early and
+    late metric loads), per-cell (unit cube: diagonal metric) and per-point
+    (deformed) geometry, with and without degree levels; one V-cycle in FP64
+    and in mixed precision, and equal CG iteration counts."""
+    torch, P = require_gpu()
+    banner(f"fused smoother k={k} {mesh_name} p_coarsening={rule} {smoother}")
+    mesh = unit_cube((4, 2, 2), 0.1 if mesh_name == "deformed" else 0.0)
+    r = np.random.default_rng(90 + k).uniform(-1, 1, mesh.ncells * (k + 1) ** 3)
+    for precision in ("f64", "mixed"):
+        out, its = [], []
+        for fused in (1, 0):
+            mg = P.Multigrid(mesh, k, 2.0, precision=precision, smoother=smoother, fused_smoother=fused,
+                             p_coarsening=rule, lanczos_steps=8)
+            out.append(mg.vcycle(torch.from_numpy(r).cuda()).cpu().numpy())
+            x, info = mg.solve(torch.from_numpy(r).cuda(), rel_tol=1e-9, max_iter=100)
+            its.append(info.iterations)
+            mg.close()
+        diff = np.max(np.abs(out[0] - out[1])) / np.max(np.abs(out[1]))
+        assert diff <= (1e-13 if precision == "f64" else 1e-6), (precision, diff)
+        assert its[0] == its[1], (precision, its)
+
+
+@pytest.mark.parametrize("k", [3, 5])
+@pytest.mark.parametrize("mesh_name", ["cartesian", "deformed"])
+def test_hermite_like_with_gl_basis_change_equals_gl_point_jacobi(k, mesh_name):
+    """Section 6.3: multigrid with the Hermite-like basis and point Jacobi in
+    the nodal Gauss-Lobatto basis (through the basis change of eq. (jacobi))
+    is the same method as multigrid in the Gauss-Lobatto basis with point
+    Jacobi.  With A_GL = V^T A_HL V and P_HL^-1 = V diag(A_GL)^-1 V^T the
+    smoothed operators are similar, the coarse spaces are the same, and with
+    the same eigenvalue-estimate start in both bases (lanczos_start = 1) the
+    two preconditioned CG runs produce x_HL = V x_GL iterate by iterate."""
+    torch, P = require_gpu()
+    banner(f"HL+GL basis change vs GL point Jacobi k={k} {mesh_name}")
+    mesh = unit_cube(4, 0.1 if mesh_name == "deformed" else 0.0)
+    amps, waves = [3 * np.pi ** 2, 0.8], [(1, 1, 1), (2, 3, 1)]
+    res = {}
+    for basis in ("hermite_like", "nodal_gl"):
+        op = P.Operator(mesh, k, 2.0, basis)
+        b = op.assemble_rhs(amps, waves)
+        mg = P.Multigrid(mesh, k, 2.0, basis, precision="f64", smoother="pjacobi", lanczos_start=1)
+        # a fixed number of iterations (the residual norms differ by V^T)
+        x6, info6 = mg.solve(b, rel_tol=1e-30, max_iter=6, raise_on_noconv=False)
+        x, info = mg.solve(b, rel_tol=1e-10)
+        res[basis] = (x6, x, info.iterations, mg.info.lambda_max_fine, op)
+        mg.close()
+    hl, gl = res["hermite_like"], res["nodal_gl"]
+    # the same eigenvalue estimate (similar operators, equivalent starts)
+    assert abs(hl[3] - gl[3]) <= 1e-10 * gl[3], (hl[3], gl[3])
+    # x_HL = V x_GL (V = T^T cell by cell: GL coefficients -> HL coefficients)
+    for a, g in ((hl[0], gl[0]), (hl[1], gl[1])):
+        mapped = hl[4].basis_change("TT", g)
+        e = float(torch.linalg.norm(a - mapped) / torch.linalg.norm(a))
+        assert e <= 1e-10, e
+    assert hl[2] == gl[2], (hl[2], gl[2])
+    hl[4].close()
+    gl[4].close()
+
+
 @pytest.mark.parametrize("smoother", ["pjacobi", "fdm"])
 @pytest.mark.parametrize("precision", ["mixed", "f64"])
 def test_fused_smoother_matches_two_launch_smoother(smoother, precision):
