@@ -239,6 +239,19 @@ int sipg_basis_change(const sipg_op* op, int mode, const void* in, void* out, vo
 int sipg_apply_pjacobi(const sipg_op* op, const void* x, void* y, void* z, void* stream);
 
 /*
+ * Measurement aid, not part of the method: moves exactly the bytes of
+ * sipg_apply_pjacobi (x, the operator's metric terms and 1/diag(A_GL) read
+ * once, y and z written once) with no arithmetic, every workgroup reading one
+ * contiguous share of each array in 16-byte pieces.  Its duration is the
+ * step's duration if it were bound by HBM alone for that mix of reads and
+ * writes; the contents written to y and z are meaningless.  x, y, z: device
+ * pointers, ndofs elements, 16-byte aligned, not overlapping.  Needs
+ * sipg_compute_gl_diagonal first (SIPG_E_ARG).  Allocates nothing; stream
+ * ordered.
+ */
+int sipg_stream_bound(const sipg_op* op, const void* x, void* y, void* z, void* stream);
+
+/*
  * Compute diag(A) of the operator in the nodal Gauss-Lobatto basis, i.e. the
  * element-wise diagonal P_d of eq. (jacobi), and keep its inverse inside the
  * operator for SIPG_BC_PJACOBI.  Computed on the device by the same weak form.

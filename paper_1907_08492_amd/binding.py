@@ -48,7 +48,7 @@ EXPORTED = [
     "sipg_release", "sipg_server_stats", "sipg_server_destroy", "sipg_copy_device",
     "sipg_batch_create", "sipg_batch_apply", "sipg_batch_get_info", "sipg_batch_destroy",
     "sipg_host_fdm_tables", "sipg_mg_level_degree", "sipg_batch_tune",
-    "sipg_cg_solve_static", "sipg_cg_static_max_dofs", "sipg_host_block_order",
+    "sipg_cg_solve_static", "sipg_cg_static_max_dofs", "sipg_host_block_order", "sipg_stream_bound",
 ]
 
 
@@ -135,6 +135,7 @@ lib.sipg_get_info.argtypes = [_vp, C.POINTER(SipgOpInfo)]
 lib.sipg_apply.argtypes = [_vp, _vp, _vp, _vp]
 lib.sipg_apply_pjacobi.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.sipg_basis_change.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
+lib.sipg_stream_bound.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.sipg_compute_gl_diagonal.argtypes = [_vp, _vp, _vp]
 lib.sipg_cg_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
 lib.sipg_cg_solve_static.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
@@ -350,6 +351,13 @@ class Operator:
         _check(lib.sipg_apply_pjacobi(self._h, self._vec(x, "x"), self._vec(y, "y"), self._vec(z, "z"),
                                       _vp(_stream_ptr(stream))), "sipg_apply_pjacobi")
         return y, z
+
+    def stream_bound(self, x, y, z, stream=None):
+        """The step's bytes moved with no arithmetic (sipg_stream_bound): a
+        measurement of the HBM bound of apply_pjacobi; y, z get meaningless
+        values."""
+        _check(lib.sipg_stream_bound(self._h, self._vec(x, "x"), self._vec(y, "y"), self._vec(z, "z"),
+                                     _vp(_stream_ptr(stream))), "sipg_stream_bound")
 
     def basis_change(self, mode: str, x, out=None, stream=None):
         y = self.empty() if out is None else out

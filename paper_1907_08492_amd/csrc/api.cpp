@@ -436,6 +436,21 @@ int sipg_apply_pjacobi(const sipg_op* op, const void* x, void* y, void* z, void*
     return launch_matvec_pjacobi(op, x, y, z, static_cast<hipStream_t>(stream));
 }
 
+int sipg_stream_bound(const sipg_op* op, const void* x, void* y, void* z, void* stream) {
+    if (!op || !x || !y || !z) { set_error("sipg_stream_bound: null argument"); return SIPG_E_ARG; }
+    if (!op->gl_inv_diag) { set_error("sipg_stream_bound: needs sipg_compute_gl_diagonal first"); return SIPG_E_ARG; }
+    const size_t bytes = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
+    if (ranges_overlap(x, y, bytes) || ranges_overlap(x, z, bytes) || ranges_overlap(y, z, bytes)) {
+        set_error("sipg_stream_bound: x, y and z must not overlap");
+        return SIPG_E_ARG;
+    }
+    if ((reinterpret_cast<uintptr_t>(x) | reinterpret_cast<uintptr_t>(y) | reinterpret_cast<uintptr_t>(z)) % 16) {
+        set_error("sipg_stream_bound: x, y and z must be 16-byte aligned");
+        return SIPG_E_ARG;
+    }
+    return launch_stream_bound(op, x, y, z, static_cast<hipStream_t>(stream));
+}
+
 int sipg_basis_change(const sipg_op* op, int mode, const void* in, void* out, void* stream) {
     if (!op || !in || !out) { set_error("sipg_basis_change: null argument"); return SIPG_E_ARG; }
     if (mode < SIPG_BC_T || mode > SIPG_BC_FDM) { set_error("sipg_basis_change: bad mode"); return SIPG_E_ARG; }

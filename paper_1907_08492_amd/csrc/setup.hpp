@@ -56,6 +56,9 @@ int launch_basis_change(const sipg_op* op, int mode, const void* in, void* out, 
 int launch_precond_cheb(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
                         double sigma, double theta, hipStream_t st);
 
+// Bandwidth bound of the fused step (see sipg_stream_bound).
+int launch_stream_bound(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st);
+
 // Right-hand side of a sum of sine modes (see sipg_assemble_rhs_sines).
 int launch_rhs_sines(const sipg_op* op, int nmodes, const double* amps, const int* waves, void* b, hipStream_t st);
 
