@@ -274,6 +274,7 @@ def batch_benchmark(torch, P, dtype: str, reps: int = 10, count: int = 256):
         alone.append(float(timed(lambda: op.apply(x, y), 3).min()))
     alone = np.array(alone)
     out = {"dtype": dtype, "operators": count, "ndofs": ndofs, "launches": int(b.info.launches),
+           "streams": int(b.info.streams),
            "batched": {"dof_per_s": ndofs / tb.mean(), "avg_ms": tb.mean() * 1e3, "min_ms": tb.min() * 1e3,
                        "alg_GBs": alg / tb.mean() / 1e9, "hbm_frac": alg / tb.mean() / 1e9 / HBM_PEAK_GBS},
            "one_by_one": {"dof_per_s": ndofs / ts.mean(), "avg_ms": ts.mean() * 1e3,
@@ -416,6 +417,8 @@ def main():
     ap.add_argument("--serve-workers", type=int, default=8)
     ap.add_argument("--serve-sustained-rate", type=float, default=25.0,
                     help="arrival rate of the below-saturation latency run (0 skips it)")
+    ap.add_argument("--serve-capacity-rate", type=float, default=400.0,
+                    help="arrival rate of the saturated mixed-precision capacity run (0 skips it)")
     ap.add_argument("--no-protocol", dest="protocol", action="store_false",
                     help="skip the 40 x 200 launch timing protocol of Section 5")
     args = ap.parse_args()
@@ -641,6 +644,12 @@ def main():
             serve[prec] = serve_benchmark(P, prec, args.serve_seconds, args.serve_rate, args.serve_workers)
             torch.cuda.empty_cache()
         serve["mixed_over_f64_solves_per_s"] = serve["mixed"]["solves_per_s"] / serve["f64"]["solves_per_s"]
+        # capacity of the mixed-precision server: the same stream offered
+        # at twice the rate (saturated), solves per second over the run
+        if args.serve_capacity_rate > 0:
+            print(f"[bench] serving mixed capacity: {args.serve_capacity_rate}/s for 10 s", file=sys.stderr, flush=True)
+            serve["capacity_mixed"] = serve_benchmark(P, "mixed", 10.0, args.serve_capacity_rate, args.serve_workers)
+            torch.cuda.empty_cache()
         # latency below saturation: the same stream thinned to a rate both
         # precisions sustain, over a longer window
         if args.serve_sustained_rate > 0:

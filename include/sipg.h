@@ -173,9 +173,13 @@ int sipg_apply(const sipg_op* op, const void* x, void* y, void* stream);
  *                      SIPG_E_ARG.  Allocates one small device table
  *                      (kernel parameters, workgroup -> operator map) and
  *                      copies it synchronously.
- *   sipg_batch_apply   launches the groups on `stream`; allocates nothing,
- *                      stream ordered.  Each y_i is bit-identical to
- *                      sipg_apply(ops[i], x[i], y[i]).
+ *   sipg_batch_apply   launches the groups, spread over `stream` and up to
+ *                      three streams of the batch that start after the work
+ *                      queued on `stream` and that `stream` waits for
+ *                      (events), so groups run concurrently; allocates
+ *                      nothing, stream ordered with respect to `stream`.
+ *                      Each y_i is bit-identical to sipg_apply(ops[i], x[i],
+ *                      y[i]).  Calls on one batch must not overlap.
  *   sipg_batch_destroy frees the table (NULL accepted); no queued work may
  *                      still use it.
  */
@@ -185,6 +189,7 @@ typedef struct {
     int64_t ndofs, ncells, workgroups;
     int64_t device_bytes;
     int32_t per_operator_groups; /* groups that sipg_batch_tune set to one launch per operator */
+    int32_t streams;             /* streams the groups are spread over (the caller's included) */
 } sipg_batch_info;
 int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x, void* const* y,
                       sipg_batch** out);

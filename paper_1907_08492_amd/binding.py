@@ -108,7 +108,7 @@ class SipgServerStats(C.Structure):
 class SipgBatchInfo(C.Structure):
     _fields_ = [("nops", C.c_int32), ("launches", C.c_int32), ("ndofs", C.c_int64),
                 ("ncells", C.c_int64), ("workgroups", C.c_int64), ("device_bytes", C.c_int64),
-                ("per_operator_groups", C.c_int32)]
+                ("per_operator_groups", C.c_int32), ("streams", C.c_int32)]
 
 
 _ALLOC_FN = C.CFUNCTYPE(C.c_void_p, C.c_size_t, C.c_void_p)

@@ -7,6 +7,11 @@
 // each of them alone would leave mostly idle.  The per-operator kernel
 // parameters and the workgroup -> operator table live in one device buffer
 // made at creation; sipg_batch_apply only launches (one kernel per group).
+// The groups are spread over the caller's stream and up to three more
+// streams of the batch (default priority), forked from and joined back into
+// the caller's stream with events, so that the grids of different groups run
+// concurrently and the small ones fill the compute units the large ones leave
+// idle at their ends.
 #include <hip/hip_runtime.h>
 
 #include <algorithm>
@@ -35,6 +40,12 @@ struct sipg_batch {
     std::vector<void*> y;
     void* mem = nullptr;
     sipg::DevAlloc alloc;           // provider of mem (the first operator's)
+    // concurrent groups: stream of each group (0 = the caller's, j > 0 =
+    // aux[j - 1]), and the fork / join events
+    std::vector<int> lane;
+    std::vector<hipStream_t> aux;
+    hipEvent_t fork = nullptr;
+    std::vector<hipEvent_t> join;
     size_t bytes = 0;
 };
 
@@ -208,6 +219,37 @@ int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x,
         return arc != SIPG_OK ? arc : hip_fail(e, "sipg_batch_create: device tables");
     }
     b->bytes = host.size();
+    // groups to streams: largest first, each to the stream with the fewest
+    // workgroups so far (at most 4 streams: the device's hardware queues)
+    {
+        const int nlanes = int(std::min<size_t>(4, b->groups.size()));
+        std::vector<size_t> idx(b->groups.size());
+        for (size_t i = 0; i < idx.size(); ++i) idx[i] = i;
+        std::sort(idx.begin(), idx.end(), [&](size_t a, size_t c) { return b->groups[a].nblocks > b->groups[c].nblocks; });
+        std::vector<int64_t> load(nlanes, 0);
+        b->lane.assign(b->groups.size(), 0);
+        for (size_t i : idx) {
+            const int l = int(std::min_element(load.begin(), load.end()) - load.begin());
+            b->lane[i] = l;
+            load[l] += b->groups[i].nblocks;
+        }
+        (void)hipGetDevice(&prev);
+        hipError_t se = hipSetDevice(device);
+        if (se == hipSuccess) se = hipEventCreateWithFlags(&b->fork, hipEventDisableTiming);
+        for (int l = 1; l < nlanes && se == hipSuccess; ++l) {
+            hipStream_t s2 = nullptr;
+            hipEvent_t ev = nullptr;
+            se = hipStreamCreateWithFlags(&s2, hipStreamNonBlocking);
+            if (se == hipSuccess) b->aux.push_back(s2);
+            if (se == hipSuccess) se = hipEventCreateWithFlags(&ev, hipEventDisableTiming);
+            if (se == hipSuccess) b->join.push_back(ev);
+        }
+        (void)hipSetDevice(prev);
+        if (se != hipSuccess) {
+            sipg_batch_destroy(b);
+            return hip_fail(se, "sipg_batch_create: streams");
+        }
+    }
     char* base = static_cast<char*>(b->mem);
     for (size_t gi = 0; gi < b->groups.size(); ++gi) {
         b->groups[gi].params = base + offs[gi].params;
@@ -228,9 +270,19 @@ static int run_group(const sipg_batch* b, size_t gi, int schedule, hipStream_t s
 int sipg_batch_apply(const sipg_batch* b, void* stream) {
     if (!b) { set_error("sipg_batch_apply: null batch"); return SIPG_E_ARG; }
     hipStream_t st = static_cast<hipStream_t>(stream);
-    for (size_t gi = 0; gi < b->groups.size(); ++gi)
-        if (int rc = run_group(b, gi, b->schedule[gi], st)) return rc;
-    return SIPG_OK;
+    // the aux streams start after the work queued on the caller's stream
+    SIPG_HIP(hipEventRecord(b->fork, st));
+    for (hipStream_t s2 : b->aux) SIPG_HIP(hipStreamWaitEvent(s2, b->fork, 0));
+    int rc = SIPG_OK;
+    for (size_t gi = 0; gi < b->groups.size() && rc == SIPG_OK; ++gi)
+        rc = run_group(b, gi, b->schedule[gi], b->lane[gi] == 0 ? st : b->aux[b->lane[gi] - 1]);
+    // and the caller's stream continues after all of them (also on error, so
+    // that nothing queued later overtakes a launched group)
+    for (size_t j = 0; j < b->aux.size(); ++j) {
+        SIPG_HIP(hipEventRecord(b->join[j], b->aux[j]));
+        SIPG_HIP(hipStreamWaitEvent(st, b->join[j], 0));
+    }
+    return rc;
 }
 
 int sipg_batch_tune(sipg_batch* b, int reps, void* stream) {
@@ -271,12 +323,16 @@ int sipg_batch_get_info(const sipg_batch* b, sipg_batch_info* info) {
     info->device_bytes = int64_t(b->bytes);
     info->per_operator_groups = 0;
     for (int sch : b->schedule) info->per_operator_groups += sch;
+    info->streams = int32_t(b->aux.size()) + 1;
     return SIPG_OK;
 }
 
 int sipg_batch_destroy(sipg_batch* b) {
     if (!b) return SIPG_OK;
     b->alloc.release(b->mem);
+    for (hipStream_t s2 : b->aux) (void)hipStreamDestroy(s2);
+    for (hipEvent_t ev : b->join) (void)hipEventDestroy(ev);
+    if (b->fork) (void)hipEventDestroy(b->fork);
     delete b;
     return SIPG_OK;
 }
