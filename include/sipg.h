@@ -324,11 +324,11 @@ int sipg_launch_shape(int degree, int dtype, int32_t* cells_per_block, int32_t* 
  * least min_coarse_cells coarse cells remain) the V-cycle smooths with a
  * Chebyshev iteration (eq. chebyshev) around P^-1 of the form of eq. (jacobi)
  * (point Jacobi in the nodal Gauss-Lobatto basis through the basis change,
- * or the block Jacobi of Section 6.4 by fast diagonalization).  The
- * Optionally the first levels lower the polynomial degree on the fine mesh
- * (p_coarsening); the transfer between degrees is the exact embedding of
- * the lower-degree space and its transpose.  The
- * smoothing range is [range_lo, range_hi] times the largest eigenvalue of
+ * or the block Jacobi of Section 6.4 by fast diagonalization).  Optionally
+ * the first levels lower the polynomial degree on the fine mesh
+ * (p_coarsening); the transfer between degrees is the exact embedding of the
+ * lower-degree space and its transpose.  The smoothing range is
+ * [range_lo, range_hi] times the largest eigenvalue of
  * P^-1 A estimated by lanczos_steps conjugate-gradient (Lanczos) steps from
  * [-5.5, -4.5, ..., 5.5, -5.5, ...] (Section 6.2); the coarsest level is
  * solved by a Chebyshev iteration whose degree guarantees a residual
