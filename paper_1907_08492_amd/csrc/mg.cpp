@@ -132,13 +132,19 @@ constexpr int kMaxLanczos = 512;
 struct Scratch {
     DevBuf<double> partial, scal, coef;
     double* host = nullptr;
-    ~Scratch() { if (host) (void)hipHostFree(host); }
+    hipEvent_t ev[2] = {nullptr, nullptr};   // residual copies of the lagged stopping test
+    ~Scratch() {
+        if (host) (void)hipHostFree(host);
+        for (hipEvent_t e : ev)
+            if (e) (void)hipEventDestroy(e);
+    }
     int init(const DevAlloc& mem) {
         int rc;
         if ((rc = partial.alloc(kVecPartials, mem)) != SIPG_OK) return rc;
         if ((rc = scal.alloc(8, mem)) != SIPG_OK) return rc;
         if ((rc = coef.alloc(2 * kMaxLanczos, mem)) != SIPG_OK) return rc;
         SIPG_HIP(hipHostMalloc(&host, sizeof(double) * 8, hipHostMallocDefault));
+        for (hipEvent_t& e : ev) SIPG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         return SIPG_OK;
     }
     // scal[slot] = a . b on the device (no host synchronisation)
@@ -601,12 +607,38 @@ int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int m
     if ((rc = sc.dot<double>(r.p, r.p, n, rr, st)) != SIPG_OK) return rc;
     info->initial_residual = std::sqrt(rr);
     // CG coefficients stay on the device (scalar slots 0: r.z, 1: p.Ap,
-    // 2: new r.z, 3: r.r); the host reads r.r once per iteration.
+    // 2: new r.z, 4 + it % 2: r.r of iteration it).  The stopping test is
+    // lagged: r.r of iteration it is copied to pinned host memory behind its
+    // work, and before queueing iteration it + 2 the host reads the value of
+    // iteration it, while iteration it + 1 runs, so the device does not wait
+    // for the host between iterations.  Only when the observed reduction
+    // rate predicts that the running iteration reaches the tolerance does the
+    // host wait for that iteration too, so that no iteration is done beyond
+    // the first one that converged.
     double* s_rz = sc.scal.p;
     double* s_pap = sc.scal.p + 1;
     double* s_rzn = sc.scal.p + 2;
     int it = 0;
-    while (std::sqrt(rr) > target && it < max_iter) {
+    bool converged = std::sqrt(rr) <= target;
+    double rr_prev = rr;                       // r.r of the iteration before the last one read
+    while (!converged && it < max_iter) {
+        if (it >= 2) {
+            // iteration it - 2 has finished (it - 1 may still run)
+            SIPG_HIP(hipEventSynchronize(sc.ev[it % 2]));
+            const double r2 = sc.host[4 + it % 2];
+            const double rate = rr_prev > 0.0 ? std::min(1.0, r2 / rr_prev) : 1.0;
+            rr_prev = r2;
+            rr = r2;
+            if (std::sqrt(rr) <= target) { converged = true; break; }
+            if (std::sqrt(r2 * rate) <= 1.5 * target) {
+                // iteration it - 1 likely converges: wait for it
+                SIPG_HIP(hipEventSynchronize(sc.ev[(it - 1) % 2]));
+                rr = sc.host[4 + (it - 1) % 2];
+                if (std::sqrt(rr) <= target) { converged = true; break; }
+            }
+        } else if (it == 1) {
+            rr_prev = rr;
+        }
         if ((rc = sipg_mg_apply_vcycle(mg, r.p, z.p, stream)) != SIPG_OK) return rc;
         if ((rc = sc.dot_dev<double>(r.p, z.p, n, 2, st)) != SIPG_OK) return rc;
         if (it == 0) {
@@ -619,9 +651,16 @@ int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int m
         if ((rc = sc.dot_dev<double>(p.p, ap.p, n, 1, st)) != SIPG_OK) return rc;
         if ((rc = vec_axpy_dev<double>(s_rz, s_pap, 1.0, p.p, x, n, st)) != SIPG_OK) return rc;
         if ((rc = vec_axpy_dev<double>(s_rz, s_pap, -1.0, ap.p, r.p, n, st)) != SIPG_OK) return rc;
-        if ((rc = sc.dot_dev<double>(r.p, r.p, n, 3, st)) != SIPG_OK) return rc;
-        if ((rc = sc.read(3, rr, st)) != SIPG_OK) return rc;
+        if ((rc = sc.dot_dev<double>(r.p, r.p, n, 4 + it % 2, st)) != SIPG_OK) return rc;
+        SIPG_HIP(hipMemcpyAsync(sc.host + 4 + it % 2, sc.scal.p + 4 + it % 2, sizeof(double), hipMemcpyDeviceToHost, st));
+        SIPG_HIP(hipEventRecord(sc.ev[it % 2], st));
         ++it;
+    }
+    if (it > 0) {
+        // the residual of the last queued iteration (the solution returned)
+        SIPG_HIP(hipEventSynchronize(sc.ev[(it - 1) % 2]));
+        rr = sc.host[4 + (it - 1) % 2];
+        converged = converged || std::sqrt(rr) <= target;
     }
     info->iterations = it;
     info->final_residual = std::sqrt(rr);
@@ -630,7 +669,7 @@ int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int m
     double tr;
     if ((rc = sc.dot<double>(r.p, r.p, n, tr, st)) != SIPG_OK) return rc;
     info->true_residual = std::sqrt(tr);
-    if (std::sqrt(rr) > target) {
+    if (!converged) {
         set_error("sipg_mg_solve: no convergence within max_iter");
         return SIPG_E_NOCONV;
     }
