@@ -419,6 +419,8 @@ def main():
                     help="arrival rate of the below-saturation latency run (0 skips it)")
     ap.add_argument("--serve-capacity-rate", type=float, default=400.0,
                     help="arrival rate of the saturated mixed-precision capacity run (0 skips it)")
+    ap.add_argument("--capacity-only", action="store_true",
+                    help="of the serving legs, run only the saturated capacity run")
     ap.add_argument("--no-protocol", dest="protocol", action="store_false",
                     help="skip the 40 x 200 launch timing protocol of Section 5")
     args = ap.parse_args()
@@ -636,28 +638,29 @@ def main():
             out["batch"].append(batch_benchmark(torch, P, dt))
             torch.cuda.empty_cache()
 
-    if args.serve_seconds > 0:
-        serve = {}
+    serve = {}
+    if args.serve_seconds > 0 and not args.capacity_only:
         for prec in ("mixed", "f64"):
             print(f"[bench] serving {prec}: {args.serve_rate}/s for {args.serve_seconds} s",
                   file=sys.stderr, flush=True)
             serve[prec] = serve_benchmark(P, prec, args.serve_seconds, args.serve_rate, args.serve_workers)
             torch.cuda.empty_cache()
         serve["mixed_over_f64_solves_per_s"] = serve["mixed"]["solves_per_s"] / serve["f64"]["solves_per_s"]
-        # capacity of the mixed-precision server: the same stream offered
-        # at twice the rate (saturated), solves per second over the run
-        if args.serve_capacity_rate > 0:
-            print(f"[bench] serving mixed capacity: {args.serve_capacity_rate}/s for 10 s", file=sys.stderr, flush=True)
-            serve["capacity_mixed"] = serve_benchmark(P, "mixed", 10.0, args.serve_capacity_rate, args.serve_workers)
+    # capacity of the mixed-precision server: the same stream offered at
+    # twice the rate (saturated), solves per second over the run
+    if args.serve_seconds > 0 and args.serve_capacity_rate > 0:
+        print(f"[bench] serving mixed capacity: {args.serve_capacity_rate}/s for 10 s", file=sys.stderr, flush=True)
+        serve["capacity_mixed"] = serve_benchmark(P, "mixed", 10.0, args.serve_capacity_rate, args.serve_workers)
+        torch.cuda.empty_cache()
+    # latency below saturation: the same stream thinned to a rate both
+    # precisions sustain, over a longer window
+    if args.serve_seconds > 0 and args.serve_sustained_rate > 0 and not args.capacity_only:
+        serve["sustained"] = {}
+        for prec in ("mixed", "f64"):
+            print(f"[bench] serving {prec}: {args.serve_sustained_rate}/s for 4 s", file=sys.stderr, flush=True)
+            serve["sustained"][prec] = serve_benchmark(P, prec, 4.0, args.serve_sustained_rate, args.serve_workers)
             torch.cuda.empty_cache()
-        # latency below saturation: the same stream thinned to a rate both
-        # precisions sustain, over a longer window
-        if args.serve_sustained_rate > 0:
-            serve["sustained"] = {}
-            for prec in ("mixed", "f64"):
-                print(f"[bench] serving {prec}: {args.serve_sustained_rate}/s for 4 s", file=sys.stderr, flush=True)
-                serve["sustained"][prec] = serve_benchmark(P, prec, 4.0, args.serve_sustained_rate, args.serve_workers)
-                torch.cuda.empty_cache()
+    if serve:
         out["serving"] = serve
 
     if not args.no_cpu:
