@@ -43,10 +43,14 @@ TABLE4_FLOP = {"hermite_like": {1: 244, 2: 191, 3: 218, 4: 206, 5: 225, 7: 241},
 
 def _eo_flops(n: int, eps: int) -> int:
     """FLOPs of one even-odd 1D contraction of an n-point pencil (an FMA
-    counts 2): sums/differences of mirrored entries, n/2 pairs of outputs, and
+    counts 2, the first product of an accumulation 1): sums/differences of
+    mirrored entries, n/2 pairs of outputs from two half-length products, and
     the middle row for odd n."""
     h, odd = n // 2, n % 2
-    return 2 * h + h * (odd + 4 * h + 2) + odd * (2 * h + (1 if eps > 0 else 0))
+    ev = 1 + 2 * h if odd else 2 * h - 1
+    od = 2 * h - 1
+    mid = (1 + 2 * h if eps > 0 else 2 * h - 1) if odd else 0
+    return 2 * h + h * (ev + od + 2) + mid
 
 
 def kernel_flops_per_dof(k: int, basis: str = "hermite_like", geom: str = "qpoint", epilogue: str = "none") -> float:

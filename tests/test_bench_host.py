@@ -48,3 +48,93 @@ def test_several_gpus_refused_before_any_gpu_work():
     assert r.returncode == 2
     assert "one GPU only" in r.stderr
     assert r.stdout == ""
+
+
+class _Counted:
+    """A number that counts the floating-point operations applied to it (an
+    FMA written as a * b + c counts 2, like the kernels' fused multiply-add)."""
+    ops = 0
+
+    def __init__(self, v):
+        self.v = v
+
+    def _op(self, o, f):
+        _Counted.ops += 1
+        return _Counted(f(self.v, o.v if isinstance(o, _Counted) else o))
+
+    def __add__(self, o):
+        return self._op(o, lambda a, b: a + b)
+
+    __radd__ = __add__
+
+    def __sub__(self, o):
+        return self._op(o, lambda a, b: a - b)
+
+    def __rsub__(self, o):
+        return self._op(o, lambda a, b: b - a)
+
+    def __mul__(self, o):
+        return self._op(o, lambda a, b: a * b)
+
+    __rmul__ = __mul__
+
+
+def _even_odd_sweep(M, x, eps):
+    """out = M x by the even-odd decomposition of a matrix with
+    M[n-1-q][n-1-j] = eps M[q][j]: sums and differences of mirrored inputs,
+    half-size products, and the outputs as their sum and difference."""
+    n = len(x)
+    h = n // 2
+    e = [x[j] + x[n - 1 - j] for j in range(h)]
+    o = [x[j] - x[n - 1 - j] for j in range(h)]
+    out = [None] * n
+    for q in range(h):
+        ev = M[q][h] * x[h] if n % 2 else None
+        od = None
+        for j in range(h):
+            a = (M[q][j] + M[q][n - 1 - j]) / 2
+            b = (M[q][j] - M[q][n - 1 - j]) / 2
+            ev = a * e[j] if ev is None else ev + a * e[j]
+            od = b * o[j] if od is None else od + b * o[j]
+        out[q] = ev + od
+        out[n - 1 - q] = ev - od if eps > 0 else od - ev
+    if n % 2:
+        if eps > 0:
+            m = M[h][h] * x[h]
+            for j in range(h):
+                m = m + (M[h][j] + M[h][n - 1 - j]) / 2 * e[j]
+        else:
+            m = None
+            for j in range(h):
+                t = (M[h][j] - M[h][n - 1 - j]) / 2 * o[j]
+                m = t if m is None else m + t
+        out[h] = m
+    return out
+
+
+@pytest.mark.parametrize("n", [2, 3, 4, 5, 6, 7, 8, 9])
+@pytest.mark.parametrize("eps", [1, -1])
+def test_even_odd_flop_count(n, eps):
+    """The analytic FLOP count of one 1D sweep equals the operations of the
+    even-odd algorithm counted one by one (a multiply followed by an add into
+    an accumulator is the kernel's FMA: 2), and the sweep is correct."""
+    import numpy as np
+    rng = np.random.default_rng(n)
+    A = rng.normal(size=(n, n))
+    M = (A + eps * A[::-1, ::-1]) / 2          # M[n-1-q][n-1-j] = eps M[q][j]
+    x = rng.normal(size=n)
+    _Counted.ops = 0
+    out = _even_odd_sweep(M.tolist(), [_Counted(v) for v in x], eps)
+    assert np.allclose([o.v for o in out], M @ x)
+    assert _Counted.ops == bench._eo_flops(n, eps)
+
+
+def test_kernel_flop_counts_ordering():
+    # per unknown: the per-point metric costs more than the per-cell one, the
+    # diagonal-metric (reference-coordinate) cell term less, and the
+    # Gauss-Lobatto basis (dense face rows) more than the Hermite-like one
+    for k in (3, 4, 5, 7):
+        q, c, d = (bench.kernel_flops_per_dof(k, "hermite_like", g) for g in ("qpoint", "cell", "diag"))
+        assert d < c < q
+        assert bench.kernel_flops_per_dof(k, "nodal_gl", "qpoint") > q
+        assert bench.kernel_flops_per_dof(k, "hermite_like", "qpoint", "pjacobi") > q
