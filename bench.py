@@ -612,7 +612,7 @@ def main():
             tdt = torch.float64 if dt == "f64" else torch.float32
             vx = make_inputs(torch, o.ndofs, tdt, nrot)
             vy = [torch.empty_like(vx[0]) for _ in range(nrot)]
-            avg, mn = time_matvec(torch, o, vx, vy, launches=max(10, args.steps // 2), warmup=3)
+            avg, mn = time_matvec(torch, o, vx, vy, launches=max(10, 4 * args.steps), warmup=20)
             per_point = c.mesh.deformed
             b = alg_bytes_per_dof(c.mesh, c.degree, 8 if dt == "f64" else 4, per_point)
             gbs = b * o.ndofs / avg / 1e9

@@ -44,7 +44,8 @@ __global__ void gl_diagonal_kernel(const T* __restrict__ tab, int n, const T* __
                     for (int m = 0; m < 6; ++m) G[m] = double(cgeom[size_t(cell) * 8 + m]) * wq;
                 } else {
                     const int q = q1 + n * (q2 + n * q3);
-                    for (int m = 0; m < 6; ++m) G[m] = double(cgeom[size_t(cell) * 6 * n3 + cell_metric_offset(n, m, q)]);
+                    for (int m = 0; m < 6; ++m)
+                        G[m] = double(cgeom[size_t(cell) * 6 * n3 + cell_metric_offset(n, 16 / int(sizeof(T)), m, q)]);
                 }
                 acc += G[0] * g[0] * g[0] + G[3] * g[1] * g[1] + G[5] * g[2] * g[2] +
                        2.0 * (G[1] * g[0] * g[1] + G[2] * g[0] * g[2] + G[4] * g[1] * g[2]);

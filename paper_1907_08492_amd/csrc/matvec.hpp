@@ -712,16 +712,16 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 #pragma unroll
             for (int m = 0; m < 6; ++m) gpre[m] = p.cgeom[size_t(cell) * 8 + m];
         } else {
-            // pairs of points along z with 16-byte loads, then the last point
-            // for odd n (layout of cell_metric_offset)
+            // chunks of points along z with 16-byte loads, then the
+            // remaining points (layout of cell_metric_offset)
             const T* gq = p.cgeom + size_t(cell) * (6 * N3);
             const int tp = ta + N * tb;
-            constexpr int H = N / 2;
+            constexpr int CH = 16 / int(sizeof(T)), J = N / CH, R = N % CH;
 #pragma unroll
             for (int m = 0; m < 6; ++m) {
 #pragma unroll
-                for (int kp = 0; kp < H; ++kp) load_run<2>(gq + (m * H + kp) * 2 * N2 + 2 * tp, gpre + m * N + 2 * kp);
-                if constexpr (N % 2 == 1) gpre[m * N + N - 1] = gq[12 * H * N2 + m * N2 + tp];
+                for (int j = 0; j < J; ++j) load_run<CH>(gq + (m * J + j) * CH * N2 + CH * tp, gpre + m * N + j * CH);
+                if constexpr (R > 0) load_run<R>(gq + 6 * J * CH * N2 + m * R * N2 + R * tp, gpre + m * N + J * CH);
             }
         }
     };

@@ -98,7 +98,8 @@ __global__ void cell_geometry_kernel(MeshDev m, Rule r, T* __restrict__ out,
                 for (int b = a; b < 3; ++b)
                     G[k++] = (Ji[3 * a] * Ji[3 * b] + Ji[3 * a + 1] * Ji[3 * b + 1] + Ji[3 * a + 2] * Ji[3 * b + 2]) * det;
             if (MODE == GEOM_QPOINT) {
-                for (int k2 = 0; k2 < 6; ++k2) out[c * 6 * n3 + cell_metric_offset(n, k2, q)] = T(G[k2] * w);
+                for (int k2 = 0; k2 < 6; ++k2)
+                    out[c * 6 * n3 + cell_metric_offset(n, 16 / int(sizeof(T)), k2, q)] = T(G[k2] * w);
             } else {
                 for (int k2 = 0; k2 < 6; ++k2) out[c * 8 + k2] = T(G[k2]);
                 out[c * 8 + 6] = T(0);

@@ -80,15 +80,17 @@ __host__ __device__ constexpr int cell_geom_stride(int mode, int n) { return mod
 __host__ __device__ constexpr int face_geom_stride(int mode, int n) { return mode == GEOM_QPOINT ? 7 * n * n : 8; }
 
 // Offset, inside a cell's per-point record of 6 n^3 values, of metric
-// component m at point q = q1 + n (q2 + n q3).  The points of one (q1, q2)
-// pencil along q3 are stored in pairs next to each other, so that the thread
-// of a pencil reads them with 16-byte loads and a wavefront's load is one
-// contiguous, 16-byte aligned range per cell: first the pairs of every
-// component ([m][q3 / 2][pencil][2]), then, for odd n, the last point of
-// every pencil ([m][pencil]).
-__host__ __device__ constexpr int cell_metric_offset(int n, int m, int q) {
-    const int n2 = n * n, t = q % n2, k = q / n2, h = n / 2;
-    return k < 2 * h ? (m * h + k / 2) * 2 * n2 + 2 * t + (k & 1) : 12 * h * n2 + m * n2 + t;
+// component m at point q = q1 + n (q2 + n q3), with `chunk` = 16 / sizeof
+// (element) points per load.  The points of one (q1, q2) pencil along q3
+// are stored in chunks next to each other, so that the thread of a pencil
+// reads them with 16-byte loads and a wavefront's load is one contiguous,
+// 16-byte aligned range per cell: first the chunks of every component
+// ([m][q3 / chunk][pencil][chunk]), then the remaining points of every pencil
+// ([m][pencil][rest]).
+__host__ __device__ constexpr int cell_metric_offset(int n, int chunk, int m, int q) {
+    const int n2 = n * n, t = q % n2, k = q / n2, J = n / chunk, R = n % chunk;
+    return k < J * chunk ? (m * J + k / chunk) * chunk * n2 + chunk * t + k % chunk
+                         : 6 * J * chunk * n2 + m * R * n2 + R * t + (k - J * chunk);
 }
 
 // Offset of stored value k (0..6) at face point (qa along t1, qb along t2) of
