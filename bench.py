@@ -338,14 +338,14 @@ def solver_benchmark(torch, P, reps: int = 3):
 
 
 def serve_benchmark(P, precision: str, seconds: float, rate: float, workers: int = 8,
-                    budget_bytes: int = 96 << 30, tol: float = 1e-8):
+                    budget_bytes: int = 96 << 30, tol: float = 1e-8, server_opts=None):
     """Poisson arrivals of multigrid Poisson solves (unit cube n^3, n log-uniform
     in [8, 48], k in {3, 4, 5}, 8 random sine modes, tolerance 1e-8) served by
     the request loop; solves/s, latency percentiles and unknowns/s."""
     import threading
     from workloads import serving_requests, unit_cube
     reqs = serving_requests(rate, seconds, 0)
-    srv = P.Server(hbm_budget_bytes=budget_bytes, workers=workers, precision=precision)
+    srv = P.Server(hbm_budget_bytes=budget_bytes, workers=workers, precision=precision, **(server_opts or {}))
     tickets = []
     lock = threading.Condition()
     results = []

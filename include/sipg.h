@@ -62,13 +62,20 @@ typedef enum { SIPG_GEOM_AUTO = 0, SIPG_GEOM_CELL = 1, SIPG_GEOM_QPOINT = 2 } si
  *     Y = L X                 (L = lin, row major; all zeros means identity),
  *     x = Y + deform_amp * sin(pi Y1) sin(pi Y2) sin(pi Y3) * (1,1,1).
  * The first two steps give the affine benchmark geometry of Section 5; the
- * last one is a smooth deformation that keeps the unit cube's boundary. */
+ * last one is a smooth deformation that keeps the unit cube's boundary.
+ * A graded brick sets width (all three entries > 0; all zero means the
+ * uniform brick above): in direction d, cells 0 .. n[d]-2 have width
+ * width[d] and the last cell ends at hi[d], so its width
+ * hi[d] - lo[d] - (n[d]-1) width[d] must lie in (0, width[d]].  The
+ * multigrid hierarchy uses such bricks for its coarse levels of meshes whose
+ * cell counts are odd. */
 typedef struct {
     int32_t n[3];
     double lo[3];
     double hi[3];
     double lin[9];
     double deform_amp;
+    double width[3];
 } sipg_mesh;
 
 /*
@@ -321,7 +328,8 @@ int sipg_launch_shape(int degree, int dtype, int32_t* cells_per_block, int32_t* 
  * Geometric multigrid solver of Section 6: FP64 conjugate gradient
  * preconditioned by one V-cycle per iteration.  On every level of the brick
  * coarsened by two in each direction (while all cell counts are even and at
- * least min_coarse_cells coarse cells remain) the V-cycle smooths with a
+ * least min_coarse_cells coarse cells remain; or graded, see
+ * graded_coarsening) the V-cycle smooths with a
  * Chebyshev iteration (eq. chebyshev) around P^-1 of the form of eq. (jacobi)
  * (point Jacobi in the nodal Gauss-Lobatto basis through the basis change,
  * or the block Jacobi of Section 6.4 by fast diagonalization).  Optionally
@@ -332,7 +340,8 @@ int sipg_launch_shape(int degree, int dtype, int32_t* cells_per_block, int32_t* 
  * P^-1 A estimated by lanczos_steps conjugate-gradient (Lanczos) steps from
  * [-5.5, -4.5, ..., 5.5, -5.5, ...] (Section 6.2); the coarsest level is
  * solved by a Chebyshev iteration whose degree guarantees a residual
- * reduction of coarse_reduction.  Grid transfer: exact embedding of the
+ * reduction of coarse_reduction, or, when small, by its dense inverse
+ * (coarse_direct_max_dofs).  Grid transfer: exact embedding of the
  * coarse space and its transpose.
  *   precision 0: the V-cycle runs in FP32 (mixed precision, Section 6.2);
  *   precision 1: everything in FP64.
@@ -361,6 +370,18 @@ typedef struct {
                                     whose nodal Gauss-Lobatto values are that sequence, the same
                                     start in every basis, so that hierarchies in the Hermite-like
                                     and the nodal basis get the same estimates (Section 6.3) */
+    int32_t graded_coarsening;   /* 0 (default): the mesh is coarsened by two while every cell
+                                    count is even (the paper's 2^L bricks).  1: every direction
+                                    with more than one cell goes from n to ceil(n/2) cells, the
+                                    cells paired from lo on; for odd n the last cell stays alone,
+                                    so coarse levels are graded bricks (sipg_mesh.width) and
+                                    every mesh coarsens down to one cell */
+    int32_t coarse_direct_max_dofs; /* 0 (default): the coarsest level is solved by the Chebyshev
+                                    iteration above.  n in [1, 4096]: a coarsest level of at most
+                                    n unknowns is solved exactly instead, by a dense inverse of
+                                    its matrix formed at set-up (one launch per V-cycle); with
+                                    graded_coarsening, coarsening stops at the first level that
+                                    small */
 } sipg_mg_opts;
 typedef struct {
     int32_t levels;
@@ -368,7 +389,7 @@ typedef struct {
     int32_t precision;
     double lambda_max_fine;      /* estimated largest eigenvalue of P^-1 A, finest level */
     double lambda_min_coarse, lambda_max_coarse;
-    int32_t coarse_steps;        /* Chebyshev degree of the coarse solve */
+    int32_t coarse_steps;        /* Chebyshev degree of the coarse solve (0: dense inverse) */
     int64_t device_bytes;        /* device memory owned by the solver */
 } sipg_mg_info;
 typedef struct sipg_mg sipg_mg;
@@ -438,6 +459,10 @@ typedef struct {
                                     a reduction of 10 there (instead of the 1e5 of the
                                     plain solver) halves the solve time of the served mix
                                     for the same final residual, at 3% more CG steps */
+    int32_t graded_coarsening;   /* sipg_mg_opts.graded_coarsening of every solve (0: on the
+                                    served mix the graded levels cost more CG steps than their
+                                    cheaper coarse solves save) */
+    int32_t coarse_direct_max_dofs; /* sipg_mg_opts.coarse_direct_max_dofs of every solve (256) */
 } sipg_server_opts;
 typedef struct {
     sipg_mesh mesh;

@@ -7,7 +7,7 @@ from __future__ import annotations
 import numpy as np
 
 from . import basis as b1d
-from .mesh import map_points, cell_coords
+from .mesh import cell_bounds, cell_coords, map_points
 from .sipg import tensor_eval
 
 
@@ -85,15 +85,16 @@ def interpolate_cartesian_product(op, funcs_1d) -> np.ndarray:
     n = op.n
     pts = b1d.gauss_lobatto_points(n)      # any n distinct points
     Vb = op.basis.values(pts)               # [n, n]
-    lo = np.asarray(mesh.lo, float)
-    h = (np.asarray(mesh.hi, float) - lo) / np.asarray(mesh.n, float)
+    bounds = [cell_bounds(mesh, t) for t in range(3)]
     out = np.zeros((op.ncells, n ** 3))
     ix, iy, iz = cell_coords(mesh, np.arange(op.ncells))
     idx = [ix, iy, iz]
     for c in range(op.ncells):
         coef = []
         for t in range(3):
-            xt = lo[t] + (idx[t][c] + pts) * h[t]
+            b = bounds[t]
+            i = idx[t][c]
+            xt = b[i] + pts * (b[i + 1] - b[i])
             coef.append(np.linalg.solve(Vb, funcs_1d[t](xt)))
         out[c] = np.einsum("a,b,c->cba", coef[0], coef[1], coef[2]).ravel()
     return out.reshape(-1)

@@ -54,7 +54,7 @@ EXPORTED = [
 
 class SipgMesh(C.Structure):
     _fields_ = [("n", C.c_int32 * 3), ("lo", C.c_double * 3), ("hi", C.c_double * 3),
-                ("lin", C.c_double * 9), ("deform_amp", C.c_double)]
+                ("lin", C.c_double * 9), ("deform_amp", C.c_double), ("width", C.c_double * 3)]
 
 
 class SipgOpInfo(C.Structure):
@@ -73,7 +73,8 @@ class SipgMgOpts(C.Structure):
     _fields_ = [("smoother_degree", C.c_int32), ("lanczos_steps", C.c_int32), ("range_lo", C.c_double),
                 ("range_hi", C.c_double), ("coarse_reduction", C.c_double), ("min_coarse_cells", C.c_int32),
                 ("precision", C.c_int32), ("smoother", C.c_int32), ("p_coarsening", C.c_int32),
-                ("fused_smoother", C.c_int32), ("lanczos_start", C.c_int32)]
+                ("fused_smoother", C.c_int32), ("lanczos_start", C.c_int32), ("graded_coarsening", C.c_int32),
+                ("coarse_direct_max_dofs", C.c_int32)]
 
 
 class SipgMgInfo(C.Structure):
@@ -84,7 +85,8 @@ class SipgMgInfo(C.Structure):
 
 class SipgServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("workers", C.c_int32), ("precision", C.c_int32),
-                ("smoother", C.c_int32), ("p_coarsening", C.c_int32), ("coarse_reduction", C.c_double)]
+                ("smoother", C.c_int32), ("p_coarsening", C.c_int32), ("coarse_reduction", C.c_double),
+                ("graded_coarsening", C.c_int32), ("coarse_direct_max_dofs", C.c_int32)]
 
 
 class SipgRequest(C.Structure):
@@ -229,7 +231,8 @@ def host_block_order(nblocks: int, layer_blocks: int) -> np.ndarray:
 
 
 def make_mesh(mesh) -> SipgMesh:
-    """Convert any object with n, lo, hi, lin, deform_amp attributes."""
+    """Convert any object with n, lo, hi, lin, deform_amp (and optionally
+    width, for a graded brick) attributes."""
     m = SipgMesh()
     for d in range(3):
         m.n[d] = int(mesh.n[d])
@@ -241,6 +244,10 @@ def make_mesh(mesh) -> SipgMesh:
         for i in range(9):
             m.lin[i] = float(flat[i])
     m.deform_amp = float(getattr(mesh, "deform_amp", 0.0))
+    width = getattr(mesh, "width", None)
+    if width is not None:
+        for d in range(3):
+            m.width[d] = float(width[d])
     return m
 
 
@@ -560,13 +567,14 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 8, precision: str = "mixed",
                  smoother: str = "fdm", p_coarsening: int = 1, coarse_reduction: float = 10.0,
-                 allocator="torch"):
+                 allocator="torch", graded_coarsening: int = 0, coarse_direct_max_dofs: int = 256):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Server needs a GPU (HIP device)")
         torch.cuda.init()
         o = SipgServerOpts(int(hbm_budget_bytes), int(workers), {"mixed": 0, "f64": 1}[precision],
-                           SMOOTHERS[smoother], int(p_coarsening), float(coarse_reduction))
+                           SMOOTHERS[smoother], int(p_coarsening), float(coarse_reduction),
+                           int(graded_coarsening), int(coarse_direct_max_dofs))
         h = _vp()
         _check(lib.sipg_server_create(C.byref(o), _allocator(allocator), C.byref(h)), "sipg_server_create")
         self._h = h

@@ -268,6 +268,16 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
         if (mesh->n[d] <= 0) { set_error("sipg_setup: cell counts must be positive"); return SIPG_E_ARG; }
         if (!(mesh->hi[d] > mesh->lo[d])) { set_error("sipg_setup: need hi > lo in every direction"); return SIPG_E_ARG; }
     }
+    const bool graded = mesh->width[0] != 0.0 || mesh->width[1] != 0.0 || mesh->width[2] != 0.0;
+    if (graded) {
+        for (int d = 0; d < 3; ++d) {
+            const double w = mesh->width[d], last = mesh->hi[d] - mesh->lo[d] - (mesh->n[d] - 1) * w;
+            if (!(w > 0.0) || !std::isfinite(w) || !(last > 0.0) || last > w * (1.0 + 1e-12)) {
+                set_error("sipg_setup: graded brick needs width > 0 and a last cell of width in (0, width]");
+                return SIPG_E_ARG;
+            }
+        }
+    }
     const int64_t ncells = int64_t(mesh->n[0]) * mesh->n[1] * mesh->n[2];
     const int n = degree + 1;
     if (ncells * n * n * n > (int64_t(1) << 31) - 1 || ncells > (int64_t(1) << 30)) {
@@ -305,7 +315,8 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
     for (int d = 0; d < 3; ++d) {
         m.n[d] = mesh->n[d];
         m.lo[d] = mesh->lo[d];
-        m.h[d] = (mesh->hi[d] - mesh->lo[d]) / mesh->n[d];
+        m.h[d] = graded ? mesh->width[d] : (mesh->hi[d] - mesh->lo[d]) / mesh->n[d];
+        m.hl[d] = graded ? mesh->hi[d] - mesh->lo[d] - (mesh->n[d] - 1) * mesh->width[d] : m.h[d];
     }
     for (int i = 0; i < 9; ++i) m.L[i] = lin_zero ? (i % 4 == 0 ? 1.0 : 0.0) : mesh->lin[i];
     m.a = mesh->deform_amp;

@@ -279,22 +279,24 @@ bool build_tables(int kind, int p, Tables1D& t) {
     return invert(n, t.E, t.T);
 }
 
-bool child_embedding(int kind, int p, std::vector<double>& M0, std::vector<double>& M1) {
+bool child_embedding(int kind, int p, double a, std::vector<double>& M0, std::vector<double>& M1) {
     const int n = p + 1;
     const std::vector<ProductPoly> f = make_basis(kind, p);
     const std::vector<double> x = gauss_lobatto_points(n);   // n distinct points
-    // V[m][i] = phi_i(x_m); C_s[m][j] = phi_j((s + x_m)/2); M_s = V^-1 C_s
+    // V[m][i] = phi_i(x_m); C_s[m][j] = phi_j(o_s + l_s x_m) with child 0 on
+    // [0, a] and child 1 on [a, 1]; M_s = V^-1 C_s
     std::vector<double> V(n * n), Vi;
     for (int m = 0; m < n; ++m)
         for (int i = 0; i < n; ++i) V[m * n + i] = f[i].value(x[m]);
     if (!invert(n, V, Vi)) return false;
     for (int s = 0; s < 2; ++s) {
+        const double o = s == 0 ? 0.0 : a, l = s == 0 ? a : 1.0 - a;
         std::vector<double>& M = s == 0 ? M0 : M1;
         M.assign(n * n, 0.0);
         for (int i = 0; i < n; ++i)
             for (int j = 0; j < n; ++j) {
                 double acc = 0.0;
-                for (int m = 0; m < n; ++m) acc += Vi[i * n + m] * f[j].value(0.5 * (s + x[m]));
+                for (int m = 0; m < n; ++m) acc += Vi[i * n + m] * f[j].value(o + l * x[m]);
                 M[i * n + j] = acc;
             }
     }

@@ -40,10 +40,11 @@ struct Tables1D {
 };
 bool build_tables(int kind, int p, Tables1D& t);
 
-// Embedding of the coarse 1D space into the two halves of a coarse interval:
-// phi_j((s + xi) / 2) = sum_i M_s[i][j] phi_i(xi) for child side s = 0, 1
-// (row major, n x n).  Exact: both sides are polynomials of degree p.
-bool child_embedding(int kind, int p, std::vector<double>& M0, std::vector<double>& M1);
+// Embedding of the coarse 1D space into the two children [0, a] and [a, 1]
+// of a coarse interval: phi_j(a xi) = sum_i M_0[i][j] phi_i(xi) and
+// phi_j(a + (1 - a) xi) = sum_i M_1[i][j] phi_i(xi) (row major, n x n; a = 1/2
+// for two halves).  Exact: both sides are polynomials of degree p.
+bool child_embedding(int kind, int p, double a, std::vector<double>& M0, std::vector<double>& M1);
 
 // Embedding of the degree-pc space into the degree-pf space (pc <= pf) of
 // the same basis kind on one interval: phi^pc_j = sum_i E[i][j] phi^pf_i

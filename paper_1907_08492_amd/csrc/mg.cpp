@@ -93,22 +93,29 @@ struct Level {
     int steps = 0;                      // Lanczos steps of its eigenvalue estimate
     std::vector<double> key;            // what defines the level operator (eigenvalue cache)
     std::vector<double> sigma, theta;   // Chebyshev coefficients per step
+    bool direct = false;                // coarsest level solved by its dense inverse
+    DevBuf<T> ainv;                     // that inverse (n x n)
     int64_t ncells() const { return int64_t(nc[0]) * nc[1] * nc[2]; }
     ~Level() { if (op) sipg_destroy(op); }
 };
 
 // Level sequence of the hierarchy: first the degree is lowered on the fine
 // mesh (p_coarsening 1: k -> max(1, k/2); 2: k -> k-1), then the brick is
-// coarsened by two while every cell count is even and at least
-// min_coarse_cells coarse cells remain (at most 16 levels).
+// coarsened while at least min_coarse_cells coarse cells remain (at most 16
+// levels): by two while every cell count is even, or with graded_coarsening
+// from n to ceil(n/2) cells in every direction with n > 1 (fine cells paired
+// from lo on, the last one alone for odd n: a graded brick of twice the
+// regular width).  With coarse_direct_max_dofs, coarsening stops at the
+// first level of at most that many unknowns.
 struct LevelSpec {
     int nc[3];
+    double width[3];   // sipg_mesh.width of the level (all zero: uniform brick)
     int degree;
     int next;
 };
-std::vector<LevelSpec> mg_level_sequence(const int n[3], int degree, const sipg_mg_opts& o) {
+std::vector<LevelSpec> mg_level_sequence(const sipg_mesh& mesh, int degree, const sipg_mg_opts& o) {
     std::vector<LevelSpec> seq;
-    LevelSpec cur{{n[0], n[1], n[2]}, degree, 0};
+    LevelSpec cur{{mesh.n[0], mesh.n[1], mesh.n[2]}, {mesh.width[0], mesh.width[1], mesh.width[2]}, degree, 0};
     for (;;) {
         seq.push_back(cur);
         if (seq.size() >= 16) break;
@@ -117,13 +124,78 @@ std::vector<LevelSpec> mg_level_sequence(const int n[3], int degree, const sipg_
             cur.degree = o.p_coarsening == 1 ? std::max(1, cur.degree / 2) : cur.degree - 1;
             continue;
         }
-        const bool can = cur.nc[0] % 2 == 0 && cur.nc[1] % 2 == 0 && cur.nc[2] % 2 == 0 &&
-                         int64_t(cur.nc[0] / 2) * (cur.nc[1] / 2) * (cur.nc[2] / 2) >= o.min_coarse_cells;
-        if (!can) break;
+        const int64_t np = cur.degree + 1;
+        if (o.coarse_direct_max_dofs > 0 &&
+            int64_t(cur.nc[0]) * cur.nc[1] * cur.nc[2] * np * np * np <= o.coarse_direct_max_dofs)
+            break;
+        const bool even = cur.nc[0] % 2 == 0 && cur.nc[1] % 2 == 0 && cur.nc[2] % 2 == 0;
+        const bool uniform = cur.width[0] == 0.0 && cur.width[1] == 0.0 && cur.width[2] == 0.0;
+        int nn[3];
+        if (o.graded_coarsening) {
+            for (int d = 0; d < 3; ++d) nn[d] = (cur.nc[d] + 1) / 2;
+        } else {
+            if (!even) break;
+            for (int d = 0; d < 3; ++d) nn[d] = cur.nc[d] / 2;
+        }
+        const int64_t cells = int64_t(cur.nc[0]) * cur.nc[1] * cur.nc[2];
+        if (cells == 1 || int64_t(nn[0]) * nn[1] * nn[2] < o.min_coarse_cells) break;
         seq.back().next = 0;
-        for (int d = 0; d < 3; ++d) cur.nc[d] /= 2;
+        // an even uniform brick coarsens to a uniform one (the paper's case);
+        // otherwise every regular width doubles where cells are paired
+        if (!(uniform && even)) {
+            for (int d = 0; d < 3; ++d) {
+                const double w = uniform ? (mesh.hi[d] - mesh.lo[d]) / cur.nc[d] : cur.width[d];
+                cur.width[d] = cur.nc[d] > 1 ? 2.0 * w : w;
+            }
+        }
+        for (int d = 0; d < 3; ++d) cur.nc[d] = nn[d];
     }
     return seq;
+}
+
+// Regular and last cell widths of a level in every direction.
+static void level_widths(const sipg_mesh& mesh, const LevelSpec& sp, double w[3], double last[3]) {
+    const bool uniform = sp.width[0] == 0.0 && sp.width[1] == 0.0 && sp.width[2] == 0.0;
+    for (int d = 0; d < 3; ++d) {
+        w[d] = uniform ? (mesh.hi[d] - mesh.lo[d]) / sp.nc[d] : sp.width[d];
+        last[d] = uniform ? w[d] : mesh.hi[d] - mesh.lo[d] - (sp.nc[d] - 1) * sp.width[d];
+    }
+}
+
+// Inverse of the symmetric positive definite n x n matrix a (row major), in
+// place, through its Cholesky factor a = L L^T; false when a is not positive
+// definite.
+static bool spd_inverse(int n, std::vector<double>& a) {
+    for (int j = 0; j < n; ++j) {
+        double d = a[size_t(j) * n + j];
+        for (int k = 0; k < j; ++k) d -= a[size_t(j) * n + k] * a[size_t(j) * n + k];
+        if (!(d > 0.0) || !std::isfinite(d)) return false;
+        d = std::sqrt(d);
+        a[size_t(j) * n + j] = d;
+        for (int i = j + 1; i < n; ++i) {
+            double s = a[size_t(i) * n + j];
+            for (int k = 0; k < j; ++k) s -= a[size_t(i) * n + k] * a[size_t(j) * n + k];
+            a[size_t(i) * n + j] = s / d;
+        }
+    }
+    std::vector<double> inv(size_t(n) * n), y(n);
+    for (int c = 0; c < n; ++c) {
+        // L y = e_c (y_i = 0 for i < c), then L^T x = y
+        for (int i = 0; i < c; ++i) y[i] = 0.0;
+        for (int i = c; i < n; ++i) {
+            double s = i == c ? 1.0 : 0.0;
+            for (int k = c; k < i; ++k) s -= a[size_t(i) * n + k] * y[k];
+            y[i] = s / a[size_t(i) * n + i];
+        }
+        for (int i = n - 1; i >= 0; --i) {
+            double s = y[i];
+            for (int k = i + 1; k < n; ++k) s -= a[size_t(k) * n + i] * y[k];
+            y[i] = s / a[size_t(i) * n + i];
+        }
+        for (int i = 0; i < n; ++i) inv[size_t(i) * n + c] = y[i];
+    }
+    a.swap(inv);
+    return true;
 }
 
 // Lanczos steps are bounded so that their coefficients fit the scratch.
@@ -229,7 +301,9 @@ struct Hierarchy {
     int vcycle(int l, hipStream_t st) {
         Level<T>& L = *lv[l];
         int rc;
-        if (l + 1 == int(lv.size())) return smooth(l, true, coarse_steps, L.sigma, L.theta, st);
+        if (l + 1 == int(lv.size()))
+            return L.direct ? vec_dense_mv<T>(L.ainv.p, L.b.p, L.u.p, int(L.n), st)
+                            : smooth(l, true, coarse_steps, L.sigma, L.theta, st);
         if ((rc = smooth(l, true, smooth_steps, L.sigma, L.theta, st)) != SIPG_OK) return rc;
         if ((rc = launch_matvec(L.op, L.u.p, L.r.p, st)) != SIPG_OK) return rc;
         if ((rc = vec_sub<T>(L.b.p, L.r.p, L.r.p, L.n, st)) != SIPG_OK) return rc;
@@ -358,11 +432,15 @@ int64_t mg_estimate_bytes(const sipg_mesh& mesh, int degree, const sipg_mg_opts&
     const int n0 = degree + 1;
     const int64_t cells0 = int64_t(mesh.n[0]) * mesh.n[1] * mesh.n[2];
     int64_t bytes = 8 * (geo(n0) * cells0 + 6 * cells0 * n0 * n0 * n0) + (int64_t(1) << 20);
-    for (const LevelSpec& sp : mg_level_sequence(mesh.n, degree, o)) {
+    const std::vector<LevelSpec> seq = mg_level_sequence(mesh, degree, o);
+    for (const LevelSpec& sp : seq) {
         const int n = sp.degree + 1;
         const int64_t cells = int64_t(sp.nc[0]) * sp.nc[1] * sp.nc[2];
         bytes += esz * (geo(n) * cells + 6 * cells * n * n * n) + 4096 * 8;
     }
+    const LevelSpec& c = seq.back();
+    const int64_t nc = int64_t(c.nc[0]) * c.nc[1] * c.nc[2] * (c.degree + 1) * (c.degree + 1) * (c.degree + 1);
+    if (nc <= o.coarse_direct_max_dofs) bytes += esz * nc * nc;
     return bytes;
 }
 
@@ -382,7 +460,7 @@ static std::map<std::vector<double>, std::pair<double, double>> g_lambda;
 static std::vector<double> level_key(const sipg_mesh& m, int degree, double penalty, int basis, int dtype,
                                      int pmode, int steps, int start) {
     std::vector<double> k = {double(m.n[0]), double(m.n[1]), double(m.n[2])};
-    for (int d = 0; d < 3; ++d) { k.push_back(m.lo[d]); k.push_back(m.hi[d]); }
+    for (int d = 0; d < 3; ++d) { k.push_back(m.lo[d]); k.push_back(m.hi[d]); k.push_back(m.width[d]); }
     for (int i = 0; i < 9; ++i) k.push_back(m.lin[i]);
     k.insert(k.end(), {m.deform_amp, double(degree), penalty, double(basis), double(dtype), double(pmode),
                        double(steps), double(start)});
@@ -397,13 +475,13 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
     H.pmode = o.smoother == 1 ? SIPG_BC_FDM : SIPG_BC_PJACOBI;
     H.fused = o.fused_smoother != 0;
     H.lanczos_start = o.lanczos_start;
-    const std::vector<LevelSpec> seq = mg_level_sequence(mesh->n, degree, o);
+    const std::vector<LevelSpec> seq = mg_level_sequence(*mesh, degree, o);
     int rc;
     for (size_t l = 0; l < seq.size(); ++l) {
         const LevelSpec& sp = seq[l];
         auto L = std::make_unique<Level<T>>();
         sipg_mesh m = *mesh;
-        for (int d = 0; d < 3; ++d) { m.n[d] = sp.nc[d]; L->nc[d] = sp.nc[d]; }
+        for (int d = 0; d < 3; ++d) { m.n[d] = sp.nc[d]; m.width[d] = sp.width[d]; L->nc[d] = sp.nc[d]; }
         L->np = sp.degree + 1;
         L->next = sp.next;
         {
@@ -426,11 +504,28 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
         if (l + 1 < seq.size()) {
             std::vector<T> e;
             if (sp.next == 0) {
+                // two halves, then per direction the children of the last
+                // coarse cell: the last two fine cells (unequal on a graded
+                // brick) or, for an odd count, the last fine cell alone
                 std::vector<double> M0, M1;
-                if (!child_embedding(basis, sp.degree, M0, M1)) { set_error("multigrid: singular embedding"); return SIPG_E_ARG; }
+                if (!child_embedding(basis, sp.degree, 0.5, M0, M1)) { set_error("multigrid: singular embedding"); return SIPG_E_ARG; }
                 const int nn = L->np * L->np;
-                e.resize(2 * nn);
+                e.assign(8 * nn, T(0));
                 for (int i = 0; i < nn; ++i) { e[i] = T(M0[i]); e[nn + i] = T(M1[i]); }
+                double w[3], last[3];
+                level_widths(*mesh, sp, w, last);
+                for (int d = 0; d < 3; ++d) {
+                    T* dst = e.data() + (2 + 2 * d) * nn;
+                    if (sp.nc[d] % 2 == 1) {
+                        for (int i = 0; i < L->np; ++i) dst[i * L->np + i] = T(1);
+                        continue;
+                    }
+                    if (!child_embedding(basis, sp.degree, w[d] / (w[d] + last[d]), M0, M1)) {
+                        set_error("multigrid: singular embedding");
+                        return SIPG_E_ARG;
+                    }
+                    for (int i = 0; i < nn; ++i) { dst[i] = T(M0[i]); dst[nn + i] = T(M1[i]); }
+                }
             } else {
                 std::vector<double> E;
                 const int nf = L->np, ncd = seq[l + 1].degree + 1;
@@ -451,10 +546,58 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
         }
         H.lv.push_back(std::move(L));
     }
+    // a small coarsest level: its matrix, column by column (A e_i with the
+    // FP64 operator of the level), inverted on the host
+    {
+        Level<T>& C = *H.lv.back();
+        const LevelSpec& sp = seq.back();
+        if (C.n <= o.coarse_direct_max_dofs) {
+            const int n = int(C.n);
+            sipg_mesh m = *mesh;
+            for (int d = 0; d < 3; ++d) { m.n[d] = sp.nc[d]; m.width[d] = sp.width[d]; }
+            sipg_op* op64 = nullptr;
+            if ((rc = sipg_setup(&m, sp.degree, penalty, basis, SIPG_F64, SIPG_GEOM_AUTO, &mg->user_alloc, st, &op64)) != SIPG_OK)
+                return rc;
+            std::unique_ptr<sipg_op, int (*)(sipg_op*)> own(op64, sipg_destroy);
+            // columns e_i and A e_i at a 32-byte aligned stride
+            const size_t ld = (size_t(n) + 3) & ~size_t(3);
+            DevBuf<double> X, Y;
+            if ((rc = X.alloc(int64_t(ld) * n, mg->mem)) || (rc = Y.alloc(int64_t(ld) * n, mg->mem))) return rc;
+            std::vector<double> a(ld * n, 0.0);
+            for (int i = 0; i < n; ++i) a[size_t(i) * ld + i] = 1.0;
+            SIPG_HIP(hipMemcpyAsync(X.p, a.data(), sizeof(double) * a.size(), hipMemcpyHostToDevice, st));
+            for (int i = 0; i < n; ++i)
+                if ((rc = launch_matvec(op64, X.p + size_t(i) * ld, Y.p + size_t(i) * ld, st)) != SIPG_OK) return rc;
+            SIPG_HIP(hipMemcpyAsync(a.data(), Y.p, sizeof(double) * a.size(), hipMemcpyDeviceToHost, st));
+            SIPG_HIP(hipStreamSynchronize(st));
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < n; ++j) a[size_t(i) * n + j] = a[size_t(i) * ld + j];   // close the stride
+            a.resize(size_t(n) * n);
+            // row i holds A e_i; A is symmetric: average out the rounding
+            for (int i = 0; i < n; ++i)
+                for (int j = 0; j < i; ++j) {
+                    const double s = 0.5 * (a[size_t(i) * n + j] + a[size_t(j) * n + i]);
+                    a[size_t(i) * n + j] = a[size_t(j) * n + i] = s;
+                }
+            if (!spd_inverse(n, a)) { set_error("multigrid: coarse matrix not positive definite"); return SIPG_E_NOCONV; }
+            std::vector<T> at(a.size());
+            for (size_t i = 0; i < a.size(); ++i) at[i] = T(a[i]);
+            if ((rc = C.ainv.alloc(int64_t(n) * n, mg->mem)) != SIPG_OK) return rc;
+            SIPG_HIP(hipMemcpyAsync(C.ainv.p, at.data(), sizeof(T) * at.size(), hipMemcpyHostToDevice, st));
+            SIPG_HIP(hipStreamSynchronize(st));
+            C.direct = true;
+        }
+    }
     // eigenvalue estimates and Chebyshev coefficients
     for (size_t l = 0; l < H.lv.size(); ++l) {
         const bool coarsest = l + 1 == H.lv.size();
         Level<T>& L = *H.lv[l];
+        if (coarsest && L.direct) {
+            H.coarse_steps = 0;
+            mg->lmin_coarse = mg->lmax_coarse = 0.0;
+            mg->coarse_steps = 0;
+            continue;
+        }
         bool known = false;
         {
             std::lock_guard<std::mutex> g(g_lambda_mu);
@@ -488,7 +631,7 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
     mg->lmax0 = H.lv[0]->lmax;
     mg->levels = int(H.lv.size());
     int64_t bytes = mg->fine64 ? mg->fine64->device_bytes : 0;
-    for (auto& L : H.lv) bytes += L->op->device_bytes + int64_t(5 * sizeof(T)) * L->n;
+    for (auto& L : H.lv) bytes += L->op->device_bytes + int64_t(5 * sizeof(T)) * L->n + (L->direct ? int64_t(sizeof(T)) * L->n * L->n : 0);
     mg->device_bytes = bytes + int64_t(sizeof(double)) * (kVecPartials + 8 + 2 * kMaxLanczos + 5 * mg->ndofs);
     return SIPG_OK;
 }
@@ -508,6 +651,8 @@ int sipg_mg_default_opts(sipg_mg_opts* o) {
     o->p_coarsening = 0;
     o->fused_smoother = 1;
     o->lanczos_start = 0;
+    o->graded_coarsening = 0;
+    o->coarse_direct_max_dofs = 0;
     return SIPG_OK;
 }
 
@@ -522,7 +667,9 @@ int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, 
     if (o.smoother_degree < 1 || o.smoother_degree > 64 || o.lanczos_steps < 2 || o.lanczos_steps > kMaxLanczos || !(o.range_lo > 0.0) ||
         !(o.range_hi > o.range_lo) || !(o.coarse_reduction > 1.0) || (o.precision != 0 && o.precision != 1) ||
         o.min_coarse_cells < 1 || (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2 ||
-        (o.fused_smoother != 0 && o.fused_smoother != 1) || (o.lanczos_start != 0 && o.lanczos_start != 1)) {
+        (o.fused_smoother != 0 && o.fused_smoother != 1) || (o.lanczos_start != 0 && o.lanczos_start != 1) ||
+        (o.graded_coarsening != 0 && o.graded_coarsening != 1) || o.coarse_direct_max_dofs < 0 ||
+        o.coarse_direct_max_dofs > 4096) {
         set_error("sipg_mg_setup: invalid options");
         return SIPG_E_ARG;
     }

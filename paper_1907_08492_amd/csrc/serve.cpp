@@ -35,7 +35,7 @@ namespace {
 
 struct Key {
     int32_t n[3];
-    double lo[3], hi[3], lin[9], a;
+    double lo[3], hi[3], width[3], lin[9], a;
     int degree, basis, precision;
     double penalty;
     bool operator<(const Key& o) const { return std::memcmp(this, &o, sizeof(Key)) < 0; }
@@ -87,7 +87,12 @@ namespace sipg {
 static Key make_key(const sipg_request& r, int precision) {
     Key k;
     std::memset(&k, 0, sizeof(k));
-    for (int d = 0; d < 3; ++d) { k.n[d] = r.mesh.n[d]; k.lo[d] = r.mesh.lo[d]; k.hi[d] = r.mesh.hi[d]; }
+    for (int d = 0; d < 3; ++d) {
+        k.n[d] = r.mesh.n[d];
+        k.lo[d] = r.mesh.lo[d];
+        k.hi[d] = r.mesh.hi[d];
+        k.width[d] = r.mesh.width[d];
+    }
     for (int i = 0; i < 9; ++i) k.lin[i] = r.mesh.lin[i];
     k.a = r.mesh.deform_amp;
     k.degree = r.degree;
@@ -105,6 +110,8 @@ static sipg_mg_opts solver_opts(const sipg_server_opts& so) {
     o.smoother = so.smoother;
     o.p_coarsening = so.p_coarsening;
     o.coarse_reduction = so.coarse_reduction;
+    o.graded_coarsening = so.graded_coarsening;
+    o.coarse_direct_max_dofs = so.coarse_direct_max_dofs;
     return o;
 }
 
@@ -295,6 +302,8 @@ int sipg_server_default_opts(sipg_server_opts* o) {
     o->smoother = 1;
     o->p_coarsening = 1;
     o->coarse_reduction = 10.0;
+    o->graded_coarsening = 0;
+    o->coarse_direct_max_dofs = 256;
     return SIPG_OK;
 }
 
@@ -307,7 +316,8 @@ int sipg_server_create(const sipg_server_opts* opts, const sipg_allocator* alloc
     if (opts) o = *opts;
     if (o.workers < 1 || o.workers > 16 || o.hbm_budget_bytes <= 0 || (o.precision != 0 && o.precision != 1) ||
         (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2 ||
-        !(o.coarse_reduction > 1.0)) {
+        !(o.coarse_reduction > 1.0) || (o.graded_coarsening != 0 && o.graded_coarsening != 1) ||
+        o.coarse_direct_max_dofs < 0 || o.coarse_direct_max_dofs > 4096) {
         set_error("sipg_server_create: workers in [1,16], budget > 0, precision and smoother 0 or 1, p_coarsening 0..2, "
                   "coarse_reduction > 1");
         return SIPG_E_ARG;

@@ -9,15 +9,26 @@
 
 namespace sipg {
 
+// Brick point X of cell (ix, iy, iz) at reference point xi, and the cell's
+// widths w.
+__device__ void brick_point(const MeshDev& m, const int i[3], const double xi[3], double X[3], double w[3]) {
+    for (int d = 0; d < 3; ++d) {
+        w[d] = i[d] == m.n[d] - 1 ? m.hl[d] : m.h[d];
+        X[d] = m.lo[d] + i[d] * m.h[d] + xi[d] * w[d];
+    }
+}
+
 // J[a][b] = dx_a / dxi_b of the map of cell (ix, iy, iz) at reference point xi.
 __device__ void map_jacobian(const MeshDev& m, int ix, int iy, int iz, double x0, double x1,
                              double x2, double J[9]) {
-    const double X[3] = {m.lo[0] + (ix + x0) * m.h[0], m.lo[1] + (iy + x1) * m.h[1],
-                         m.lo[2] + (iz + x2) * m.h[2]};
+    const int ci[3] = {ix, iy, iz};
+    const double xi[3] = {x0, x1, x2};
+    double X[3], w[3];
+    brick_point(m, ci, xi, X, w);
     double LH[9], Y[3];
     for (int i = 0; i < 3; ++i) {
         Y[i] = m.L[3 * i] * X[0] + m.L[3 * i + 1] * X[1] + m.L[3 * i + 2] * X[2];
-        for (int j = 0; j < 3; ++j) LH[3 * i + j] = m.L[3 * i + j] * m.h[j];
+        for (int j = 0; j < 3; ++j) LH[3 * i + j] = m.L[3 * i + j] * w[j];
     }
     if (m.a == 0.0) {
         for (int i = 0; i < 9; ++i) J[i] = LH[i];
@@ -28,7 +39,7 @@ __device__ void map_jacobian(const MeshDev& m, int ix, int iy, int iz, double x0
     for (int i = 0; i < 3; ++i) sincos(pi * Y[i], &sn[i], &cs[i]);
     const double gs[3] = {pi * cs[0] * sn[1] * sn[2], pi * sn[0] * cs[1] * sn[2],
                           pi * sn[0] * sn[1] * cs[2]};
-    // J = (I + a (1,1,1) grad s^T) L diag(h)
+    // J = (I + a (1,1,1) grad s^T) L diag(w)
     double t[3];
     for (int j = 0; j < 3; ++j) t[j] = gs[0] * LH[j] + gs[1] * LH[3 + j] + gs[2] * LH[6 + j];
     for (int i = 0; i < 3; ++i)
@@ -38,8 +49,10 @@ __device__ void map_jacobian(const MeshDev& m, int ix, int iy, int iz, double x0
 // Physical point of cell (ix, iy, iz) at reference point xi (same map).
 __device__ void map_point(const MeshDev& m, int ix, int iy, int iz, double x0, double x1, double x2,
                           double x[3]) {
-    const double X[3] = {m.lo[0] + (ix + x0) * m.h[0], m.lo[1] + (iy + x1) * m.h[1],
-                         m.lo[2] + (iz + x2) * m.h[2]};
+    const int ci[3] = {ix, iy, iz};
+    const double xi[3] = {x0, x1, x2};
+    double X[3], w[3];
+    brick_point(m, ci, xi, X, w);
     double Y[3];
     for (int i = 0; i < 3; ++i) Y[i] = m.L[3 * i] * X[0] + m.L[3 * i + 1] * X[1] + m.L[3 * i + 2] * X[2];
     double s = 0.0;

@@ -138,10 +138,12 @@ struct DevAlloc {
 // neither (neither: hipMalloc / hipFree).
 inline bool allocator_valid(const sipg_allocator* a) { return !a || (a->alloc != nullptr) == (a->free != nullptr); }
 
-// Mesh description in the form the device kernels take it.
+// Mesh description in the form the device kernels take it: in direction d
+// cell i spans [lo + i h, lo + i h + w] with w = h, except the last cell,
+// whose width is hl (hl = h on a uniform brick).
 struct MeshDev {
     int n[3];
-    double lo[3], h[3];
+    double lo[3], h[3], hl[3];
     double L[9];
     double a;
 };

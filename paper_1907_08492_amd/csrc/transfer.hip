@@ -1,11 +1,17 @@
-// Geometric multigrid transfer between a brick of cells and its coarsening
-// by two in every direction.  The coarse and fine maps differ by an affine
-// map per child, so the coarse space is a subspace of the fine one and the
-// prolongation is the exact embedding: on child (s1,s2,s3) the fine
+// Geometric multigrid transfer between a brick of cells and its coarsening:
+// in every direction the fine cells are paired from the low end on, coarse
+// cell i owning fine cells 2i and 2i+1; for an odd fine count the last coarse
+// cell owns only the last fine cell.  The coarse and fine maps differ by an
+// affine map per child, so the coarse space is a subspace of the fine one and
+// the prolongation is the exact embedding: on child (s1,s2,s3) the fine
 // coefficients are (M_s3 x M_s2 x M_s1) times the coarse ones, with the 1D
-// matrices M_0, M_1 of the two halves of the coarse interval.  Restriction is
-// the transpose.  One workgroup per coarse cell, one thread per pencil; the
-// 1D contractions are shared between children with the same sides.
+// matrices M_s of the child intervals within the coarse interval.  The
+// matrices (emb, N x N each, row major): M_0, M_1 of the two halves, then for
+// each direction d the pair of the last coarse cell of that direction (its
+// children may be unequal on a graded brick; with one child the first matrix
+// is the identity).  Restriction is the transpose.  One workgroup per coarse
+// cell, one thread per pencil; the 1D contractions are shared between
+// children with the same sides.
 #include "sipg_common.hpp"
 #include "vecops.hpp"
 
@@ -30,19 +36,30 @@ __device__ __forceinline__ void mat1d(const T* __restrict__ M, const T* in, T* o
     }
 }
 
+// Children and embedding matrices of coarse cell index i in direction d.
+struct ChildMap {
+    int nf[3], nc[3], nl[3];   // fine and coarse counts, children of the last coarse cell
+    __device__ int children(int d, int i) const { return i == nc[d] - 1 ? nl[d] : 2; }
+    template <int N, typename T>
+    __device__ const T* matrix(const T* emb, int d, int i, int s) const {
+        return emb + (i == nc[d] - 1 ? 2 + 2 * d + s : s) * (N * N);
+    }
+};
+
 template <int N, typename T>
 __global__ void __launch_bounds__(TrShape<N>::NT)
-prolongate_kernel(const T* __restrict__ coarse, T* __restrict__ fine, const T* __restrict__ emb, int fx, int fy, int fz) {
+prolongate_kernel(const T* __restrict__ coarse, T* __restrict__ fine, const T* __restrict__ emb, ChildMap cm) {
     using S = TrShape<N>;
-    constexpr int N2 = S::N2, N3 = S::N3;
+    constexpr int N3 = S::N3;
     __shared__ T C[N3];
     __shared__ T Z[2][N3];
     __shared__ T Y[4][N3];
-    const int cx = fx / 2, cy = fy / 2;
+    const int cx = cm.nc[0], cy = cm.nc[1];
     const int cc = blockIdx.x;
     const int ix = cc % cx, iy = (cc / cx) % cy, iz = cc / (cx * cy);
+    const int n1 = cm.children(0, ix), n2 = cm.children(1, iy), n3 = cm.children(2, iz);
     const int tid = threadIdx.x;
-    const bool act = tid < N2;
+    const bool act = tid < S::N2;
     const int ta = tid % N, tb = tid / N;
     for (int e = tid; e < N3; e += S::NT) C[e] = coarse[size_t(cc) * N3 + e];
     __syncthreads();
@@ -50,38 +67,35 @@ prolongate_kernel(const T* __restrict__ coarse, T* __restrict__ fine, const T* _
     if (act) {   // z: thread (j1, j2)
 #pragma unroll
         for (int k = 0; k < N; ++k) v[k] = C[S::idx(ta, tb, k)];
-#pragma unroll
-        for (int s3 = 0; s3 < 2; ++s3) {
-            mat1d<N, false>(emb + s3 * N2, v, r);
+        for (int s3 = 0; s3 < n3; ++s3) {
+            mat1d<N, false>(cm.matrix<N>(emb, 2, iz, s3), v, r);
 #pragma unroll
             for (int k = 0; k < N; ++k) Z[s3][S::idx(ta, tb, k)] = r[k];
         }
     }
     __syncthreads();
     if (act) {   // y: thread (j1, i3)
-#pragma unroll
-        for (int s3 = 0; s3 < 2; ++s3) {
+        for (int s3 = 0; s3 < n3; ++s3) {
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] = Z[s3][S::idx(ta, k, tb)];
-#pragma unroll
-            for (int s2 = 0; s2 < 2; ++s2) {
-                mat1d<N, false>(emb + s2 * N2, v, r);
+            for (int s2 = 0; s2 < n2; ++s2) {
+                mat1d<N, false>(cm.matrix<N>(emb, 1, iy, s2), v, r);
 #pragma unroll
                 for (int k = 0; k < N; ++k) Y[s2 + 2 * s3][S::idx(ta, k, tb)] = r[k];
             }
         }
     }
     __syncthreads();
-    if (act) {   // x: thread (i2, i3), add into the 8 children
-#pragma unroll
+    if (act) {   // x: thread (i2, i3), add into the children
         for (int q = 0; q < 4; ++q) {
             const int s2 = q & 1, s3 = q >> 1;
+            if (s2 >= n2 || s3 >= n3) continue;
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] = Y[q][S::idx(k, ta, tb)];
-#pragma unroll
-            for (int s1 = 0; s1 < 2; ++s1) {
-                mat1d<N, false>(emb + s1 * N2, v, r);
-                const size_t child = size_t(2 * ix + s1) + size_t(fx) * (size_t(2 * iy + s2) + size_t(fy) * size_t(2 * iz + s3));
+            for (int s1 = 0; s1 < n1; ++s1) {
+                mat1d<N, false>(cm.matrix<N>(emb, 0, ix, s1), v, r);
+                const size_t child = size_t(2 * ix + s1) +
+                                     size_t(cm.nf[0]) * (size_t(2 * iy + s2) + size_t(cm.nf[1]) * size_t(2 * iz + s3));
                 T* __restrict__ dst = fine + child * N3 + N * (ta + N * tb);
 #pragma unroll
                 for (int k = 0; k < N; ++k) dst[k] += r[k];
@@ -92,31 +106,32 @@ prolongate_kernel(const T* __restrict__ coarse, T* __restrict__ fine, const T* _
 
 template <int N, typename T>
 __global__ void __launch_bounds__(TrShape<N>::NT)
-restrict_kernel(const T* __restrict__ fine, T* __restrict__ coarse, const T* __restrict__ emb, int fx, int fy, int fz) {
+restrict_kernel(const T* __restrict__ fine, T* __restrict__ coarse, const T* __restrict__ emb, ChildMap cm) {
     using S = TrShape<N>;
-    constexpr int N2 = S::N2, N3 = S::N3;
+    constexpr int N3 = S::N3;
     __shared__ T X[4][N3];
     __shared__ T Y[2][N3];
-    const int cx = fx / 2, cy = fy / 2;
+    const int cx = cm.nc[0], cy = cm.nc[1];
     const int cc = blockIdx.x;
     const int ix = cc % cx, iy = (cc / cx) % cy, iz = cc / (cx * cy);
+    const int n1 = cm.children(0, ix), n2 = cm.children(1, iy), n3 = cm.children(2, iz);
     const int tid = threadIdx.x;
-    const bool act = tid < N2;
+    const bool act = tid < S::N2;
     const int ta = tid % N, tb = tid / N;
     T v[N], r[N], acc[N];
-    if (act) {   // x: thread (i2, i3); sum the two children along x
-#pragma unroll
+    if (act) {   // x: thread (i2, i3); sum the children along x
         for (int q = 0; q < 4; ++q) {
             const int s2 = q & 1, s3 = q >> 1;
+            if (s2 >= n2 || s3 >= n3) continue;
 #pragma unroll
             for (int k = 0; k < N; ++k) acc[k] = T(0);
-#pragma unroll
-            for (int s1 = 0; s1 < 2; ++s1) {
-                const size_t child = size_t(2 * ix + s1) + size_t(fx) * (size_t(2 * iy + s2) + size_t(fy) * size_t(2 * iz + s3));
+            for (int s1 = 0; s1 < n1; ++s1) {
+                const size_t child = size_t(2 * ix + s1) +
+                                     size_t(cm.nf[0]) * (size_t(2 * iy + s2) + size_t(cm.nf[1]) * size_t(2 * iz + s3));
                 const T* __restrict__ src = fine + child * N3 + N * (ta + N * tb);
 #pragma unroll
                 for (int k = 0; k < N; ++k) v[k] = src[k];
-                mat1d<N, true>(emb + s1 * N2, v, r);
+                mat1d<N, true>(cm.matrix<N>(emb, 0, ix, s1), v, r);
 #pragma unroll
                 for (int k = 0; k < N; ++k) acc[k] += r[k];
             }
@@ -126,15 +141,13 @@ restrict_kernel(const T* __restrict__ fine, T* __restrict__ coarse, const T* __r
     }
     __syncthreads();
     if (act) {   // y: thread (j1, i3)
-#pragma unroll
-        for (int s3 = 0; s3 < 2; ++s3) {
+        for (int s3 = 0; s3 < n3; ++s3) {
 #pragma unroll
             for (int k = 0; k < N; ++k) acc[k] = T(0);
-#pragma unroll
-            for (int s2 = 0; s2 < 2; ++s2) {
+            for (int s2 = 0; s2 < n2; ++s2) {
 #pragma unroll
                 for (int k = 0; k < N; ++k) v[k] = X[s2 + 2 * s3][S::idx(ta, k, tb)];
-                mat1d<N, true>(emb + s2 * N2, v, r);
+                mat1d<N, true>(cm.matrix<N>(emb, 1, iy, s2), v, r);
 #pragma unroll
                 for (int k = 0; k < N; ++k) acc[k] += r[k];
             }
@@ -146,27 +159,37 @@ restrict_kernel(const T* __restrict__ fine, T* __restrict__ coarse, const T* __r
     if (act) {   // z: thread (j1, j2)
 #pragma unroll
         for (int k = 0; k < N; ++k) acc[k] = T(0);
-#pragma unroll
-        for (int s3 = 0; s3 < 2; ++s3) {
+        for (int s3 = 0; s3 < n3; ++s3) {
 #pragma unroll
             for (int k = 0; k < N; ++k) v[k] = Y[s3][S::idx(ta, tb, k)];
-            mat1d<N, true>(emb + s3 * N2, v, r);
+            mat1d<N, true>(cm.matrix<N>(emb, 2, iz, s3), v, r);
 #pragma unroll
             for (int k = 0; k < N; ++k) acc[k] += r[k];
         }
         T* __restrict__ dst = coarse + size_t(cc) * N3 + ta + N * tb;
 #pragma unroll
-        for (int k = 0; k < N; ++k) dst[k * N2] = acc[k];
+        for (int k = 0; k < N; ++k) dst[k * S::N2] = acc[k];
     }
+}
+
+static ChildMap child_map(const int nf[3]) {
+    ChildMap cm;
+    for (int d = 0; d < 3; ++d) {
+        cm.nf[d] = nf[d];
+        cm.nc[d] = (nf[d] + 1) / 2;
+        cm.nl[d] = nf[d] % 2 == 1 ? 1 : 2;
+    }
+    return cm;
 }
 
 template <typename T>
 int transfer_prolongate_add(int n, const int nf[3], const T* coarse, T* fine, const T* emb, hipStream_t st) {
-    const unsigned ncoarse = unsigned((nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2));
+    const ChildMap cm = child_map(nf);
+    const unsigned ncoarse = unsigned(cm.nc[0] * cm.nc[1] * cm.nc[2]);
     switch (n) {
-#define SIPG_TR_CASE(NN)                                                                                      \
-    case NN:                                                                                                  \
-        prolongate_kernel<NN, T><<<ncoarse, TrShape<NN>::NT, 0, st>>>(coarse, fine, emb, nf[0], nf[1], nf[2]); \
+#define SIPG_TR_CASE(NN)                                                                          \
+    case NN:                                                                                      \
+        prolongate_kernel<NN, T><<<ncoarse, TrShape<NN>::NT, 0, st>>>(coarse, fine, emb, cm);      \
         break;
         SIPG_TR_CASE(2) SIPG_TR_CASE(3) SIPG_TR_CASE(4) SIPG_TR_CASE(5)
         SIPG_TR_CASE(6) SIPG_TR_CASE(7) SIPG_TR_CASE(8) SIPG_TR_CASE(9)
@@ -179,11 +202,12 @@ int transfer_prolongate_add(int n, const int nf[3], const T* coarse, T* fine, co
 
 template <typename T>
 int transfer_restrict(int n, const int nf[3], const T* fine, T* coarse, const T* emb, hipStream_t st) {
-    const unsigned ncoarse = unsigned((nf[0] / 2) * (nf[1] / 2) * (nf[2] / 2));
+    const ChildMap cm = child_map(nf);
+    const unsigned ncoarse = unsigned(cm.nc[0] * cm.nc[1] * cm.nc[2]);
     switch (n) {
-#define SIPG_TR_CASE(NN)                                                                                    \
-    case NN:                                                                                                \
-        restrict_kernel<NN, T><<<ncoarse, TrShape<NN>::NT, 0, st>>>(fine, coarse, emb, nf[0], nf[1], nf[2]); \
+#define SIPG_TR_CASE(NN)                                                                        \
+    case NN:                                                                                    \
+        restrict_kernel<NN, T><<<ncoarse, TrShape<NN>::NT, 0, st>>>(fine, coarse, emb, cm);      \
         break;
         SIPG_TR_CASE(2) SIPG_TR_CASE(3) SIPG_TR_CASE(4) SIPG_TR_CASE(5)
         SIPG_TR_CASE(6) SIPG_TR_CASE(7) SIPG_TR_CASE(8) SIPG_TR_CASE(9)

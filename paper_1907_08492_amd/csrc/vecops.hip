@@ -164,6 +164,28 @@ int scalar_ratio(const double* num, const double* den, double* out, hipStream_t 
     return SIPG_OK;
 }
 
+// y = A x, A dense n x n row major: one wavefront per row, its lanes striding
+// over the columns, then a shuffle reduction.
+template <typename T>
+__global__ void __launch_bounds__(kVT) dense_mv_kernel(const T* __restrict__ A, const T* __restrict__ x,
+                                                       T* __restrict__ y, int n) {
+    const int row = blockIdx.x * (kVT / 64) + threadIdx.x / 64, lane = threadIdx.x % 64;
+    if (row >= n) return;
+    const T* __restrict__ a = A + size_t(row) * n;
+    T acc = T(0);
+    for (int j = lane; j < n; j += 64) acc = fma(a[j], x[j], acc);
+    for (int o = 32; o > 0; o >>= 1) acc += __shfl_down(acc, o, 64);
+    if (lane == 0) y[row] = acc;
+}
+
+template <typename T>
+int vec_dense_mv(const T* A, const T* x, T* y, int n, hipStream_t st) {
+    const unsigned g = unsigned((n + kVT / 64 - 1) / (kVT / 64));
+    dense_mv_kernel<T><<<g, kVT, 0, st>>>(A, x, y, n);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
 #define SIPG_VEC_INST(T)                                                                        \
     template int vec_axpy_dev<T>(const double*, const double*, double, const T*, T*, int64_t, hipStream_t); \
     template int vec_xpby_dev<T>(const T*, const double*, const double*, T*, int64_t, hipStream_t); \
@@ -172,7 +194,8 @@ int scalar_ratio(const double* num, const double* den, double* out, hipStream_t 
     template int vec_axpby<T>(double, const T*, double, T*, int64_t, hipStream_t);           \
     template int vec_scale<T>(double, const T*, T*, int64_t, hipStream_t);                   \
     template int vec_sawtooth<T>(T*, int64_t, hipStream_t);                                  \
-    template int vec_dot_async<T>(const T*, const T*, double*, double*, int64_t, hipStream_t);
+    template int vec_dot_async<T>(const T*, const T*, double*, double*, int64_t, hipStream_t); \
+    template int vec_dense_mv<T>(const T*, const T*, T*, int, hipStream_t);
 SIPG_VEC_INST(float)
 SIPG_VEC_INST(double)
 template int vec_convert<float, double>(const double*, float*, int64_t, hipStream_t);

@@ -21,12 +21,17 @@ template <typename T> int vec_sawtooth(T* x, int64_t n, hipStream_t st);
 template <typename T> int vec_axpy_dev(const double* num, const double* den, double sign, const T* x, T* y, int64_t n, hipStream_t st);
 template <typename T> int vec_xpby_dev(const T* x, const double* num, const double* den, T* y, int64_t n, hipStream_t st);
 int scalar_ratio(const double* num, const double* den, double* out, hipStream_t st);
+// y = A x for a dense n x n matrix A (row major)
+template <typename T> int vec_dense_mv(const T* A, const T* x, T* y, int n, hipStream_t st);
 // *out = sum a_i b_i (device scalar, double); partial holds kVecPartials doubles
 template <typename T> int vec_dot_async(const T* a, const T* b, double* partial, double* out, int64_t n, hipStream_t st);
 
-// Grid transfer between a mesh and its coarsening by two in every direction
-// (tensor-product embedding of the coarse cell into its 8 children).
-// Prolongation: fine += P coarse.  Restriction: coarse = P^T fine.
+// Grid transfer between a mesh and its coarsening in every direction (fine
+// cells paired from the low end, the last coarse cell of an odd count with one
+// child): tensor-product embedding of each coarse cell into its children.
+// emb: M_0, M_1 of two halves, then per direction the pair of the last coarse
+// cell (8 n x n matrices).  Prolongation: fine += P coarse.  Restriction:
+// coarse = P^T fine.
 template <typename T>
 int transfer_prolongate_add(int n, const int nc_fine[3], const T* coarse, T* fine, const T* emb, hipStream_t st);
 template <typename T>

@@ -7,7 +7,7 @@ import scipy.sparse.linalg as spla
 from oracle import mms
 from oracle import multigrid as omg
 from oracle.sipg import SIPG
-from workloads import unit_cube, paper_affine_brick
+from workloads import Mesh, unit_cube, paper_affine_brick
 from tests.gpu_util import banner, rel_errors, require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -340,3 +340,84 @@ def test_fused_smoother_matches_two_launch_smoother(smoother, precision):
         mg.close()
     diff = np.max(np.abs(out[0] - out[1])) / np.max(np.abs(out[1]))
     assert diff <= (1e-13 if precision == "f64" else 1e-6), diff
+
+
+# graded coarsening of a 5 x 4 x 3 unit cube (fine cells paired from 0 on, the
+# last one alone for odd counts): one-child cells, then unequal pairs
+GRADED_CHAIN = [unit_cube((5, 4, 3)),
+                Mesh(n=(3, 2, 2), width=(0.4, 0.5, 2 / 3)),
+                Mesh(n=(2, 1, 1), width=(0.8, 1.0, 4 / 3)),
+                Mesh(n=(1, 1, 1), width=(1.6, 1.0, 4 / 3))]
+
+
+@pytest.mark.parametrize("k", [1, 2, 5])
+@pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl", "nodal_gauss"])
+def test_graded_transfer_matches_oracle(k, basis):
+    """graded_coarsening: the level bricks are the expected graded bricks and
+    every mesh transfer equals the oracle's embedding between the two nested
+    bricks (found from the cell bounds alone)."""
+    torch, P = require_gpu()
+    banner(f"graded transfer k={k} {basis}")
+    mg = P.Multigrid(GRADED_CHAIN[0], k, 2.0, basis, precision="f64", lanczos_steps=4, graded_coarsening=1)
+    assert [mg.level(l)[1] for l in range(mg.info.levels)] == [m.n for m in GRADED_CHAIN]
+    rng = np.random.default_rng(k)
+    for l in range(3):
+        fine, coarse = GRADED_CHAIN[l], GRADED_CHAIN[l + 1]
+        nf, nc = mg.level(l)[0], mg.level(l + 1)[0]
+        c = rng.uniform(-1, 1, nc)
+        f = rng.uniform(-1, 1, nf)
+        out_f = torch.empty(nf, dtype=torch.float64, device="cuda")
+        out_c = torch.empty(nc, dtype=torch.float64, device="cuda")
+        pf = mg.transfer(l, "prolongate", torch.from_numpy(c).cuda(), out_f).cpu().numpy()
+        rc = mg.transfer(l, "restrict", torch.from_numpy(f).cuda(), out_c).cpu().numpy()
+        e = rel_errors(pf, omg.prolongate_nested(c, fine, coarse, basis, k))
+        assert e[0] < 1e-12 and e[1] < 1e-12, (l, e)
+        e = rel_errors(rc, omg.restrict_nested(f, fine, coarse, basis, k))
+        assert e[0] < 1e-12 and e[1] < 1e-12, (l, e)
+    mg.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "f64"])
+@pytest.mark.parametrize("k,mesh_name", [(1, "cube2"), (2, "brick")])
+def test_direct_coarse_solve_is_exact(precision, k, mesh_name):
+    """A level of at most coarse_direct_max_dofs unknowns is solved by its
+    dense inverse: with one level the V-cycle is A^-1 (oracle: dense solve of
+    the assembled matrix), and CG converges at once."""
+    torch, P = require_gpu()
+    banner(f"direct coarse {precision} k={k} {mesh_name}")
+    mesh = unit_cube(2) if mesh_name == "cube2" else Mesh(n=(2, 1, 3), width=(0.6, 1.0, 0.4), deform_amp=0.1)
+    ref = SIPG(mesh, k, 2.0)
+    mg = P.Multigrid(mesh, k, 2.0, precision=precision, coarse_direct_max_dofs=ref.ndofs)
+    assert mg.info.levels == 1 and mg.info.coarse_steps == 0
+    r = np.random.default_rng(k).uniform(-1, 1, ref.ndofs)
+    z = mg.vcycle(torch.from_numpy(r).cuda()).cpu().numpy()
+    zref = np.linalg.solve(ref.assemble().toarray(), r)
+    e = rel_errors(z, zref)
+    tol = 1e-12 if precision == "f64" else 2e-5
+    assert e[0] < tol, e
+    # converged after the first iteration; the lagged stopping test may add one
+    x, info = mg.solve(torch.from_numpy(r).cuda(), rel_tol=1e-10)
+    assert info.iterations <= (2 if precision == "f64" else 4), info.iterations
+    mg.close()
+
+
+@pytest.mark.parametrize("precision", ["mixed", "f64"])
+@pytest.mark.parametrize("n,k,deform", [(7, 4, 0.1), (9, 3, 0.0), (5, 5, 0.0)])
+def test_mg_solve_graded_levels_with_direct_coarse(precision, n, k, deform):
+    """Odd meshes coarsened by graded levels down to a dense coarse solve
+    converge to 1e-10 and give the oracle's discrete solution."""
+    torch, P = require_gpu()
+    banner(f"mg solve graded n={n} k={k} {precision}")
+    mesh = unit_cube(n, deform)
+    ref = SIPG(mesh, k, 2.0)
+    b = mms.rhs(ref, mms.sine_rhs)
+    mg = P.Multigrid(mesh, k, 2.0, precision=precision, smoother="fdm", p_coarsening=1, coarse_reduction=10.0,
+                     graded_coarsening=1, coarse_direct_max_dofs=256)
+    assert mg.info.coarse_steps == 0
+    cells = [mg.level(l)[1] for l in range(mg.info.levels)]
+    assert cells[-1][0] < n and mg.level(mg.info.levels - 1)[0] <= 256, cells
+    x, info = mg.solve(torch.from_numpy(b).cuda(), rel_tol=1e-10)
+    r = b - ref.apply_naive(x.cpu().numpy())
+    assert np.linalg.norm(r) / np.linalg.norm(b) <= 1.5e-10
+    assert info.iterations <= 25, info.iterations
+    mg.close()

@@ -6,7 +6,7 @@ import numpy as np
 import pytest
 
 from oracle.sipg import SIPG
-from workloads import Mesh, paper_affine_brick, unit_cube, uniform_vector
+from workloads import PAPER_BRICK_HI, PAPER_BRICK_LO, PAPER_LINEAR_MAP, Mesh, paper_affine_brick, unit_cube, uniform_vector
 from tests.gpu_util import banner, rel_errors, require_gpu
 
 pytestmark = pytest.mark.gpu
@@ -17,6 +17,12 @@ MESHES = {
     "deformed": unit_cube((3, 4, 5), 0.1),
     "paper_affine": paper_affine_brick((4, 3, 2)),
     "brick_aniso": Mesh(n=(2, 5, 3), lo=(0.0, -1.0, 0.5), hi=(1.0, 1.5, 1.1)),
+    # graded bricks (sipg_mesh.width: the last cell of each direction narrower),
+    # the coarse levels of meshes with odd cell counts
+    "graded": Mesh(n=(3, 4, 2), width=(0.4, 0.3, 0.6)),
+    "graded_deformed": Mesh(n=(4, 3, 3), width=(0.3, 0.4, 0.4), deform_amp=0.1),
+    "graded_affine": Mesh(n=(3, 2, 2), lo=PAPER_BRICK_LO, hi=PAPER_BRICK_HI, lin=PAPER_LINEAR_MAP,
+                          width=(0.7, 1.0, 0.9)),
 }
 _oracle_cache = {}
 
@@ -68,7 +74,8 @@ def test_apply_f64_per_point_geometry_on_affine_mesh(mesh_name, k):
 
 @pytest.mark.parametrize("geometry,mesh_name,expected", [
     ("auto", "cartesian", 1), ("auto", "brick_aniso", 1), ("auto", "paper_affine", 0),
-    ("auto", "deformed", 0), ("qpoint", "cartesian", 0), ("cell", "brick_aniso", 1)])
+    ("auto", "deformed", 0), ("qpoint", "cartesian", 0), ("cell", "brick_aniso", 1), ("auto", "graded", 1),
+    ("auto", "graded_affine", 0)])
 def test_diagonal_metric_variant(geometry, mesh_name, expected):
     """Per-cell storage of an affine map with a diagonal linear part selects the
     reference-coordinate cell term (sipg_op_info.diagonal_metric); the other
@@ -83,7 +90,7 @@ def test_diagonal_metric_variant(geometry, mesh_name, expected):
 
 @pytest.mark.parametrize("k", [1, 3, 4, 5, 7, 8])
 @pytest.mark.parametrize("basis", ["hermite_like", "nodal_gl", "nodal_gauss"])
-@pytest.mark.parametrize("mesh_name", ["deformed", "paper_affine", "cartesian"])
+@pytest.mark.parametrize("mesh_name", ["deformed", "paper_affine", "cartesian", "graded_deformed"])
 def test_apply_f32(mesh_name, basis, k):
     torch, P = require_gpu()
     banner(f"apply f32 {mesh_name} {basis} k={k}")

@@ -35,7 +35,8 @@ def test_single_request_matches_direct_solve():
     op = P.Operator(mesh, 3, 2.0)
     b = op.assemble_rhs(amps, waves)
     mg = P.Multigrid(mesh, 3, 2.0, precision="mixed", smoother="fdm", p_coarsening=1,
-                     coarse_reduction=10.0)   # the server's defaults
+                     coarse_reduction=10.0, graded_coarsening=0,
+                     coarse_direct_max_dofs=256)   # the server's defaults
     xd, info = mg.solve(b, rel_tol=1e-10)
     torch.cuda.synchronize()
     assert info.iterations == res["iterations"]
@@ -127,7 +128,8 @@ def test_server_with_block_jacobi_smoother_matches_direct_solve():
     assert res["status"] == 0 and res["rel_residual"] <= 1e-9
     op = P.Operator(mesh, 4, 2.0)
     b = op.assemble_rhs(amps, waves)
-    mg = P.Multigrid(mesh, 4, 2.0, precision="mixed", smoother="fdm", p_coarsening=1, coarse_reduction=10.0)
+    mg = P.Multigrid(mesh, 4, 2.0, precision="mixed", smoother="fdm", p_coarsening=1, coarse_reduction=10.0,
+                     graded_coarsening=0, coarse_direct_max_dofs=256)
     xd, info = mg.solve(b, rel_tol=1e-9)
     torch.cuda.synchronize()
     assert info.iterations == res["iterations"]

@@ -6,7 +6,8 @@ import pytest
 from oracle import multigrid as omg
 from oracle.sipg import tensor_eval
 from oracle import basis as b1d
-from workloads import unit_cube
+from oracle.mesh import cell_bounds
+from workloads import Mesh, unit_cube
 
 
 @pytest.mark.parametrize("kind", ["hermite_like", "nodal_gl"])
@@ -54,3 +55,59 @@ def test_degree_embedding_reproduces_coarse_function(kind, kf, kc):
     lhs = omg.p_prolongate(c, 2, kind, kf, kc) @ g
     rhs = c @ omg.p_restrict(g, 2, kind, kf, kc)
     assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+# graded coarsening of a 5 x 4 x 3 unit cube: fine cells paired from 0 on, the
+# last one alone for odd counts (twice the regular width)
+GRADED_CHAIN = [unit_cube((5, 4, 3)),
+                Mesh(n=(3, 2, 2), width=(0.4, 0.5, 2 / 3)),
+                Mesh(n=(2, 1, 1), width=(0.8, 1.0, 4 / 3))]
+
+
+def _eval_on_brick(mesh, kind, k, coef, pts):
+    """Values of the function with coefficients coef at physical points of a
+    Cartesian brick (cell found from the cell bounds)."""
+    bas = b1d.make_basis(kind, k)
+    n3 = (k + 1) ** 3
+    out = np.empty(len(pts))
+    for p_i, x in enumerate(pts):
+        idx, xi = [], []
+        for d in range(3):
+            b = cell_bounds(mesh, d)
+            i = min(int(np.searchsorted(b, x[d])) - 1, len(b) - 2)
+            i = max(i, 0)
+            idx.append(i)
+            xi.append((x[d] - b[i]) / (b[i + 1] - b[i]))
+        c = idx[0] + mesh.n[0] * (idx[1] + mesh.n[1] * idx[2])
+        v, _ = tensor_eval(bas, np.array([xi]))
+        out[p_i] = v[0] @ coef[c * n3:(c + 1) * n3]
+    return out
+
+
+@pytest.mark.parametrize("kind", ["hermite_like", "nodal_gl"])
+@pytest.mark.parametrize("k", [1, 2, 4])
+@pytest.mark.parametrize("level", [0, 1])
+def test_nested_embedding_reproduces_coarse_function(kind, k, level):
+    """On the graded chain (odd counts: one child; unequal pairs on the
+    second step) the fine coefficients of a coarse function take its values
+    at random points, and the restriction is the transpose."""
+    fine, coarse = GRADED_CHAIN[level], GRADED_CHAIN[level + 1]
+    n3 = (k + 1) ** 3
+    rng = np.random.default_rng(10 * k + level)
+    c = rng.uniform(-1, 1, coarse.ncells * n3)
+    f = omg.prolongate_nested(c, fine, coarse, kind, k)
+    pts = rng.uniform(0, 1, (60, 3))
+    ref = _eval_on_brick(coarse, kind, k, c, pts)
+    assert np.max(np.abs(_eval_on_brick(fine, kind, k, f, pts) - ref)) < 1e-12 * max(1.0, np.max(np.abs(ref)))
+    g = rng.uniform(-1, 1, fine.ncells * n3)
+    lhs = f @ g
+    rhs = c @ omg.restrict_nested(g, fine, coarse, kind, k)
+    assert abs(lhs - rhs) < 1e-12 * abs(lhs)
+
+
+@pytest.mark.parametrize("k", [1, 3])
+def test_nested_embedding_equals_halving_on_even_bricks(k):
+    rng = np.random.default_rng(k)
+    c = rng.uniform(-1, 1, 2 * 1 * 3 * (k + 1) ** 3)
+    a = omg.prolongate_nested(c, unit_cube((4, 2, 6)), unit_cube((2, 1, 3)), "hermite_like", k)
+    assert np.max(np.abs(a - omg.prolongate(c, (4, 2, 6), "hermite_like", k))) < 1e-13

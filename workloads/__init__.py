@@ -40,6 +40,9 @@ class Mesh:
         X(xi) = lo + ((ix, iy, iz) + xi) * (hi - lo) / n     (brick point)
         Y     = L X                                        (linear map, L = I if None)
         Z     = Y + deform_amp * sin(pi Y1) sin(pi Y2) sin(pi Y3) * (1, 1, 1)
+    With `width` = (w1, w2, w3) the brick is graded instead: in direction d the
+    cells 0 .. n_d - 2 have width w_d and the last one ends at hi_d (its width
+    hi_d - lo_d - (n_d - 1) w_d lies in (0, w_d]).
     """
 
     n: Tuple[int, int, int]
@@ -47,6 +50,7 @@ class Mesh:
     hi: Tuple[float, float, float] = (1.0, 1.0, 1.0)
     lin: Optional[Tuple[Tuple[float, float, float], ...]] = None
     deform_amp: float = 0.0
+    width: Optional[Tuple[float, float, float]] = None
 
     @property
     def ncells(self) -> int:
