@@ -38,6 +38,7 @@ struct BcMerge {
     const T* au;
     const T* u;
     T sigma, theta;
+    T* zero;   // when set, zeroed at the positions written (the next step's u_old)
 };
 
 template <int N, typename T, int MODE, bool MERGE>
@@ -174,6 +175,7 @@ basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __re
                     const T ui = mg.u ? mg.u[off + k * N2] : T(0);
                     const T uo = mg.sigma != T(0) ? dst[k * N2] : ui;
                     dst[k * N2] = ui + mg.sigma * (ui - uo) + mg.theta * v[k];
+                    if (mg.zero) mg.zero[off + k * N2] = T(0);
                 }
             } else {
 #pragma unroll
@@ -198,7 +200,7 @@ static int launch_bc_t(const sipg_op* op, int mode, const void* in, void* out, h
     const T* i_ = static_cast<const T*>(in);
     T* o_ = static_cast<T*>(out);
     constexpr int NT = threads_per_block(N);
-    const BcMerge<T> none{nullptr, nullptr, T(0), T(0)};
+    const BcMerge<T> none{nullptr, nullptr, T(0), T(0), nullptr};
     if (mode == SIPG_BC_PJACOBI) {
         basis_change_kernel<N, T, 1, false><<<nblk, NT, 0, st>>>(i_, o_, tab, 0, static_cast<const T*>(op->gl_inv_diag), ncells, none);
     } else if (mode == SIPG_BC_FDM) {
@@ -213,12 +215,12 @@ static int launch_bc_t(const sipg_op* op, int mode, const void* in, void* out, h
 
 template <int N, typename T>
 static int launch_cheb_t(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
-                         double sigma, double theta, hipStream_t st) {
+                         double sigma, double theta, void* zero, hipStream_t st) {
     const int ncells = int(op->ncells);
     const unsigned nblk = unsigned((ncells + cells_per_block(N) - 1) / cells_per_block(N));
     constexpr int NT = threads_per_block(N);
     const T* tab = static_cast<const T*>(op->tables);
-    const BcMerge<T> m{static_cast<const T*>(au), static_cast<const T*>(u), T(sigma), T(theta)};
+    const BcMerge<T> m{static_cast<const T*>(au), static_cast<const T*>(u), T(sigma), T(theta), static_cast<T*>(zero)};
     if (mode == SIPG_BC_PJACOBI)
         basis_change_kernel<N, T, 1, true><<<nblk, NT, 0, st>>>(static_cast<const T*>(b), static_cast<T*>(uo), tab, 0,
                                                                 static_cast<const T*>(op->gl_inv_diag), ncells, m);
@@ -231,26 +233,26 @@ static int launch_cheb_t(const sipg_op* op, int mode, const void* b, const void*
 
 template <int N>
 static int launch_cheb_n(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
-                         double sigma, double theta, hipStream_t st) {
-    return op->dtype == SIPG_F64 ? launch_cheb_t<N, double>(op, mode, b, au, u, uo, sigma, theta, st)
-                                 : launch_cheb_t<N, float>(op, mode, b, au, u, uo, sigma, theta, st);
+                         double sigma, double theta, void* zero, hipStream_t st) {
+    return op->dtype == SIPG_F64 ? launch_cheb_t<N, double>(op, mode, b, au, u, uo, sigma, theta, zero, st)
+                                 : launch_cheb_t<N, float>(op, mode, b, au, u, uo, sigma, theta, zero, st);
 }
 
 int launch_precond_cheb(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
-                        double sigma, double theta, hipStream_t st) {
+                        double sigma, double theta, hipStream_t st, void* zero) {
     if (mode != SIPG_BC_PJACOBI && mode != SIPG_BC_FDM) {
         set_error("merged Chebyshev step: preconditioner mode expected");
         return SIPG_E_ARG;
     }
     switch (op->n) {
-        case 2: return launch_cheb_n<2>(op, mode, b, au, u, uo, sigma, theta, st);
-        case 3: return launch_cheb_n<3>(op, mode, b, au, u, uo, sigma, theta, st);
-        case 4: return launch_cheb_n<4>(op, mode, b, au, u, uo, sigma, theta, st);
-        case 5: return launch_cheb_n<5>(op, mode, b, au, u, uo, sigma, theta, st);
-        case 6: return launch_cheb_n<6>(op, mode, b, au, u, uo, sigma, theta, st);
-        case 7: return launch_cheb_n<7>(op, mode, b, au, u, uo, sigma, theta, st);
-        case 8: return launch_cheb_n<8>(op, mode, b, au, u, uo, sigma, theta, st);
-        case 9: return launch_cheb_n<9>(op, mode, b, au, u, uo, sigma, theta, st);
+        case 2: return launch_cheb_n<2>(op, mode, b, au, u, uo, sigma, theta, zero, st);
+        case 3: return launch_cheb_n<3>(op, mode, b, au, u, uo, sigma, theta, zero, st);
+        case 4: return launch_cheb_n<4>(op, mode, b, au, u, uo, sigma, theta, zero, st);
+        case 5: return launch_cheb_n<5>(op, mode, b, au, u, uo, sigma, theta, zero, st);
+        case 6: return launch_cheb_n<6>(op, mode, b, au, u, uo, sigma, theta, zero, st);
+        case 7: return launch_cheb_n<7>(op, mode, b, au, u, uo, sigma, theta, zero, st);
+        case 8: return launch_cheb_n<8>(op, mode, b, au, u, uo, sigma, theta, zero, st);
+        case 9: return launch_cheb_n<9>(op, mode, b, au, u, uo, sigma, theta, zero, st);
     }
     set_error("merged Chebyshev step: unsupported degree");
     return SIPG_E_UNSUPPORTED;

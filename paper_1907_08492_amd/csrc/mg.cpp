@@ -274,9 +274,10 @@ struct Hierarchy {
         int rc;
         for (int j = 0; j < steps; ++j) {
             if (j == 0 && zero_init) {
-                // u_0 = 0 (kept in uo for the next step), u_1 = theta_0 P^-1 b
-                SIPG_HIP(hipMemsetAsync(L.uo.p, 0, sizeof(T) * size_t(L.n), st));
-                if ((rc = launch_precond_cheb(L.op, pmode, L.b.p, nullptr, nullptr, L.u.p, 0.0, th[0], st)) != SIPG_OK)
+                // u_0 = 0 (written into uo for the next step by the same
+                // launch), u_1 = theta_0 P^-1 b
+                if ((rc = launch_precond_cheb(L.op, pmode, L.b.p, nullptr, nullptr, L.u.p, 0.0, th[0], st,
+                                              steps > 1 ? L.uo.p : nullptr)) != SIPG_OK)
                     return rc;
                 continue;
             }

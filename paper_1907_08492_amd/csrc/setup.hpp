@@ -53,8 +53,10 @@ int launch_basis_change(const sipg_op* op, int mode, const void* in, void* out, 
 // One Chebyshev step merged with the residual and the preconditioner
 // (mode SIPG_BC_PJACOBI or SIPG_BC_FDM): uo = u + sigma (u - uo) + theta P^-1
 // (b - au); au null means au = 0, u null means u = 0, sigma = 0 does not read uo.
+// zero, when set, is zeroed where uo is written (a zero start's u_old, without
+// a fill launch).
 int launch_precond_cheb(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
-                        double sigma, double theta, hipStream_t st);
+                        double sigma, double theta, hipStream_t st, void* zero = nullptr);
 
 // Bandwidth bound of the fused step (see sipg_stream_bound).
 int launch_stream_bound(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st);
