@@ -279,8 +279,10 @@ int sipg_compute_gl_diagonal(sipg_op* op, void* diag_out, void* stream);
  * ||b||_2 (recursive CG residual) or after max_iter iterations
  * (SIPG_E_NOCONV, info still filled).  Blocks the host: it reads one scalar
  * per iteration.  Its workspace (3 vectors and a few scalars) comes from the
- * operator's allocator and is returned before the call ends.  Requires an
- * SIPG_F64 operator.
+ * operator's allocator and is returned before the call ends (with no
+ * allocator: stream-ordered memory on `stream`, hipMallocAsync and
+ * hipFreeAsync, so no device-wide synchronisation).  Requires an SIPG_F64
+ * operator.
  */
 typedef struct {
     int32_t iterations;

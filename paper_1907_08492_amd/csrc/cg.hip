@@ -162,19 +162,34 @@ int cg_solve_device(const sipg_op* op, const double* b, double* x, double rel_to
     CgWork w{};
     void* blk[5] = {nullptr, nullptr, nullptr, nullptr, nullptr};
     const size_t bytes[5] = {8 * n, 8 * n, 8 * n, 8 * size_t(kRedBlocks), 8 * 4};
+    // without a caller allocator the workspace is stream-ordered memory (no
+    // device-wide synchronisation when it goes back)
+    const bool ordered = !op->mem.a.alloc;
     int status = SIPG_OK;
-    for (int i = 0; i < 5 && status == SIPG_OK; ++i) status = op->mem.alloc(&blk[i], bytes[i], "sipg_cg_solve: workspace");
+    for (int i = 0; i < 5 && status == SIPG_OK; ++i) {
+        if (!ordered) {
+            status = op->mem.alloc(&blk[i], bytes[i], "sipg_cg_solve: workspace");
+        } else if (hipError_t e = hipMallocAsync(&blk[i], bytes[i], st); e != hipSuccess) {
+            blk[i] = nullptr;
+            status = hip_fail(e, "sipg_cg_solve: workspace");
+        }
+    }
     if (status == SIPG_OK) {
         w = CgWork{static_cast<double*>(blk[0]), static_cast<double*>(blk[1]), static_cast<double*>(blk[2]),
                    static_cast<double*>(blk[3]), static_cast<double*>(blk[4])};
         status = cg_iterate(op, b, x, rel_tol, max_iter, info, w, st);
-        // every launch of the solve is finished before the blocks go back
-        if (hipStreamSynchronize(st) != hipSuccess && status == SIPG_OK) {
+        // a caller allocator's free is not stream-ordered: every launch of the
+        // solve is finished before the blocks go back
+        if (!ordered && hipStreamSynchronize(st) != hipSuccess && status == SIPG_OK) {
             set_error("sipg_cg_solve: stream synchronisation failed");
             status = SIPG_E_HIP;
         }
     }
-    for (void* q : blk) op->mem.release(q);
+    for (void* q : blk) {
+        if (!q) continue;
+        if (ordered) (void)hipFreeAsync(q, st);
+        else op->mem.release(q);
+    }
     return status;
 }
 

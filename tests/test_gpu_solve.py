@@ -48,3 +48,22 @@ def test_cg_zero_rhs_and_noconv():
     x, info = op.cg_solve(b, rel_tol=1e-14, max_iter=3, raise_on_noconv=False)
     assert info.status == -6 and info.iterations == 3
     op.close()
+
+
+def test_cg_without_caller_allocator_matches():
+    """With no caller allocator the CG workspace is stream-ordered device
+    memory; the solve is the same, bit for bit, and repeated calls work."""
+    torch, P = require_gpu()
+    banner("cg stream-ordered workspace")
+    mesh = unit_cube((4, 3, 5), 0.1)
+    b = torch.from_numpy(np.random.default_rng(3).uniform(-1, 1, 4 * 3 * 5 * 27)).cuda()
+    a = P.Operator(mesh, 2, 2.0)
+    n = P.Operator(mesh, 2, 2.0, allocator=None)
+    xa, ia = a.cg_solve(b, rel_tol=1e-10)
+    for _ in range(2):
+        xn, i_n = n.cg_solve(b, rel_tol=1e-10)
+        torch.cuda.synchronize()
+        assert i_n.iterations == ia.iterations
+        assert torch.equal(xn, xa)
+    a.close()
+    n.close()
