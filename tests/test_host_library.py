@@ -158,3 +158,33 @@ def test_host_fdm_tables_diagonalize_the_oracle_1d_matrices(basis, k):
         ne = k + 1 - (k + 1) // 2
         assert np.array_equal(zt[:ne], zt[:ne, ::-1])
         assert np.array_equal(zt[ne:], -zt[ne:, ::-1])
+
+
+def test_graded_mesh_and_multigrid_option_errors_without_gpu():
+    """Argument checks of the graded brick (sipg_mesh.width) and of the
+    multigrid and server options are made before any device work."""
+    from workloads import Mesh
+    h = C.c_void_p()
+    ok = P.make_mesh(Mesh(n=(3, 2, 2), width=(0.4, 0.6, 0.55)))
+    for width in ((0.4, 0.6, 0.45),          # last cell of z wider than the others
+                  (0.3, 0.6, 0.55),          # last cell of x wider (0.4 > 0.3)
+                  (0.5, 0.6, 0.55),          # the first two x cells already reach hi
+                  (-0.4, 0.6, 0.55)):
+        bad = P.make_mesh(Mesh(n=(3, 2, 2), width=width))
+        assert P.lib.sipg_setup(C.byref(bad), 2, 1.0, 0, 0, 0, None, None, C.byref(h)) == -1, width
+        assert "graded brick" in P.lib.sipg_last_error().decode()
+    B = P.binding
+    o = B.SipgMgOpts()
+    assert P.lib.sipg_mg_default_opts(C.byref(o)) == 0
+    assert o.graded_coarsening == 0 and o.coarse_direct_max_dofs == 0
+    for field, value in (("graded_coarsening", 2), ("coarse_direct_max_dofs", 5000), ("coarse_direct_max_dofs", -1)):
+        o2 = B.SipgMgOpts()
+        P.lib.sipg_mg_default_opts(C.byref(o2))
+        setattr(o2, field, value)
+        assert P.lib.sipg_mg_setup(C.byref(ok), 2, 2.0, 0, C.byref(o2), None, None, C.byref(h)) == -1, field
+        assert "invalid options" in P.lib.sipg_last_error().decode()
+    s = B.SipgServerOpts()
+    assert P.lib.sipg_server_default_opts(C.byref(s)) == 0
+    assert s.graded_coarsening == 0 and s.coarse_direct_max_dofs == 256
+    s.coarse_direct_max_dofs = 5000
+    assert P.lib.sipg_server_create(C.byref(s), None, C.byref(h)) == -1
