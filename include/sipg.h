@@ -379,11 +379,12 @@ typedef struct {
                                     so coarse levels are graded bricks (sipg_mesh.width) and
                                     every mesh coarsens down to one cell */
     int32_t coarse_direct_max_dofs; /* 0 (default): the coarsest level is solved by the Chebyshev
-                                    iteration above.  n in [1, 4096]: a coarsest level of at most
+                                    iteration above.  n in [1, 1024]: a coarsest level of at most
                                     n unknowns is solved exactly instead, by a dense inverse of
-                                    its matrix formed at set-up (one launch per V-cycle); with
-                                    graded_coarsening, coarsening stops at the first level that
-                                    small */
+                                    its matrix formed at set-up (n products with the level's
+                                    FP64 operator, then a Cholesky inverse on the host: about
+                                    10 ms at 256, 1 s at 1024) and applied in one launch per
+                                    V-cycle.  Coarsening stops at the first level that small */
 } sipg_mg_opts;
 typedef struct {
     int32_t levels;

@@ -567,8 +567,12 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
             std::vector<double> a(ld * n, 0.0);
             for (int i = 0; i < n; ++i) a[size_t(i) * ld + i] = 1.0;
             SIPG_HIP(hipMemcpyAsync(X.p, a.data(), sizeof(double) * a.size(), hipMemcpyHostToDevice, st));
-            for (int i = 0; i < n; ++i)
-                if ((rc = launch_matvec(op64, X.p + size_t(i) * ld, Y.p + size_t(i) * ld, st)) != SIPG_OK) return rc;
+            for (int i = 0; i < n && rc == SIPG_OK; ++i)
+                rc = launch_matvec(op64, X.p + size_t(i) * ld, Y.p + size_t(i) * ld, st);
+            if (rc != SIPG_OK) {
+                (void)hipStreamSynchronize(st);   // nothing in flight on X, Y when they go back
+                return rc;
+            }
             SIPG_HIP(hipMemcpyAsync(a.data(), Y.p, sizeof(double) * a.size(), hipMemcpyDeviceToHost, st));
             SIPG_HIP(hipStreamSynchronize(st));
             for (int i = 0; i < n; ++i)
@@ -670,7 +674,7 @@ int sipg_mg_setup(const sipg_mesh* mesh, int degree, double penalty, int basis, 
         o.min_coarse_cells < 1 || (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2 ||
         (o.fused_smoother != 0 && o.fused_smoother != 1) || (o.lanczos_start != 0 && o.lanczos_start != 1) ||
         (o.graded_coarsening != 0 && o.graded_coarsening != 1) || o.coarse_direct_max_dofs < 0 ||
-        o.coarse_direct_max_dofs > 4096) {
+        o.coarse_direct_max_dofs > 1024) {
         set_error("sipg_mg_setup: invalid options");
         return SIPG_E_ARG;
     }

@@ -317,7 +317,7 @@ int sipg_server_create(const sipg_server_opts* opts, const sipg_allocator* alloc
     if (o.workers < 1 || o.workers > 16 || o.hbm_budget_bytes <= 0 || (o.precision != 0 && o.precision != 1) ||
         (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2 ||
         !(o.coarse_reduction > 1.0) || (o.graded_coarsening != 0 && o.graded_coarsening != 1) ||
-        o.coarse_direct_max_dofs < 0 || o.coarse_direct_max_dofs > 4096) {
+        o.coarse_direct_max_dofs < 0 || o.coarse_direct_max_dofs > 1024) {
         set_error("sipg_server_create: workers in [1,16], budget > 0, precision and smoother 0 or 1, p_coarsening 0..2, "
                   "coarse_reduction > 1");
         return SIPG_E_ARG;
