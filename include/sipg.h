@@ -264,6 +264,51 @@ int sipg_apply_pjacobi(const sipg_op* op, const void* x, void* y, void* z, void*
 int sipg_stream_bound(const sipg_op* op, const void* x, void* y, void* z, void* stream);
 
 /*
+ * One GPU's share of a partition of the mesh into z-slabs (Section 5: in a
+ * distributed run only the value and derivative layers of the cells next to
+ * a partition boundary travel between processes, 2 n^2 values per face in
+ * the Hermite-like basis against n^3 for a nodal one).
+ *
+ * sipg_setup_slab: the operator of the cells z0 <= iz < z1 of `mesh` (0 <=
+ * z0 < z1 <= mesh->n[2]; other arguments and errors as sipg_setup).  Its
+ * metric terms are those of the whole mesh: the faces on the planes z0 (if
+ * z0 > 0) and z1 (if z1 < n[2]) are interior faces, whose neighbour cells
+ * belong to the slabs below and above.  A slab with a neighbouring slab is
+ * applied only through sipg_apply_slab (sipg_apply, sipg_apply_pjacobi, the
+ * solvers and batches reject it: SIPG_E_ARG); sipg_basis_change and
+ * sipg_compute_gl_diagonal work on it as on any operator.  Vectors are the
+ * slab's own cells, in the usual cell-wise layout (ndofs = nx ny (z1-z0) n^3).
+ *
+ * sipg_ghost_size: values of one ghost buffer, nx ny NL n^2 with NL = 2
+ * (Hermite-like) or n (nodal bases); -1 for a null operator.
+ *
+ * sipg_pack_ghost: out = the layers that the neighbouring slab reads from
+ * this one: side 0, of the bottom row of cells (for the slab below, whose
+ * ghost_hi it is); side 1, of the top row (the ghost_lo of the slab above).
+ * Layout [column ix + nx iy][layer j][point i1 + n i2]: in the Hermite-like
+ * basis the value and derivative layers, 0 and 1 of the bottom row (side 0)
+ * or n-2 and n-1 of the top row (side 1); in the nodal bases all n layers,
+ * bottom up.
+ * x: this slab's vector; out: device, sipg_ghost_size values, not
+ * overlapping x.  Stream ordered; allocates nothing.
+ *
+ * sipg_apply_slab: y = A x for the slab, the neighbour layers across its
+ * lower and upper z planes read from ghost_lo and ghost_hi (the packed
+ * buffers of the slabs below and above); a ghost buffer is required exactly
+ * where the slab has a neighbour (SIPG_E_ARG otherwise).  With z non-null,
+ * also z = P^-1 y of eq. (jacobi) in the same pass (needs
+ * sipg_compute_gl_diagonal on this operator).  x, y, z: device, ndofs
+ * values of the operator's dtype, not overlapping.  Stream ordered; the
+ * results equal the rows of these cells of the whole mesh's operator.
+ */
+int sipg_setup_slab(const sipg_mesh* mesh, int z0, int z1, int degree, double penalty_factor, int basis,
+                    int dtype, int geometry, const sipg_allocator* allocator, void* stream, sipg_op** out);
+int64_t sipg_ghost_size(const sipg_op* op);
+int sipg_pack_ghost(const sipg_op* op, int side, const void* x, void* out, void* stream);
+int sipg_apply_slab(const sipg_op* op, const void* x, const void* ghost_lo, const void* ghost_hi, void* y,
+                    void* z, void* stream);
+
+/*
  * Compute diag(A) of the operator in the nodal Gauss-Lobatto basis, i.e. the
  * element-wise diagonal P_d of eq. (jacobi), and keep its inverse inside the
  * operator for SIPG_BC_PJACOBI.  Computed on the device by the same weak form.

@@ -49,6 +49,7 @@ EXPORTED = [
     "sipg_batch_create", "sipg_batch_apply", "sipg_batch_get_info", "sipg_batch_destroy",
     "sipg_host_fdm_tables", "sipg_mg_level_degree", "sipg_batch_tune",
     "sipg_cg_solve_static", "sipg_cg_static_max_dofs", "sipg_host_block_order", "sipg_stream_bound",
+    "sipg_setup_slab", "sipg_ghost_size", "sipg_pack_ghost", "sipg_apply_slab",
 ]
 
 
@@ -138,6 +139,12 @@ lib.sipg_apply.argtypes = [_vp, _vp, _vp, _vp]
 lib.sipg_apply_pjacobi.argtypes = [_vp, _vp, _vp, _vp, _vp]
 lib.sipg_basis_change.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
 lib.sipg_stream_bound.argtypes = [_vp, _vp, _vp, _vp, _vp]
+lib.sipg_setup_slab.argtypes = [C.POINTER(SipgMesh), C.c_int, C.c_int, C.c_int, C.c_double, C.c_int, C.c_int,
+                                C.c_int, C.POINTER(SipgAllocator), _vp, C.POINTER(_vp)]
+lib.sipg_ghost_size.argtypes = [_vp]
+lib.sipg_ghost_size.restype = C.c_int64
+lib.sipg_pack_ghost.argtypes = [_vp, C.c_int, _vp, _vp, _vp]
+lib.sipg_apply_slab.argtypes = [_vp, _vp, _vp, _vp, _vp, _vp, _vp]
 lib.sipg_compute_gl_diagonal.argtypes = [_vp, _vp, _vp]
 lib.sipg_cg_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
 lib.sipg_cg_solve_static.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
@@ -175,7 +182,7 @@ lib.sipg_batch_destroy.argtypes = [_vp]
 lib.sipg_batch_tune.argtypes = [_vp, C.c_int, _vp]
 lib.sipg_host_fdm_tables.argtypes = [C.c_int, C.c_int, C.c_double, C.POINTER(C.c_double), C.POINTER(C.c_double)]
 for _f in EXPORTED:
-    if _f not in ("sipg_ndofs", "sipg_last_error", "sipg_cg_static_max_dofs"):
+    if _f not in ("sipg_ndofs", "sipg_last_error", "sipg_cg_static_max_dofs", "sipg_ghost_size"):
         getattr(lib, _f).restype = C.c_int
 
 
@@ -308,7 +315,9 @@ class Operator:
     """The SIPG operator of one mesh, degree and basis on the current device."""
 
     def __init__(self, mesh, degree: int, penalty: float = 2.0, basis: str = "hermite_like",
-                 dtype: str = "f64", geometry: str = "auto", stream=None, allocator="torch"):
+                 dtype: str = "f64", geometry: str = "auto", stream=None, allocator="torch", slab=None):
+        """slab=(z0, z1): the operator of the cells z0 <= iz < z1 of the mesh
+        (one GPU's share of a z-partition, sipg_setup_slab)."""
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Operator needs a GPU (HIP device)")
@@ -319,9 +328,15 @@ class Operator:
         self.torch_dtype = torch.float64 if dtype == "f64" else torch.float32
         self._mesh = make_mesh(mesh)
         h = _vp()
-        _check(lib.sipg_setup(C.byref(self._mesh), self.degree, float(penalty), BASIS[basis],
-                              DTYPE[dtype], GEOMETRY[geometry], _allocator(allocator), _vp(_stream_ptr(stream)),
-                              C.byref(h)), "sipg_setup")
+        if slab is None:
+            _check(lib.sipg_setup(C.byref(self._mesh), self.degree, float(penalty), BASIS[basis],
+                                  DTYPE[dtype], GEOMETRY[geometry], _allocator(allocator), _vp(_stream_ptr(stream)),
+                                  C.byref(h)), "sipg_setup")
+        else:
+            _check(lib.sipg_setup_slab(C.byref(self._mesh), int(slab[0]), int(slab[1]), self.degree, float(penalty),
+                                       BASIS[basis], DTYPE[dtype], GEOMETRY[geometry], _allocator(allocator),
+                                       _vp(_stream_ptr(stream)), C.byref(h)), "sipg_setup_slab")
+        self.slab = None if slab is None else (int(slab[0]), int(slab[1]))
         self._h = h
         self.ndofs = int(lib.sipg_ndofs(h))
         info = SipgOpInfo()
@@ -342,6 +357,30 @@ class Operator:
 
     def empty(self):
         return _torch().empty(self.ndofs, dtype=self.torch_dtype, device="cuda")
+
+    def ghost_size(self) -> int:
+        return int(lib.sipg_ghost_size(self._h))
+
+    def pack_ghost(self, side: int, x, out=None, stream=None):
+        """The layers of the bottom (side 0) or top (side 1) cell row that the
+        neighbouring slab reads (sipg_pack_ghost)."""
+        torch = _torch()
+        g = torch.empty(self.ghost_size(), dtype=self.torch_dtype, device="cuda") if out is None else out
+        if g.dtype != self.torch_dtype or g.numel() != self.ghost_size() or not g.is_contiguous():
+            raise ValueError(f"out must be contiguous {self.torch_dtype} with {self.ghost_size()} elements")
+        _check(lib.sipg_pack_ghost(self._h, int(side), self._vec(x, "x"), _vp(g.data_ptr()), _vp(_stream_ptr(stream))),
+               "sipg_pack_ghost")
+        return g
+
+    def apply_slab(self, x, ghost_lo=None, ghost_hi=None, y=None, z=None, stream=None):
+        """y = A x on a slab with the neighbours' ghost layers; with z, also
+        z = P^-1 y (sipg_apply_slab).  Returns y (and z when given)."""
+        y = self.empty() if y is None else y
+        gp = lambda g: None if g is None else _vp(g.data_ptr())
+        _check(lib.sipg_apply_slab(self._h, self._vec(x, "x"), gp(ghost_lo), gp(ghost_hi), self._vec(y, "y"),
+                                   None if z is None else self._vec(z, "z"), _vp(_stream_ptr(stream))),
+               "sipg_apply_slab")
+        return y if z is None else (y, z)
 
     def apply(self, x, out=None, stream=None):
         """out = A x (stream ordered)."""

@@ -139,31 +139,31 @@ static int free_op(sipg_op* op) {
     return SIPG_OK;
 }
 
-int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st) {
+int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g) {
     switch (op->n) {
-        case 2: return launch_matvec_n<2>(op, x, y, st);
-        case 3: return launch_matvec_n<3>(op, x, y, st);
-        case 4: return launch_matvec_n<4>(op, x, y, st);
-        case 5: return launch_matvec_n<5>(op, x, y, st);
-        case 6: return launch_matvec_n<6>(op, x, y, st);
-        case 7: return launch_matvec_n<7>(op, x, y, st);
-        case 8: return launch_matvec_n<8>(op, x, y, st);
-        case 9: return launch_matvec_n<9>(op, x, y, st);
+        case 2: return launch_matvec_n<2>(op, x, y, st, g);
+        case 3: return launch_matvec_n<3>(op, x, y, st, g);
+        case 4: return launch_matvec_n<4>(op, x, y, st, g);
+        case 5: return launch_matvec_n<5>(op, x, y, st, g);
+        case 6: return launch_matvec_n<6>(op, x, y, st, g);
+        case 7: return launch_matvec_n<7>(op, x, y, st, g);
+        case 8: return launch_matvec_n<8>(op, x, y, st, g);
+        case 9: return launch_matvec_n<9>(op, x, y, st, g);
     }
     set_error("unsupported degree");
     return SIPG_E_UNSUPPORTED;
 }
 
-int launch_matvec_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st) {
+int launch_matvec_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st, Ghosts g) {
     switch (op->n) {
-        case 2: return launch_matvec_pjacobi_n<2>(op, x, y, z, st);
-        case 3: return launch_matvec_pjacobi_n<3>(op, x, y, z, st);
-        case 4: return launch_matvec_pjacobi_n<4>(op, x, y, z, st);
-        case 5: return launch_matvec_pjacobi_n<5>(op, x, y, z, st);
-        case 6: return launch_matvec_pjacobi_n<6>(op, x, y, z, st);
-        case 7: return launch_matvec_pjacobi_n<7>(op, x, y, z, st);
-        case 8: return launch_matvec_pjacobi_n<8>(op, x, y, z, st);
-        case 9: return launch_matvec_pjacobi_n<9>(op, x, y, z, st);
+        case 2: return launch_matvec_pjacobi_n<2>(op, x, y, z, st, g);
+        case 3: return launch_matvec_pjacobi_n<3>(op, x, y, z, st, g);
+        case 4: return launch_matvec_pjacobi_n<4>(op, x, y, z, st, g);
+        case 5: return launch_matvec_pjacobi_n<5>(op, x, y, z, st, g);
+        case 6: return launch_matvec_pjacobi_n<6>(op, x, y, z, st, g);
+        case 7: return launch_matvec_pjacobi_n<7>(op, x, y, z, st, g);
+        case 8: return launch_matvec_pjacobi_n<8>(op, x, y, z, st, g);
+        case 9: return launch_matvec_pjacobi_n<9>(op, x, y, z, st, g);
     }
     set_error("unsupported degree");
     return SIPG_E_UNSUPPORTED;
@@ -199,6 +199,16 @@ static bool ranges_overlap(const void* a, const void* b, size_t bytes) {
     const char* pb = static_cast<const char*>(b);
     return pa < pb + bytes && pb < pa + bytes;
 }
+
+// [a, a + la) and [b, b + lb) share a byte
+static bool ranges_overlap(const void* a, size_t la, const void* b, size_t lb) {
+    const char* pa = static_cast<const char*>(a);
+    const char* pb = static_cast<const char*>(b);
+    return pa < pb + lb && pb < pa + la;
+}
+
+// A slab of a z-partition with a neighbouring slab: its product needs ghost layers.
+static bool is_inner_slab(const sipg_op* op) { return op->mesh.z0 > 0 || op->mesh.z0 + op->nc[2] < op->mesh.nzg; }
 
 }  // namespace sipg
 
@@ -251,8 +261,10 @@ int sipg_host_fdm_tables(int degree, int basis, double penalty_factor, double* z
     return SIPG_OK;
 }
 
-int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int basis, int dtype,
-               int geometry, const sipg_allocator* allocator, void* stream, sipg_op** out) {
+// The operator of the cells z0 <= iz < z1 of `mesh` (the whole mesh: z0 = 0,
+// z1 = mesh->n[2]).
+static int setup_impl(const sipg_mesh* mesh, int z0, int z1, int degree, double penalty_factor, int basis,
+                      int dtype, int geometry, const sipg_allocator* allocator, void* stream, sipg_op** out) {
     if (!mesh || !out) { set_error("sipg_setup: null mesh or out"); return SIPG_E_ARG; }
     *out = nullptr;
     if (!allocator_valid(allocator)) { set_error("sipg_setup: allocator needs both callbacks"); return SIPG_E_ARG; }
@@ -278,7 +290,12 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
             }
         }
     }
-    const int64_t ncells = int64_t(mesh->n[0]) * mesh->n[1] * mesh->n[2];
+    if (z0 < 0 || z1 > mesh->n[2] || z0 >= z1) {
+        set_error("sipg_setup_slab: need 0 <= z0 < z1 <= n[2]");
+        return SIPG_E_ARG;
+    }
+    const int nloc[3] = {mesh->n[0], mesh->n[1], z1 - z0};   // cells of this operator
+    const int64_t ncells = int64_t(nloc[0]) * nloc[1] * nloc[2];
     const int n = degree + 1;
     if (ncells * n * n * n > (int64_t(1) << 31) - 1 || ncells > (int64_t(1) << 30)) {
         set_error("sipg_setup: mesh too large (dofs must fit in 31 bits)");
@@ -306,14 +323,16 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
         op->diag_metric = op->geom == GEOM_CELL && offdiag_zero ? 1 : 0;
     }
     op->eta = penalty_factor;
-    for (int d = 0; d < 3; ++d) op->nc[d] = mesh->n[d];
+    for (int d = 0; d < 3; ++d) op->nc[d] = nloc[d];
     op->ncells = ncells;
     op->ndofs = ncells * n * n * n;
     MeshDev& m = op->mesh;
     bool lin_zero = true;
     for (int i = 0; i < 9; ++i) lin_zero = lin_zero && mesh->lin[i] == 0.0;
+    m.z0 = z0;
+    m.nzg = mesh->n[2];
     for (int d = 0; d < 3; ++d) {
-        m.n[d] = mesh->n[d];
+        m.n[d] = nloc[d];
         m.lo[d] = mesh->lo[d];
         m.h[d] = graded ? mesh->width[d] : (mesh->hi[d] - mesh->lo[d]) / mesh->n[d];
         m.hl[d] = graded ? mesh->hi[d] - mesh->lo[d] - (mesh->n[d] - 1) * mesh->width[d] : m.h[d];
@@ -342,7 +361,7 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
     const size_t tab_bytes = esz * (L.total + 1);
     for (int d = 0; d < 3; ++d) {
         int64_t nf = 1;
-        for (int k = 0; k < 3; ++k) nf *= (k == d ? mesh->n[k] + 1 : mesh->n[k]);
+        for (int k = 0; k < 3; ++k) nf *= (k == d ? nloc[k] + 1 : nloc[k]);
         op->nfaces[d] = nf;
     }
     const size_t cg_bytes = esz * size_t(ncells) * cell_geom_stride(op->geom, n);
@@ -378,6 +397,17 @@ int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int bas
     }
     *out = op;
     return SIPG_OK;
+}
+
+int sipg_setup(const sipg_mesh* mesh, int degree, double penalty_factor, int basis, int dtype,
+               int geometry, const sipg_allocator* allocator, void* stream, sipg_op** out) {
+    return setup_impl(mesh, 0, mesh ? mesh->n[2] : 1, degree, penalty_factor, basis, dtype, geometry, allocator, stream,
+                      out);
+}
+
+int sipg_setup_slab(const sipg_mesh* mesh, int z0, int z1, int degree, double penalty_factor, int basis, int dtype,
+                    int geometry, const sipg_allocator* allocator, void* stream, sipg_op** out) {
+    return setup_impl(mesh, z0, z1, degree, penalty_factor, basis, dtype, geometry, allocator, stream, out);
 }
 
 int sipg_destroy(sipg_op* op) { return free_op(op); }
@@ -426,8 +456,51 @@ int sipg_get_info(const sipg_op* op, sipg_op_info* info) {
     return SIPG_OK;
 }
 
+int64_t sipg_ghost_size(const sipg_op* op) {
+    if (!op) return -1;
+    const int64_t nl = op->basis == SIPG_BASIS_HERMITE_LIKE ? 2 : op->n;
+    return int64_t(op->nc[0]) * op->nc[1] * nl * op->n * op->n;
+}
+
+int sipg_pack_ghost(const sipg_op* op, int side, const void* x, void* out, void* stream) {
+    if (!op || !x || !out || (side != 0 && side != 1)) {
+        set_error("sipg_pack_ghost: null argument or side not 0 / 1");
+        return SIPG_E_ARG;
+    }
+    const size_t esz = op->dtype == SIPG_F64 ? 8 : 4;
+    if (ranges_overlap(x, size_t(op->ndofs) * esz, out, size_t(sipg_ghost_size(op)) * esz)) {
+        set_error("sipg_pack_ghost: x and out overlap");
+        return SIPG_E_ARG;
+    }
+    return launch_pack_ghost(op, side, x, out, static_cast<hipStream_t>(stream));
+}
+
+int sipg_apply_slab(const sipg_op* op, const void* x, const void* ghost_lo, const void* ghost_hi, void* y, void* z,
+                    void* stream) {
+    if (!op || !x || !y) { set_error("sipg_apply_slab: null argument"); return SIPG_E_ARG; }
+    const bool below = op->mesh.z0 > 0, above = op->mesh.z0 + op->nc[2] < op->mesh.nzg;
+    if (bool(ghost_lo) != below || bool(ghost_hi) != above) {
+        set_error("sipg_apply_slab: a ghost buffer is needed exactly for each side with a neighbouring slab");
+        return SIPG_E_ARG;
+    }
+    const size_t bytes = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
+    if (ranges_overlap(x, y, bytes) || (z && (ranges_overlap(x, z, bytes) || ranges_overlap(y, z, bytes)))) {
+        set_error("sipg_apply_slab: x, y and z must not overlap");
+        return SIPG_E_ARG;
+    }
+    const Ghosts g{ghost_lo, ghost_hi};
+    hipStream_t st = static_cast<hipStream_t>(stream);
+    if (!z) return launch_matvec(op, x, y, st, g);
+    if (!op->gl_inv_diag) {
+        set_error("sipg_apply_slab: z = P^-1 y needs sipg_compute_gl_diagonal first");
+        return SIPG_E_ARG;
+    }
+    return launch_matvec_pjacobi(op, x, y, z, st, g);
+}
+
 int sipg_apply(const sipg_op* op, const void* x, void* y, void* stream) {
     if (!op || !x || !y) { set_error("sipg_apply: null argument"); return SIPG_E_ARG; }
+    if (is_inner_slab(op)) { set_error("sipg_apply: a slab with neighbours needs sipg_apply_slab"); return SIPG_E_ARG; }
     const size_t bytes = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
     if (ranges_overlap(x, y, bytes)) { set_error("sipg_apply: x and y overlap"); return SIPG_E_ARG; }
     return launch_matvec(op, x, y, static_cast<hipStream_t>(stream));
@@ -435,6 +508,10 @@ int sipg_apply(const sipg_op* op, const void* x, void* y, void* stream) {
 
 int sipg_apply_pjacobi(const sipg_op* op, const void* x, void* y, void* z, void* stream) {
     if (!op || !x || !y || !z) { set_error("sipg_apply_pjacobi: null argument"); return SIPG_E_ARG; }
+    if (is_inner_slab(op)) {
+        set_error("sipg_apply_pjacobi: a slab with neighbours needs sipg_apply_slab");
+        return SIPG_E_ARG;
+    }
     if (!op->gl_inv_diag) {
         set_error("sipg_apply_pjacobi: needs sipg_compute_gl_diagonal first");
         return SIPG_E_ARG;
@@ -493,6 +570,7 @@ int sipg_cg_solve(const sipg_op* op, const double* b, double* x, double rel_tol,
                   sipg_solve_info* info, void* stream) {
     if (!op || !b || !x || !info) { set_error("sipg_cg_solve: null argument"); return SIPG_E_ARG; }
     if (op->dtype != SIPG_F64) { set_error("sipg_cg_solve: needs an SIPG_F64 operator"); return SIPG_E_ARG; }
+    if (is_inner_slab(op)) { set_error("sipg_cg_solve: not for a slab with neighbours"); return SIPG_E_ARG; }
     if (!(rel_tol > 0.0) || max_iter < 0) { set_error("sipg_cg_solve: rel_tol must be > 0, max_iter >= 0"); return SIPG_E_ARG; }
     if (ranges_overlap(b, x, size_t(op->ndofs) * 8)) { set_error("sipg_cg_solve: b and x overlap"); return SIPG_E_ARG; }
     std::memset(info, 0, sizeof(*info));
@@ -503,6 +581,7 @@ int sipg_cg_solve_static(const sipg_op* op, const double* b, double* x, double r
                          sipg_solve_info* info, void* stream) {
     if (!op || !b || !x || !info) { set_error("sipg_cg_solve_static: null argument"); return SIPG_E_ARG; }
     if (op->dtype != SIPG_F64) { set_error("sipg_cg_solve_static: needs an SIPG_F64 operator"); return SIPG_E_ARG; }
+    if (is_inner_slab(op)) { set_error("sipg_cg_solve_static: not for a slab with neighbours"); return SIPG_E_ARG; }
     if (!(rel_tol > 0.0) || max_iter < 0) {
         set_error("sipg_cg_solve_static: rel_tol must be > 0, max_iter >= 0");
         return SIPG_E_ARG;

@@ -122,6 +122,10 @@ int sipg_batch_create(int nops, const sipg_op* const* ops, const void* const* x,
             set_error("sipg_batch_create: null operator or vector at entry " + std::to_string(i));
             return SIPG_E_ARG;
         }
+        if (ops[i]->mesh.z0 > 0 || ops[i]->mesh.z0 + ops[i]->nc[2] < ops[i]->mesh.nzg) {
+            set_error("sipg_batch_create: entry " + std::to_string(i) + " is a slab with neighbours");
+            return SIPG_E_ARG;
+        }
         if (device >= 0 && ops[i]->device != device) {
             set_error("sipg_batch_create: operators live on different devices");
             return SIPG_E_ARG;

@@ -15,7 +15,7 @@ namespace sipg {
 template <typename T, int GEOM>
 __global__ void gl_diagonal_kernel(const T* __restrict__ tab, int n, const T* __restrict__ cgeom,
                                    const T* __restrict__ fg0, const T* __restrict__ fg1,
-                                   const T* __restrict__ fg2, int nx, int ny, int nz,
+                                   const T* __restrict__ fg2, int nx, int ny, int nz, int z0, int nzg,
                                    T* __restrict__ diag, T* __restrict__ inv_diag) {
     const TableLayout TL(n);
     const int cell = blockIdx.x;
@@ -58,7 +58,9 @@ __global__ void gl_diagonal_kernel(const T* __restrict__ tab, int n, const T* __
         const int layer = s ? n - 1 : 0;
         if (ii[d] != layer) continue;
         const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
-        const bool interior = s ? idx[d] + 1 < nd[d] : idx[d] > 0;
+        // on a z-slab the faces at its z boundaries are interior faces of the mesh
+        const int gi = d == 2 ? idx[2] + z0 : idx[d], gn = d == 2 ? nzg : nd[d];
+        const bool interior = s ? gi + 1 < gn : gi > 0;
         int fi[3] = {idx[0], idx[1], idx[2]};
         fi[d] += s;
         int64_t fidx, nf;
@@ -105,14 +107,14 @@ int launch_gl_diagonal(const sipg_op* op, void* diag, hipStream_t st) {
         k<<<nb, bs, 0, st>>>(static_cast<const T*>(op->tables), op->n, static_cast<const T*>(op->cell_geom),
                              static_cast<const T*>(op->face_geom[0]), static_cast<const T*>(op->face_geom[1]),
                              static_cast<const T*>(op->face_geom[2]), op->nc[0], op->nc[1], op->nc[2],
-                             static_cast<T*>(diag), static_cast<T*>(op->gl_inv_diag));
+                             op->mesh.z0, op->mesh.nzg, static_cast<T*>(diag), static_cast<T*>(op->gl_inv_diag));
     } else {
         using T = float;
         auto k = op->geom == GEOM_CELL ? gl_diagonal_kernel<T, GEOM_CELL> : gl_diagonal_kernel<T, GEOM_QPOINT>;
         k<<<nb, bs, 0, st>>>(static_cast<const T*>(op->tables), op->n, static_cast<const T*>(op->cell_geom),
                              static_cast<const T*>(op->face_geom[0]), static_cast<const T*>(op->face_geom[1]),
                              static_cast<const T*>(op->face_geom[2]), op->nc[0], op->nc[1], op->nc[2],
-                             static_cast<T*>(diag), static_cast<T*>(op->gl_inv_diag));
+                             op->mesh.z0, op->mesh.nzg, static_cast<T*>(diag), static_cast<T*>(op->gl_inv_diag));
     }
     SIPG_HIP(hipGetLastError());
     return SIPG_OK;

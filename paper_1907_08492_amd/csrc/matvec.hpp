@@ -59,6 +59,11 @@ struct MatvecParams {
     const T* __restrict__ b;
     T* __restrict__ uo;
     double sigma, theta;   // double in both precisions: one parameter layout
+    // slab of a z-partition: the neighbour layers across its lower / upper
+    // z boundary (null: a boundary face of the mesh), NL layers of n^2 values
+    // per (x, y) column
+    const T* __restrict__ ghost_lo;
+    const T* __restrict__ ghost_hi;
 };
 
 // Epilogues of the product kernel, applied per cell once y = A x is known:
@@ -91,6 +96,8 @@ inline MatvecParams<T> matvec_params(const sipg_op* op, const void* x, void* y) 
     p.uo = nullptr;
     p.sigma = 0.0;
     p.theta = 0.0;
+    p.ghost_lo = nullptr;
+    p.ghost_hi = nullptr;
     return p;
 }
 
@@ -284,10 +291,12 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     const int fc = lane / (2 * N), fs = (lane / N) & 1, fab = lane % N;
     const bool fact = lane < ncb * 2 * N;
     int fnb = -1, fidx = 0;
+    int gcol = -1;                   // (x, y) column of a ghost neighbour (slab z boundary)
     if (fact) {
         int ix, iy, iz;
         cell_coords(bx, by, bz, fc, p.nx, p.ny, ix, iy, iz);
         face_topology(ix, iy, iz, 2 * wave + fs, p.nx, p.ny, p.nz, fnb, fidx);
+        if (wave == 2 && fnb < 0 && (fs ? p.ghost_hi : p.ghost_lo)) gcol = ix + p.nx * iy;
     }
 
     // The workgroup's x tile, one contiguous range, as XPER loads per thread
@@ -383,6 +392,15 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 for (int j = 0; j < Ly::NL; ++j) load_run<N>(xn + face_gidx<N, D>(Ly::layer(1 - fs, j), 0, fab), nbv[j]);
             }
         }
+        if constexpr (D == 2) {
+            // a neighbour in another slab: its layers Ly::layer(1 - fs, j)
+            // packed per column (sipg_pack_ghost), in the same row order
+            if (gcol >= 0) {
+                const T* __restrict__ xn = (fs ? p.ghost_hi : p.ghost_lo) + size_t(gcol) * (Ly::NL * N2);
+#pragma unroll
+                for (int j = 0; j < Ly::NL; ++j) load_run<N>(xn + face_gidx<N, D>(j, 0, fab), nbv[j]);
+            }
+        }
         if constexpr (EARLY) load_frec(dc, 3);
     });
     // --------------------------------------------------------------- x tile
@@ -415,7 +433,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         constexpr int D = decltype(dc)::value;
         constexpr int t1 = D == 0 ? 1 : 0, t2 = D == 2 ? 1 : 2;
         const int s = fs, c = fc, rc = fab;   // rc: this lane's row (G) / column (F)
-        const bool interior = fnb >= 0;
+        const bool interior = fnb >= 0 || gcol >= 0;
         T r[N];
         auto put_row = [&](int m, const T* v) {
             T* o = fel(m, D, c, s) + rc * FR;

@@ -23,22 +23,27 @@ static int set_lds_limit(K kernel) {
 }
 
 template <int N, int BASIS, typename T, int GEOM>
-static int launch_one(const sipg_op* op, const void* x, void* y, hipStream_t st) {
+static int launch_one(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g) {
     auto kern = &sipg_matvec_kernel<N, BASIS, T, GEOM>;
     if (int rc = set_lds_limit<N, BASIS, T, GEOM, 0>(kern)) return rc;
     const unsigned nblk = unsigned((op->ncells + cells_per_block(N) - 1) / cells_per_block(N));
-    kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(matvec_params<T>(op, x, y));
+    MatvecParams<T> p = matvec_params<T>(op, x, y);
+    p.ghost_lo = static_cast<const T*>(g.lo);
+    p.ghost_hi = static_cast<const T*>(g.hi);
+    kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
     SIPG_HIP(hipGetLastError());
     return SIPG_OK;
 }
 
 // y = A x and z = P^-1 y (eq. (jacobi)) in one pass; op->gl_inv_diag is set.
 template <int N, int BASIS, typename T, int GEOM>
-static int launch_one_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st) {
+static int launch_one_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st, Ghosts g) {
     auto kern = &sipg_matvec_pjacobi_kernel<N, BASIS, T, GEOM>;
     if (int rc = set_lds_limit<N, BASIS, T, GEOM, 2>(kern)) return rc;
     const unsigned nblk = unsigned((op->ncells + cells_per_block(N) - 1) / cells_per_block(N));
     MatvecParams<T> p = matvec_params<T>(op, x, y);
+    p.ghost_lo = static_cast<const T*>(g.lo);
+    p.ghost_hi = static_cast<const T*>(g.hi);
     p.dinv = static_cast<const T*>(op->gl_inv_diag);
     p.z = static_cast<T*>(z);
     kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
@@ -126,16 +131,17 @@ static int dispatch_hl(int dtype, int geom, F&& launch) {
 #define SIPG_MATVEC_DEGREE(NV)                                                                          \
     namespace sipg {                                                                                    \
     template <>                                                                                         \
-    int launch_matvec_n<NV>(const sipg_op* op, const void* x, void* y, hipStream_t st) {                \
+    int launch_matvec_n<NV>(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts gh) {     \
         return dispatch<NV>(op->basis, op->dtype, matvec_geom(op), [&](auto b, auto t, auto g) {        \
-            return launch_one<NV, decltype(b)::value, decltype(t), decltype(g)::value>(op, x, y, st);   \
+            return launch_one<NV, decltype(b)::value, decltype(t), decltype(g)::value>(op, x, y, st, gh); \
         });                                                                                             \
     }                                                                                                   \
     template <>                                                                                         \
-    int launch_matvec_pjacobi_n<NV>(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st) { \
+    int launch_matvec_pjacobi_n<NV>(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st,  \
+                                    Ghosts gh) {                                                        \
         return dispatch<NV>(op->basis, op->dtype, matvec_geom(op), [&](auto b, auto t, auto g) {        \
             return launch_one_pjacobi<NV, decltype(b)::value, decltype(t), decltype(g)::value>(op, x, y, z, \
-                                                                                                 st);   \
+                                                                                                 st, gh); \
         });                                                                                             \
     }                                                                                                   \
     template <>                                                                                         \

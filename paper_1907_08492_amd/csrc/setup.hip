@@ -13,8 +13,9 @@ namespace sipg {
 // widths w.
 __device__ void brick_point(const MeshDev& m, const int i[3], const double xi[3], double X[3], double w[3]) {
     for (int d = 0; d < 3; ++d) {
-        w[d] = i[d] == m.n[d] - 1 ? m.hl[d] : m.h[d];
-        X[d] = m.lo[d] + i[d] * m.h[d] + xi[d] * w[d];
+        const int gi = d == 2 ? i[2] + m.z0 : i[d], gn = d == 2 ? m.nzg : m.n[d];   // index in the mesh
+        w[d] = gi == gn - 1 ? m.hl[d] : m.h[d];
+        X[d] = m.lo[d] + gi * m.h[d] + xi[d] * w[d];
     }
 }
 
@@ -123,6 +124,27 @@ __global__ void cell_geometry_kernel(MeshDev m, Rule r, T* __restrict__ out,
     vol[c] = v;
 }
 
+// Volumes of the cells across a slab's z boundaries, summed in the order of
+// cell_geometry_kernel: below the slab gvol[column], above it
+// gvol[nx ny + column] (column = ix + nx iy).  One thread per cell.
+__global__ void ghost_volume_kernel(MeshDev m, Rule r, double* __restrict__ gvol) {
+    const int64_t ncol = int64_t(m.n[0]) * m.n[1];
+    const int64_t t = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
+    if (t >= 2 * ncol) return;
+    const int64_t col = t % ncol;
+    const int ix = int(col % m.n[0]), iy = int(col / m.n[0]), iz = t < ncol ? -1 : m.n[2];
+    const int n = r.n, n3 = n * n * n;
+    double v = 0.0;
+    for (int q = 0; q < n3; ++q) {
+        const int q1 = q % n, q2 = (q / n) % n, q3 = q / (n * n);
+        double J[9], Ji[9];
+        map_jacobian(m, ix, iy, iz, r.x[q1], r.x[q2], r.x[q3], J);
+        const double det = inverse3(J, Ji);
+        v += det * (r.w[q1] * r.w[q2] * r.w[q3]);
+    }
+    gvol[t] = v;
+}
+
 // Face records for the faces normal to direction d, one thread per face.
 // Record = {JxW sigma, JxW J_L^-1 n, JxW J_R^-1 n} with n the unit normal
 // pointing from the lower cell L to the upper cell R; on boundary faces the
@@ -132,7 +154,7 @@ __global__ void cell_geometry_kernel(MeshDev m, Rule r, T* __restrict__ out,
 // weight-free constant of an affine face.
 template <typename T, int MODE>
 __global__ void face_geometry_kernel(MeshDev m, Rule r, int d, double sigma0, T* __restrict__ out,
-                                     const double* __restrict__ vol, int64_t nfaces) {
+                                     const double* __restrict__ vol, const double* __restrict__ gvol, int64_t nfaces) {
     const int64_t f = int64_t(blockIdx.x) * blockDim.x + threadIdx.x;
     if (f >= nfaces) return;
     int ext[3] = {m.n[0], m.n[1], m.n[2]};
@@ -141,11 +163,19 @@ __global__ void face_geometry_kernel(MeshDev m, Rule r, int d, double sigma0, T*
     idx[0] = f % ext[0];
     idx[1] = (f / ext[0]) % ext[1];
     idx[2] = f / (int64_t(ext[0]) * ext[1]);
-    const bool hasL = idx[d] > 0, hasR = idx[d] < m.n[d];
+    // a side exists if its cell is in the mesh; on a slab, the cells across
+    // its z boundaries are in the mesh but not in the slab: their volumes are
+    // gvol[column] (below) and gvol[nx ny + column] (above)
+    const int gz = d == 2 ? idx[2] + m.z0 : idx[d], gn = d == 2 ? m.nzg : m.n[d];
+    const bool hasL = gz > 0, hasR = gz < gn;
     int cl[3] = {idx[0], idx[1], idx[2]}, cr[3] = {idx[0], idx[1], idx[2]};
     cl[d] -= 1;
-    const int64_t cellL = hasL ? cl[0] + int64_t(m.n[0]) * (cl[1] + int64_t(m.n[1]) * cl[2]) : -1;
-    const int64_t cellR = hasR ? cr[0] + int64_t(m.n[0]) * (cr[1] + int64_t(m.n[1]) * cr[2]) : -1;
+    const int64_t col = idx[0] + int64_t(m.n[0]) * idx[1];
+    const bool ghostL = d == 2 && hasL && cl[2] < 0, ghostR = d == 2 && hasR && cr[2] >= m.n[2];
+    const int64_t cellL = hasL && !ghostL ? cl[0] + int64_t(m.n[0]) * (cl[1] + int64_t(m.n[1]) * cl[2]) : -1;
+    const int64_t cellR = hasR && !ghostR ? cr[0] + int64_t(m.n[0]) * (cr[1] + int64_t(m.n[1]) * cr[2]) : -1;
+    const double volL = ghostL ? gvol[col] : hasL ? vol[cellL] : 0.0;
+    const double volR = ghostR ? gvol[int64_t(m.n[0]) * m.n[1] + col] : hasR ? vol[cellR] : 0.0;
     const int t1 = d == 0 ? 1 : 0, t2 = d == 2 ? 1 : 2;
     const int n = r.n, n2 = n * n;
     const int npts = MODE == GEOM_QPOINT ? n2 : 1;
@@ -154,8 +184,8 @@ __global__ void face_geometry_kernel(MeshDev m, Rule r, int d, double sigma0, T*
         double sigma = 0.0;
         if (pass == 1) {
             double ih = 0.0;
-            if (hasL) ih = fmax(ih, area / vol[cellL]);
-            if (hasR) ih = fmax(ih, area / vol[cellR]);
+            if (hasL) ih = fmax(ih, area / volL);
+            if (hasR) ih = fmax(ih, area / volR);
             sigma = sigma0 * ih;
         }
         for (int q = 0; q < npts; ++q) {
@@ -306,8 +336,11 @@ int build_geometry(sipg_op* op, const std::vector<double>& xq, const std::vector
     for (int i = 0; i < op->n; ++i) { r.x[i] = xq[i]; r.w[i] = wq[i]; }
     // stream-ordered temporaries: a plain free would wait for the whole device
     double* vol = nullptr;
+    double* gvol = nullptr;
     int* bad = nullptr;
+    const int64_t ncol = int64_t(op->nc[0]) * op->nc[1];
     SIPG_HIP(hipMallocAsync(reinterpret_cast<void**>(&vol), sizeof(double) * op->ncells, st));
+    SIPG_HIP(hipMallocAsync(reinterpret_cast<void**>(&gvol), sizeof(double) * 2 * ncol, st));
     SIPG_HIP(hipMallocAsync(reinterpret_cast<void**>(&bad), sizeof(int), st));
     SIPG_HIP(hipMemsetAsync(bad, 0, sizeof(int), st));
     const int bs = 128;
@@ -320,19 +353,24 @@ int build_geometry(sipg_op* op, const std::vector<double>& xq, const std::vector
     SIPG_HIP(hipGetLastError());
     fdm_cell_kernel<T><<<gc, bs, 0, st>>>(op->mesh, static_cast<T*>(op->fdm_cell), op->ncells);
     SIPG_HIP(hipGetLastError());
+    if (op->mesh.z0 > 0 || op->mesh.z0 + op->nc[2] < op->mesh.nzg) {
+        ghost_volume_kernel<<<unsigned((2 * ncol + bs - 1) / bs), bs, 0, st>>>(op->mesh, r, gvol);
+        SIPG_HIP(hipGetLastError());
+    }
     const double sigma0 = op->eta * double(op->degree + 1) * double(op->degree + 1);
     for (int d = 0; d < 3; ++d) {
         const unsigned gf = unsigned((op->nfaces[d] + bs - 1) / bs);
         T* fg = static_cast<T*>(op->face_geom[d]);
         if (op->geom == GEOM_QPOINT)
-            face_geometry_kernel<T, GEOM_QPOINT><<<gf, bs, 0, st>>>(op->mesh, r, d, sigma0, fg, vol, op->nfaces[d]);
+            face_geometry_kernel<T, GEOM_QPOINT><<<gf, bs, 0, st>>>(op->mesh, r, d, sigma0, fg, vol, gvol, op->nfaces[d]);
         else
-            face_geometry_kernel<T, GEOM_CELL><<<gf, bs, 0, st>>>(op->mesh, r, d, sigma0, fg, vol, op->nfaces[d]);
+            face_geometry_kernel<T, GEOM_CELL><<<gf, bs, 0, st>>>(op->mesh, r, d, sigma0, fg, vol, gvol, op->nfaces[d]);
         SIPG_HIP(hipGetLastError());
     }
     int hbad = 0;
     SIPG_HIP(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
     SIPG_HIP(hipFreeAsync(vol, st));
+    SIPG_HIP(hipFreeAsync(gvol, st));
     SIPG_HIP(hipFreeAsync(bad, st));
     SIPG_HIP(hipStreamSynchronize(st));
     if (hbad) {

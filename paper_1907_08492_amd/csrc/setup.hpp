@@ -11,15 +11,24 @@ template <typename T>
 int build_geometry(sipg_op* op, const std::vector<double>& xq, const std::vector<double>& wq,
                    hipStream_t st);
 
+// Neighbour layers across the z boundaries of a slab operator (null: none).
+struct Ghosts {
+    const void* lo = nullptr;
+    const void* hi = nullptr;
+};
+
 // y = A x for the operator (dispatch over degree, basis, precision, geometry).
-int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st);
+int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g = {});
 // Per-degree launchers (one translation unit each).
 template <int N>
-int launch_matvec_n(const sipg_op* op, const void* x, void* y, hipStream_t st);
+int launch_matvec_n(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g);
 // y = A x and z = P^-1 y of eq. (jacobi) in one pass (needs op->gl_inv_diag).
-int launch_matvec_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st);
+int launch_matvec_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st, Ghosts g = {});
 template <int N>
-int launch_matvec_pjacobi_n(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st);
+int launch_matvec_pjacobi_n(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st, Ghosts g);
+// The layers of the slab's bottom (side 0) or top (side 1) cells that the
+// neighbouring slab reads as its ghost layers.
+int launch_pack_ghost(const sipg_op* op, int side, const void* x, void* out, hipStream_t st);
 // One Chebyshev smoothing step fused into the product, Hermite-like basis
 // only: uo = u + sigma (u - uo) + theta P^-1 (b - A u), P^-1 by mode
 // (SIPG_BC_PJACOBI or SIPG_BC_FDM); sigma = 0 does not read uo.  u, uo, b

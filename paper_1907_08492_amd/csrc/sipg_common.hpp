@@ -140,12 +140,15 @@ inline bool allocator_valid(const sipg_allocator* a) { return !a || (a->alloc !=
 
 // Mesh description in the form the device kernels take it: in direction d
 // cell i spans [lo + i h, lo + i h + w] with w = h, except the last cell,
-// whose width is hl (hl = h on a uniform brick).
+// whose width is hl (hl = h on a uniform brick).  An operator on a z-slab of
+// a mesh holds the cells z0 <= iz < z0 + n[2] of a mesh of nzg cells along z:
+// local cell iz is mesh cell z0 + iz (z0 = 0, nzg = n[2] otherwise).
 struct MeshDev {
     int n[3];
     double lo[3], h[3], hl[3];
     double L[9];
     double a;
+    int z0, nzg;
 };
 
 }  // namespace sipg

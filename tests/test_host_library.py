@@ -188,3 +188,15 @@ def test_graded_mesh_and_multigrid_option_errors_without_gpu():
     assert s.graded_coarsening == 0 and s.coarse_direct_max_dofs == 256
     s.coarse_direct_max_dofs = 5000
     assert P.lib.sipg_server_create(C.byref(s), None, C.byref(h)) == -1
+
+
+def test_slab_argument_errors_without_gpu():
+    from workloads import unit_cube
+    h = C.c_void_p()
+    m = P.make_mesh(unit_cube((2, 2, 4)))
+    for z0, z1 in ((2, 2), (3, 1), (-1, 2), (0, 5)):
+        assert P.lib.sipg_setup_slab(C.byref(m), z0, z1, 2, 2.0, 0, 0, 0, None, None, C.byref(h)) == -1, (z0, z1)
+        assert "z0 < z1" in P.lib.sipg_last_error().decode()
+    assert P.lib.sipg_apply_slab(None, None, None, None, None, None, None) == -1
+    assert P.lib.sipg_pack_ghost(None, 0, None, None, None) == -1
+    assert P.lib.sipg_ghost_size(None) == -1
