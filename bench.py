@@ -35,6 +35,7 @@ sys.path.insert(0, ROOT)
 HBM_PEAK_GBS = 8000.0          # MI355X HBM3E
 FP64_PEAK_TFLOPS = 78.6        # MI355X FP64 vector
 FP32_PEAK_TFLOPS = 157.3       # MI355X FP32 vector (packed FP32; the kernels issue unpacked FP32)
+XGMI_LINK_GBS = 153.0          # one MI355X xGMI link
 # FLOP per unknown of the matrix-free product, Table 4 (Hermite-like / nodal GL)
 TABLE4_FLOP = {"hermite_like": {1: 244, 2: 191, 3: 218, 4: 206, 5: 225, 7: 241},
                "nodal_gl": {1: 258, 2: 210, 3: 240, 4: 229, 5: 250, 7: 267},
@@ -295,6 +296,42 @@ def batch_benchmark(torch, P, dtype: str, reps: int = 10, count: int = 256):
     return out
 
 
+def slab_benchmark(torch, P, launches: int = 200, gpus: int = 8):
+    """One GPU's share of the headline step on `gpus` GPUs: the middle z-slab
+    (64 x 64 x 64/gpus cells) of the 64^3 deformed mesh, k = 4, FP64, with
+    ghost layers from both neighbours.  Times the slab step (y = A x and
+    z = P^-1 y with the ghost layers, sipg_apply_slab) and the packing of the
+    two ghost buffers a slab sends; the exchange itself (xGMI) is not run."""
+    from workloads import CONFIGS, uniform_vector
+    cfg = CONFIGS["scale_k4_64c_deformed"]
+    nz = cfg.mesh.n[2]
+    w = nz // gpus
+    z0 = (gpus // 2 - 1) * w
+    op = P.Operator(cfg.mesh, cfg.degree, cfg.eta, slab=(z0, z0 + w))
+    op.compute_gl_diagonal(return_diag=False)
+    x = torch.from_numpy(uniform_vector(op.ndofs, 0)).cuda()
+    lo = torch.from_numpy(uniform_vector(op.ghost_size(), 1)).cuda()
+    hi = torch.from_numpy(uniform_vector(op.ghost_size(), 2)).cuda()
+    y, z = op.empty(), op.empty()
+    g0, g1 = torch.empty_like(lo), torch.empty_like(hi)
+    step = time_launches(torch, lambda i: op.apply_slab(x, lo, hi, y, z), launches, 10)
+    pack = time_launches(torch, lambda i: (op.pack_ghost(0, x, g0), op.pack_ghost(1, x, g1)), launches, 10)
+    step_s = float(np.mean(step)) * 1e-3
+    n3 = (cfg.degree + 1) ** 3
+    bpd = alg_bytes_per_dof(cfg.mesh, cfg.degree, 8, True) + 16.0   # as the whole mesh's step
+    ghost_bytes = 2 * 8 * op.ghost_size()
+    out = {"gpus": gpus, "cells": [cfg.mesh.n[0], cfg.mesh.n[1], w], "z_range": [z0, z0 + w], "ndofs": op.ndofs,
+           "step_ms": step_s * 1e3, "dof_per_s": op.ndofs / step_s,
+           "alg_GBs": (bpd * op.ndofs + ghost_bytes) / step_s / 1e9,
+           "hbm_frac": (bpd * op.ndofs + ghost_bytes) / step_s / 1e9 / HBM_PEAK_GBS,
+           "pack_ms": float(np.mean(pack)), "ghost_bytes_sent": ghost_bytes,
+           # one xGMI link per neighbour, both directions at once
+           "xgmi_ms_per_neighbour": 8 * op.ghost_size() / XGMI_LINK_GBS / 1e6,
+           "cells_per_ghost_layer": cfg.mesh.n[0] * cfg.mesh.n[1], "dofs_per_cell": n3}
+    op.close()
+    return out
+
+
 def solver_benchmark(torch, P, reps: int = 3):
     """Multigrid-preconditioned CG (Section 6) on 48^3 cells of the deformed
     unit cube, k = 5, manufactured sine solution, residual 1e-10: mixed
@@ -415,6 +452,7 @@ def main():
                     help="also run one plain 1 GiB device copy (counter calibration)")
     ap.add_argument("--no-batch", action="store_true", help="skip the 256-operator batched leg")
     ap.add_argument("--no-solver", action="store_true", help="skip the multigrid solver leg")
+    ap.add_argument("--no-slab", action="store_true", help="skip the per-GPU slab leg")
     ap.add_argument("--serve-seconds", type=float, default=60.0,
                     help="arrival window of the serving leg (0 skips it; 60 is the full stream)")
     ap.add_argument("--serve-rate", type=float, default=200.0)
@@ -629,6 +667,11 @@ def main():
             del vx, vy
             torch.cuda.empty_cache()
         out["variants"] = variants
+
+    if not args.no_slab:
+        print("[bench] one GPU's slab of the step (8-way z partition)", file=sys.stderr, flush=True)
+        out["slab"] = slab_benchmark(torch, P)
+        torch.cuda.empty_cache()
 
     if not args.no_solver:
         print("[bench] multigrid solver 48^3 k=5", file=sys.stderr, flush=True)
