@@ -14,6 +14,8 @@ CASES = {
     "deformed": (unit_cube((5, 4, 7), 0.1), [(0, 2), (2, 5), (5, 7)]),
     "paper_affine": (paper_affine_brick((3, 4, 6)), [(0, 3), (3, 6)]),
     "cartesian_thin": (unit_cube((4, 3, 5)), [(0, 1), (1, 2), (2, 5)]),
+    # graded brick: the narrower last cell of z lies in the top slab
+    "graded_deformed": (Mesh(n=(3, 4, 5), width=(0.4, 0.3, 0.22), deform_amp=0.1), [(0, 2), (2, 5)]),
 }
 
 
@@ -60,6 +62,19 @@ def test_slabs_reproduce_the_whole_operator(case, basis, k):
     per = mesh.n[0] * mesh.n[1] * (k + 1) ** 3
     e2, emax = rel_errors(y[z0 * per:z1 * per].cpu().numpy(), ref)
     assert e2 <= 1e-12 and emax <= 1e-12, (e2, emax)
+    whole.close()
+
+
+@pytest.mark.parametrize("basis", ["nodal_gl", "nodal_gauss"])
+def test_slabs_fp32_nodal(basis):
+    torch, P = require_gpu()
+    banner(f"slab f32 {basis}")
+    mesh, splits = CASES["deformed"]
+    whole = P.Operator(mesh, 3, 2.0, basis, "f32")
+    x = torch.from_numpy(uniform_vector(whole.ndofs, 9)).to("cuda", torch.float32)
+    y_ref = whole.apply(x)
+    y, _ = _slab_products(torch, P, mesh, 3, basis, "f32", splits, x)
+    assert float((y - y_ref).abs().max()) <= 1e-6 * float(y_ref.abs().max())
     whole.close()
 
 
