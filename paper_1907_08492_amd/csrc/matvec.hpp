@@ -201,9 +201,13 @@ __device__ __forceinline__ void wave_sync() {
 // n >= 7 with per-cell metric terms, so that two workgroups share a compute
 // unit (the few spilled registers cost less than the idle SIMD); with
 // per-point metric terms the spill traffic would compete with the HBM
-// stream, so those keep one.
-template <int N, int GEOM>
-constexpr int matvec_min_waves() { return (N >= 7 && GEOM != GEOM_QPOINT) ? 2 : 1; }
+// stream, so those keep one.  The FP32 Hermite-like per-point kernels at
+// n = 6 fit five wavefronts per SIMD without spills (95 registers instead of
+// 100), which lets the LDS limit of six workgroups per compute unit bind.
+template <int N, int BASIS, typename T, int GEOM>
+constexpr int matvec_min_waves() {
+    return (N >= 7 && GEOM != GEOM_QPOINT) ? 2 : (N == 6 && BASIS == 0 && sizeof(T) == 4 && GEOM == GEOM_QPOINT) ? 5 : 1;
+}
 
 // XCD-aware order: consecutive workgroups are dispatched round-robin over
 // the 8 XCDs, so give each XCD a contiguous range of block indices (a range
@@ -1114,7 +1118,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
 // One operator: workgroup b handles cells b*CPB ... of it, in the
 // z-interleaved XCD order (P = blocks per z-layer of cells, rounded).
 template <int N, int BASIS, typename T, int GEOM>
-__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
+__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, BASIS, T, GEOM>()))
 sipg_matvec_kernel(MatvecParams<T> p) {
     constexpr int CPB = cells_per_block(N);
     const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
@@ -1124,7 +1128,7 @@ sipg_matvec_kernel(MatvecParams<T> p) {
 // The same product followed, cell by cell, by P^-1 of eq. (jacobi): y = A x
 // and z = P^-1 y in one pass (p.dinv, p.z set).
 template <int N, int BASIS, typename T, int GEOM>
-__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
+__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, BASIS, T, GEOM>()))
 sipg_matvec_pjacobi_kernel(MatvecParams<T> p) {
     constexpr int CPB = cells_per_block(N);
     const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
@@ -1135,7 +1139,7 @@ sipg_matvec_pjacobi_kernel(MatvecParams<T> p) {
 // p.uo, p.dinv, p.sigma, p.theta set): uo <- u + sigma (u - uo) + theta P^-1
 // (b - A u), P^-1 point Jacobi (EPI_CHEB_PJ) or block Jacobi (EPI_CHEB_FDM).
 template <int N, int BASIS, typename T, int GEOM, int EPI>
-__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
+__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, BASIS, T, GEOM>()))
 sipg_matvec_cheb_kernel(MatvecParams<T> p) {
     constexpr int CPB = cells_per_block(N);
     const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
@@ -1147,7 +1151,7 @@ sipg_matvec_cheb_kernel(MatvecParams<T> p) {
 // indices blk_first[o] ... blk_first[o+1]-1 of the concatenated list, and
 // blk_op[b] names the operator of block b.
 template <int N, int BASIS, typename T, int GEOM>
-__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, GEOM>()))
+__global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, BASIS, T, GEOM>()))
 sipg_matvec_batched_kernel(const MatvecParams<T>* __restrict__ ops, const int* __restrict__ blk_op,
                            const int* __restrict__ blk_first) {
     const int b = xcd_block(blockIdx.x, gridDim.x);
