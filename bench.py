@@ -278,6 +278,25 @@ def batch_benchmark(torch, P, dtype: str, reps: int = 10, count: int = 256):
     for op, x, y in zip(ops, xs, ys):
         alone.append(float(timed(lambda: op.apply(x, y), 3).min()))
     alone = np.array(alone)
+    # each half of the mix alone, against its own roofline: the affine half is
+    # instruction-bound (fraction of the vector peak by the kernels' own FLOP
+    # counts), the deformed half HBM-bound
+    halves = {}
+    peak = FP64_PEAK_TFLOPS if dtype == "f64" else FP32_PEAK_TFLOPS
+    for name, sel in (("affine", range(count // 2)), ("deformed", range(count // 2, count))):
+        sel = list(sel)
+        hb = P.Batch([ops[i] for i in sel], [xs[i] for i in sel], [ys[i] for i in sel])
+        hb.apply()
+        th = timed(hb.apply, reps).mean()
+        hd = sum(ops[i].ndofs for i in sel)
+        hbytes = sum(alg_bytes_per_dof(specs[i].mesh, specs[i].degree, esz, specs[i].mesh.deformed) * ops[i].ndofs
+                     for i in sel)
+        hflop = sum(kernel_flops_per_dof(specs[i].degree, "hermite_like",
+                                         "qpoint" if specs[i].mesh.deformed else
+                                         ("diag" if ops[i].info.diagonal_metric else "cell")) * ops[i].ndofs for i in sel)
+        halves[name] = {"operators": len(sel), "ndofs": hd, "avg_ms": th * 1e3, "dof_per_s": hd / th,
+                        "hbm_frac": hbytes / th / 1e9 / HBM_PEAK_GBS, "valu_frac": hflop / th / (peak * 1e12)}
+        hb.close()
     out = {"dtype": dtype, "operators": count, "ndofs": ndofs, "launches": int(b.info.launches),
            "streams": int(b.info.streams),
            "batched": {"dof_per_s": ndofs / tb.mean(), "avg_ms": tb.mean() * 1e3, "min_ms": tb.min() * 1e3,
@@ -289,7 +308,7 @@ def batch_benchmark(torch, P, dtype: str, reps: int = 10, count: int = 256):
                      "per_operator_groups": int(b.info.per_operator_groups)},
            "alone_ms": {"p50": float(np.percentile(alone, 50)) * 1e3, "p90": float(np.percentile(alone, 90)) * 1e3,
                         "max": float(alone.max()) * 1e3, "sum": float(alone.sum()) * 1e3},
-           "alg_bytes": alg}
+           "alg_bytes": alg, "halves": halves}
     b.close()
     for op in ops:
         op.close()
