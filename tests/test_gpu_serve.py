@@ -138,3 +138,30 @@ def test_server_with_block_jacobi_smoother_matches_direct_solve():
     srv.close()
     mg.close()
     op.close()
+
+
+def test_server_with_graded_levels_matches_direct_solve():
+    """The server's graded coarsening option (odd meshes coarsened through
+    graded bricks down to a dense coarse solve) gives the direct solve's
+    result, bit for bit."""
+    torch, P = require_gpu()
+    banner("serve graded levels")
+    mesh = unit_cube(9)
+    amps, waves = [1.0, 0.3], [(1, 1, 1), (1, 2, 3)]
+    srv = P.Server(workers=2, precision="mixed", graded_coarsening=1, coarse_direct_max_dofs=256)
+    t = srv.submit(P.Server.make_request(mesh, 3, amps, waves, rel_tol=1e-9))
+    res = srv.wait(t)
+    assert res["status"] == 0 and res["rel_residual"] <= 1e-9
+    op = P.Operator(mesh, 3, 2.0)
+    b = op.assemble_rhs(amps, waves)
+    mg = P.Multigrid(mesh, 3, 2.0, precision="mixed", smoother="fdm", p_coarsening=1, coarse_reduction=10.0,
+                     graded_coarsening=1, coarse_direct_max_dofs=256)
+    assert mg.info.coarse_steps == 0 and mg.info.levels >= 4
+    xd, info = mg.solve(b, rel_tol=1e-9)
+    torch.cuda.synchronize()
+    assert info.iterations == res["iterations"]
+    assert torch.equal(srv.solution(res), xd)
+    srv.release(t)
+    srv.close()
+    mg.close()
+    op.close()
