@@ -456,12 +456,35 @@ int sipg_mg_get_info(const sipg_mg* mg, sipg_mg_info* info);
 /* z = V-cycle(r): one application of the preconditioner (device, double, ndofs). */
 int sipg_mg_apply_vcycle(sipg_mg* mg, const double* r, double* z, void* stream);
 /* Solve A x = b (device, double) to ||b - A x|| <= rel_tol ||b|| with the
- * preconditioned CG; x holds the initial guess.  Blocks the host (one scalar
- * read per convergence check).  Uses the FP64 work vectors allocated by
- * sipg_mg_setup (so concurrent solves on one hierarchy are not allowed).
- * SIPG_E_NOCONV after max_iter iterations (info still filled). */
+ * preconditioned CG; x holds the initial guess, b and x must not overlap.
+ * The stopping test is taken on the device after every iteration and read by
+ * the host with a lag (the device does not wait for the host); x is the
+ * iterate of the first iteration that meets the tolerance.  Blocks the host
+ * until then.  Uses the FP64 work vectors allocated by sipg_mg_setup (so
+ * concurrent solves on one hierarchy are not allowed).  SIPG_E_NOCONV after
+ * max_iter iterations (info still filled). */
 int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int max_iter,
                   sipg_solve_info* info, void* stream);
+/* nrhs right-hand sides of the same problem solved together (Section 6's
+ * solver; several requests for one operator co-scheduled): every product,
+ * smoothing step, transfer and vector update of an iteration is one launch
+ * covering all of them.
+ *   nrhs        1 .. 16
+ *   b, x        device, double, nrhs * ndofs each: right-hand side v at
+ *               b + v * ndofs, x likewise (initial guesses in, solutions out);
+ *               b and x must not overlap
+ *   info        host array of nrhs results
+ * Each right-hand side stops being updated at the first iteration where its
+ * residual meets rel_tol ||b_v||: its iterate and iteration count are those
+ * sipg_mg_solve gives for it alone.  The call returns when all have stopped.  A workspace of the level vectors of nrhs right-hand sides and
+ * four FP64 CG vectors per right-hand side is taken from the solver's
+ * allocator for the call (without one: stream-ordered hipMallocAsync /
+ * hipFreeAsync).  Blocks the host; not concurrent with other solves on the
+ * same hierarchy.  SIPG_E_ARG for bad sizes or overlapping b and x,
+ * SIPG_E_OOM when the workspace cannot be had, SIPG_E_NOCONV when some
+ * right-hand side did not converge within max_iter (info still filled). */
+int sipg_mg_solve_many(sipg_mg* mg, int nrhs, const double* b, double* x, double rel_tol, int max_iter,
+                       sipg_solve_info* info, void* stream);
 
 /* Grid transfer between level `level` and level+1 of the hierarchy (0 =
  * finest), in the V-cycle's precision (float for precision 0, double for 1):
@@ -511,6 +534,11 @@ typedef struct {
                                     served mix the graded levels cost more CG steps than their
                                     cheaper coarse solves save) */
     int32_t coarse_direct_max_dofs; /* sipg_mg_opts.coarse_direct_max_dofs of every solve (256) */
+    int32_t batch_max_rhs;       /* queued requests of one problem (same mesh, degree, basis,
+                                    penalty, rel_tol and max_iter) solved together by one
+                                    sipg_mg_solve_many, at most this many (1..16; 8; 1: each
+                                    request alone) */
+    int64_t batch_max_dofs;      /* ... while their unknowns add up to at most this (2^22) */
 } sipg_server_opts;
 typedef struct {
     sipg_mesh mesh;
@@ -536,6 +564,8 @@ typedef struct {
 } sipg_result;
 typedef struct {
     int64_t queued, completed, cached_hierarchies, used_bytes, peak_bytes;
+    int64_t batched_solves;      /* sipg_mg_solve_many calls over 2 or more requests */
+    int64_t batched_requests;    /* requests solved in those */
 } sipg_server_stats_t;
 typedef struct sipg_server sipg_server;
 

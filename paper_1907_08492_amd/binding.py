@@ -42,7 +42,7 @@ EXPORTED = [
     "sipg_basis_change", "sipg_compute_gl_diagonal", "sipg_cg_solve",
     "sipg_last_error", "sipg_host_tables", "sipg_launch_shape",
     "sipg_mg_default_opts", "sipg_mg_setup", "sipg_mg_destroy", "sipg_mg_get_info",
-    "sipg_mg_apply_vcycle", "sipg_mg_solve", "sipg_mg_transfer", "sipg_mg_level_ndofs",
+    "sipg_mg_apply_vcycle", "sipg_mg_solve", "sipg_mg_solve_many", "sipg_mg_transfer", "sipg_mg_level_ndofs",
     "sipg_assemble_rhs_sines",
     "sipg_server_default_opts", "sipg_server_create", "sipg_submit", "sipg_poll", "sipg_wait",
     "sipg_release", "sipg_server_stats", "sipg_server_destroy", "sipg_copy_device",
@@ -87,7 +87,8 @@ class SipgMgInfo(C.Structure):
 class SipgServerOpts(C.Structure):
     _fields_ = [("hbm_budget_bytes", C.c_int64), ("workers", C.c_int32), ("precision", C.c_int32),
                 ("smoother", C.c_int32), ("p_coarsening", C.c_int32), ("coarse_reduction", C.c_double),
-                ("graded_coarsening", C.c_int32), ("coarse_direct_max_dofs", C.c_int32)]
+                ("graded_coarsening", C.c_int32), ("coarse_direct_max_dofs", C.c_int32),
+                ("batch_max_rhs", C.c_int32), ("batch_max_dofs", C.c_int64)]
 
 
 class SipgRequest(C.Structure):
@@ -105,7 +106,8 @@ class SipgResult(C.Structure):
 
 class SipgServerStats(C.Structure):
     _fields_ = [("queued", C.c_int64), ("completed", C.c_int64), ("cached_hierarchies", C.c_int64),
-                ("used_bytes", C.c_int64), ("peak_bytes", C.c_int64)]
+                ("used_bytes", C.c_int64), ("peak_bytes", C.c_int64), ("batched_solves", C.c_int64),
+                ("batched_requests", C.c_int64)]
 
 
 class SipgBatchInfo(C.Structure):
@@ -162,6 +164,7 @@ lib.sipg_mg_destroy.argtypes = [_vp]
 lib.sipg_mg_get_info.argtypes = [_vp, C.POINTER(SipgMgInfo)]
 lib.sipg_mg_apply_vcycle.argtypes = [_vp, _vp, _vp, _vp]
 lib.sipg_mg_solve.argtypes = [_vp, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
+lib.sipg_mg_solve_many.argtypes = [_vp, C.c_int, _vp, _vp, C.c_double, C.c_int, C.POINTER(SipgSolveInfo), _vp]
 lib.sipg_mg_transfer.argtypes = [_vp, C.c_int, C.c_int, _vp, _vp, _vp]
 lib.sipg_mg_level_ndofs.argtypes = [_vp, C.c_int, C.POINTER(C.c_int64), C.POINTER(C.c_int32)]
 lib.sipg_mg_level_degree.argtypes = [_vp, C.c_int, C.POINTER(C.c_int32)]
@@ -583,6 +586,23 @@ class Multigrid:
         return x, SolveInfo(info.iterations, info.initial_residual, info.final_residual,
                             info.true_residual, rc)
 
+    def solve_many(self, b, x=None, rel_tol: float = 1e-10, max_iter: int = 200, stream=None,
+                   raise_on_noconv: bool = True):
+        """Solve for the rows of b (nrhs x ndofs, at most 16) together
+        (sipg_mg_solve_many); returns x and one SolveInfo per row."""
+        if b.dim() != 2 or b.shape[1] != self.ndofs:
+            raise ValueError("b must have shape (nrhs, ndofs)")
+        if x is None:
+            x = _torch().zeros_like(b)
+        nrhs = int(b.shape[0])
+        infos = (SipgSolveInfo * max(nrhs, 1))()
+        rc = lib.sipg_mg_solve_many(self._h, nrhs, self._vec(b, "b"), self._vec(x, "x"), float(rel_tol),
+                                    int(max_iter), infos, _vp(_stream_ptr(stream)))
+        if rc != SIPG_OK and (rc != SIPG_E_NOCONV or raise_on_noconv):
+            raise SipgError(rc, "sipg_mg_solve_many")
+        return x, [SolveInfo(i.iterations, i.initial_residual, i.final_residual, i.true_residual, rc)
+                   for i in infos[:nrhs]]
+
     def close(self):
         if getattr(self, "_h", None):
             if self._allocator == "torch":
@@ -606,14 +626,16 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 8, precision: str = "mixed",
                  smoother: str = "fdm", p_coarsening: int = 1, coarse_reduction: float = 10.0,
-                 allocator="torch", graded_coarsening: int = 0, coarse_direct_max_dofs: int = 256):
+                 allocator="torch", graded_coarsening: int = 0, coarse_direct_max_dofs: int = 256,
+                 batch_max_rhs: int = 8, batch_max_dofs: int = 1 << 22):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Server needs a GPU (HIP device)")
         torch.cuda.init()
         o = SipgServerOpts(int(hbm_budget_bytes), int(workers), {"mixed": 0, "f64": 1}[precision],
                            SMOOTHERS[smoother], int(p_coarsening), float(coarse_reduction),
-                           int(graded_coarsening), int(coarse_direct_max_dofs))
+                           int(graded_coarsening), int(coarse_direct_max_dofs), int(batch_max_rhs),
+                           int(batch_max_dofs))
         h = _vp()
         _check(lib.sipg_server_create(C.byref(o), _allocator(allocator), C.byref(h)), "sipg_server_create")
         self._h = h

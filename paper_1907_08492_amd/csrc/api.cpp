@@ -139,16 +139,20 @@ static int free_op(sipg_op* op) {
     return SIPG_OK;
 }
 
-int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g) {
+int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g, int nv) {
+    if (nv < 1 || (nv > 1 && (g.lo || g.hi))) {
+        set_error("product: one right-hand side with ghost layers, at least one otherwise");
+        return SIPG_E_ARG;
+    }
     switch (op->n) {
-        case 2: return launch_matvec_n<2>(op, x, y, st, g);
-        case 3: return launch_matvec_n<3>(op, x, y, st, g);
-        case 4: return launch_matvec_n<4>(op, x, y, st, g);
-        case 5: return launch_matvec_n<5>(op, x, y, st, g);
-        case 6: return launch_matvec_n<6>(op, x, y, st, g);
-        case 7: return launch_matvec_n<7>(op, x, y, st, g);
-        case 8: return launch_matvec_n<8>(op, x, y, st, g);
-        case 9: return launch_matvec_n<9>(op, x, y, st, g);
+        case 2: return launch_matvec_n<2>(op, x, y, st, g, nv);
+        case 3: return launch_matvec_n<3>(op, x, y, st, g, nv);
+        case 4: return launch_matvec_n<4>(op, x, y, st, g, nv);
+        case 5: return launch_matvec_n<5>(op, x, y, st, g, nv);
+        case 6: return launch_matvec_n<6>(op, x, y, st, g, nv);
+        case 7: return launch_matvec_n<7>(op, x, y, st, g, nv);
+        case 8: return launch_matvec_n<8>(op, x, y, st, g, nv);
+        case 9: return launch_matvec_n<9>(op, x, y, st, g, nv);
     }
     set_error("unsupported degree");
     return SIPG_E_UNSUPPORTED;
@@ -170,7 +174,7 @@ int launch_matvec_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hi
 }
 
 int launch_matvec_cheb(const sipg_op* op, int mode, const void* b, const void* u, void* uo, double sigma,
-                       double theta, hipStream_t st) {
+                       double theta, hipStream_t st, int nv) {
     if (op->basis != SIPG_BASIS_HERMITE_LIKE) {
         set_error("fused Chebyshev step: Hermite-like basis only");
         return SIPG_E_UNSUPPORTED;
@@ -181,14 +185,14 @@ int launch_matvec_cheb(const sipg_op* op, int mode, const void* b, const void* u
         return SIPG_E_ARG;
     }
     switch (op->n) {
-        case 2: return launch_matvec_cheb_n<2>(op, mode, b, u, uo, sigma, theta, st);
-        case 3: return launch_matvec_cheb_n<3>(op, mode, b, u, uo, sigma, theta, st);
-        case 4: return launch_matvec_cheb_n<4>(op, mode, b, u, uo, sigma, theta, st);
-        case 5: return launch_matvec_cheb_n<5>(op, mode, b, u, uo, sigma, theta, st);
-        case 6: return launch_matvec_cheb_n<6>(op, mode, b, u, uo, sigma, theta, st);
-        case 7: return launch_matvec_cheb_n<7>(op, mode, b, u, uo, sigma, theta, st);
-        case 8: return launch_matvec_cheb_n<8>(op, mode, b, u, uo, sigma, theta, st);
-        case 9: return launch_matvec_cheb_n<9>(op, mode, b, u, uo, sigma, theta, st);
+        case 2: return launch_matvec_cheb_n<2>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 3: return launch_matvec_cheb_n<3>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 4: return launch_matvec_cheb_n<4>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 5: return launch_matvec_cheb_n<5>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 6: return launch_matvec_cheb_n<6>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 7: return launch_matvec_cheb_n<7>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 8: return launch_matvec_cheb_n<8>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 9: return launch_matvec_cheb_n<9>(op, mode, b, u, uo, sigma, theta, st, nv);
     }
     set_error("unsupported degree");
     return SIPG_E_UNSUPPORTED;

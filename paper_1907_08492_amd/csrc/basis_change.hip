@@ -52,6 +52,16 @@ basis_change_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __re
     __shared__ T lds[CPB * CS];
     const int tid = threadIdx.x;
     const int cell0 = blockIdx.x * CPB;
+    if constexpr (MERGE) {
+        // several right-hand sides stored one after another: blockIdx.y
+        // picks one (the preconditioner's data are shared)
+        const size_t voff = size_t(blockIdx.y) * size_t(ncells) * N3;
+        in += voff;
+        out += voff;
+        if (mg.au) mg.au += voff;
+        if (mg.u) mg.u += voff;
+        if (mg.zero) mg.zero += voff;
+    }
     const int ncb = min(CPB, ncells - cell0);
     const T* __restrict__ src = in + size_t(cell0) * N3;
     // all loads of the workgroup's input tile issued back to back
@@ -215,9 +225,9 @@ static int launch_bc_t(const sipg_op* op, int mode, const void* in, void* out, h
 
 template <int N, typename T>
 static int launch_cheb_t(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
-                         double sigma, double theta, void* zero, hipStream_t st) {
+                         double sigma, double theta, void* zero, hipStream_t st, int nv) {
     const int ncells = int(op->ncells);
-    const unsigned nblk = unsigned((ncells + cells_per_block(N) - 1) / cells_per_block(N));
+    const dim3 nblk = dim3(unsigned((ncells + cells_per_block(N) - 1) / cells_per_block(N)), unsigned(nv));
     constexpr int NT = threads_per_block(N);
     const T* tab = static_cast<const T*>(op->tables);
     const BcMerge<T> m{static_cast<const T*>(au), static_cast<const T*>(u), T(sigma), T(theta), static_cast<T*>(zero)};
@@ -233,26 +243,26 @@ static int launch_cheb_t(const sipg_op* op, int mode, const void* b, const void*
 
 template <int N>
 static int launch_cheb_n(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
-                         double sigma, double theta, void* zero, hipStream_t st) {
-    return op->dtype == SIPG_F64 ? launch_cheb_t<N, double>(op, mode, b, au, u, uo, sigma, theta, zero, st)
-                                 : launch_cheb_t<N, float>(op, mode, b, au, u, uo, sigma, theta, zero, st);
+                         double sigma, double theta, void* zero, hipStream_t st, int nv) {
+    return op->dtype == SIPG_F64 ? launch_cheb_t<N, double>(op, mode, b, au, u, uo, sigma, theta, zero, st, nv)
+                                 : launch_cheb_t<N, float>(op, mode, b, au, u, uo, sigma, theta, zero, st, nv);
 }
 
 int launch_precond_cheb(const sipg_op* op, int mode, const void* b, const void* au, const void* u, void* uo,
-                        double sigma, double theta, hipStream_t st, void* zero) {
-    if (mode != SIPG_BC_PJACOBI && mode != SIPG_BC_FDM) {
-        set_error("merged Chebyshev step: preconditioner mode expected");
+                        double sigma, double theta, hipStream_t st, void* zero, int nv) {
+    if ((mode != SIPG_BC_PJACOBI && mode != SIPG_BC_FDM) || nv < 1) {
+        set_error("merged Chebyshev step: preconditioner mode and at least one right-hand side expected");
         return SIPG_E_ARG;
     }
     switch (op->n) {
-        case 2: return launch_cheb_n<2>(op, mode, b, au, u, uo, sigma, theta, zero, st);
-        case 3: return launch_cheb_n<3>(op, mode, b, au, u, uo, sigma, theta, zero, st);
-        case 4: return launch_cheb_n<4>(op, mode, b, au, u, uo, sigma, theta, zero, st);
-        case 5: return launch_cheb_n<5>(op, mode, b, au, u, uo, sigma, theta, zero, st);
-        case 6: return launch_cheb_n<6>(op, mode, b, au, u, uo, sigma, theta, zero, st);
-        case 7: return launch_cheb_n<7>(op, mode, b, au, u, uo, sigma, theta, zero, st);
-        case 8: return launch_cheb_n<8>(op, mode, b, au, u, uo, sigma, theta, zero, st);
-        case 9: return launch_cheb_n<9>(op, mode, b, au, u, uo, sigma, theta, zero, st);
+        case 2: return launch_cheb_n<2>(op, mode, b, au, u, uo, sigma, theta, zero, st, nv);
+        case 3: return launch_cheb_n<3>(op, mode, b, au, u, uo, sigma, theta, zero, st, nv);
+        case 4: return launch_cheb_n<4>(op, mode, b, au, u, uo, sigma, theta, zero, st, nv);
+        case 5: return launch_cheb_n<5>(op, mode, b, au, u, uo, sigma, theta, zero, st, nv);
+        case 6: return launch_cheb_n<6>(op, mode, b, au, u, uo, sigma, theta, zero, st, nv);
+        case 7: return launch_cheb_n<7>(op, mode, b, au, u, uo, sigma, theta, zero, st, nv);
+        case 8: return launch_cheb_n<8>(op, mode, b, au, u, uo, sigma, theta, zero, st, nv);
+        case 9: return launch_cheb_n<9>(op, mode, b, au, u, uo, sigma, theta, zero, st, nv);
     }
     set_error("merged Chebyshev step: unsupported degree");
     return SIPG_E_UNSUPPORTED;

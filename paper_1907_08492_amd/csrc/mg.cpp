@@ -95,6 +95,9 @@ struct Level {
     std::vector<double> sigma, theta;   // Chebyshev coefficients per step
     bool direct = false;                // coarsest level solved by its dense inverse
     DevBuf<T> ainv;                     // that inverse (n x n)
+    // b, u, uo, r of several right-hand sides stored one after another (n
+    // apart), set for the duration of sipg_mg_solve_many (its workspace)
+    T *mb = nullptr, *mu = nullptr, *muo = nullptr, *mr = nullptr;
     int64_t ncells() const { return int64_t(nc[0]) * nc[1] * nc[2]; }
     ~Level() { if (op) sipg_destroy(op); }
 };
@@ -200,6 +203,8 @@ static bool spd_inverse(int n, std::vector<double>& a) {
 
 // Lanczos steps are bounded so that their coefficients fit the scratch.
 constexpr int kMaxLanczos = 512;
+// Right-hand sides of one sipg_mg_solve_many call, at most.
+constexpr int kMaxRhs = kMaxSolveRhs;
 
 struct Scratch {
     DevBuf<double> partial, scal, coef;
@@ -213,9 +218,9 @@ struct Scratch {
     int init(const DevAlloc& mem) {
         int rc;
         if ((rc = partial.alloc(kVecPartials, mem)) != SIPG_OK) return rc;
-        if ((rc = scal.alloc(8, mem)) != SIPG_OK) return rc;
+        if ((rc = scal.alloc(8 * kMaxRhs, mem)) != SIPG_OK) return rc;
         if ((rc = coef.alloc(2 * kMaxLanczos, mem)) != SIPG_OK) return rc;
-        SIPG_HIP(hipHostMalloc(&host, sizeof(double) * 8, hipHostMallocDefault));
+        SIPG_HIP(hipHostMalloc(&host, sizeof(double) * (8 + 5 * kMaxRhs), hipHostMallocDefault));
         for (hipEvent_t& e : ev) SIPG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         return SIPG_OK;
     }
@@ -223,21 +228,6 @@ struct Scratch {
     template <typename T>
     int dot_dev(const T* a, const T* b, int64_t n, int slot, hipStream_t st) {
         return vec_dot_async<T>(a, b, partial.p, scal.p + slot, n, st);
-    }
-    int read(int slot, double& out, hipStream_t st) {
-        SIPG_HIP(hipMemcpyAsync(host, scal.p + slot, sizeof(double), hipMemcpyDeviceToHost, st));
-        SIPG_HIP(hipStreamSynchronize(st));
-        out = host[0];
-        return SIPG_OK;
-    }
-    template <typename T>
-    int dot(const T* a, const T* b, int64_t n, double& out, hipStream_t st) {
-        int rc = vec_dot_async<T>(a, b, partial.p, scal.p, n, st);
-        if (rc != SIPG_OK) return rc;
-        SIPG_HIP(hipMemcpyAsync(host, scal.p, sizeof(double), hipMemcpyDeviceToHost, st));
-        SIPG_HIP(hipStreamSynchronize(st));
-        out = host[0];
-        return SIPG_OK;
     }
 };
 
@@ -258,6 +248,9 @@ static void chebyshev_coefficients(double a, double b, int m, std::vector<double
     }
 }
 
+// Byte sizes of the pieces of a workspace, rounded to 256 bytes.
+static inline int64_t many_align(int64_t bytes) { return (bytes + 255) / 256 * 256; }
+
 template <typename T>
 struct Hierarchy {
     std::vector<std::unique_ptr<Level<T>>> lv;
@@ -267,17 +260,29 @@ struct Hierarchy {
     bool fused = true;             // Chebyshev steps fused into the product (Hermite-like levels)
     int lanczos_start = 0;         // sipg_mg_opts.lanczos_start
 
-    // u = S^m(b; u) on level l (u = 0 on entry when zero_init).
+    // Level vectors b, u, uo, r: the level's own (nv = 1), or those of nv
+    // right-hand sides stored one after another (sipg_mg_solve_many).
+    T*& vec_u(int l, int nv) { return nv > 1 ? lv[l]->mu : lv[l]->u.p; }
+    T*& vec_uo(int l, int nv) { return nv > 1 ? lv[l]->muo : lv[l]->uo.p; }
+    T* vec_b(int l, int nv) { return nv > 1 ? lv[l]->mb : lv[l]->b.p; }
+    T* vec_r(int l, int nv) { return nv > 1 ? lv[l]->mr : lv[l]->r.p; }
+
+    // u = S^m(b; u) on level l (u = 0 on entry when zero_init), for nv
+    // right-hand sides at once (every launch covers all of them).
     int smooth(int l, bool zero_init, int steps, const std::vector<double>& sig, const std::vector<double>& th,
-               hipStream_t st) {
+               hipStream_t st, int nv = 1) {
         Level<T>& L = *lv[l];
+        T*& u = vec_u(l, nv);
+        T*& uo = vec_uo(l, nv);
+        T* b = vec_b(l, nv);
+        T* r = vec_r(l, nv);
         int rc;
         for (int j = 0; j < steps; ++j) {
             if (j == 0 && zero_init) {
                 // u_0 = 0 (written into uo for the next step by the same
                 // launch), u_1 = theta_0 P^-1 b
-                if ((rc = launch_precond_cheb(L.op, pmode, L.b.p, nullptr, nullptr, L.u.p, 0.0, th[0], st,
-                                              steps > 1 ? L.uo.p : nullptr)) != SIPG_OK)
+                if ((rc = launch_precond_cheb(L.op, pmode, b, nullptr, nullptr, u, 0.0, th[0], st,
+                                              steps > 1 ? uo : nullptr, nv)) != SIPG_OK)
                     return rc;
                 continue;
             }
@@ -287,46 +292,67 @@ struct Hierarchy {
             // one merged pass
             const double sj = j == 0 ? 0.0 : sig[j];
             if (fused && L.op->basis == SIPG_BASIS_HERMITE_LIKE) {
-                if ((rc = launch_matvec_cheb(L.op, pmode, L.b.p, L.u.p, L.uo.p, sj, th[j], st)) != SIPG_OK) return rc;
+                if ((rc = launch_matvec_cheb(L.op, pmode, b, u, uo, sj, th[j], st, nv)) != SIPG_OK) return rc;
             } else {
-                if ((rc = launch_matvec(L.op, L.u.p, L.r.p, st)) != SIPG_OK) return rc;
-                if ((rc = launch_precond_cheb(L.op, pmode, L.b.p, L.r.p, L.u.p, L.uo.p, sj, th[j], st)) != SIPG_OK)
+                if ((rc = launch_matvec(L.op, u, r, st, {}, nv)) != SIPG_OK) return rc;
+                if ((rc = launch_precond_cheb(L.op, pmode, b, r, u, uo, sj, th[j], st, nullptr, nv)) != SIPG_OK)
                     return rc;
             }
-            std::swap(L.u.p, L.uo.p);
+            std::swap(u, uo);
         }
         return SIPG_OK;
     }
 
-    // u_l = V-cycle(b_l) with zero initial guess.
-    int vcycle(int l, hipStream_t st) {
+    // u_l = V-cycle(b_l) with zero initial guess (nv right-hand sides).
+    int vcycle(int l, hipStream_t st, int nv = 1) {
         Level<T>& L = *lv[l];
         int rc;
         if (l + 1 == int(lv.size()))
-            return L.direct ? vec_dense_mv<T>(L.ainv.p, L.b.p, L.u.p, int(L.n), st)
-                            : smooth(l, true, coarse_steps, L.sigma, L.theta, st);
-        if ((rc = smooth(l, true, smooth_steps, L.sigma, L.theta, st)) != SIPG_OK) return rc;
-        if ((rc = launch_matvec(L.op, L.u.p, L.r.p, st)) != SIPG_OK) return rc;
-        if ((rc = vec_sub<T>(L.b.p, L.r.p, L.r.p, L.n, st)) != SIPG_OK) return rc;
-        if ((rc = restrict_to(l, L.r.p, lv[l + 1]->b.p, st)) != SIPG_OK) return rc;
-        if ((rc = vcycle(l + 1, st)) != SIPG_OK) return rc;
-        if ((rc = prolongate_add(l, lv[l + 1]->u.p, L.u.p, st)) != SIPG_OK) return rc;
-        return smooth(l, false, smooth_steps, L.sigma, L.theta, st);
+            return L.direct ? vec_dense_mv<T>(L.ainv.p, vec_b(l, nv), vec_u(l, nv), int(L.n), st, nv)
+                            : smooth(l, true, coarse_steps, L.sigma, L.theta, st, nv);
+        if ((rc = smooth(l, true, smooth_steps, L.sigma, L.theta, st, nv)) != SIPG_OK) return rc;
+        T* r = vec_r(l, nv);
+        if ((rc = launch_matvec(L.op, vec_u(l, nv), r, st, {}, nv)) != SIPG_OK) return rc;
+        if ((rc = vec_sub<T>(vec_b(l, nv), r, r, L.n * nv, st)) != SIPG_OK) return rc;
+        if ((rc = restrict_to(l, r, vec_b(l + 1, nv), st, nv)) != SIPG_OK) return rc;
+        if ((rc = vcycle(l + 1, st, nv)) != SIPG_OK) return rc;
+        if ((rc = prolongate_add(l, vec_u(l + 1, nv), vec_u(l, nv), st, nv)) != SIPG_OK) return rc;
+        return smooth(l, false, smooth_steps, L.sigma, L.theta, st, nv);
     }
 
     // coarse = R fine  from level l to level l+1
-    int restrict_to(int l, const T* fine, T* coarse, hipStream_t st) {
+    int restrict_to(int l, const T* fine, T* coarse, hipStream_t st, int nv = 1) {
         Level<T>& L = *lv[l];
         const Level<T>& C = *lv[l + 1];
-        if (L.next == 0) return transfer_restrict<T>(L.np, L.nc, fine, coarse, L.emb.p, st);
-        return transfer_degree<T>(L.np, C.np, L.ncells(), true, fine, coarse, L.emb.p, L.emb.p + L.np * C.np, st);
+        if (L.next == 0) return transfer_restrict<T>(L.np, L.nc, fine, coarse, L.emb.p, st, nv);
+        return transfer_degree<T>(L.np, C.np, L.ncells(), true, fine, coarse, L.emb.p, L.emb.p + L.np * C.np, st, nv);
     }
     // fine += P coarse  from level l+1 to level l
-    int prolongate_add(int l, const T* coarse, T* fine, hipStream_t st) {
+    int prolongate_add(int l, const T* coarse, T* fine, hipStream_t st, int nv = 1) {
         Level<T>& L = *lv[l];
         const Level<T>& C = *lv[l + 1];
-        if (L.next == 0) return transfer_prolongate_add<T>(L.np, L.nc, coarse, fine, L.emb.p, st);
-        return transfer_degree<T>(L.np, C.np, L.ncells(), false, coarse, fine, L.emb.p, L.emb.p + L.np * C.np, st);
+        if (L.next == 0) return transfer_prolongate_add<T>(L.np, L.nc, coarse, fine, L.emb.p, st, nv);
+        return transfer_degree<T>(L.np, C.np, L.ncells(), false, coarse, fine, L.emb.p, L.emb.p + L.np * C.np, st,
+                                  nv);
+    }
+
+    // Device bytes of the level vectors of nv right-hand sides.
+    int64_t many_bytes(int nv) const {
+        int64_t b = 0;
+        for (const auto& L : lv) b += 4 * many_align(int64_t(sizeof(T)) * L->n * nv);
+        return b;
+    }
+    // Points the levels' multi-right-hand-side vectors into `ws` (many_bytes(nv)
+    // bytes), or back to null.
+    void set_many(char* ws, int nv) {
+        for (auto& L : lv) {
+            const int64_t sz = many_align(int64_t(sizeof(T)) * L->n * nv);
+            T** v[4] = {&L->mb, &L->mu, &L->muo, &L->mr};
+            for (T** q : v) {
+                *q = ws ? reinterpret_cast<T*>(ws) : nullptr;
+                if (ws) ws += sz;
+            }
+        }
     }
 
     // Extreme eigenvalues of P^-1 A on level l from `steps` conjugate gradient
@@ -641,6 +667,242 @@ static int build_hierarchy(sipg_mg* mg, Hierarchy<T>& H, const sipg_mesh* mesh, 
     return SIPG_OK;
 }
 
+namespace sipg {
+
+// z = V-cycle(r) for nv right-hand sides stored one after another (FP64 in
+// and out; the hierarchy's multi-right-hand-side vectors are set).
+static int mg_vcycle_many(sipg_mg* mg, const double* r, double* z, int nv, hipStream_t st) {
+    int rc;
+    const int64_t n = mg->ndofs * nv;
+    if (mg->precision == 0) {
+        auto& H = mg->h32;
+        if ((rc = vec_convert<float, double>(r, H.vec_b(0, nv), n, st)) != SIPG_OK) return rc;
+        if ((rc = H.vcycle(0, st, nv)) != SIPG_OK) return rc;
+        return vec_convert<double, float>(H.vec_u(0, nv), z, n, st);
+    }
+    auto& H = mg->h64;
+    SIPG_HIP(hipMemcpyAsync(H.vec_b(0, nv), r, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    if ((rc = H.vcycle(0, st, nv)) != SIPG_OK) return rc;
+    SIPG_HIP(hipMemcpyAsync(z, H.vec_u(0, nv), sizeof(double) * n, hipMemcpyDeviceToDevice, st));
+    return SIPG_OK;
+}
+
+// Workspace of sipg_mg_solve_many: the level vectors of nv right-hand sides,
+// the FP64 vectors r, z, p, Ap of each, per-vector scalars and dot partials.
+struct ManyWork {
+    sipg_mg* mg = nullptr;
+    char* base = nullptr;
+    hipStream_t st = nullptr;
+    ~ManyWork() {
+        if (!base) return;
+        mg->h32.set_many(nullptr, 0);
+        mg->h64.set_many(nullptr, 0);
+        if (mg->mem.a.alloc) {
+            (void)hipStreamSynchronize(st);
+            mg->mem.release(base);
+        } else {
+            (void)hipFreeAsync(base, st);
+        }
+    }
+};
+
+// Device bytes of the workspace of nv right-hand sides: of an existing solver,
+// or of the solver sipg_mg_setup would build for (mesh, degree, o).
+int64_t mg_many_estimate(const sipg_mesh& mesh, int degree, const sipg_mg_opts& o, int nv) {
+    const int esz = o.precision == 0 ? 4 : 8;
+    auto dofs = [](const int nc[3], int deg) { return int64_t(nc[0]) * nc[1] * nc[2] * (deg + 1) * (deg + 1) * (deg + 1); };
+    int64_t bytes = 4 * many_align(8 * dofs(mesh.n, degree) * nv) + many_align(int64_t(sizeof(double)) * 8 * kMaxRhs) +
+                    many_align(int64_t(sizeof(double)) * kVecPartials * nv);
+    for (const LevelSpec& sp : mg_level_sequence(mesh, degree, o)) bytes += 4 * many_align(esz * dofs(sp.nc, sp.degree) * nv);
+    return bytes;
+}
+
+int64_t mg_many_bytes(const sipg_mg* mg, int nv) {
+    const int64_t vec = many_align(int64_t(sizeof(double)) * mg->ndofs * nv);
+    return (mg->precision == 0 ? mg->h32.many_bytes(nv) : mg->h64.many_bytes(nv)) + 4 * vec +
+           many_align(int64_t(sizeof(double)) * 8 * kMaxRhs) +
+           many_align(int64_t(sizeof(double)) * kVecPartials * nv);
+}
+
+// FP64 preconditioned conjugate gradient with one V-cycle per iteration for
+// nrhs right-hand sides of one hierarchy advanced in lockstep: every product,
+// smoothing step, transfer and vector operation is one launch for all of
+// them.  Vector v stops (its x, r and p are no longer updated) at the first
+// iteration whose residual meets its tolerance (decided on the device, so
+// no vector takes an iteration beyond it); the loop ends when every vector
+// has stopped.
+int mg_solve_many(sipg_mg* mg, int nrhs, const double* b, double* x, double rel_tol, int max_iter,
+                  sipg_solve_info* info, double* bnorm, int* conv, hipStream_t st) {
+    if (!mg || !b || !x || !info) { set_error("multigrid solve: null argument"); return SIPG_E_ARG; }
+    if (nrhs < 1 || nrhs > kMaxRhs) { set_error("multigrid solve: nrhs must lie in [1, 16]"); return SIPG_E_ARG; }
+    if (!(rel_tol > 0.0) || max_iter < 0) {
+        set_error("multigrid solve: rel_tol must be > 0, max_iter >= 0");
+        return SIPG_E_ARG;
+    }
+    const int nv = nrhs;
+    const int64_t n = mg->ndofs;
+    const size_t vbytes = sizeof(double) * size_t(n) * nv;
+    {
+        const char *b0 = reinterpret_cast<const char*>(b), *x0 = reinterpret_cast<const char*>(x);
+        if (b0 < x0 + vbytes && x0 < b0 + vbytes) { set_error("multigrid solve: b and x overlap"); return SIPG_E_ARG; }
+    }
+    std::memset(info, 0, sizeof(*info) * size_t(nv));
+    Scratch& sc = mg->sc;
+    ManyWork w;
+    double *r, *z, *p, *ap, *scal, *partial;
+    if (nv == 1) {
+        // one right-hand side: the solver's own vectors and scalars
+        r = mg->wr.p;
+        z = mg->wz.p;
+        p = mg->wp.p;
+        ap = mg->wap.p;
+        scal = sc.scal.p;
+        partial = sc.partial.p;
+    } else {
+        w.mg = mg;
+        w.st = st;
+        const int64_t total = mg_many_bytes(mg, nv);
+        void* q = nullptr;
+        if (mg->mem.a.alloc) {
+            if (int rc = mg->mem.alloc(&q, size_t(total), "sipg_mg_solve_many workspace")) return rc;
+        } else if (hipMallocAsync(&q, size_t(total), st) != hipSuccess) {
+            (void)hipGetLastError();
+            set_error("sipg_mg_solve_many: out of device memory for the workspace");
+            return SIPG_E_OOM;
+        }
+        w.base = static_cast<char*>(q);
+        char* ws = w.base;
+        if (mg->precision == 0) {
+            mg->h32.set_many(ws, nv);
+            ws += mg->h32.many_bytes(nv);
+        } else {
+            mg->h64.set_many(ws, nv);
+            ws += mg->h64.many_bytes(nv);
+        }
+        const int64_t vec = many_align(int64_t(vbytes));
+        r = reinterpret_cast<double*>(ws);
+        z = reinterpret_cast<double*>(ws + vec);
+        p = reinterpret_cast<double*>(ws + 2 * vec);
+        ap = reinterpret_cast<double*>(ws + 3 * vec);
+        ws += 4 * vec;
+        scal = reinterpret_cast<double*>(ws);
+        ws += many_align(int64_t(sizeof(double)) * 8 * kMaxRhs);
+        partial = reinterpret_cast<double*>(ws);
+    }
+    // per-vector scalars (kMaxRhs apart): r.z, p.Ap, new r.z, r.r, active
+    // flag (r.r and the flags adjacent: one copy to the host), b.b, target,
+    // iterations
+    double *s_rz = scal, *s_pap = scal + kMaxRhs, *s_rzn = scal + 2 * kMaxRhs, *s_rr = scal + 3 * kMaxRhs;
+    double *s_act = scal + 4 * kMaxRhs, *s_bb = scal + 5 * kMaxRhs, *s_tgt = scal + 6 * kMaxRhs,
+           *s_it = scal + 7 * kMaxRhs;
+    // pinned host memory: nv values read synchronously, then two lagged slots
+    // of (r.r, active flags), kMaxRhs each
+    double* hb = sc.host + 8;
+    int rc;
+    auto read_now = [&](const double* dev, std::vector<double>& out) -> int {
+        out.resize(nv);
+        SIPG_HIP(hipMemcpyAsync(hb, dev, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
+        SIPG_HIP(hipStreamSynchronize(st));
+        std::copy(hb, hb + nv, out.begin());
+        return SIPG_OK;
+    };
+    // ||b_v||, r = b - A x, ||r_v||, targets and active flags
+    if ((rc = vec_dot_many<double>(b, b, partial, s_bb, n, nv, st)) != SIPG_OK) return rc;
+    if ((rc = launch_matvec(mg->fine64, x, ap, st, {}, nv)) != SIPG_OK) return rc;
+    if ((rc = vec_sub<double>(b, ap, r, n * nv, st)) != SIPG_OK) return rc;
+    if ((rc = vec_dot_many<double>(r, r, partial, s_rr, n, nv, st)) != SIPG_OK) return rc;
+    if ((rc = cg_start_many(s_bb, s_rr, rel_tol, s_tgt, s_act, s_it, nv, st)) != SIPG_OK) return rc;
+    std::vector<double> bb, rr, act, its;
+    if ((rc = read_now(s_bb, bb)) != SIPG_OK) return rc;
+    if ((rc = read_now(s_rr, rr)) != SIPG_OK) return rc;
+    if ((rc = read_now(s_act, act)) != SIPG_OK) return rc;
+    std::vector<double> target(nv);
+    for (int v = 0; v < nv; ++v) {
+        info[v].initial_residual = std::sqrt(rr[v]);
+        target[v] = rel_tol * (bb[v] > 0.0 ? std::sqrt(bb[v]) : 1.0);
+    }
+    auto all_stopped = [&](const double* a) {
+        for (int v = 0; v < nv; ++v)
+            if (a[v] != 0.0) return false;
+        return true;
+    };
+    // The stopping test is decided on the device (the flags) and read by the
+    // host with a lag: r.r and the flags of iteration it are copied to pinned
+    // host memory behind its work, and before queueing iteration it + 2 the
+    // host reads those of iteration it while iteration it + 1 runs, so the
+    // device does not wait for the host between iterations.  Only when the
+    // observed reduction rates predict that every running vector stops in
+    // iteration it + 1 does the host wait for that iteration too.  Iterations
+    // queued after every vector stopped change nothing (the flags gate every
+    // update), so the lag costs at most device time, never the result.
+    std::vector<double> rr_prev = rr;
+    int it = 0;
+    bool done = all_stopped(act.data());
+    while (!done && it < max_iter) {
+        if (it >= 2) {
+            SIPG_HIP(hipEventSynchronize(sc.ev[it % 2]));
+            const double* h = hb + kMaxRhs + (it % 2) * 2 * kMaxRhs;   // r.r, flags of iteration it - 2
+            if (all_stopped(h + kMaxRhs)) { done = true; break; }
+            bool likely = true;
+            for (int v = 0; v < nv; ++v) {
+                if (h[kMaxRhs + v] == 0.0) continue;
+                const double rate = rr_prev[v] > 0.0 ? std::min(1.0, h[v] / rr_prev[v]) : 1.0;
+                likely = likely && std::sqrt(h[v] * rate) <= 1.5 * target[v];
+            }
+            for (int v = 0; v < nv; ++v) rr_prev[v] = h[v];
+            if (likely) {
+                SIPG_HIP(hipEventSynchronize(sc.ev[(it - 1) % 2]));
+                if (all_stopped(hb + kMaxRhs + ((it - 1) % 2) * 2 * kMaxRhs + kMaxRhs)) { done = true; break; }
+            }
+        }
+        if ((rc = mg_vcycle_many(mg, r, z, nv, st)) != SIPG_OK) return rc;
+        if ((rc = vec_dot_many<double>(r, z, partial, s_rzn, n, nv, st)) != SIPG_OK) return rc;
+        if (it == 0) {
+            SIPG_HIP(hipMemcpyAsync(p, z, vbytes, hipMemcpyDeviceToDevice, st));
+        } else {
+            if ((rc = vec_xpby_many<double>(z, s_rzn, s_rz, s_act, p, n, nv, st)) != SIPG_OK) return rc;
+        }
+        if ((rc = scalar_copy_many(s_rzn, s_act, s_rz, nv, st)) != SIPG_OK) return rc;
+        if ((rc = launch_matvec(mg->fine64, p, ap, st, {}, nv)) != SIPG_OK) return rc;
+        if ((rc = vec_dot_many<double>(p, ap, partial, s_pap, n, nv, st)) != SIPG_OK) return rc;
+        if ((rc = vec_axpy_many<double>(s_rz, s_pap, s_act, 1.0, p, x, n, nv, st)) != SIPG_OK) return rc;
+        if ((rc = vec_axpy_many<double>(s_rz, s_pap, s_act, -1.0, ap, r, n, nv, st)) != SIPG_OK) return rc;
+        if ((rc = vec_dot_many<double>(r, r, partial, s_rr, n, nv, st)) != SIPG_OK) return rc;
+        if ((rc = cg_mask_many(s_rr, s_tgt, s_act, s_it, nv, st)) != SIPG_OK) return rc;
+        double* h = hb + kMaxRhs + (it % 2) * 2 * kMaxRhs;
+        SIPG_HIP(hipMemcpyAsync(h, s_rr, sizeof(double) * 2 * kMaxRhs, hipMemcpyDeviceToHost, st));
+        SIPG_HIP(hipEventRecord(sc.ev[it % 2], st));
+        ++it;
+    }
+    // per-vector results: iterations, the residual at which each stopped, and
+    // the true residual ||b - A x||
+    if ((rc = read_now(s_it, its)) != SIPG_OK) return rc;
+    if ((rc = read_now(s_rr, rr)) != SIPG_OK) return rc;
+    if ((rc = read_now(s_act, act)) != SIPG_OK) return rc;
+    if ((rc = launch_matvec(mg->fine64, x, ap, st, {}, nv)) != SIPG_OK) return rc;
+    if ((rc = vec_sub<double>(b, ap, r, n * nv, st)) != SIPG_OK) return rc;
+    if ((rc = vec_dot_many<double>(r, r, partial, s_bb, n, nv, st)) != SIPG_OK) return rc;
+    std::vector<double> tr;
+    if ((rc = read_now(s_bb, tr)) != SIPG_OK) return rc;
+    bool all_converged = true;
+    for (int v = 0; v < nv; ++v) {
+        info[v].iterations = int(its[v]);
+        info[v].final_residual = std::sqrt(rr[v]);
+        info[v].true_residual = std::sqrt(tr[v]);
+        all_converged = all_converged && act[v] == 0.0;
+        if (conv) conv[v] = act[v] == 0.0;
+    }
+    if (bnorm)
+        for (int v = 0; v < nv; ++v) bnorm[v] = std::sqrt(bb[v]);
+    if (!all_converged) {
+        set_error("multigrid solve: no convergence within max_iter");
+        return SIPG_E_NOCONV;
+    }
+    return SIPG_OK;
+}
+
+}  // namespace sipg
+
 extern "C" {
 
 int sipg_mg_default_opts(sipg_mg_opts* o) {
@@ -735,97 +997,20 @@ int sipg_mg_apply_vcycle(sipg_mg* mg, const double* r, double* z, void* stream) 
     return SIPG_OK;
 }
 
-// FP64 preconditioned conjugate gradient with one V-cycle per iteration.
+// FP64 preconditioned conjugate gradient with one V-cycle per iteration: the
+// lockstep solve of one right-hand side, on the solver's own vectors.
 int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int max_iter, sipg_solve_info* info,
                   void* stream) {
-    if (!mg || !b || !x || !info) { set_error("sipg_mg_solve: null argument"); return SIPG_E_ARG; }
-    if (!(rel_tol > 0.0) || max_iter < 0) { set_error("sipg_mg_solve: rel_tol must be > 0, max_iter >= 0"); return SIPG_E_ARG; }
-    hipStream_t st = static_cast<hipStream_t>(stream);
-    const int64_t n = mg->ndofs;
-    std::memset(info, 0, sizeof(*info));
-    DevBuf<double>& r = mg->wr;
-    DevBuf<double>& z = mg->wz;
-    DevBuf<double>& p = mg->wp;
-    DevBuf<double>& ap = mg->wap;
-    int rc;
-    Scratch& sc = mg->sc;
-    double bb;
-    if ((rc = sc.dot<double>(b, b, n, bb, st)) != SIPG_OK) return rc;
-    mg->last_bnorm = std::sqrt(bb);
-    const double target = rel_tol * (bb > 0.0 ? std::sqrt(bb) : 1.0);
-    if ((rc = launch_matvec(mg->fine64, x, ap.p, st)) != SIPG_OK) return rc;
-    if ((rc = vec_sub<double>(b, ap.p, r.p, n, st)) != SIPG_OK) return rc;
-    double rr;
-    if ((rc = sc.dot<double>(r.p, r.p, n, rr, st)) != SIPG_OK) return rc;
-    info->initial_residual = std::sqrt(rr);
-    // CG coefficients stay on the device (scalar slots 0: r.z, 1: p.Ap,
-    // 2: new r.z, 4 + it % 2: r.r of iteration it).  The stopping test is
-    // lagged: r.r of iteration it is copied to pinned host memory behind its
-    // work, and before queueing iteration it + 2 the host reads the value of
-    // iteration it, while iteration it + 1 runs, so the device does not wait
-    // for the host between iterations.  Only when the observed reduction
-    // rate predicts that the running iteration reaches the tolerance does the
-    // host wait for that iteration too, so that no iteration is done beyond
-    // the first one that converged.
-    double* s_rz = sc.scal.p;
-    double* s_pap = sc.scal.p + 1;
-    double* s_rzn = sc.scal.p + 2;
-    int it = 0;
-    bool converged = std::sqrt(rr) <= target;
-    double rr_prev = rr;                       // r.r of the iteration before the last one read
-    while (!converged && it < max_iter) {
-        if (it >= 2) {
-            // iteration it - 2 has finished (it - 1 may still run)
-            SIPG_HIP(hipEventSynchronize(sc.ev[it % 2]));
-            const double r2 = sc.host[4 + it % 2];
-            const double rate = rr_prev > 0.0 ? std::min(1.0, r2 / rr_prev) : 1.0;
-            rr_prev = r2;
-            rr = r2;
-            if (std::sqrt(rr) <= target) { converged = true; break; }
-            if (std::sqrt(r2 * rate) <= 1.5 * target) {
-                // iteration it - 1 likely converges: wait for it
-                SIPG_HIP(hipEventSynchronize(sc.ev[(it - 1) % 2]));
-                rr = sc.host[4 + (it - 1) % 2];
-                if (std::sqrt(rr) <= target) { converged = true; break; }
-            }
-        } else if (it == 1) {
-            rr_prev = rr;
-        }
-        if ((rc = sipg_mg_apply_vcycle(mg, r.p, z.p, stream)) != SIPG_OK) return rc;
-        if ((rc = sc.dot_dev<double>(r.p, z.p, n, 2, st)) != SIPG_OK) return rc;
-        if (it == 0) {
-            SIPG_HIP(hipMemcpyAsync(p.p, z.p, sizeof(double) * n, hipMemcpyDeviceToDevice, st));
-        } else {
-            if ((rc = vec_xpby_dev<double>(z.p, s_rzn, s_rz, p.p, n, st)) != SIPG_OK) return rc;
-        }
-        if ((rc = scalar_ratio(s_rzn, nullptr, s_rz, st)) != SIPG_OK) return rc;
-        if ((rc = launch_matvec(mg->fine64, p.p, ap.p, st)) != SIPG_OK) return rc;
-        if ((rc = sc.dot_dev<double>(p.p, ap.p, n, 1, st)) != SIPG_OK) return rc;
-        if ((rc = vec_axpy_dev<double>(s_rz, s_pap, 1.0, p.p, x, n, st)) != SIPG_OK) return rc;
-        if ((rc = vec_axpy_dev<double>(s_rz, s_pap, -1.0, ap.p, r.p, n, st)) != SIPG_OK) return rc;
-        if ((rc = sc.dot_dev<double>(r.p, r.p, n, 4 + it % 2, st)) != SIPG_OK) return rc;
-        SIPG_HIP(hipMemcpyAsync(sc.host + 4 + it % 2, sc.scal.p + 4 + it % 2, sizeof(double), hipMemcpyDeviceToHost, st));
-        SIPG_HIP(hipEventRecord(sc.ev[it % 2], st));
-        ++it;
-    }
-    if (it > 0) {
-        // the residual of the last queued iteration (the solution returned)
-        SIPG_HIP(hipEventSynchronize(sc.ev[(it - 1) % 2]));
-        rr = sc.host[4 + (it - 1) % 2];
-        converged = converged || std::sqrt(rr) <= target;
-    }
-    info->iterations = it;
-    info->final_residual = std::sqrt(rr);
-    if ((rc = launch_matvec(mg->fine64, x, ap.p, st)) != SIPG_OK) return rc;
-    if ((rc = vec_sub<double>(b, ap.p, r.p, n, st)) != SIPG_OK) return rc;
-    double tr;
-    if ((rc = sc.dot<double>(r.p, r.p, n, tr, st)) != SIPG_OK) return rc;
-    info->true_residual = std::sqrt(tr);
-    if (!converged) {
-        set_error("sipg_mg_solve: no convergence within max_iter");
-        return SIPG_E_NOCONV;
-    }
-    return SIPG_OK;
+    double bn = 0.0;
+    const int rc = mg_solve_many(mg, 1, b, x, rel_tol, max_iter, info, &bn, nullptr, static_cast<hipStream_t>(stream));
+    if (mg) mg->last_bnorm = bn;
+    return rc;
+}
+
+// nrhs right-hand sides of one hierarchy solved in lockstep (see mg_solve_many).
+int sipg_mg_solve_many(sipg_mg* mg, int nrhs, const double* b, double* x, double rel_tol, int max_iter,
+                       sipg_solve_info* info, void* stream) {
+    return mg_solve_many(mg, nrhs, b, x, rel_tol, max_iter, info, nullptr, nullptr, static_cast<hipStream_t>(stream));
 }
 
 int sipg_mg_transfer(sipg_mg* mg, int level, int mode, const void* in, void* out, void* stream) {

@@ -6,6 +6,9 @@
 // a worker checks out an idle multigrid hierarchy of the request's problem
 // from a cache (or builds one), assembles the right-hand side on the device,
 // runs the FP64-CG / multigrid solve and returns the hierarchy to the cache.
+// Queued requests of the same problem are taken along (batch_max_rhs,
+// batch_max_dofs) and solved together by one sipg_mg_solve_many, whose
+// launches cover all of their right-hand sides.
 // Solves of different requests therefore run concurrently on the device;
 // requests that arrive while others run are admitted as soon as a worker and
 // enough of the HBM budget are free.  The budget counts the cached
@@ -79,6 +82,8 @@ struct sipg_server {
     std::vector<sipg_mg*> evicted;   // hierarchies to free outside the lock
     int64_t peak_bytes = 0;
     int64_t completed = 0;
+    int64_t batched_solves = 0;      // solves over 2 or more requests
+    int64_t batched_requests = 0;
     int running = 0;                 // admitted jobs not yet finished
 };
 
@@ -195,6 +200,115 @@ static Job* admit(sipg_server* s) {
     return nullptr;
 }
 
+// Queued requests of j's problem (same key, tolerance and iteration limit)
+// that join j in one sipg_mg_solve_many, within the batch limits and the
+// budget; called with the lock held right after admit(j), which charged j.
+// The group's workspace (its level and CG vectors, and the stacked b and x)
+// is charged to j.
+static std::vector<Job*> gather_batch(sipg_server* s, Job* j) {
+    std::vector<Job*> group{j};
+    const int maxr = s->opts.batch_max_rhs;
+    if (maxr < 2) return group;
+    std::vector<std::deque<Job*>::iterator> cand;
+    int64_t dofs = j->ndofs, vec_need = 0;
+    for (auto it = s->queue.begin(); it != s->queue.end() && int(cand.size()) + 1 < maxr; ++it) {
+        Job* c = *it;
+        if (c->key < j->key || j->key < c->key || c->req.rel_tol != j->req.rel_tol ||
+            c->req.max_iter != j->req.max_iter || dofs + c->ndofs > s->opts.batch_max_dofs)
+            continue;
+        cand.push_back(it);
+        dofs += c->ndofs;
+    }
+    // the largest group whose vectors and workspace fit the budget
+    while (!cand.empty()) {
+        const int k = int(cand.size()) + 1;
+        vec_need = 0;
+        for (auto it : cand) vec_need += (*it)->req.x_out ? 0 : 8 * (*it)->ndofs;
+        const int64_t ws = mg_many_estimate(j->req.mesh, j->req.degree, solver_opts(s->opts), k) +
+                           2 * 8 * int64_t(k) * j->ndofs;
+        if (s->used_bytes + vec_need + ws <= s->opts.hbm_budget_bytes) {
+            j->est_bytes += ws;
+            s->used_bytes += ws;
+            break;
+        }
+        cand.pop_back();
+    }
+    // erase back to front (deque iterators stay valid for the earlier ones)
+    for (auto r = cand.rbegin(); r != cand.rend(); ++r) {
+        Job* c = **r;
+        c->est_bytes = c->req.x_out ? 0 : 8 * c->ndofs;
+        s->used_bytes += c->est_bytes;
+        s->running++;
+        s->queue.erase(*r);
+        group.insert(group.begin() + 1, c);
+    }
+    s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
+    return group;
+}
+
+// Solves the requests of `group` (one problem) on hierarchy mg: one
+// sipg_mg_solve alone, else one sipg_mg_solve_many over their stacked
+// right-hand sides, the solutions then copied to each request's vector.
+// Fills every request's result fields except status; returns the status of
+// each in `status`.
+static void solve_group(sipg_server* s, sipg_mg* mg, const std::vector<Job*>& group, std::vector<double*>& xs,
+                        std::vector<int>& status, hipStream_t st) {
+    const int k = int(group.size());
+    const Job* j = group[0];
+    const int64_t n = j->ndofs;
+    sipg_op* fine = mg_fine_operator(mg);
+    if (k == 1) {
+        double* b = mg_rhs_buffer(mg);
+        sipg_solve_info info{};
+        int rc = launch_rhs_sines(fine, j->req.nmodes, j->req.amps, &j->req.waves[0][0], b, st);
+        if (rc == SIPG_OK && hipMemsetAsync(xs[0], 0, sizeof(double) * size_t(n), st) != hipSuccess) rc = SIPG_E_HIP;
+        if (rc == SIPG_OK) rc = sipg_mg_solve(mg, b, xs[0], j->req.rel_tol, j->req.max_iter, &info, st);
+        double bn = 0.0;
+        if (rc == SIPG_OK || rc == SIPG_E_NOCONV) bn = mg_last_rhs_norm(mg);
+        group[0]->res.iterations = info.iterations;
+        group[0]->res.true_residual = info.true_residual;
+        group[0]->res.rel_residual = bn > 0.0 ? info.true_residual / bn : info.true_residual;
+        status[0] = rc;
+        return;
+    }
+    // stacked right-hand sides and solutions (stream-ordered, or the caller's allocator)
+    const size_t bytes = sizeof(double) * size_t(n) * k;
+    void* q = nullptr;
+    int rc = SIPG_OK;
+    if (s->mem.a.alloc) rc = s->mem.alloc(&q, 2 * bytes, "request loop: stacked vectors");
+    else if (hipMallocAsync(&q, 2 * bytes, st) != hipSuccess) { (void)hipGetLastError(); rc = SIPG_E_OOM; }
+    double* bw = static_cast<double*>(q);
+    double* xw = bw ? bw + size_t(n) * k : nullptr;
+    for (int v = 0; v < k && rc == SIPG_OK; ++v)
+        rc = launch_rhs_sines(fine, group[v]->req.nmodes, group[v]->req.amps, &group[v]->req.waves[0][0],
+                              bw + size_t(v) * n, st);
+    if (rc == SIPG_OK && hipMemsetAsync(xw, 0, bytes, st) != hipSuccess) rc = SIPG_E_HIP;
+    std::vector<sipg_solve_info> info(k);
+    std::vector<double> bn(k, 0.0);
+    std::vector<int> conv(k, 0);
+    if (rc == SIPG_OK)
+        rc = mg_solve_many(mg, k, bw, xw, j->req.rel_tol, j->req.max_iter, info.data(), bn.data(), conv.data(), st);
+    for (int v = 0; v < k; ++v) {
+        int sv = rc == SIPG_OK || rc == SIPG_E_NOCONV ? (conv[v] ? SIPG_OK : SIPG_E_NOCONV) : rc;
+        if ((rc == SIPG_OK || rc == SIPG_E_NOCONV) &&
+            hipMemcpyAsync(xs[v], xw + size_t(v) * n, sizeof(double) * size_t(n), hipMemcpyDeviceToDevice, st) !=
+                hipSuccess)
+            sv = SIPG_E_HIP;
+        group[v]->res.iterations = info[v].iterations;
+        group[v]->res.true_residual = info[v].true_residual;
+        group[v]->res.rel_residual = bn[v] > 0.0 ? info[v].true_residual / bn[v] : info[v].true_residual;
+        status[v] = sv;
+    }
+    if (q) {
+        if (s->mem.a.alloc) {
+            (void)hipStreamSynchronize(st);
+            s->mem.release(q);
+        } else {
+            (void)hipFreeAsync(q, st);
+        }
+    }
+}
+
 static void worker_main(sipg_server* s) {
     hipStream_t st = nullptr;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return;
@@ -203,7 +317,10 @@ static void worker_main(sipg_server* s) {
         Job* j = nullptr;
         s->cv_work.wait(lk, [&] { return s->stop || (j = admit(s)) != nullptr; });
         if (!j) break;   // stop requested and nothing admissible
-        j->t_start = Clock::now();
+        const std::vector<Job*> group = gather_batch(s, j);
+        const int k = int(group.size());
+        const Clock::time_point t0 = Clock::now();
+        for (Job* g : group) g->t_start = t0;
         // check out a cached hierarchy
         sipg_mg* mg = nullptr;
         CacheEntry* ce = nullptr;
@@ -228,43 +345,42 @@ static void worker_main(sipg_server* s) {
                 built_bytes = info.device_bytes;
             }
         }
-        double* b = status == SIPG_OK ? mg_rhs_buffer(mg) : nullptr;
-        double* x = j->req.x_out;
-        if (status == SIPG_OK && !x) {
-            const size_t xb = sizeof(double) * size_t(j->ndofs);
+        // result vectors: the request's own, or server-owned (stream-ordered:
+        // no device-wide synchronisation between workers)
+        std::vector<double*> xs(k, nullptr);
+        std::vector<int> stat(k, status);
+        for (int v = 0; v < k && status == SIPG_OK; ++v) {
+            Job* g = group[v];
+            xs[v] = g->req.x_out;
+            if (xs[v]) continue;
+            const size_t xb = sizeof(double) * size_t(g->ndofs);
             if (s->mem.a.alloc) {
                 void* q = nullptr;
                 status = s->mem.alloc(&q, xb, "request loop: solution buffer");
-                j->x_owned = static_cast<double*>(q);
-            } else if (hipMallocAsync(reinterpret_cast<void**>(&j->x_owned), xb, st) != hipSuccess) {
-                // stream-ordered: no device-wide synchronisation between workers
-                j->x_owned = nullptr;
+                g->x_owned = static_cast<double*>(q);
+            } else if (hipMallocAsync(reinterpret_cast<void**>(&g->x_owned), xb, st) != hipSuccess) {
+                g->x_owned = nullptr;
                 status = SIPG_E_OOM;
             }
-            x = j->x_owned;
+            xs[v] = g->x_owned;
         }
-        sipg_solve_info info{};
         if (status == SIPG_OK) {
-            status = launch_rhs_sines(mg_fine_operator(mg), j->req.nmodes, j->req.amps, &j->req.waves[0][0], b, st);
-            if (status == SIPG_OK && hipMemsetAsync(x, 0, sizeof(double) * size_t(j->ndofs), st) != hipSuccess)
-                status = SIPG_E_HIP;
-            if (status == SIPG_OK)
-                status = sipg_mg_solve(mg, b, x, j->req.rel_tol, j->req.max_iter, &info, st);
-            double bn = 0.0;
-            if (status == SIPG_OK || status == SIPG_E_NOCONV) bn = mg_last_rhs_norm(mg);
-            j->res.iterations = info.iterations;
-            j->res.true_residual = info.true_residual;
-            j->res.rel_residual = bn > 0.0 ? info.true_residual / bn : info.true_residual;
+            solve_group(s, mg, group, xs, stat, st);
             (void)hipStreamSynchronize(st);
+        } else {
+            std::fill(stat.begin(), stat.end(), status);
         }
-        j->res.x = x;
+        for (int v = 0; v < k; ++v) group[v]->res.x = xs[v];
 
         lk.lock();
         // return or insert the hierarchy into the cache, settle the budget;
         // a server-owned result buffer stays charged until it is released
-        s->used_bytes -= j->est_bytes;
-        s->running--;
-        const int64_t kept = j->x_owned ? 8 * j->ndofs : 0;
+        int64_t kept = 0;
+        for (Job* g : group) {
+            s->used_bytes -= g->est_bytes;
+            s->running--;
+            kept += g->x_owned ? 8 * g->ndofs : 0;
+        }
         if (ce) {
             ce->busy = false;
             ce->last_used = Clock::now();
@@ -280,7 +396,11 @@ static void worker_main(sipg_server* s) {
             s->used_bytes += kept;
         }
         s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
-        finish_job(s, j, status);
+        if (k > 1) {
+            s->batched_solves++;
+            s->batched_requests += k;
+        }
+        for (int v = 0; v < k; ++v) finish_job(s, group[v], stat[v]);
         s->cv_done.notify_all();
         s->cv_work.notify_all();
     }
@@ -304,6 +424,8 @@ int sipg_server_default_opts(sipg_server_opts* o) {
     o->coarse_reduction = 10.0;
     o->graded_coarsening = 0;
     o->coarse_direct_max_dofs = 256;
+    o->batch_max_rhs = 8;
+    o->batch_max_dofs = int64_t(1) << 22;
     return SIPG_OK;
 }
 
@@ -317,9 +439,11 @@ int sipg_server_create(const sipg_server_opts* opts, const sipg_allocator* alloc
     if (o.workers < 1 || o.workers > 16 || o.hbm_budget_bytes <= 0 || (o.precision != 0 && o.precision != 1) ||
         (o.smoother != 0 && o.smoother != 1) || o.p_coarsening < 0 || o.p_coarsening > 2 ||
         !(o.coarse_reduction > 1.0) || (o.graded_coarsening != 0 && o.graded_coarsening != 1) ||
-        o.coarse_direct_max_dofs < 0 || o.coarse_direct_max_dofs > 1024) {
+        o.coarse_direct_max_dofs < 0 || o.coarse_direct_max_dofs > 1024 || o.batch_max_rhs < 1 ||
+        o.batch_max_rhs > kMaxSolveRhs || o.batch_max_dofs < 0) {
         set_error("sipg_server_create: workers in [1,16], budget > 0, precision and smoother 0 or 1, p_coarsening 0..2, "
-                  "coarse_reduction > 1");
+                  "coarse_reduction > 1, graded_coarsening 0 or 1, coarse_direct_max_dofs 0..1024, batch_max_rhs "
+                  "1..16, batch_max_dofs >= 0");
         return SIPG_E_ARG;
     }
     sipg_server* s = new (std::nothrow) sipg_server();
@@ -439,6 +563,8 @@ int sipg_server_stats(sipg_server* s, sipg_server_stats_t* st) {
     st->cached_hierarchies = int64_t(s->cache.size());
     st->used_bytes = s->used_bytes;
     st->peak_bytes = s->peak_bytes;
+    st->batched_solves = s->batched_solves;
+    st->batched_requests = s->batched_requests;
     return SIPG_OK;
 }
 

@@ -56,6 +56,9 @@ prolongate_kernel(const T* __restrict__ coarse, T* __restrict__ fine, const T* _
     __shared__ T Y[4][N3];
     const int cx = cm.nc[0], cy = cm.nc[1];
     const int cc = blockIdx.x;
+    // several right-hand sides stored one after another: blockIdx.y picks one
+    coarse += size_t(blockIdx.y) * gridDim.x * N3;
+    fine += size_t(blockIdx.y) * (size_t(cm.nf[0]) * cm.nf[1] * cm.nf[2]) * N3;
     const int ix = cc % cx, iy = (cc / cx) % cy, iz = cc / (cx * cy);
     const int n1 = cm.children(0, ix), n2 = cm.children(1, iy), n3 = cm.children(2, iz);
     const int tid = threadIdx.x;
@@ -113,6 +116,9 @@ restrict_kernel(const T* __restrict__ fine, T* __restrict__ coarse, const T* __r
     __shared__ T Y[2][N3];
     const int cx = cm.nc[0], cy = cm.nc[1];
     const int cc = blockIdx.x;
+    // several right-hand sides stored one after another: blockIdx.y picks one
+    coarse += size_t(blockIdx.y) * gridDim.x * N3;
+    fine += size_t(blockIdx.y) * (size_t(cm.nf[0]) * cm.nf[1] * cm.nf[2]) * N3;
     const int ix = cc % cx, iy = (cc / cx) % cy, iz = cc / (cx * cy);
     const int n1 = cm.children(0, ix), n2 = cm.children(1, iy), n3 = cm.children(2, iz);
     const int tid = threadIdx.x;
@@ -183,9 +189,9 @@ static ChildMap child_map(const int nf[3]) {
 }
 
 template <typename T>
-int transfer_prolongate_add(int n, const int nf[3], const T* coarse, T* fine, const T* emb, hipStream_t st) {
+int transfer_prolongate_add(int n, const int nf[3], const T* coarse, T* fine, const T* emb, hipStream_t st, int nv) {
     const ChildMap cm = child_map(nf);
-    const unsigned ncoarse = unsigned(cm.nc[0] * cm.nc[1] * cm.nc[2]);
+    const dim3 ncoarse = dim3(unsigned(cm.nc[0] * cm.nc[1] * cm.nc[2]), unsigned(nv));
     switch (n) {
 #define SIPG_TR_CASE(NN)                                                                          \
     case NN:                                                                                      \
@@ -201,9 +207,9 @@ int transfer_prolongate_add(int n, const int nf[3], const T* coarse, T* fine, co
 }
 
 template <typename T>
-int transfer_restrict(int n, const int nf[3], const T* fine, T* coarse, const T* emb, hipStream_t st) {
+int transfer_restrict(int n, const int nf[3], const T* fine, T* coarse, const T* emb, hipStream_t st, int nv) {
     const ChildMap cm = child_map(nf);
-    const unsigned ncoarse = unsigned(cm.nc[0] * cm.nc[1] * cm.nc[2]);
+    const dim3 ncoarse = dim3(unsigned(cm.nc[0] * cm.nc[1] * cm.nc[2]), unsigned(nv));
     switch (n) {
 #define SIPG_TR_CASE(NN)                                                                        \
     case NN:                                                                                    \
@@ -231,6 +237,9 @@ ptransfer_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __restr
     __shared__ T c[C];
     const size_t cell = blockIdx.x;
     const int tid = threadIdx.x;
+    // several right-hand sides stored one after another: blockIdx.y picks one
+    in += size_t(blockIdx.y) * gridDim.x * I3;
+    out += size_t(blockIdx.y) * gridDim.x * O3;
     for (int e = tid; e < I3; e += 64) a[e] = in[cell * I3 + e];
     __syncthreads();
     for (int e = tid; e < B; e += 64) {   // b[i3][i2][o1]
@@ -267,8 +276,8 @@ ptransfer_kernel(const T* __restrict__ in, T* __restrict__ out, const T* __restr
 
 template <typename T>
 int transfer_degree(int nf, int nc, int64_t ncells, bool restrict_, const T* in, T* out, const T* E,
-                    const T* Et, hipStream_t st) {
-    const unsigned g = unsigned(ncells);
+                    const T* Et, hipStream_t st, int nv) {
+    const dim3 g = dim3(unsigned(ncells), unsigned(nv));
 #define SIPG_PCASE(F, C)                                                                     \
     if (nf == F && nc == C) {                                                                \
         if (restrict_) ptransfer_kernel<F, C, T, false><<<g, 64, 0, st>>>(in, out, Et);      \
@@ -282,12 +291,12 @@ int transfer_degree(int nf, int nc, int64_t ncells, bool restrict_, const T* in,
     return SIPG_E_UNSUPPORTED;
 }
 
-template int transfer_degree<float>(int, int, int64_t, bool, const float*, float*, const float*, const float*, hipStream_t);
-template int transfer_degree<double>(int, int, int64_t, bool, const double*, double*, const double*, const double*, hipStream_t);
+template int transfer_degree<float>(int, int, int64_t, bool, const float*, float*, const float*, const float*, hipStream_t, int);
+template int transfer_degree<double>(int, int, int64_t, bool, const double*, double*, const double*, const double*, hipStream_t, int);
 
-template int transfer_prolongate_add<float>(int, const int[3], const float*, float*, const float*, hipStream_t);
-template int transfer_prolongate_add<double>(int, const int[3], const double*, double*, const double*, hipStream_t);
-template int transfer_restrict<float>(int, const int[3], const float*, float*, const float*, hipStream_t);
-template int transfer_restrict<double>(int, const int[3], const double*, double*, const double*, hipStream_t);
+template int transfer_prolongate_add<float>(int, const int[3], const float*, float*, const float*, hipStream_t, int);
+template int transfer_prolongate_add<double>(int, const int[3], const double*, double*, const double*, hipStream_t, int);
+template int transfer_restrict<float>(int, const int[3], const float*, float*, const float*, hipStream_t, int);
+template int transfer_restrict<double>(int, const int[3], const double*, double*, const double*, hipStream_t, int);
 
 }  // namespace sipg

@@ -85,16 +85,23 @@ __device__ __forceinline__ double vblock_sum(double v) {
     return s;
 }
 
-// partial[block] = sum a_i b_i, accumulated in double
+// partial[block] = sum a_i b_i, accumulated in double; blockIdx.y picks one
+// of several vector pairs stored one after another (partials gridDim.x apart)
 template <typename T>
 __global__ void __launch_bounds__(kVT) vdot_kernel(const T* __restrict__ a, const T* __restrict__ b, double* __restrict__ partial, int64_t n) {
+    a += size_t(blockIdx.y) * n;
+    b += size_t(blockIdx.y) * n;
+    partial += size_t(blockIdx.y) * gridDim.x;
     double s = 0.0;
     for (int64_t i = int64_t(blockIdx.x) * kVT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kVT) s += double(a[i]) * double(b[i]);
     s = vblock_sum(s);
     if (threadIdx.x == 0) partial[blockIdx.x] = s;
 }
 
+// out[block] = sum of the block's nb partials
 __global__ void __launch_bounds__(kVT) vfinish_kernel(const double* __restrict__ partial, int nb, double* __restrict__ out) {
+    partial += size_t(blockIdx.x) * nb;
+    out += blockIdx.x;
     double s = 0.0;
     for (int i = threadIdx.x; i < nb; i += kVT) s += partial[i];
     s = vblock_sum(s);
@@ -147,6 +154,100 @@ int vec_dot_async(const T* a, const T* b, double* partial, double* out, int64_t 
 }
 
 template <typename T>
+int vec_dot_many(const T* a, const T* b, double* partial, double* out, int64_t n, int nv, hipStream_t st) {
+    const unsigned nb = vblocks(n);
+    vdot_kernel<T><<<dim3(nb, unsigned(nv)), kVT, 0, st>>>(a, b, partial, n);
+    vfinish_kernel<<<unsigned(nv), kVT, 0, st>>>(partial, int(nb), out);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
+// Several right-hand sides of one conjugate gradient iteration, stored one
+// after another (n apart), blockIdx.y picking one; vector v is updated only
+// while active[v] != 0, with c = sign * num[v] / den[v]:  y = c x + y  and
+// y = x + c y.
+template <typename T>
+__global__ void __launch_bounds__(kVT) axpy_many_kernel(const double* __restrict__ num, const double* __restrict__ den,
+                                                        const double* __restrict__ active, double sign,
+                                                        const T* __restrict__ x, T* __restrict__ y, int64_t n) {
+    const int v = blockIdx.y;
+    if (active[v] == 0.0) return;
+    const T c = T(sign * (num[v] / den[v]));
+    x += size_t(v) * n;
+    y += size_t(v) * n;
+    for (int64_t i = int64_t(blockIdx.x) * kVT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kVT) y[i] = c * x[i] + y[i];
+}
+template <typename T>
+__global__ void __launch_bounds__(kVT) xpby_many_kernel(const T* __restrict__ x, const double* __restrict__ num,
+                                                        const double* __restrict__ den, const double* __restrict__ active,
+                                                        T* __restrict__ y, int64_t n) {
+    const int v = blockIdx.y;
+    if (active[v] == 0.0) return;
+    const T c = T(num[v] / den[v]);
+    x += size_t(v) * n;
+    y += size_t(v) * n;
+    for (int64_t i = int64_t(blockIdx.x) * kVT + threadIdx.x; i < n; i += int64_t(gridDim.x) * kVT) y[i] = x[i] + c * y[i];
+}
+// out[v] = num[v] while active[v] != 0
+__global__ void copy_many_kernel(const double* __restrict__ num, const double* __restrict__ active,
+                                 double* __restrict__ out, int nv) {
+    const int v = threadIdx.x;
+    if (v < nv && active[v] != 0.0) out[v] = num[v];
+}
+// Start of the iteration: target[v] = rel_tol ||b_v|| (rel_tol for b_v = 0)
+// from bb[v] = ||b_v||^2, active[v] = 1 while ||r_v|| > target[v], iters[v] = 0.
+__global__ void cg_start_many_kernel(const double* __restrict__ bb, const double* __restrict__ rr, double rel_tol,
+                                     double* __restrict__ target, double* __restrict__ active,
+                                     double* __restrict__ iters, int nv) {
+    const int v = threadIdx.x;
+    if (v >= nv) return;
+    const double t = rel_tol * (bb[v] > 0.0 ? sqrt(bb[v]) : 1.0);
+    target[v] = t;
+    active[v] = sqrt(rr[v]) <= t ? 0.0 : 1.0;
+    iters[v] = 0.0;
+}
+// End of an iteration (rr[v] = r_v.r_v after it): an active vector counts
+// the iteration and stops once ||r_v|| <= target[v].
+__global__ void cg_mask_many_kernel(const double* __restrict__ rr, const double* __restrict__ target,
+                                    double* __restrict__ active, double* __restrict__ iters, int nv) {
+    const int v = threadIdx.x;
+    if (v >= nv || active[v] == 0.0) return;
+    iters[v] += 1.0;
+    if (sqrt(rr[v]) <= target[v]) active[v] = 0.0;
+}
+
+template <typename T>
+int vec_axpy_many(const double* num, const double* den, const double* active, double sign, const T* x, T* y, int64_t n,
+                  int nv, hipStream_t st) {
+    axpy_many_kernel<T><<<dim3(vblocks(n), unsigned(nv)), kVT, 0, st>>>(num, den, active, sign, x, y, n);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+template <typename T>
+int vec_xpby_many(const T* x, const double* num, const double* den, const double* active, T* y, int64_t n, int nv,
+                  hipStream_t st) {
+    xpby_many_kernel<T><<<dim3(vblocks(n), unsigned(nv)), kVT, 0, st>>>(x, num, den, active, y, n);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+int scalar_copy_many(const double* num, const double* active, double* out, int nv, hipStream_t st) {
+    copy_many_kernel<<<1, 64, 0, st>>>(num, active, out, nv);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+int cg_start_many(const double* bb, const double* rr, double rel_tol, double* target, double* active, double* iters,
+                  int nv, hipStream_t st) {
+    cg_start_many_kernel<<<1, 64, 0, st>>>(bb, rr, rel_tol, target, active, iters, nv);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+int cg_mask_many(const double* rr, const double* target, double* active, double* iters, int nv, hipStream_t st) {
+    cg_mask_many_kernel<<<1, 64, 0, st>>>(rr, target, active, iters, nv);
+    SIPG_HIP(hipGetLastError());
+    return SIPG_OK;
+}
+
+template <typename T>
 int vec_axpy_dev(const double* num, const double* den, double sign, const T* x, T* y, int64_t n, hipStream_t st) {
     axpy_dev_kernel<T><<<vblocks(n), kVT, 0, st>>>(num, den, sign, x, y, n);
     SIPG_HIP(hipGetLastError());
@@ -165,12 +266,15 @@ int scalar_ratio(const double* num, const double* den, double* out, hipStream_t 
 }
 
 // y = A x, A dense n x n row major: one wavefront per row, its lanes striding
-// over the columns, then a shuffle reduction.
+// over the columns, then a shuffle reduction; blockIdx.y picks one of several
+// x (and y) stored one after another.
 template <typename T>
 __global__ void __launch_bounds__(kVT) dense_mv_kernel(const T* __restrict__ A, const T* __restrict__ x,
                                                        T* __restrict__ y, int n) {
     const int row = blockIdx.x * (kVT / 64) + threadIdx.x / 64, lane = threadIdx.x % 64;
     if (row >= n) return;
+    x += size_t(blockIdx.y) * n;
+    y += size_t(blockIdx.y) * n;
     const T* __restrict__ a = A + size_t(row) * n;
     T acc = T(0);
     for (int j = lane; j < n; j += 64) acc = fma(a[j], x[j], acc);
@@ -179,8 +283,8 @@ __global__ void __launch_bounds__(kVT) dense_mv_kernel(const T* __restrict__ A, 
 }
 
 template <typename T>
-int vec_dense_mv(const T* A, const T* x, T* y, int n, hipStream_t st) {
-    const unsigned g = unsigned((n + kVT / 64 - 1) / (kVT / 64));
+int vec_dense_mv(const T* A, const T* x, T* y, int n, hipStream_t st, int nv) {
+    const dim3 g = dim3(unsigned((n + kVT / 64 - 1) / (kVT / 64)), unsigned(nv));
     dense_mv_kernel<T><<<g, kVT, 0, st>>>(A, x, y, n);
     SIPG_HIP(hipGetLastError());
     return SIPG_OK;
@@ -195,7 +299,11 @@ int vec_dense_mv(const T* A, const T* x, T* y, int n, hipStream_t st) {
     template int vec_scale<T>(double, const T*, T*, int64_t, hipStream_t);                   \
     template int vec_sawtooth<T>(T*, int64_t, hipStream_t);                                  \
     template int vec_dot_async<T>(const T*, const T*, double*, double*, int64_t, hipStream_t); \
-    template int vec_dense_mv<T>(const T*, const T*, T*, int, hipStream_t);
+    template int vec_dot_many<T>(const T*, const T*, double*, double*, int64_t, int, hipStream_t); \
+    template int vec_axpy_many<T>(const double*, const double*, const double*, double, const T*, T*, int64_t, int, \
+                                  hipStream_t);                                               \
+    template int vec_xpby_many<T>(const T*, const double*, const double*, const double*, T*, int64_t, int, hipStream_t); \
+    template int vec_dense_mv<T>(const T*, const T*, T*, int, hipStream_t, int);
 SIPG_VEC_INST(float)
 SIPG_VEC_INST(double)
 template int vec_convert<float, double>(const double*, float*, int64_t, hipStream_t);

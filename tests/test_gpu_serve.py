@@ -165,3 +165,50 @@ def test_server_with_graded_levels_matches_direct_solve():
     srv.close()
     mg.close()
     op.close()
+
+
+def test_server_solves_queued_requests_of_one_problem_together():
+    """Requests of one problem queued behind a running solve are taken along
+    into one multi-right-hand-side solve (sipg_mg_solve_many); every result
+    is its own direct solve's, bit for bit, and other problems in between
+    are served as before."""
+    torch, P = require_gpu()
+    banner("serve grouped requests")
+    rng = np.random.default_rng(21)
+    mesh, k = unit_cube(6), 3
+    other, ko = unit_cube(5, 0.1), 2
+    specs = []
+    for i in range(9):
+        m, d = (other, ko) if i in (3, 6) else (mesh, k)
+        specs.append((m, d, list(rng.normal(size=3)), [tuple(w) for w in rng.integers(1, 4, size=(3, 3))]))
+    # one worker: while it builds the first hierarchy the rest queue up
+    srv = P.Server(workers=1, precision="mixed", batch_max_rhs=8)
+    tickets = [srv.submit(P.Server.make_request(m, d, a, w, rel_tol=1e-9)) for m, d, a, w in specs]
+    results = [srv.wait(t) for t in tickets]
+    st = srv.stats()
+    assert st["batched_solves"] >= 1 and st["batched_requests"] >= 2, st
+    mgs = {}
+    for (m, d, a, w), t, res in zip(specs, tickets, results):
+        assert res["status"] == 0 and res["rel_residual"] <= 1e-9, res
+        if d not in mgs:
+            mgs[d] = (P.Operator(m, d, 2.0),
+                      P.Multigrid(m, d, 2.0, precision="mixed", smoother="fdm", p_coarsening=1,
+                                  coarse_reduction=10.0, graded_coarsening=0, coarse_direct_max_dofs=256))
+        op, mg = mgs[d]
+        xd, info = mg.solve(op.assemble_rhs(a, w), rel_tol=1e-9)
+        torch.cuda.synchronize()
+        assert info.iterations == res["iterations"], (info, res)
+        assert torch.equal(srv.solution(res), xd)
+        srv.release(t)
+    srv.close()
+    for op, mg in mgs.values():
+        mg.close()
+        op.close()
+    # batching off: every request alone
+    srv = P.Server(workers=1, precision="mixed", batch_max_rhs=1)
+    tickets = [srv.submit(P.Server.make_request(m, d, a, w, rel_tol=1e-9)) for m, d, a, w in specs[:4]]
+    for t in tickets:
+        assert srv.wait(t)["status"] == 0
+        srv.release(t)
+    assert srv.stats()["batched_solves"] == 0
+    srv.close()

@@ -188,6 +188,24 @@ def test_graded_mesh_and_multigrid_option_errors_without_gpu():
     assert s.graded_coarsening == 0 and s.coarse_direct_max_dofs == 256
     s.coarse_direct_max_dofs = 5000
     assert P.lib.sipg_server_create(C.byref(s), None, C.byref(h)) == -1
+    # grouping of same-problem requests into one multi-right-hand-side solve
+    s = B.SipgServerOpts()
+    P.lib.sipg_server_default_opts(C.byref(s))
+    assert s.batch_max_rhs == 8 and s.batch_max_dofs == 1 << 22
+    for field, value in (("batch_max_rhs", 0), ("batch_max_rhs", 17), ("batch_max_dofs", -1)):
+        s2 = B.SipgServerOpts()
+        P.lib.sipg_server_default_opts(C.byref(s2))
+        setattr(s2, field, value)
+        assert P.lib.sipg_server_create(C.byref(s2), None, C.byref(h)) == -1, field
+        assert "batch_max_rhs" in P.lib.sipg_last_error().decode()
+
+
+def test_solve_many_argument_errors_without_gpu():
+    """sipg_mg_solve_many rejects null handles, bad right-hand-side counts and
+    tolerances before any device work."""
+    infos = (P.binding.SipgSolveInfo * 2)()
+    assert P.lib.sipg_mg_solve_many(None, 2, None, None, 1e-8, 10, infos, None) == -1
+    assert "null argument" in P.lib.sipg_last_error().decode()
 
 
 def test_slab_argument_errors_without_gpu():
