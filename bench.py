@@ -393,6 +393,47 @@ def solver_benchmark(torch, P, reps: int = 3):
     return out
 
 
+def many_benchmark(torch, P, nrhs: int = 8, reps: int = 3):
+    """Right-hand sides of one problem solved together (sipg_mg_solve_many:
+    one launch per kernel for all of them) against the same solves one after
+    another: served-request problems (unit cube n^3, degree k, 8 sine modes,
+    tolerance 1e-8, mixed precision, the server's solver options)."""
+    from workloads import serving_requests, unit_cube
+    reqs = serving_requests(200.0, 2.0, 1)
+    out = []
+    for n, k in ((8, 3), (12, 4), (16, 4), (24, 4), (32, 5), (48, 5)):
+        mesh = unit_cube(n)
+        op = P.Operator(mesh, k, 2.0)
+        b = torch.stack([op.assemble_rhs(list(a), [tuple(w) for w in wv])
+                         for _, _, _, a, wv in reqs[:nrhs]]).contiguous()
+        op.close()
+        mg = P.Multigrid(mesh, k, 2.0, precision="mixed", smoother="fdm", p_coarsening=1, coarse_reduction=10.0,
+                         coarse_direct_max_dofs=256)
+        one, many, its = [], [], []
+        for rep in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for v in range(nrhs):
+                _, info = mg.solve(b[v], rel_tol=1e-8)
+                its.append(info.iterations)
+            torch.cuda.synchronize()
+            t1 = time.perf_counter()
+            x, infos = mg.solve_many(b, rel_tol=1e-8)
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            if rep:   # the first round warms up
+                one.append(t1 - t0)
+                many.append(t2 - t1)
+        t_one, t_many = float(np.median(one)), float(np.median(many))
+        out.append({"n": n, "degree": k, "ndofs": mg.ndofs, "nrhs": nrhs,
+                    "one_by_one_solves_per_s": nrhs / t_one, "lockstep_solves_per_s": nrhs / t_many,
+                    "speedup": t_one / t_many, "mean_iterations": float(np.mean(its)),
+                    "lockstep_max_iterations": max(i.iterations for i in infos)})
+        mg.close()
+        del b, x
+    return out
+
+
 def serve_benchmark(P, precision: str, seconds: float, rate: float, workers: int = 8,
                     budget_bytes: int = 96 << 30, tol: float = 1e-8, server_opts=None):
     """Poisson arrivals of multigrid Poisson solves (unit cube n^3, n log-uniform
@@ -456,7 +497,9 @@ def serve_benchmark(P, precision: str, seconds: float, rate: float, workers: int
             "mean_queue_s": float(np.mean([r["queue_s"] for r in results])),
             "mean_iterations": float(np.mean([r["iterations"] for r in results])),
             "max_rel_residual": float(max(r["rel_residual"] for r in results)),
-            "cached_hierarchies": st["cached_hierarchies"], "peak_bytes": st["peak_bytes"], "workers": workers}
+            "cached_hierarchies": st["cached_hierarchies"], "peak_bytes": st["peak_bytes"], "workers": workers,
+            "batched_solves": st["batched_solves"], "batched_requests": st["batched_requests"],
+            "server_opts": server_opts or {}}
 
 
 def main():
@@ -697,6 +740,11 @@ def main():
         out["solver"] = solver_benchmark(torch, P)
         torch.cuda.empty_cache()
 
+    if not args.no_solver:
+        print("[bench] lockstep solves of 8 right-hand sides", file=sys.stderr, flush=True)
+        out["solve_many"] = many_benchmark(torch, P)
+        torch.cuda.empty_cache()
+
     if not args.no_batch:
         out["batch"] = []
         for dt in ("f64", "f32"):
@@ -717,6 +765,11 @@ def main():
     if args.serve_seconds > 0 and args.serve_capacity_rate > 0:
         print(f"[bench] serving mixed capacity: {args.serve_capacity_rate}/s for 10 s", file=sys.stderr, flush=True)
         serve["capacity_mixed"] = serve_benchmark(P, "mixed", 10.0, args.serve_capacity_rate, args.serve_workers)
+        torch.cuda.empty_cache()
+        # the same without grouping same-problem requests into one solve
+        print(f"[bench] serving mixed capacity, every request alone", file=sys.stderr, flush=True)
+        serve["capacity_mixed_unbatched"] = serve_benchmark(P, "mixed", 10.0, args.serve_capacity_rate,
+                                                            args.serve_workers, server_opts={"batch_max_rhs": 1})
         torch.cuda.empty_cache()
     # latency below saturation: the same stream thinned to a rate both
     # precisions sustain, over a longer window

@@ -466,9 +466,11 @@ int sipg_mg_apply_vcycle(sipg_mg* mg, const double* r, double* z, void* stream);
 int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int max_iter,
                   sipg_solve_info* info, void* stream);
 /* nrhs right-hand sides of the same problem solved together (Section 6's
- * solver; several requests for one operator co-scheduled): every product,
- * smoothing step, transfer and vector update of an iteration is one launch
- * covering all of them.
+ * solver; several requests for one operator co-scheduled): one iteration
+ * loop for all of them, whose transfers, merged smoothing passes, coarse
+ * solves, dot products and vector updates are one launch each covering all
+ * right-hand sides; the products and fused smoothing steps are launched per
+ * right-hand side, back to back on the stream.
  *   nrhs        1 .. 16
  *   b, x        device, double, nrhs * ndofs each: right-hand side v at
  *               b + v * ndofs, x likewise (initial guesses in, solutions out);
@@ -534,11 +536,14 @@ typedef struct {
                                     served mix the graded levels cost more CG steps than their
                                     cheaper coarse solves save) */
     int32_t coarse_direct_max_dofs; /* sipg_mg_opts.coarse_direct_max_dofs of every solve (256) */
-    int32_t batch_max_rhs;       /* queued requests of one problem (same mesh, degree, basis,
-                                    penalty, rel_tol and max_iter) solved together by one
-                                    sipg_mg_solve_many, at most this many (1..16; 8; 1: each
-                                    request alone) */
-    int64_t batch_max_dofs;      /* ... while their unknowns add up to at most this (2^22) */
+    int32_t batch_max_rhs;       /* requests of one problem (same mesh, degree, basis, penalty,
+                                    rel_tol and max_iter) among the next 2 x workers queued
+                                    ones are solved together by one sipg_mg_solve_many, at
+                                    most this many (1..16; 8; 1: each request alone) */
+    int64_t batch_max_dofs;      /* ... while their unknowns add up to at most this (2^20:
+                                    small problems, whose solves are bound by launch latency
+                                    and gain most; a group of larger ones delays each member
+                                    by the whole group's solve) */
 } sipg_server_opts;
 typedef struct {
     sipg_mesh mesh;

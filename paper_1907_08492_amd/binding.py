@@ -627,7 +627,7 @@ class Server:
     def __init__(self, hbm_budget_bytes: int = 64 << 30, workers: int = 8, precision: str = "mixed",
                  smoother: str = "fdm", p_coarsening: int = 1, coarse_reduction: float = 10.0,
                  allocator="torch", graded_coarsening: int = 0, coarse_direct_max_dofs: int = 256,
-                 batch_max_rhs: int = 8, batch_max_dofs: int = 1 << 22):
+                 batch_max_rhs: int = 8, batch_max_dofs: int = 1 << 20):
         torch = _torch()
         if not torch.cuda.is_available():
             raise RuntimeError("Server needs a GPU (HIP device)")

@@ -1122,10 +1122,6 @@ __global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, BASIS, T, G
 sipg_matvec_kernel(MatvecParams<T> p) {
     constexpr int CPB = cells_per_block(N);
     const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
-    // several right-hand sides stored one after another: blockIdx.y picks one
-    const size_t off = size_t(blockIdx.y) * size_t(p.ncells) * (N * N * N);
-    p.x += off;
-    p.y += off;
     matvec_block<N, BASIS, T, GEOM>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks));
 }
 
@@ -1147,12 +1143,6 @@ __global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, BASIS, T, G
 sipg_matvec_cheb_kernel(MatvecParams<T> p) {
     constexpr int CPB = cells_per_block(N);
     const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
-    // several right-hand sides stored one after another: blockIdx.y picks one
-    const size_t off = size_t(blockIdx.y) * size_t(p.ncells) * (N * N * N);
-    p.x += off;
-    p.y += off;
-    p.b += off;
-    p.uo += off;
     matvec_block<N, BASIS, T, GEOM, EPI>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks));
 }
 

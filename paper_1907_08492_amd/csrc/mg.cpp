@@ -220,7 +220,7 @@ struct Scratch {
         if ((rc = partial.alloc(kVecPartials, mem)) != SIPG_OK) return rc;
         if ((rc = scal.alloc(8 * kMaxRhs, mem)) != SIPG_OK) return rc;
         if ((rc = coef.alloc(2 * kMaxLanczos, mem)) != SIPG_OK) return rc;
-        SIPG_HIP(hipHostMalloc(&host, sizeof(double) * (8 + 5 * kMaxRhs), hipHostMallocDefault));
+        SIPG_HIP(hipHostMalloc(&host, sizeof(double) * (8 + 6 * kMaxRhs), hipHostMallocDefault));
         for (hipEvent_t& e : ev) SIPG_HIP(hipEventCreateWithFlags(&e, hipEventDisableTiming));
         return SIPG_OK;
     }
@@ -725,9 +725,10 @@ int64_t mg_many_bytes(const sipg_mg* mg, int nv) {
 }
 
 // FP64 preconditioned conjugate gradient with one V-cycle per iteration for
-// nrhs right-hand sides of one hierarchy advanced in lockstep: every product,
-// smoothing step, transfer and vector operation is one launch for all of
-// them.  Vector v stops (its x, r and p are no longer updated) at the first
+// nrhs right-hand sides of one hierarchy advanced in lockstep: transfers,
+// merged smoothing passes, coarse solves, dot products and vector updates
+// are one launch for all of them (the products and fused smoothing steps one
+// launch per right-hand side, back to back).  Vector v stops (its x, r and p are no longer updated) at the first
 // iteration whose residual meets its tolerance (decided on the device, so
 // no vector takes an iteration beyond it); the loop ends when every vector
 // has stopped.
@@ -795,27 +796,20 @@ int mg_solve_many(sipg_mg* mg, int nrhs, const double* b, double* x, double rel_
     double *s_rz = scal, *s_pap = scal + kMaxRhs, *s_rzn = scal + 2 * kMaxRhs, *s_rr = scal + 3 * kMaxRhs;
     double *s_act = scal + 4 * kMaxRhs, *s_bb = scal + 5 * kMaxRhs, *s_tgt = scal + 6 * kMaxRhs,
            *s_it = scal + 7 * kMaxRhs;
-    // pinned host memory: nv values read synchronously, then two lagged slots
-    // of (r.r, active flags), kMaxRhs each
+    // pinned host memory: the start's and the end's scalars (one copy each),
+    // and in between two lagged slots of (r.r, active flags), kMaxRhs each
     double* hb = sc.host + 8;
     int rc;
-    auto read_now = [&](const double* dev, std::vector<double>& out) -> int {
-        out.resize(nv);
-        SIPG_HIP(hipMemcpyAsync(hb, dev, sizeof(double) * nv, hipMemcpyDeviceToHost, st));
-        SIPG_HIP(hipStreamSynchronize(st));
-        std::copy(hb, hb + nv, out.begin());
-        return SIPG_OK;
-    };
     // ||b_v||, r = b - A x, ||r_v||, targets and active flags
     if ((rc = vec_dot_many<double>(b, b, partial, s_bb, n, nv, st)) != SIPG_OK) return rc;
     if ((rc = launch_matvec(mg->fine64, x, ap, st, {}, nv)) != SIPG_OK) return rc;
     if ((rc = vec_sub<double>(b, ap, r, n * nv, st)) != SIPG_OK) return rc;
     if ((rc = vec_dot_many<double>(r, r, partial, s_rr, n, nv, st)) != SIPG_OK) return rc;
     if ((rc = cg_start_many(s_bb, s_rr, rel_tol, s_tgt, s_act, s_it, nv, st)) != SIPG_OK) return rc;
-    std::vector<double> bb, rr, act, its;
-    if ((rc = read_now(s_bb, bb)) != SIPG_OK) return rc;
-    if ((rc = read_now(s_rr, rr)) != SIPG_OK) return rc;
-    if ((rc = read_now(s_act, act)) != SIPG_OK) return rc;
+    SIPG_HIP(hipMemcpyAsync(hb, s_rr, sizeof(double) * 3 * kMaxRhs, hipMemcpyDeviceToHost, st));   // r.r, flags, b.b
+    SIPG_HIP(hipStreamSynchronize(st));
+    std::vector<double> rr(hb, hb + nv), act(hb + kMaxRhs, hb + kMaxRhs + nv),
+        bb(hb + 2 * kMaxRhs, hb + 2 * kMaxRhs + nv);
     std::vector<double> target(nv);
     for (int v = 0; v < nv; ++v) {
         info[v].initial_residual = std::sqrt(rr[v]);
@@ -874,16 +868,17 @@ int mg_solve_many(sipg_mg* mg, int nrhs, const double* b, double* x, double rel_
         SIPG_HIP(hipEventRecord(sc.ev[it % 2], st));
         ++it;
     }
-    // per-vector results: iterations, the residual at which each stopped, and
-    // the true residual ||b - A x||
-    if ((rc = read_now(s_it, its)) != SIPG_OK) return rc;
-    if ((rc = read_now(s_rr, rr)) != SIPG_OK) return rc;
-    if ((rc = read_now(s_act, act)) != SIPG_OK) return rc;
+    // per-vector results: the true residual ||b - A x|| (into the r.z slots),
+    // the residual at which each stopped, its flag and its iterations, in one
+    // copy
     if ((rc = launch_matvec(mg->fine64, x, ap, st, {}, nv)) != SIPG_OK) return rc;
     if ((rc = vec_sub<double>(b, ap, r, n * nv, st)) != SIPG_OK) return rc;
-    if ((rc = vec_dot_many<double>(r, r, partial, s_bb, n, nv, st)) != SIPG_OK) return rc;
-    std::vector<double> tr;
-    if ((rc = read_now(s_bb, tr)) != SIPG_OK) return rc;
+    if ((rc = vec_dot_many<double>(r, r, partial, s_rzn, n, nv, st)) != SIPG_OK) return rc;
+    SIPG_HIP(hipMemcpyAsync(hb, s_rzn, sizeof(double) * 6 * kMaxRhs, hipMemcpyDeviceToHost, st));
+    SIPG_HIP(hipStreamSynchronize(st));
+    std::vector<double> tr(hb, hb + nv), its(hb + 5 * kMaxRhs, hb + 5 * kMaxRhs + nv);
+    rr.assign(hb + kMaxRhs, hb + kMaxRhs + nv);
+    act.assign(hb + 2 * kMaxRhs, hb + 2 * kMaxRhs + nv);
     bool all_converged = true;
     for (int v = 0; v < nv; ++v) {
         info[v].iterations = int(its[v]);

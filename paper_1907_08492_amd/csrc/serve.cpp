@@ -7,8 +7,8 @@
 // from a cache (or builds one), assembles the right-hand side on the device,
 // runs the FP64-CG / multigrid solve and returns the hierarchy to the cache.
 // Queued requests of the same problem are taken along (batch_max_rhs,
-// batch_max_dofs) and solved together by one sipg_mg_solve_many, whose
-// launches cover all of their right-hand sides.
+// batch_max_dofs) and solved together by one sipg_mg_solve_many (one
+// iteration loop for all of their right-hand sides).
 // Solves of different requests therefore run concurrently on the device;
 // requests that arrive while others run are admitted as soon as a worker and
 // enough of the HBM budget are free.  The budget counts the cached
@@ -16,6 +16,7 @@
 // least-recently-used order when a request needs the memory.
 #include <hip/hip_runtime.h>
 
+#include <algorithm>
 #include <chrono>
 #include <condition_variable>
 #include <cstring>
@@ -203,27 +204,30 @@ static Job* admit(sipg_server* s) {
 // Queued requests of j's problem (same key, tolerance and iteration limit)
 // that join j in one sipg_mg_solve_many, within the batch limits and the
 // budget; called with the lock held right after admit(j), which charged j.
-// The group's workspace (its level and CG vectors, and the stacked b and x)
-// is charged to j.
+// Only the next 2 x workers queued requests are looked at, so that requests
+// finish in about the order they arrived (a client that consumes results in
+// order holds the finished ones' memory until then).  The group's workspace
+// (its level and CG vectors, and the stacked b and x) is charged to j.
 static std::vector<Job*> gather_batch(sipg_server* s, Job* j) {
     std::vector<Job*> group{j};
     const int maxr = s->opts.batch_max_rhs;
     if (maxr < 2) return group;
-    std::vector<std::deque<Job*>::iterator> cand;
-    int64_t dofs = j->ndofs, vec_need = 0;
-    for (auto it = s->queue.begin(); it != s->queue.end() && int(cand.size()) + 1 < maxr; ++it) {
-        Job* c = *it;
+    std::vector<Job*> cand;   // in queue order
+    int64_t dofs = j->ndofs;
+    int seen = 0;
+    for (Job* c : s->queue) {
+        if (int(cand.size()) + 1 >= maxr || ++seen > 2 * s->opts.workers) break;
         if (c->key < j->key || j->key < c->key || c->req.rel_tol != j->req.rel_tol ||
             c->req.max_iter != j->req.max_iter || dofs + c->ndofs > s->opts.batch_max_dofs)
             continue;
-        cand.push_back(it);
+        cand.push_back(c);
         dofs += c->ndofs;
     }
     // the largest group whose vectors and workspace fit the budget
     while (!cand.empty()) {
         const int k = int(cand.size()) + 1;
-        vec_need = 0;
-        for (auto it : cand) vec_need += (*it)->req.x_out ? 0 : 8 * (*it)->ndofs;
+        int64_t vec_need = 0;
+        for (Job* c : cand) vec_need += c->req.x_out ? 0 : 8 * c->ndofs;
         const int64_t ws = mg_many_estimate(j->req.mesh, j->req.degree, solver_opts(s->opts), k) +
                            2 * 8 * int64_t(k) * j->ndofs;
         if (s->used_bytes + vec_need + ws <= s->opts.hbm_budget_bytes) {
@@ -233,15 +237,18 @@ static std::vector<Job*> gather_batch(sipg_server* s, Job* j) {
         }
         cand.pop_back();
     }
-    // erase back to front (deque iterators stay valid for the earlier ones)
-    for (auto r = cand.rbegin(); r != cand.rend(); ++r) {
-        Job* c = **r;
+    if (cand.empty()) return group;
+    for (Job* c : cand) {
         c->est_bytes = c->req.x_out ? 0 : 8 * c->ndofs;
         s->used_bytes += c->est_bytes;
         s->running++;
-        s->queue.erase(*r);
-        group.insert(group.begin() + 1, c);
+        group.push_back(c);
     }
+    // take them out of the queue in one pass (an erase in the middle of a
+    // deque invalidates its iterators)
+    s->queue.erase(std::remove_if(s->queue.begin(), s->queue.end(),
+                                  [&](Job* q) { return std::find(cand.begin(), cand.end(), q) != cand.end(); }),
+                   s->queue.end());
     s->peak_bytes = std::max(s->peak_bytes, s->used_bytes);
     return group;
 }
@@ -270,6 +277,13 @@ static void solve_group(sipg_server* s, sipg_mg* mg, const std::vector<Job*>& gr
         group[0]->res.rel_residual = bn > 0.0 ? info.true_residual / bn : info.true_residual;
         status[0] = rc;
         return;
+    }
+    for (const Job* g : group) {
+        if (g->ndofs != n) {   // one problem per group (gather_batch)
+            set_error("request loop: requests of different sizes in one group");
+            std::fill(status.begin(), status.end(), SIPG_E_ARG);
+            return;
+        }
     }
     // stacked right-hand sides and solutions (stream-ordered, or the caller's allocator)
     const size_t bytes = sizeof(double) * size_t(n) * k;
@@ -425,7 +439,7 @@ int sipg_server_default_opts(sipg_server_opts* o) {
     o->graded_coarsening = 0;
     o->coarse_direct_max_dofs = 256;
     o->batch_max_rhs = 8;
-    o->batch_max_dofs = int64_t(1) << 22;
+    o->batch_max_dofs = int64_t(1) << 20;
     return SIPG_OK;
 }
 

@@ -178,15 +178,18 @@ def test_server_solves_queued_requests_of_one_problem_together():
     mesh, k = unit_cube(6), 3
     other, ko = unit_cube(5, 0.1), 2
     specs = []
-    for i in range(9):
-        m, d = (other, ko) if i in (3, 6) else (mesh, k)
+    # the queued requests of each problem sit at scattered places of a queue
+    # with many others behind them: taking them out must leave exactly the rest
+    for i in range(16):
+        m, d = (mesh, k) if i in (0, 1, 2, 4, 9, 15) else (other, ko)
         specs.append((m, d, list(rng.normal(size=3)), [tuple(w) for w in rng.integers(1, 4, size=(3, 3))]))
     # one worker: while it builds the first hierarchy the rest queue up
     srv = P.Server(workers=1, precision="mixed", batch_max_rhs=8)
     tickets = [srv.submit(P.Server.make_request(m, d, a, w, rel_tol=1e-9)) for m, d, a, w in specs]
     results = [srv.wait(t) for t in tickets]
     st = srv.stats()
-    assert st["batched_solves"] >= 1 and st["batched_requests"] >= 2, st
+    assert st["batched_solves"] >= 2 and st["batched_requests"] >= 4, st
+    assert st["completed"] == len(specs) and st["queued"] == 0, st
     mgs = {}
     for (m, d, a, w), t, res in zip(specs, tickets, results):
         assert res["status"] == 0 and res["rel_residual"] <= 1e-9, res

@@ -1,7 +1,6 @@
 """Several right-hand sides of one multigrid solver solved together
-(sipg_mg_solve_many: every launch of an iteration covers all of them)
-against the same solves one at a time, and their residuals against the
-oracle's operator."""
+(sipg_mg_solve_many: one iteration loop for all of them) against the same
+solves one at a time, and their residuals against the oracle's operator."""
 import numpy as np
 import pytest
 

@@ -191,7 +191,7 @@ def test_graded_mesh_and_multigrid_option_errors_without_gpu():
     # grouping of same-problem requests into one multi-right-hand-side solve
     s = B.SipgServerOpts()
     P.lib.sipg_server_default_opts(C.byref(s))
-    assert s.batch_max_rhs == 8 and s.batch_max_dofs == 1 << 22
+    assert s.batch_max_rhs == 8 and s.batch_max_dofs == 1 << 20
     for field, value in (("batch_max_rhs", 0), ("batch_max_rhs", 17), ("batch_max_dofs", -1)):
         s2 = B.SipgServerOpts()
         P.lib.sipg_server_default_opts(C.byref(s2))
