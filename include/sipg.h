@@ -467,10 +467,9 @@ int sipg_mg_solve(sipg_mg* mg, const double* b, double* x, double rel_tol, int m
                   sipg_solve_info* info, void* stream);
 /* nrhs right-hand sides of the same problem solved together (Section 6's
  * solver; several requests for one operator co-scheduled): one iteration
- * loop for all of them, whose transfers, merged smoothing passes, coarse
- * solves, dot products and vector updates are one launch each covering all
- * right-hand sides; the products and fused smoothing steps are launched per
- * right-hand side, back to back on the stream.
+ * loop for all of them, in which every product, smoothing step, transfer,
+ * coarse solve, dot product and vector update is one launch covering all
+ * right-hand sides.
  *   nrhs        1 .. 16
  *   b, x        device, double, nrhs * ndofs each: right-hand side v at
  *               b + v * ndofs, x likewise (initial guesses in, solutions out);

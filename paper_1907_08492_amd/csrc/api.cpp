@@ -144,22 +144,15 @@ int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st, Gho
         set_error("product: one right-hand side with ghost layers, at least one otherwise");
         return SIPG_E_ARG;
     }
-    if (nv > 1) {
-        const size_t step = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
-        for (int v = 0; v < nv; ++v)
-            if (int rc = launch_matvec(op, static_cast<const char*>(x) + v * step, static_cast<char*>(y) + v * step, st))
-                return rc;
-        return SIPG_OK;
-    }
     switch (op->n) {
-        case 2: return launch_matvec_n<2>(op, x, y, st, g);
-        case 3: return launch_matvec_n<3>(op, x, y, st, g);
-        case 4: return launch_matvec_n<4>(op, x, y, st, g);
-        case 5: return launch_matvec_n<5>(op, x, y, st, g);
-        case 6: return launch_matvec_n<6>(op, x, y, st, g);
-        case 7: return launch_matvec_n<7>(op, x, y, st, g);
-        case 8: return launch_matvec_n<8>(op, x, y, st, g);
-        case 9: return launch_matvec_n<9>(op, x, y, st, g);
+        case 2: return launch_matvec_n<2>(op, x, y, st, g, nv);
+        case 3: return launch_matvec_n<3>(op, x, y, st, g, nv);
+        case 4: return launch_matvec_n<4>(op, x, y, st, g, nv);
+        case 5: return launch_matvec_n<5>(op, x, y, st, g, nv);
+        case 6: return launch_matvec_n<6>(op, x, y, st, g, nv);
+        case 7: return launch_matvec_n<7>(op, x, y, st, g, nv);
+        case 8: return launch_matvec_n<8>(op, x, y, st, g, nv);
+        case 9: return launch_matvec_n<9>(op, x, y, st, g, nv);
     }
     set_error("unsupported degree");
     return SIPG_E_UNSUPPORTED;
@@ -191,24 +184,19 @@ int launch_matvec_cheb(const sipg_op* op, int mode, const void* b, const void* u
         set_error("fused Chebyshev step: preconditioner mode or its data missing");
         return SIPG_E_ARG;
     }
-    if (nv > 1) {   // one launch per right-hand side (see launch_matvec)
-        const size_t step = size_t(op->ndofs) * (op->dtype == SIPG_F64 ? 8 : 4);
-        for (int v = 0; v < nv; ++v)
-            if (int rc = launch_matvec_cheb(op, mode, static_cast<const char*>(b) + v * step,
-                                            static_cast<const char*>(u) + v * step, static_cast<char*>(uo) + v * step,
-                                            sigma, theta, st))
-                return rc;
-        return SIPG_OK;
+    if (nv < 1) {
+        set_error("fused Chebyshev step: at least one right-hand side");
+        return SIPG_E_ARG;
     }
     switch (op->n) {
-        case 2: return launch_matvec_cheb_n<2>(op, mode, b, u, uo, sigma, theta, st);
-        case 3: return launch_matvec_cheb_n<3>(op, mode, b, u, uo, sigma, theta, st);
-        case 4: return launch_matvec_cheb_n<4>(op, mode, b, u, uo, sigma, theta, st);
-        case 5: return launch_matvec_cheb_n<5>(op, mode, b, u, uo, sigma, theta, st);
-        case 6: return launch_matvec_cheb_n<6>(op, mode, b, u, uo, sigma, theta, st);
-        case 7: return launch_matvec_cheb_n<7>(op, mode, b, u, uo, sigma, theta, st);
-        case 8: return launch_matvec_cheb_n<8>(op, mode, b, u, uo, sigma, theta, st);
-        case 9: return launch_matvec_cheb_n<9>(op, mode, b, u, uo, sigma, theta, st);
+        case 2: return launch_matvec_cheb_n<2>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 3: return launch_matvec_cheb_n<3>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 4: return launch_matvec_cheb_n<4>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 5: return launch_matvec_cheb_n<5>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 6: return launch_matvec_cheb_n<6>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 7: return launch_matvec_cheb_n<7>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 8: return launch_matvec_cheb_n<8>(op, mode, b, u, uo, sigma, theta, st, nv);
+        case 9: return launch_matvec_cheb_n<9>(op, mode, b, u, uo, sigma, theta, st, nv);
     }
     set_error("unsupported degree");
     return SIPG_E_UNSUPPORTED;

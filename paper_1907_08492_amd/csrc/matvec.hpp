@@ -260,9 +260,12 @@ __host__ __device__ __forceinline__ int xcd_block_zinterleaved(int blk, int nblk
 }
 
 // The product on workgroup `blk` of the operator `p`: cells blk*CPB ...,
-// followed by the epilogue EPI on each cell (EPI_NONE: y only).
+// followed by the epilogue EPI on each cell (EPI_NONE: y only).  voff moves
+// every vector access (x, y, z, b, uo) by that many entries: one of several
+// right-hand sides stored one after another.  (The parameter block itself is
+// not changed: a modified copy of it would be kept in scratch memory.)
 template <int N, int BASIS, typename T, int GEOM, int EPI = EPI_NONE>
-__device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int blk) {
+__device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int blk, const size_t voff = 0) {
     using Sh = Shape<N>;
     using Ly = Layers<N, BASIS>;
     constexpr int N2 = Sh::N2, N3 = Sh::N3, RS = Sh::RS, CS = Sh::CS, FR = Sh::FR;
@@ -308,7 +311,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
     constexpr int XPER = (CPB * N3 + NT - 1) / NT;
     T xv[XPER];
     {
-        const T* __restrict__ xs = p.x + size_t(cell0) * N3;
+        const T* __restrict__ xs = p.x + voff + size_t(cell0) * N3;
 #pragma unroll
         for (int j = 0; j < XPER; ++j) {
             const int e = tid + j * NT;
@@ -381,7 +384,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         if (fnb >= 0 && !(D == 0 && (fs ? fc + 1 < ncb : fc > 0))) {
             // runs of consecutive values: the layers (x faces, whose layers
             // are contiguous), else each layer's row
-            const T* __restrict__ xn = p.x + size_t(fnb) * N3;
+            const T* __restrict__ xn = p.x + voff + size_t(fnb) * N3;
             if constexpr (D == 0) {
                 const int l0 = Ly::layer(1 - fs, 0);
 #pragma unroll
@@ -799,7 +802,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         const T* P3 = fel(0, 1, c, 1); const T* Q3 = fel(1, 1, c, 1);
         const T* P4 = fel(0, 2, c, 0); const T* Q4 = fel(1, 2, c, 0);
         const T* P5 = fel(0, 2, c, 1); const T* Q5 = fel(1, 2, c, 1);
-        T* __restrict__ yc = p.y + size_t(cell0 + c) * N3 + i1 + N * i2;
+        T* __restrict__ yc = p.y + voff + size_t(cell0 + c) * N3 + i1 + N * i2;
 #pragma unroll
         for (int k = 0; k < N; ++k) {
             T r = v[k];
@@ -842,7 +845,7 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
         if constexpr (EPI >= EPI_CHEB_PJ) {
             if (act) {
 #pragma unroll
-                for (int k = 0; k < N; ++k) eb[k] = p.b[coff + k * N2];
+                for (int k = 0; k < N; ++k) eb[k] = p.b[voff + coff + k * N2];
             }
         }
     };
@@ -1030,8 +1033,8 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
                 const bool rd = T(p.sigma) != T(0);
 #pragma unroll
                 for (int k = 0; k < N; ++k) {
-                    uu[k] = p.x[coff + k * N2];
-                    uold[k] = rd ? p.uo[coff + k * N2] : uu[k];
+                    uu[k] = p.x[voff + coff + k * N2];
+                    uold[k] = rd ? p.uo[voff + coff + k * N2] : uu[k];
                 }
                 // the residual b - A u
 #pragma unroll
@@ -1104,12 +1107,12 @@ __device__ __forceinline__ void matvec_block(const MatvecParams<T>& p, const int
             bwd(v);
             if constexpr (EPI == EPI_PJACOBI) {
 #pragma unroll
-                for (int k = 0; k < N; ++k) p.z[coff + k * N2] = v[k];
+                for (int k = 0; k < N; ++k) p.z[voff + coff + k * N2] = v[k];
             } else {
                 // uo <- u + sigma (u - uo) + theta P^-1 r  (sigma = 0: uo not read)
                 const T sg = T(p.sigma), th = T(p.theta);
 #pragma unroll
-                for (int k = 0; k < N; ++k) p.uo[coff + k * N2] = uu[k] + sg * (uu[k] - uold[k]) + th * v[k];
+                for (int k = 0; k < N; ++k) p.uo[voff + coff + k * N2] = uu[k] + sg * (uu[k] - uold[k]) + th * v[k];
             }
         }
     }
@@ -1122,7 +1125,9 @@ __global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, BASIS, T, G
 sipg_matvec_kernel(MatvecParams<T> p) {
     constexpr int CPB = cells_per_block(N);
     const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
-    matvec_block<N, BASIS, T, GEOM>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks));
+    // blockIdx.y: one of gridDim.y right-hand sides stored one after another
+    matvec_block<N, BASIS, T, GEOM>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks),
+                                    size_t(blockIdx.y) * size_t(p.ncells) * (N * N * N));
 }
 
 // The same product followed, cell by cell, by P^-1 of eq. (jacobi): y = A x
@@ -1143,7 +1148,9 @@ __global__ void __launch_bounds__(Shape<N>::NT, (matvec_min_waves<N, BASIS, T, G
 sipg_matvec_cheb_kernel(MatvecParams<T> p) {
     constexpr int CPB = cells_per_block(N);
     const int layer_blocks = (p.nx * p.ny + CPB / 2) / CPB;
-    matvec_block<N, BASIS, T, GEOM, EPI>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks));
+    // blockIdx.y: one of gridDim.y right-hand sides stored one after another
+    matvec_block<N, BASIS, T, GEOM, EPI>(p, xcd_block_zinterleaved(blockIdx.x, gridDim.x, layer_blocks),
+                                         size_t(blockIdx.y) * size_t(p.ncells) * (N * N * N));
 }
 
 // Many independent operators of the same degree, basis, precision and

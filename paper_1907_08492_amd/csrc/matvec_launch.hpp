@@ -22,15 +22,17 @@ static int set_lds_limit(K kernel) {
     return SIPG_OK;
 }
 
+// nv right-hand sides stored one after another (op->ndofs apart): grid row
+// blockIdx.y = v works on right-hand side v.
 template <int N, int BASIS, typename T, int GEOM>
-static int launch_one(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g) {
+static int launch_one(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g, int nv) {
     auto kern = &sipg_matvec_kernel<N, BASIS, T, GEOM>;
     if (int rc = set_lds_limit<N, BASIS, T, GEOM, 0>(kern)) return rc;
     const unsigned nblk = unsigned((op->ncells + cells_per_block(N) - 1) / cells_per_block(N));
     MatvecParams<T> p = matvec_params<T>(op, x, y);
     p.ghost_lo = static_cast<const T*>(g.lo);
     p.ghost_hi = static_cast<const T*>(g.hi);
-    kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
+    kern<<<dim3(nblk, unsigned(nv)), threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
     SIPG_HIP(hipGetLastError());
     return SIPG_OK;
 }
@@ -53,26 +55,27 @@ static int launch_one_pjacobi(const sipg_op* op, const void* x, void* y, void* z
 
 // One Chebyshev smoothing step fused into the product (Hermite-like basis):
 // uo = u + sigma (u - uo) + theta P^-1 (b - A u), P^-1 by `mode`
-// (SIPG_BC_PJACOBI with op->gl_inv_diag, SIPG_BC_FDM with op->fdm_cell).
+// (SIPG_BC_PJACOBI with op->gl_inv_diag, SIPG_BC_FDM with op->fdm_cell);
+// nv right-hand sides as in launch_one.
 template <int N, typename T, int GEOM>
 static int launch_one_cheb(const sipg_op* op, int mode, const void* b, const void* u, void* uo, double sigma,
-                           double theta, hipStream_t st) {
+                           double theta, hipStream_t st, int nv) {
     MatvecParams<T> p = matvec_params<T>(op, u, uo);   // y is not written by this epilogue
     p.b = static_cast<const T*>(b);
     p.uo = static_cast<T*>(uo);
     p.sigma = sigma;
     p.theta = theta;
-    const unsigned nblk = unsigned((op->ncells + cells_per_block(N) - 1) / cells_per_block(N));
+    const dim3 grid = dim3(unsigned((op->ncells + cells_per_block(N) - 1) / cells_per_block(N)), unsigned(nv));
     if (mode == SIPG_BC_PJACOBI) {
         auto kern = &sipg_matvec_cheb_kernel<N, 0, T, GEOM, EPI_CHEB_PJ>;
         if (int rc = set_lds_limit<N, 0, T, GEOM, 3>(kern)) return rc;
         p.dinv = static_cast<const T*>(op->gl_inv_diag);
-        kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
+        kern<<<grid, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
     } else {
         auto kern = &sipg_matvec_cheb_kernel<N, 0, T, GEOM, EPI_CHEB_FDM>;
         if (int rc = set_lds_limit<N, 0, T, GEOM, 4>(kern)) return rc;
         p.dinv = static_cast<const T*>(op->fdm_cell);
-        kern<<<nblk, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
+        kern<<<grid, threads_per_block(N), matvec_lds_bytes<N, T>(), st>>>(p);
     }
     SIPG_HIP(hipGetLastError());
     return SIPG_OK;
@@ -131,9 +134,9 @@ static int dispatch_hl(int dtype, int geom, F&& launch) {
 #define SIPG_MATVEC_DEGREE(NV)                                                                          \
     namespace sipg {                                                                                    \
     template <>                                                                                         \
-    int launch_matvec_n<NV>(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts gh) {     \
+    int launch_matvec_n<NV>(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts gh, int nv) { \
         return dispatch<NV>(op->basis, op->dtype, matvec_geom(op), [&](auto b, auto t, auto g) {        \
-            return launch_one<NV, decltype(b)::value, decltype(t), decltype(g)::value>(op, x, y, st, gh); \
+            return launch_one<NV, decltype(b)::value, decltype(t), decltype(g)::value>(op, x, y, st, gh, nv); \
         });                                                                                             \
     }                                                                                                   \
     template <>                                                                                         \
@@ -146,9 +149,9 @@ static int dispatch_hl(int dtype, int geom, F&& launch) {
     }                                                                                                   \
     template <>                                                                                         \
     int launch_matvec_cheb_n<NV>(const sipg_op* op, int mode, const void* b, const void* u, void* uo,   \
-                                 double sigma, double theta, hipStream_t st) {                          \
+                                 double sigma, double theta, hipStream_t st, int nv) {                  \
         return dispatch_hl<NV>(op->dtype, matvec_geom(op), [&](auto t, auto g) {                        \
-            return launch_one_cheb<NV, decltype(t), decltype(g)::value>(op, mode, b, u, uo, sigma, theta, st); \
+            return launch_one_cheb<NV, decltype(t), decltype(g)::value>(op, mode, b, u, uo, sigma, theta, st, nv); \
         });                                                                                             \
     }                                                                                                   \
     template <>                                                                                         \

@@ -268,7 +268,7 @@ struct Hierarchy {
     T* vec_r(int l, int nv) { return nv > 1 ? lv[l]->mr : lv[l]->r.p; }
 
     // u = S^m(b; u) on level l (u = 0 on entry when zero_init), for nv
-    // right-hand sides at once (every launch covers all of them).
+    // right-hand sides at once (stored one after another, n apart).
     int smooth(int l, bool zero_init, int steps, const std::vector<double>& sig, const std::vector<double>& th,
                hipStream_t st, int nv = 1) {
         Level<T>& L = *lv[l];
@@ -725,10 +725,9 @@ int64_t mg_many_bytes(const sipg_mg* mg, int nv) {
 }
 
 // FP64 preconditioned conjugate gradient with one V-cycle per iteration for
-// nrhs right-hand sides of one hierarchy advanced in lockstep: transfers,
-// merged smoothing passes, coarse solves, dot products and vector updates
-// are one launch for all of them (the products and fused smoothing steps one
-// launch per right-hand side, back to back).  Vector v stops (its x, r and p are no longer updated) at the first
+// nrhs right-hand sides of one hierarchy advanced in lockstep: every product,
+// smoothing step, transfer, coarse solve, dot product and vector update is
+// one launch for all of them.  Vector v stops (its x, r and p are no longer updated) at the first
 // iteration whose residual meets its tolerance (decided on the device, so
 // no vector takes an iteration beyond it); the loop ends when every vector
 // has stopped.

@@ -19,13 +19,11 @@ struct Ghosts {
 
 // y = A x for the operator (dispatch over degree, basis, precision, geometry);
 // with nv > 1 (no ghosts) for nv right-hand sides stored one after another
-// (op->ndofs apart): one launch per right-hand side, back to back (a kernel
-// that moved its parameter block's pointers per workgroup would keep a copy
-// of the block in scratch memory and load through it).
+// (op->ndofs apart), all in one grid.
 int launch_matvec(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g = {}, int nv = 1);
 // Per-degree launchers (one translation unit each).
 template <int N>
-int launch_matvec_n(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g);
+int launch_matvec_n(const sipg_op* op, const void* x, void* y, hipStream_t st, Ghosts g, int nv);
 // y = A x and z = P^-1 y of eq. (jacobi) in one pass (needs op->gl_inv_diag).
 int launch_matvec_pjacobi(const sipg_op* op, const void* x, void* y, void* z, hipStream_t st, Ghosts g = {});
 template <int N>
@@ -42,7 +40,7 @@ int launch_matvec_cheb(const sipg_op* op, int mode, const void* b, const void* u
                        double theta, hipStream_t st, int nv = 1);
 template <int N>
 int launch_matvec_cheb_n(const sipg_op* op, int mode, const void* b, const void* u, void* uo, double sigma,
-                         double theta, hipStream_t st);
+                         double theta, hipStream_t st, int nv);
 
 // Operators of one degree, basis, precision and geometry mode applied by one
 // grid (sipg_batch_apply).  Device arrays: `params` holds one kernel
